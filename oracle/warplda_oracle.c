@@ -1,0 +1,612 @@
+/*
+ * warplda_oracle.c - plain single-threaded CPU oracle for the WarpLDA sweep.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check and the
+ * benchmark's CPU-baseline leg may load this library.  It shares no code,
+ * header, table or helper with the HIP library; both sides are written
+ * separately from the paper (Chen, Li, Zhu, Chen, "WarpLDA: a Cache Efficient
+ * O(1) Algorithm for Latent Dirichlet Allocation", arXiv:1510.08628).
+ *
+ * What it computes (paper Section 4, Algorithm 2 of Appendix A):
+ *   - the token layout: the sparse matrix Y stored column-major, every column
+ *     sorted by document id, plus per-row pointers into it (Section 5.2);
+ *   - initialisation z ~ Dice(K) (Algorithm 2) and a first draw of the
+ *     document proposals from that Z (the word phase consumes doc proposals
+ *     "from the last iteration", which the listing never initialises);
+ *   - the word phase (VisitByColumn): c_w rebuilt from the column, M MH steps
+ *     on the pending doc proposals with the doc-proposal acceptance rate of
+ *     Eq. (7), then M new word proposals drawn from the updated column;
+ *   - the doc phase (VisitByRow): c_d rebuilt from the row, M MH steps on the
+ *     pending word proposals with the word-proposal acceptance rate of
+ *     Eq. (7), then M new doc proposals drawn from the updated row;
+ *   - c_k, the exact histogram of Z at the start of every phase (Section 4.4,
+ *     "M-step": counts computed on the fly from Z);
+ *   - the log joint likelihood of Section 6.1, in double precision;
+ *   - fold-in of new documents against frozen word-topic counts (MCEM E-step
+ *     of Eq. (5) with C_w and c_k held fixed), used by the serving path.
+ *
+ * Readings of points the paper leaves open (each listed in the design notes):
+ *   - the MH chain state starts at z and moves on acceptance (Algorithm 1);
+ *     Algorithm 2's "s <- z^(i-1)" is read as the current state;
+ *   - Algorithm 2's "C_s + beta_bar V" is read as C_s + beta_bar (Eq. 7);
+ *   - counts include the token's own assignment (Eq. 5 has no "not dn");
+ *   - proposals are drawn from the counts *after* this phase's updates;
+ *   - both proposals use random positioning (Section 4.3) over the canonical
+ *     row/column order; the word-proposal mixing weight is L_w / (L_w + K beta)
+ *     (the prior mass of C_wk + beta over K topics);
+ *   - all acceptance and coin arithmetic is IEEE binary32 with the exact
+ *     expressions below, no fused multiply-add, strict "<";
+ *   - randomness is Philox4x32-10 (Salmon et al., SC'11), one call per
+ *     (token, iteration, phase, step) with the counter layout of rng_call().
+ *
+ * Build: gcc -O2 -std=c99 -ffp-contract=off -fno-fast-math -shared -fPIC
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#include <math.h>
+
+/* ------------------------------------------------------------------------ */
+/* Philox4x32-10, from its published definition (Salmon et al., SC'11):     */
+/* ten rounds of two 32x32->64 multiplies with the Weyl key schedule.       */
+/* ------------------------------------------------------------------------ */
+#define PHILOX_MUL_A 0xD2511F53u
+#define PHILOX_MUL_B 0xCD9E8D57u
+#define PHILOX_WEYL_A 0x9E3779B9u
+#define PHILOX_WEYL_B 0xBB67AE85u
+
+void oracle_philox4x32_10(const uint32_t key_in[2], const uint32_t ctr_in[4],
+                          uint32_t out[4])
+{
+    uint32_t x0 = ctr_in[0], x1 = ctr_in[1], x2 = ctr_in[2], x3 = ctr_in[3];
+    uint32_t k0 = key_in[0], k1 = key_in[1];
+    for (int round = 0; round < 10; ++round) {
+        uint64_t pa = (uint64_t)PHILOX_MUL_A * x0;
+        uint64_t pb = (uint64_t)PHILOX_MUL_B * x2;
+        uint32_t n0 = (uint32_t)(pb >> 32) ^ x1 ^ k0;
+        uint32_t n1 = (uint32_t)pb;
+        uint32_t n2 = (uint32_t)(pa >> 32) ^ x3 ^ k1;
+        uint32_t n3 = (uint32_t)pa;
+        x0 = n0; x1 = n1; x2 = n2; x3 = n3;
+        k0 += PHILOX_WEYL_A;
+        k1 += PHILOX_WEYL_B;
+    }
+    out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
+}
+
+enum { PH_INIT = 0, PH_WORD = 1, PH_DOC = 2, PH_FOLD_DOC = 3, PH_FOLD_WORD = 4,
+       PH_FROZEN = 7 };
+
+/* One RNG call.  Counter = (token, iteration, phase<<16 | step, stream). */
+static void rng_call(uint64_t seed, uint32_t token, uint32_t iter,
+                     uint32_t phase, uint32_t step, uint32_t stream,
+                     uint32_t r[4])
+{
+    uint32_t key[2] = { (uint32_t)seed, (uint32_t)(seed >> 32) };
+    uint32_t ctr[4] = { token, iter, (phase << 16) | step, stream };
+    oracle_philox4x32_10(key, ctr, r);
+}
+
+/* Uniform in [0,1) on the 2^-24 grid. */
+static float unif24(uint32_t r) { return (float)(r >> 8) * 0x1p-24f; }
+
+/* Dice(n): a draw from {0, ..., n-1} by multiply-shift. */
+static uint32_t dice(uint32_t r, uint32_t n)
+{
+    return (uint32_t)(((uint64_t)r * (uint64_t)n) >> 32);
+}
+
+/* MH acceptance test for Eq. (7).  cnt_* are the row counts (c_w in the word
+ * phase, c_d in the doc phase) of the candidate c and the current state s,
+ * prior is beta (word phase) or alpha (doc phase); ck_* are the global topic
+ * counts.  Accept iff u * den < num, i.e. with probability min(1, num/den). */
+static int mh_accept(float u, int64_t cnt_c, int64_t cnt_s, float prior,
+                     int64_t ck_s, int64_t ck_c, float beta_bar)
+{
+    float num = ((float)cnt_c + prior) * ((float)ck_s + beta_bar);
+    float den = ((float)cnt_s + prior) * ((float)ck_c + beta_bar);
+    return u * den < num;
+}
+
+/* Mixture coin of Section 2.2 / Section 4.3: pick the count part (random
+ * positioning) with probability L / (L + prior_mass). */
+static int take_count_part(float u, uint64_t L, float prior_mass)
+{
+    return u * ((float)L + prior_mass) < (float)L;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Sampler state                                                            */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    uint32_t V, D, K, M;
+    double alpha, beta;
+    uint64_t seed;
+    uint64_t T;
+    /* layout (Section 5.2): column-major token order, rows by pointer */
+    uint64_t *colptr;   /* V+1 */
+    uint64_t *rowptr;   /* D+1 */
+    uint32_t *row;      /* T: CSC positions of each row, ascending */
+    uint32_t *inv;      /* T: input index -> CSC position */
+    uint32_t *word_of;  /* T: word of each CSC position */
+    uint32_t *doc_of;   /* T: doc of each CSC position */
+    /* per-token data y = (z, z^(1..M)) in CSC order */
+    int32_t *z;         /* T */
+    int32_t *prop;      /* M*T, proposal i (0-based) of token t at i*T + t */
+    int64_t *ck;        /* K: histogram of Z */
+    uint32_t iter;      /* completed iterations */
+    int next_phase;     /* 0 = not initialised, PH_WORD or PH_DOC */
+    uint64_t accepted_word, accepted_doc;   /* last phase of each kind */
+    int visit_reversed; /* visit rows/columns in reverse order (tests) */
+    /* binary32 constants */
+    float a, b, alpha_bar, beta_k, beta_bar;
+} oracle_t;
+
+typedef struct {
+    uint32_t V, D, K, M;
+    double alpha, beta;
+    uint64_t seed;
+} oracle_params;
+
+static void set_constants(oracle_t *o)
+{
+    o->a = (float)o->alpha;
+    o->b = (float)o->beta;
+    o->alpha_bar = (float)o->K * o->a;   /* alpha_bar = K alpha */
+    o->beta_k = (float)o->K * o->b;      /* prior mass of C_wk + beta */
+    o->beta_bar = (float)o->V * o->b;    /* beta_bar = V beta */
+}
+
+/* Layout of Section 5.2: Y in CSC form with every column sorted by row id,
+ * ties kept in input order (stable), and P_CSR pointing into it.  Built as a
+ * stable counting sort by document followed by a stable counting sort by
+ * word, which orders tokens by (word, doc, input index). */
+static int build_layout(oracle_t *o, const uint32_t *word_ids,
+                        const uint32_t *doc_ids)
+{
+    uint64_t T = o->T;
+    uint32_t *by_doc = malloc(T * sizeof(uint32_t) + 1);
+    uint64_t *cnt = calloc((size_t)(o->D > o->V ? o->D : o->V) + 1, sizeof(uint64_t));
+    if (!by_doc || !cnt) { free(by_doc); free(cnt); return -1; }
+    /* pass 1: stable sort of input indices by doc id */
+    for (uint64_t i = 0; i < T; ++i) cnt[doc_ids[i] + 1]++;
+    for (uint32_t d = 0; d < o->D; ++d) cnt[d + 1] += cnt[d];
+    for (uint64_t i = 0; i < T; ++i) by_doc[cnt[doc_ids[i]]++] = (uint32_t)i;
+    /* pass 2: stable sort of that sequence by word id */
+    memset(o->colptr, 0, (o->V + 1) * sizeof(uint64_t));
+    for (uint64_t i = 0; i < T; ++i) o->colptr[word_ids[i] + 1]++;
+    for (uint32_t w = 0; w < o->V; ++w) o->colptr[w + 1] += o->colptr[w];
+    memcpy(cnt, o->colptr, o->V * sizeof(uint64_t));
+    for (uint64_t j = 0; j < T; ++j) {
+        uint32_t i = by_doc[j];
+        uint64_t t = cnt[word_ids[i]]++;
+        o->inv[i] = (uint32_t)t;
+        o->word_of[t] = word_ids[i];
+        o->doc_of[t] = doc_ids[i];
+    }
+    /* rows: CSC positions of each document, ascending */
+    memset(o->rowptr, 0, (o->D + 1) * sizeof(uint64_t));
+    for (uint64_t t = 0; t < T; ++t) o->rowptr[o->doc_of[t] + 1]++;
+    for (uint32_t d = 0; d < o->D; ++d) o->rowptr[d + 1] += o->rowptr[d];
+    memcpy(cnt, o->rowptr, o->D * sizeof(uint64_t));
+    for (uint64_t t = 0; t < T; ++t) o->row[cnt[o->doc_of[t]]++] = (uint32_t)t;
+    free(by_doc);
+    free(cnt);
+    return 0;
+}
+
+void oracle_destroy(oracle_t *o)
+{
+    if (!o) return;
+    free(o->colptr); free(o->rowptr); free(o->row); free(o->inv);
+    free(o->word_of); free(o->doc_of); free(o->z); free(o->prop); free(o->ck);
+    free(o);
+}
+
+/* Returns NULL on invalid input or allocation failure. */
+oracle_t *oracle_create(const oracle_params *p, const uint32_t *word_ids,
+                        const uint32_t *doc_ids, uint64_t n_tokens)
+{
+    if (!p || p->K == 0 || p->M == 0 || p->M > 0xFFFF || p->V == 0 ||
+        p->D == 0 || !(p->alpha > 0) || !(p->beta > 0) ||
+        n_tokens >= ((uint64_t)1 << 32))
+        return NULL;
+    if (n_tokens > 0 && (!word_ids || !doc_ids)) return NULL;
+    for (uint64_t i = 0; i < n_tokens; ++i)
+        if (word_ids[i] >= p->V || doc_ids[i] >= p->D) return NULL;
+    oracle_t *o = calloc(1, sizeof(oracle_t));
+    if (!o) return NULL;
+    o->V = p->V; o->D = p->D; o->K = p->K; o->M = p->M;
+    o->alpha = p->alpha; o->beta = p->beta; o->seed = p->seed;
+    o->T = n_tokens;
+    set_constants(o);
+    size_t T = (size_t)n_tokens;
+    o->colptr = malloc((o->V + 1) * sizeof(uint64_t));
+    o->rowptr = malloc((o->D + 1) * sizeof(uint64_t));
+    o->row = malloc(T * sizeof(uint32_t) + 1);
+    o->inv = malloc(T * sizeof(uint32_t) + 1);
+    o->word_of = malloc(T * sizeof(uint32_t) + 1);
+    o->doc_of = malloc(T * sizeof(uint32_t) + 1);
+    o->z = malloc(T * sizeof(int32_t) + 1);
+    o->prop = malloc((size_t)o->M * T * sizeof(int32_t) + 1);
+    o->ck = calloc(o->K, sizeof(int64_t));
+    if (!o->colptr || !o->rowptr || !o->row || !o->inv || !o->word_of ||
+        !o->doc_of || !o->z || !o->prop || !o->ck ||
+        build_layout(o, word_ids, doc_ids) != 0) {
+        oracle_destroy(o);
+        return NULL;
+    }
+    return o;
+}
+
+static void recount_ck(oracle_t *o)
+{
+    memset(o->ck, 0, o->K * sizeof(int64_t));
+    for (uint64_t t = 0; t < o->T; ++t) o->ck[o->z[t]]++;
+}
+
+/* Draw M doc proposals for every token of row d from the current row
+ * (random positioning with mixing weight L_d / (L_d + alpha_bar), Section 4.3
+ * and Algorithm 2's document phase). */
+static void draw_doc_proposals(oracle_t *o, uint32_t d, uint32_t iter)
+{
+    uint64_t beg = o->rowptr[d], L = o->rowptr[d + 1] - beg;
+    for (uint64_t n = 0; n < L; ++n) {
+        uint32_t t = o->row[beg + n];
+        for (uint32_t i = 1; i <= o->M; ++i) {
+            uint32_t r[4];
+            rng_call(o->seed, t, iter, PH_DOC, i, 0, r);
+            int32_t prop;
+            if (take_count_part(unif24(r[1]), L, o->alpha_bar))
+                prop = o->z[o->row[beg + dice(r[2], (uint32_t)L)]];
+            else
+                prop = (int32_t)dice(r[2], o->K);
+            o->prop[(uint64_t)(i - 1) * o->T + t] = prop;
+        }
+    }
+}
+
+/* Initialisation: z = Dice(K) for every token (Algorithm 2), then the first
+ * doc proposals from that Z, then c_k = histogram(Z). */
+int oracle_init(oracle_t *o)
+{
+    for (uint64_t t = 0; t < o->T; ++t) {
+        uint32_t r[4];
+        rng_call(o->seed, (uint32_t)t, 0, PH_INIT, 0, 0, r);
+        o->z[t] = (int32_t)dice(r[2], o->K);
+    }
+    for (uint32_t d = 0; d < o->D; ++d) draw_doc_proposals(o, d, 0);
+    recount_ck(o);
+    o->iter = 0;
+    o->next_phase = PH_WORD;
+    o->accepted_word = o->accepted_doc = 0;
+    return 0;
+}
+
+/* Word phase, VisitByColumn with f_c (Section 4.4, Algorithm 2). */
+int oracle_word_phase(oracle_t *o)
+{
+    if (o->next_phase != PH_WORD) return -4;
+    uint32_t iter = o->iter + 1;
+    int64_t *cw = malloc(o->K * sizeof(int64_t));
+    int64_t *ck_next = calloc(o->K, sizeof(int64_t));
+    int32_t *znew = malloc(o->T * sizeof(int32_t) + 1);
+    if (!cw || !ck_next || !znew) { free(cw); free(ck_next); free(znew); return -1; }
+    uint64_t accepted = 0;
+    for (uint32_t v = 0; v < o->V; ++v) {
+        uint32_t w = o->visit_reversed ? o->V - 1 - v : v;
+        uint64_t beg = o->colptr[w], L = o->colptr[w + 1] - beg;
+        if (L == 0) continue;
+        /* c_w from the column's assignments at the start of the phase */
+        memset(cw, 0, o->K * sizeof(int64_t));
+        for (uint64_t n = 0; n < L; ++n) cw[o->z[beg + n]]++;
+        /* M MH steps on the doc proposals, counts frozen (delayed update) */
+        for (uint64_t n = 0; n < L; ++n) {
+            uint32_t t = (uint32_t)(beg + n);
+            int32_t s = o->z[t];
+            for (uint32_t i = 1; i <= o->M; ++i) {
+                uint32_t r[4];
+                rng_call(o->seed, t, iter, PH_WORD, i, 0, r);
+                int32_t c = o->prop[(uint64_t)(i - 1) * o->T + t];
+                if (mh_accept(unif24(r[0]), cw[c], cw[s], o->b, o->ck[s],
+                              o->ck[c], o->beta_bar)) {
+                    s = c;
+                    accepted++;
+                }
+            }
+            znew[t] = s;
+        }
+        /* commit the column, then draw word proposals from it */
+        for (uint64_t n = 0; n < L; ++n) o->z[beg + n] = znew[beg + n];
+        for (uint64_t n = 0; n < L; ++n) {
+            uint32_t t = (uint32_t)(beg + n);
+            for (uint32_t i = 1; i <= o->M; ++i) {
+                uint32_t r[4];
+                rng_call(o->seed, t, iter, PH_WORD, i, 0, r);
+                int32_t prop;
+                if (take_count_part(unif24(r[1]), L, o->beta_k))
+                    prop = o->z[beg + dice(r[2], (uint32_t)L)];
+                else
+                    prop = (int32_t)dice(r[2], o->K);
+                o->prop[(uint64_t)(i - 1) * o->T + t] = prop;
+            }
+            ck_next[o->z[t]]++;
+        }
+    }
+    memcpy(o->ck, ck_next, o->K * sizeof(int64_t));
+    free(cw); free(ck_next); free(znew);
+    o->accepted_word = accepted;
+    o->next_phase = PH_DOC;
+    return 0;
+}
+
+/* Document phase, VisitByRow with f_r (Section 4.4, Algorithm 2). */
+int oracle_doc_phase(oracle_t *o)
+{
+    if (o->next_phase != PH_DOC) return -4;
+    uint32_t iter = o->iter + 1;
+    int64_t *cd = malloc(o->K * sizeof(int64_t));
+    int64_t *ck_next = calloc(o->K, sizeof(int64_t));
+    int32_t *znew = malloc(o->T * sizeof(int32_t) + 1);
+    if (!cd || !ck_next || !znew) { free(cd); free(ck_next); free(znew); return -1; }
+    uint64_t accepted = 0;
+    for (uint32_t e = 0; e < o->D; ++e) {
+        uint32_t d = o->visit_reversed ? o->D - 1 - e : e;
+        uint64_t beg = o->rowptr[d], L = o->rowptr[d + 1] - beg;
+        if (L == 0) continue;
+        memset(cd, 0, o->K * sizeof(int64_t));
+        for (uint64_t n = 0; n < L; ++n) cd[o->z[o->row[beg + n]]]++;
+        for (uint64_t n = 0; n < L; ++n) {
+            uint32_t t = o->row[beg + n];
+            int32_t s = o->z[t];
+            for (uint32_t i = 1; i <= o->M; ++i) {
+                uint32_t r[4];
+                rng_call(o->seed, t, iter, PH_DOC, i, 0, r);
+                int32_t c = o->prop[(uint64_t)(i - 1) * o->T + t];
+                if (mh_accept(unif24(r[0]), cd[c], cd[s], o->a, o->ck[s],
+                              o->ck[c], o->beta_bar)) {
+                    s = c;
+                    accepted++;
+                }
+            }
+            znew[t] = s;
+        }
+        for (uint64_t n = 0; n < L; ++n) {
+            uint32_t t = o->row[beg + n];
+            o->z[t] = znew[t];
+        }
+        draw_doc_proposals(o, d, iter);
+        for (uint64_t n = 0; n < L; ++n) ck_next[o->z[o->row[beg + n]]]++;
+    }
+    memcpy(o->ck, ck_next, o->K * sizeof(int64_t));
+    free(cd); free(ck_next); free(znew);
+    o->accepted_doc = accepted;
+    o->iter = iter;
+    o->next_phase = PH_WORD;
+    return 0;
+}
+
+int oracle_iterate(oracle_t *o, uint32_t n)
+{
+    for (uint32_t k = 0; k < n; ++k) {
+        int rc = oracle_word_phase(o);
+        if (rc) return rc;
+        rc = oracle_doc_phase(o);
+        if (rc) return rc;
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Log joint likelihood log p(W, Z | alpha, beta) of Section 6.1, binary64. */
+/* ------------------------------------------------------------------------ */
+double oracle_log_joint(uint64_t T, uint32_t V, uint32_t D, uint32_t K,
+                        double alpha, double beta, const uint32_t *word_ids,
+                        const uint32_t *doc_ids, const int32_t *z)
+{
+    double alpha_bar = K * alpha, beta_bar = V * beta;
+    int64_t *cdk = calloc((size_t)D * K, sizeof(int64_t));
+    int64_t *cwk = calloc((size_t)V * K, sizeof(int64_t));
+    int64_t *ck = calloc(K, sizeof(int64_t));
+    int64_t *Ld = calloc(D, sizeof(int64_t));
+    if (!cdk || !cwk || !ck || !Ld) {
+        free(cdk); free(cwk); free(ck); free(Ld);
+        return NAN;
+    }
+    for (uint64_t i = 0; i < T; ++i) {
+        cdk[(size_t)doc_ids[i] * K + z[i]]++;
+        cwk[(size_t)word_ids[i] * K + z[i]]++;
+        ck[z[i]]++;
+        Ld[doc_ids[i]]++;
+    }
+    double ll = 0.0;
+    /* document part: prod_d Gamma(abar)/Gamma(abar+L_d) prod_k Gamma(a+C_dk)/Gamma(a) */
+    for (uint32_t d = 0; d < D; ++d) {
+        if (Ld[d] == 0) continue;
+        ll += lgamma(alpha_bar) - lgamma(alpha_bar + (double)Ld[d]);
+        for (uint32_t k = 0; k < K; ++k) {
+            int64_t c = cdk[(size_t)d * K + k];
+            if (c) ll += lgamma(alpha + (double)c) - lgamma(alpha);
+        }
+    }
+    /* word part: prod_k Gamma(bbar)/Gamma(bbar+C_k) prod_w Gamma(b+C_kw)/Gamma(b) */
+    for (uint32_t k = 0; k < K; ++k) {
+        if (ck[k]) ll += lgamma(beta_bar) - lgamma(beta_bar + (double)ck[k]);
+    }
+    for (uint32_t w = 0; w < V; ++w)
+        for (uint32_t k = 0; k < K; ++k) {
+            int64_t c = cwk[(size_t)w * K + k];
+            if (c) ll += lgamma(beta + (double)c) - lgamma(beta);
+        }
+    free(cdk); free(cwk); free(ck); free(Ld);
+    return ll;
+}
+
+/* LL of the sampler's current Z (same formula, counts from the layout). */
+double oracle_log_likelihood(const oracle_t *o)
+{
+    double alpha_bar = o->K * o->alpha, beta_bar = o->V * o->beta;
+    int64_t *cnt = calloc(o->K, sizeof(int64_t));
+    if (!cnt) return NAN;
+    double ll = 0.0;
+    for (uint32_t d = 0; d < o->D; ++d) {
+        uint64_t beg = o->rowptr[d], L = o->rowptr[d + 1] - beg;
+        if (L == 0) continue;
+        memset(cnt, 0, o->K * sizeof(int64_t));
+        for (uint64_t n = 0; n < L; ++n) cnt[o->z[o->row[beg + n]]]++;
+        ll += lgamma(alpha_bar) - lgamma(alpha_bar + (double)L);
+        for (uint32_t k = 0; k < o->K; ++k)
+            if (cnt[k]) ll += lgamma(o->alpha + (double)cnt[k]) - lgamma(o->alpha);
+    }
+    for (uint32_t w = 0; w < o->V; ++w) {
+        uint64_t beg = o->colptr[w], L = o->colptr[w + 1] - beg;
+        if (L == 0) continue;
+        memset(cnt, 0, o->K * sizeof(int64_t));
+        for (uint64_t n = 0; n < L; ++n) cnt[o->z[beg + n]]++;
+        for (uint32_t k = 0; k < o->K; ++k)
+            if (cnt[k]) ll += lgamma(o->beta + (double)cnt[k]) - lgamma(o->beta);
+    }
+    memset(cnt, 0, o->K * sizeof(int64_t));
+    for (uint64_t t = 0; t < o->T; ++t) cnt[o->z[t]]++;
+    for (uint32_t k = 0; k < o->K; ++k)
+        if (cnt[k]) ll += lgamma(beta_bar) - lgamma(beta_bar + (double)cnt[k]);
+    free(cnt);
+    return ll;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Accessors                                                                */
+/* ------------------------------------------------------------------------ */
+uint64_t oracle_num_tokens(const oracle_t *o) { return o->T; }
+uint32_t oracle_iteration(const oracle_t *o) { return o->iter; }
+uint64_t oracle_accepted(const oracle_t *o, int phase)
+{
+    return phase == PH_WORD ? o->accepted_word : o->accepted_doc;
+}
+void oracle_set_visit_reversed(oracle_t *o, int rev) { o->visit_reversed = rev; }
+
+/* z (and the M proposals, proposal-major) in input order. */
+void oracle_copy_assignments(const oracle_t *o, int32_t *z_input,
+                             int32_t *props_input)
+{
+    for (uint64_t i = 0; i < o->T; ++i) {
+        uint32_t t = o->inv[i];
+        if (z_input) z_input[i] = o->z[t];
+        if (props_input)
+            for (uint32_t m = 0; m < o->M; ++m)
+                props_input[(uint64_t)m * o->T + i] = o->prop[(uint64_t)m * o->T + t];
+    }
+}
+
+/* z and proposals in CSC (column-major) order. */
+void oracle_copy_csc(const oracle_t *o, int32_t *z_csc, int32_t *props_csc)
+{
+    if (z_csc) memcpy(z_csc, o->z, o->T * sizeof(int32_t));
+    if (props_csc) memcpy(props_csc, o->prop, (size_t)o->M * o->T * sizeof(int32_t));
+}
+
+void oracle_copy_layout(const oracle_t *o, uint64_t *colptr, uint64_t *rowptr,
+                        uint32_t *row, uint32_t *inv)
+{
+    if (colptr) memcpy(colptr, o->colptr, (o->V + 1) * sizeof(uint64_t));
+    if (rowptr) memcpy(rowptr, o->rowptr, (o->D + 1) * sizeof(uint64_t));
+    if (row) memcpy(row, o->row, o->T * sizeof(uint32_t));
+    if (inv) memcpy(inv, o->inv, o->T * sizeof(uint32_t));
+}
+
+void oracle_copy_topic_counts(const oracle_t *o, int64_t *ck)
+{
+    memcpy(ck, o->ck, o->K * sizeof(int64_t));
+}
+
+/* Checkpoint: (iteration, next phase, z, proposals, ck) in CSC order. */
+uint64_t oracle_state_bytes(const oracle_t *o)
+{
+    return 16 + (uint64_t)(1 + o->M) * o->T * 4 + (uint64_t)o->K * 8;
+}
+
+int oracle_save_state(const oracle_t *o, void *buf, uint64_t bytes)
+{
+    if (bytes < oracle_state_bytes(o)) return -1;
+    uint8_t *p = buf;
+    uint64_t hdr[2] = { o->iter, (uint64_t)o->next_phase };
+    memcpy(p, hdr, 16); p += 16;
+    memcpy(p, o->z, o->T * 4); p += o->T * 4;
+    memcpy(p, o->prop, (size_t)o->M * o->T * 4); p += (size_t)o->M * o->T * 4;
+    memcpy(p, o->ck, (size_t)o->K * 8);
+    return 0;
+}
+
+int oracle_load_state(oracle_t *o, const void *buf, uint64_t bytes)
+{
+    if (bytes < oracle_state_bytes(o)) return -1;
+    const uint8_t *p = buf;
+    uint64_t hdr[2];
+    memcpy(hdr, p, 16); p += 16;
+    o->iter = (uint32_t)hdr[0];
+    o->next_phase = (int)hdr[1];
+    memcpy(o->z, p, o->T * 4); p += o->T * 4;
+    memcpy(o->prop, p, (size_t)o->M * o->T * 4); p += (size_t)o->M * o->T * 4;
+    memcpy(o->ck, p, (size_t)o->K * 8);
+    return 0;
+}
+
+/* Overwrite z (CSC order) and recompute c_k; proposals are left unchanged.
+ * Used by the tests to start the sampler from a chosen state. */
+void oracle_set_csc_state(oracle_t *o, const int32_t *z_csc,
+                          const int32_t *props_csc)
+{
+    memcpy(o->z, z_csc, o->T * sizeof(int32_t));
+    if (props_csc) memcpy(o->prop, props_csc, (size_t)o->M * o->T * sizeof(int32_t));
+    recount_ck(o);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Frozen-count chain of one token (test harness for Eq. (5)-(7)).          */
+/* With Z held fixed, the state x of token t is moved by M steps of the doc */
+/* proposal (drawn by random positioning over row d) and/or M steps of the  */
+/* word proposal (random positioning over column w), each accepted with the */
+/* rate of Eq. (7).  Both kernels leave q(k) of Eq. (5) invariant; hist     */
+/* receives the state after every round.  mode: 1 doc, 2 word, 3 both.      */
+/* ------------------------------------------------------------------------ */
+int oracle_frozen_chain(const oracle_t *o, uint32_t t, uint32_t rounds,
+                        int mode, uint64_t *hist)
+{
+    if (t >= o->T) return -1;
+    uint32_t w = o->word_of[t], d = o->doc_of[t];
+    uint64_t cbeg = o->colptr[w], Lw = o->colptr[w + 1] - cbeg;
+    uint64_t rbeg = o->rowptr[d], Ld = o->rowptr[d + 1] - rbeg;
+    int64_t *cw = calloc(o->K, sizeof(int64_t));
+    int64_t *cd = calloc(o->K, sizeof(int64_t));
+    if (!cw || !cd) { free(cw); free(cd); return -1; }
+    for (uint64_t n = 0; n < Lw; ++n) cw[o->z[cbeg + n]]++;
+    for (uint64_t n = 0; n < Ld; ++n) cd[o->z[o->row[rbeg + n]]]++;
+    memset(hist, 0, o->K * sizeof(uint64_t));
+    int32_t x = o->z[t];
+    for (uint32_t rd = 0; rd < rounds; ++rd) {
+        for (uint32_t i = 1; i <= o->M; ++i) {
+            uint32_t r[4];
+            if (mode & 1) {   /* doc proposal, judged with c_w (Eq. 7 top) */
+                rng_call(o->seed, rd, i, PH_FROZEN, 1, t, r);
+                int32_t c = take_count_part(unif24(r[1]), Ld, o->alpha_bar)
+                                ? o->z[o->row[rbeg + dice(r[2], (uint32_t)Ld)]]
+                                : (int32_t)dice(r[2], o->K);
+                if (mh_accept(unif24(r[0]), cw[c], cw[x], o->b, o->ck[x],
+                              o->ck[c], o->beta_bar))
+                    x = c;
+            }
+            if (mode & 2) {   /* word proposal, judged with c_d (Eq. 7 bottom) */
+                rng_call(o->seed, rd, i, PH_FROZEN, 2, t, r);
+                int32_t c = take_count_part(unif24(r[1]), Lw, o->beta_k)
+                                ? o->z[cbeg + dice(r[2], (uint32_t)Lw)]
+                                : (int32_t)dice(r[2], o->K);
+                if (mh_accept(unif24(r[0]), cd[c], cd[x], o->a, o->ck[x],
+                              o->ck[c], o->beta_bar))
+                    x = c;
+            }
+        }
+        hist[x]++;
+    }
+    free(cw); free(cd);
+    return 0;
+}

@@ -1,0 +1,154 @@
+"""Seeded synthetic corpora for the WarpLDA sweep.
+
+This module only draws inputs.  It holds none of the sampler's arithmetic and
+is shared by the tests, the benchmark and the smoke check, which feed the same
+token lists to the CPU oracle and to the HIP library.
+
+Corpus shapes follow the dataset table of the paper (Section 6.1, Table 3:
+NYTimes D=300K, T=100M, V=102K; PubMed D=8.2M, T=738M, V=141K; ClueWeb12
+V=1M).  The datasets themselves are not available, so these generators stand in
+for them:
+
+* ``lda_corpus``    - the LDA generative process of Section 2.1 (theta_d ~
+  Dir(alpha), phi_k ~ Dir(beta), z ~ Mult(theta_d), w ~ Mult(phi_z)) with
+  Poisson document lengths.
+* ``zipf_corpus``   - iid words from a truncated Zipf(s) law over V ranks
+  (ranks mapped to word ids through a seeded permutation), document lengths
+  round(lognormal) with the given distribution *mean* (mu = ln m - sigma^2/2),
+  clipped to >= 1.
+
+Every array is uint32; tokens are emitted document by document, but nothing
+downstream relies on that order.
+"""
+from __future__ import annotations
+
+import dataclasses
+import numpy as np
+
+CORPUS_SEED_BASE = 20151028
+
+
+@dataclasses.dataclass
+class Corpus:
+    word_ids: np.ndarray          # uint32[T]
+    doc_ids: np.ndarray           # uint32[T]
+    V: int
+    D: int
+    true_z: np.ndarray | None = None   # int32[T] for LDA-generated corpora
+
+    @property
+    def T(self) -> int:
+        return int(self.word_ids.shape[0])
+
+
+def _lognormal_lengths(rng, D, mean, sigma, lo=1, hi=None):
+    mu = np.log(mean) - 0.5 * sigma * sigma
+    L = np.rint(rng.lognormal(mu, sigma, size=D)).astype(np.int64)
+    L = np.maximum(L, lo)
+    if hi is not None:
+        L = np.minimum(L, hi)
+    return L
+
+
+def zipf_corpus(D: int, V: int, s: float, mean_len: float, sigma: float,
+                seed: int, chunk: int = 1 << 24) -> Corpus:
+    """iid Zipf(s) words over V ranks, lognormal document lengths."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    lengths = _lognormal_lengths(rng, D, mean_len, sigma)
+    T = int(lengths.sum())
+    if T >= 1 << 32:
+        raise ValueError("corpus too large for 32-bit token indices")
+    w = np.arange(1, V + 1, dtype=np.float64) ** (-s)
+    cdf = np.cumsum(w)
+    cdf /= cdf[-1]
+    rank_to_word = rng.permutation(V).astype(np.uint32)
+    word_ids = np.empty(T, dtype=np.uint32)
+    for lo in range(0, T, chunk):
+        hi = min(T, lo + chunk)
+        u = rng.random(hi - lo)
+        r = np.searchsorted(cdf, u, side="right")
+        np.minimum(r, V - 1, out=r)
+        word_ids[lo:hi] = rank_to_word[r]
+    doc_ids = np.repeat(np.arange(D, dtype=np.uint32), lengths)
+    return Corpus(word_ids, doc_ids, V, D)
+
+
+def lda_corpus(D: int, V: int, K: int, mean_len: float, alpha: float,
+               beta: float, seed: int) -> Corpus:
+    """The LDA generative process with Poisson(mean_len) document lengths."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    phi = rng.dirichlet(np.full(V, beta), size=K)          # K x V
+    theta = rng.dirichlet(np.full(K, alpha), size=D)       # D x K
+    lengths = np.maximum(rng.poisson(mean_len, size=D), 1)
+    T = int(lengths.sum())
+    doc_ids = np.repeat(np.arange(D, dtype=np.uint32), lengths)
+    word_ids = np.empty(T, dtype=np.uint32)
+    true_z = np.empty(T, dtype=np.int32)
+    cphi = np.cumsum(phi, axis=1)
+    cphi /= cphi[:, -1:]
+    ctheta = np.cumsum(theta, axis=1)
+    ctheta /= ctheta[:, -1:]
+    pos = 0
+    for d in range(D):
+        n = int(lengths[d])
+        z = np.searchsorted(ctheta[d], rng.random(n), side="right")
+        np.minimum(z, K - 1, out=z)
+        u = rng.random(n)
+        wv = np.empty(n, dtype=np.int64)
+        for k in np.unique(z):
+            m = z == k
+            wv[m] = np.searchsorted(cphi[k], u[m], side="right")
+        np.minimum(wv, V - 1, out=wv)
+        word_ids[pos:pos + n] = wv
+        true_z[pos:pos + n] = z
+        pos += n
+    return Corpus(word_ids, doc_ids, V, D, true_z)
+
+
+def random_corpus(T: int, V: int, D: int, seed: int) -> Corpus:
+    """Uniform word and doc ids (small edge-case corpora for the tests)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return Corpus(rng.integers(0, V, T, dtype=np.uint32),
+                  rng.integers(0, D, T, dtype=np.uint32), V, D)
+
+
+# --------------------------------------------------------------------------
+# Named workloads (sizes from the paper's dataset table; fit settings from the
+# paper's experimental setup: alpha = 50/K, beta = 0.01).
+# --------------------------------------------------------------------------
+@dataclasses.dataclass
+class Workload:
+    name: str
+    K: int
+    M: int
+    alpha: float
+    beta: float
+    iters: int
+    make: object          # () -> Corpus
+
+
+WORKLOADS = {
+    "tiny-lda-k16": Workload(
+        "tiny-lda-k16", K=16, M=2, alpha=50.0 / 16, beta=0.01, iters=50,
+        make=lambda: lda_corpus(1000, 2000, 16, 100.0, 50.0 / 16, 0.01,
+                                CORPUS_SEED_BASE + 0)),
+    "nytimes-shape-k1e3": Workload(
+        "nytimes-shape-k1e3", K=1000, M=2, alpha=0.05, beta=0.01, iters=100,
+        make=lambda: zipf_corpus(300_000, 100_000, 1.0, 330.0, 0.8,
+                                 CORPUS_SEED_BASE + 1)),
+    "pubmed-shape-k1e4": Workload(
+        "pubmed-shape-k1e4", K=10_000, M=4, alpha=0.005, beta=0.01, iters=50,
+        make=lambda: zipf_corpus(8_000_000, 140_000, 1.05, 90.0, 0.7,
+                                 CORPUS_SEED_BASE + 2)),
+    "clueweb-share-k1e6": Workload(
+        "clueweb-share-k1e6", K=1_000_000, M=2, alpha=0.01, beta=0.01, iters=20,
+        make=lambda: zipf_corpus(20_000_000, 1_000_000, 1.1, 100.0, 1.0,
+                                 CORPUS_SEED_BASE + 3)),
+}
+
+
+def doc_prefix(c: Corpus, n_docs: int) -> Corpus:
+    """The tokens of documents [0, n_docs) (the generators emit docs in order)."""
+    n = int(np.searchsorted(c.doc_ids, n_docs, side="left"))
+    tz = None if c.true_z is None else c.true_z[:n]
+    return Corpus(c.word_ids[:n], c.doc_ids[:n], c.V, n_docs, tz)
