@@ -1,0 +1,150 @@
+/*
+ * warplda.h - C ABI of the MI355X (gfx950) WarpLDA sampler.
+ *
+ * The library runs the per-iteration Metropolis-Hastings sweep of WarpLDA
+ * (Chen, Li, Zhu, Chen, arXiv:1510.08628): a word phase that visits the
+ * tokens grouped by word and a document phase that visits them grouped by
+ * document (Section 4.4 "Reordering the computation"; Algorithm 2 of
+ * Appendix A).  The calls mirror the paper's statement of the problem
+ * (Section 2.1: a corpus of word-id / doc-id tokens, K topics, symmetric
+ * Dirichlet priors alpha and beta; Section 4.1: M proposals per token) and its
+ * programming model (Section 5.1: AddEntry = create, VisitByColumn = word
+ * phase, VisitByRow = document phase).
+ *
+ * Conventions
+ *   - Every call returns a wlda_status; WLDA_OK == 0.  No call aborts or
+ *     throws.  After WLDA_E_HIP the handle is unusable except for destroy.
+ *   - Host arrays passed in are read during the call only; the caller keeps
+ *     ownership.  Output arrays are caller-allocated host memory.
+ *   - Device memory: the caller allocates ONE device buffer ("workspace") of
+ *     at least wlda_workspace_bytes() bytes and keeps it alive until
+ *     wlda_destroy(); the library carves all device state out of it and makes
+ *     no device allocation of its own.  Its base must be 256-byte aligned.
+ *   - Streams: every call enqueues its work on the hipStream_t given to
+ *     wlda_create (passed as void*; NULL = the default stream).  Only the
+ *     calls marked "synchronises" wait for that stream.
+ *   - One handle must not be used from two threads at once.
+ *   - Limits: 1 <= M <= 4, 1 <= K <= 2^21 - 1, n_tokens < 2^32, V, D >= 1.
+ *
+ * Randomness: Philox4x32-10 (Salmon et al., SC'11) keyed by the 64-bit seed,
+ * one call per (token, iteration, phase, step) with counter
+ * (t, iteration, phase << 16 | step, 0), where t is the token's position in
+ * the canonical column-major order (tokens sorted by word, then document,
+ * then input index).  Results are therefore independent of launch geometry
+ * and bit-identical to any implementation of the same definition.
+ */
+#ifndef WARPLDA_H
+#define WARPLDA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    WLDA_OK = 0,
+    WLDA_E_INVALID = -1,     /* bad argument: null pointer, id out of range,
+                                K/M/alpha/beta/size outside the limits      */
+    WLDA_E_WORKSPACE = -2,   /* workspace too small or misaligned          */
+    WLDA_E_HIP = -3,         /* a HIP runtime call failed (sticky)          */
+    WLDA_E_STATE = -4,       /* call out of order (e.g. a phase before init,
+                                a doc phase before the word phase)          */
+    WLDA_E_UNSUPPORTED = -5  /* valid input this build does not handle      */
+} wlda_status;
+
+/* Problem definition (Section 2.1; Section 4.1 for M). */
+typedef struct {
+    uint32_t V;      /* vocabulary size (declared; enters beta_bar = V beta) */
+    uint32_t D;      /* number of documents                                  */
+    uint32_t K;      /* number of topics                                     */
+    uint32_t M;      /* MH steps (= proposals stored) per token per phase    */
+    double alpha;    /* symmetric document-topic prior, > 0                  */
+    double beta;     /* symmetric topic-word prior, > 0                      */
+    uint64_t seed;   /* Philox key                                           */
+} wlda_params;
+
+typedef struct wlda_sampler_s *wlda_sampler;
+
+/* Exact workspace size for this corpus (reads the token arrays once).
+ * word_ids[i] < V and doc_ids[i] < D for all i < n_tokens (host arrays). */
+wlda_status wlda_workspace_bytes(const wlda_params *p, const uint32_t *word_ids,
+                                 const uint32_t *doc_ids, uint64_t n_tokens,
+                                 uint64_t *bytes);
+
+/* AddEntry for every token (Section 5.1): builds the column-major token
+ * layout with each column sorted by document id and the per-row pointers into
+ * it (Section 5.2), uploads it into the workspace and returns a handle.  The
+ * token arrays are host memory in any order; token i is (word_ids[i],
+ * doc_ids[i]).  Synchronises. */
+wlda_status wlda_create(const wlda_params *p, const uint32_t *word_ids,
+                        const uint32_t *doc_ids, uint64_t n_tokens,
+                        void *dev_workspace, uint64_t workspace_bytes,
+                        void *hip_stream, wlda_sampler *out);
+
+/* Initialisation (Algorithm 2): z = Dice(K) for every token, then the first
+ * M document proposals per token drawn from that Z by the document phase's
+ * proposal rule, then c_k = histogram(Z).  May be called again to restart. */
+wlda_status wlda_init(wlda_sampler s);
+
+/* Word phase = VisitByColumn (Section 4.4, Algorithm 2): per word, c_w is
+ * rebuilt from the column, each token runs M MH steps over its pending
+ * document proposals with the acceptance rate pi_doc of Eq. (7) (counts held
+ * fixed for the whole phase), and then draws M word proposals from the
+ * updated column (random positioning, Section 4.3, mixing weight
+ * L_w / (L_w + K beta)).  Requires init; must alternate with doc_phase. */
+wlda_status wlda_word_phase(wlda_sampler s);
+
+/* Document phase = VisitByRow: c_d rebuilt per document, M MH steps over the
+ * pending word proposals with pi_word of Eq. (7), then M document proposals
+ * drawn from the updated row (mixing weight L_d / (L_d + K alpha)).
+ * Completes one iteration. */
+wlda_status wlda_doc_phase(wlda_sampler s);
+
+/* n x (word phase, doc phase), enqueued back to back. */
+wlda_status wlda_iterate(wlda_sampler s, uint32_t n);
+
+/* Log joint likelihood log p(W, Z | alpha, beta) of Section 6.1 for the
+ * current Z, accumulated in binary64.  Synchronises. */
+wlda_status wlda_log_likelihood(wlda_sampler s, double *ll);
+
+/* Copies z (n_tokens int32, caller's input order) and, if props != NULL, the
+ * M pending proposals (M x n_tokens int32, proposal-major, input order).
+ * Synchronises. */
+wlda_status wlda_copy_assignments(wlda_sampler s, int32_t *z, int32_t *props);
+
+/* Copies z and the proposals in the canonical column-major order (same
+ * shapes as above).  Synchronises. */
+wlda_status wlda_copy_assignments_csc(wlda_sampler s, int32_t *z, int32_t *props);
+
+/* Copies c_k (K entries), the exact histogram of the current Z.  Synchronises. */
+wlda_status wlda_copy_topic_counts(wlda_sampler s, int64_t *ck);
+
+/* Number of MH steps whose acceptance test passed in the most recent word
+ * phase (phase = 1) or document phase (phase = 2).  Synchronises. */
+wlda_status wlda_accepted(wlda_sampler s, int phase, uint64_t *count);
+
+/* Completed iterations. */
+wlda_status wlda_iteration(wlda_sampler s, uint32_t *iteration);
+
+/* Checkpoint of (iteration, next phase, z, proposals) - the whole sampler
+ * state; the layout is rebuilt from the corpus at create.  save synchronises;
+ * load replaces the state and recomputes c_k on the device. */
+wlda_status wlda_state_bytes(wlda_sampler s, uint64_t *bytes);
+wlda_status wlda_save_state(wlda_sampler s, void *host_buf, uint64_t bytes);
+wlda_status wlda_load_state(wlda_sampler s, const void *host_buf, uint64_t bytes);
+
+/* Sets z (input order, host) and keeps the pending proposals, recomputing c_k;
+ * the next call must be a word phase.  For tests and warm starts. */
+wlda_status wlda_set_assignments(wlda_sampler s, const int32_t *z, const int32_t *props);
+
+/* Releases host-side state; the workspace is the caller's to free. */
+wlda_status wlda_destroy(wlda_sampler s);
+
+const char *wlda_strerror(wlda_status e);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WARPLDA_H */

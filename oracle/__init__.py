@@ -85,6 +85,8 @@ def lib():
         L.oracle_frozen_chain.argtypes = [vp, u32, u32, C.c_int, vp]
         L.oracle_frozen_chain.restype = C.c_int
         L.oracle_philox4x32_10.argtypes = [vp, vp, vp]
+        L.oracle_phase_subset.argtypes = [vp, C.c_int, u32, vp, u64]
+        L.oracle_phase_subset.restype = C.c_int
         _lib = L
     return _lib
 
@@ -200,6 +202,10 @@ class Oracle:
             lib().oracle_set_csc_state(self.h, _ptr(z), _ptr(p))
         else:
             lib().oracle_set_csc_state(self.h, _ptr(z), None)
+
+    def phase_subset(self, phase: int, iteration: int, segments):
+        segs = np.ascontiguousarray(segments, dtype=np.uint32)
+        self._check(lib().oracle_phase_subset(self.h, phase, iteration, _ptr(segs), len(segs)))
 
     def frozen_chain(self, t: int, rounds: int, mode: int) -> np.ndarray:
         hist = np.zeros(self.K, dtype=np.uint64)

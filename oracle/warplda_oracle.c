@@ -283,6 +283,51 @@ int oracle_init(oracle_t *o)
     return 0;
 }
 
+/* f_c of Section 5.1 for one column w: c_w from the column's assignments at
+ * the start of the phase, M MH steps per token on its doc proposals with the
+ * counts frozen (delayed update, Section 4.2), commit of the whole column,
+ * then M word proposals per token drawn from the updated column.  Adds the
+ * column's new assignments to ck_next (if given) and the passed acceptance
+ * tests to *accepted.  cw and znew are scratch (K and T entries). */
+static void word_column(oracle_t *o, uint32_t w, uint32_t iter, int64_t *ck_next,
+                        uint64_t *accepted, int64_t *cw, int32_t *znew)
+{
+    uint64_t beg = o->colptr[w], L = o->colptr[w + 1] - beg;
+    if (L == 0) return;
+    memset(cw, 0, o->K * sizeof(int64_t));
+    for (uint64_t n = 0; n < L; ++n) cw[o->z[beg + n]]++;
+    for (uint64_t n = 0; n < L; ++n) {
+        uint32_t t = (uint32_t)(beg + n);
+        int32_t s = o->z[t];
+        for (uint32_t i = 1; i <= o->M; ++i) {
+            uint32_t r[4];
+            rng_call(o->seed, t, iter, PH_WORD, i, 0, r);
+            int32_t c = o->prop[(uint64_t)(i - 1) * o->T + t];
+            if (mh_accept(unif24(r[0]), cw[c], cw[s], o->b, o->ck[s],
+                          o->ck[c], o->beta_bar)) {
+                s = c;
+                (*accepted)++;
+            }
+        }
+        znew[t] = s;
+    }
+    for (uint64_t n = 0; n < L; ++n) o->z[beg + n] = znew[beg + n];
+    for (uint64_t n = 0; n < L; ++n) {
+        uint32_t t = (uint32_t)(beg + n);
+        for (uint32_t i = 1; i <= o->M; ++i) {
+            uint32_t r[4];
+            rng_call(o->seed, t, iter, PH_WORD, i, 0, r);
+            int32_t prop;
+            if (take_count_part(unif24(r[1]), L, o->beta_k))
+                prop = o->z[beg + dice(r[2], (uint32_t)L)];
+            else
+                prop = (int32_t)dice(r[2], o->K);
+            o->prop[(uint64_t)(i - 1) * o->T + t] = prop;
+        }
+        if (ck_next) ck_next[o->z[t]]++;
+    }
+}
+
 /* Word phase, VisitByColumn with f_c (Section 4.4, Algorithm 2). */
 int oracle_word_phase(oracle_t *o)
 {
@@ -295,49 +340,47 @@ int oracle_word_phase(oracle_t *o)
     uint64_t accepted = 0;
     for (uint32_t v = 0; v < o->V; ++v) {
         uint32_t w = o->visit_reversed ? o->V - 1 - v : v;
-        uint64_t beg = o->colptr[w], L = o->colptr[w + 1] - beg;
-        if (L == 0) continue;
-        /* c_w from the column's assignments at the start of the phase */
-        memset(cw, 0, o->K * sizeof(int64_t));
-        for (uint64_t n = 0; n < L; ++n) cw[o->z[beg + n]]++;
-        /* M MH steps on the doc proposals, counts frozen (delayed update) */
-        for (uint64_t n = 0; n < L; ++n) {
-            uint32_t t = (uint32_t)(beg + n);
-            int32_t s = o->z[t];
-            for (uint32_t i = 1; i <= o->M; ++i) {
-                uint32_t r[4];
-                rng_call(o->seed, t, iter, PH_WORD, i, 0, r);
-                int32_t c = o->prop[(uint64_t)(i - 1) * o->T + t];
-                if (mh_accept(unif24(r[0]), cw[c], cw[s], o->b, o->ck[s],
-                              o->ck[c], o->beta_bar)) {
-                    s = c;
-                    accepted++;
-                }
-            }
-            znew[t] = s;
-        }
-        /* commit the column, then draw word proposals from it */
-        for (uint64_t n = 0; n < L; ++n) o->z[beg + n] = znew[beg + n];
-        for (uint64_t n = 0; n < L; ++n) {
-            uint32_t t = (uint32_t)(beg + n);
-            for (uint32_t i = 1; i <= o->M; ++i) {
-                uint32_t r[4];
-                rng_call(o->seed, t, iter, PH_WORD, i, 0, r);
-                int32_t prop;
-                if (take_count_part(unif24(r[1]), L, o->beta_k))
-                    prop = o->z[beg + dice(r[2], (uint32_t)L)];
-                else
-                    prop = (int32_t)dice(r[2], o->K);
-                o->prop[(uint64_t)(i - 1) * o->T + t] = prop;
-            }
-            ck_next[o->z[t]]++;
-        }
+        word_column(o, w, iter, ck_next, &accepted, cw, znew);
     }
     memcpy(o->ck, ck_next, o->K * sizeof(int64_t));
     free(cw); free(ck_next); free(znew);
     o->accepted_word = accepted;
     o->next_phase = PH_DOC;
     return 0;
+}
+
+/* f_r of Section 5.1 for one row d: c_d from the row, M MH steps per token
+ * on its word proposals, commit of the row, M doc proposals per token drawn
+ * from the updated row. */
+static void doc_row(oracle_t *o, uint32_t d, uint32_t iter, int64_t *ck_next,
+                    uint64_t *accepted, int64_t *cd, int32_t *znew)
+{
+    uint64_t beg = o->rowptr[d], L = o->rowptr[d + 1] - beg;
+    if (L == 0) return;
+    memset(cd, 0, o->K * sizeof(int64_t));
+    for (uint64_t n = 0; n < L; ++n) cd[o->z[o->row[beg + n]]]++;
+    for (uint64_t n = 0; n < L; ++n) {
+        uint32_t t = o->row[beg + n];
+        int32_t s = o->z[t];
+        for (uint32_t i = 1; i <= o->M; ++i) {
+            uint32_t r[4];
+            rng_call(o->seed, t, iter, PH_DOC, i, 0, r);
+            int32_t c = o->prop[(uint64_t)(i - 1) * o->T + t];
+            if (mh_accept(unif24(r[0]), cd[c], cd[s], o->a, o->ck[s],
+                          o->ck[c], o->beta_bar)) {
+                s = c;
+                (*accepted)++;
+            }
+        }
+        znew[t] = s;
+    }
+    for (uint64_t n = 0; n < L; ++n) {
+        uint32_t t = o->row[beg + n];
+        o->z[t] = znew[t];
+    }
+    draw_doc_proposals(o, d, iter);
+    if (ck_next)
+        for (uint64_t n = 0; n < L; ++n) ck_next[o->z[o->row[beg + n]]]++;
 }
 
 /* Document phase, VisitByRow with f_r (Section 4.4, Algorithm 2). */
@@ -352,37 +395,35 @@ int oracle_doc_phase(oracle_t *o)
     uint64_t accepted = 0;
     for (uint32_t e = 0; e < o->D; ++e) {
         uint32_t d = o->visit_reversed ? o->D - 1 - e : e;
-        uint64_t beg = o->rowptr[d], L = o->rowptr[d + 1] - beg;
-        if (L == 0) continue;
-        memset(cd, 0, o->K * sizeof(int64_t));
-        for (uint64_t n = 0; n < L; ++n) cd[o->z[o->row[beg + n]]]++;
-        for (uint64_t n = 0; n < L; ++n) {
-            uint32_t t = o->row[beg + n];
-            int32_t s = o->z[t];
-            for (uint32_t i = 1; i <= o->M; ++i) {
-                uint32_t r[4];
-                rng_call(o->seed, t, iter, PH_DOC, i, 0, r);
-                int32_t c = o->prop[(uint64_t)(i - 1) * o->T + t];
-                if (mh_accept(unif24(r[0]), cd[c], cd[s], o->a, o->ck[s],
-                              o->ck[c], o->beta_bar)) {
-                    s = c;
-                    accepted++;
-                }
-            }
-            znew[t] = s;
-        }
-        for (uint64_t n = 0; n < L; ++n) {
-            uint32_t t = o->row[beg + n];
-            o->z[t] = znew[t];
-        }
-        draw_doc_proposals(o, d, iter);
-        for (uint64_t n = 0; n < L; ++n) ck_next[o->z[o->row[beg + n]]]++;
+        doc_row(o, d, iter, ck_next, &accepted, cd, znew);
     }
     memcpy(o->ck, ck_next, o->K * sizeof(int64_t));
     free(cd); free(ck_next); free(znew);
     o->accepted_doc = accepted;
     o->iter = iter;
     o->next_phase = PH_WORD;
+    return 0;
+}
+
+/* The phase restricted to the listed columns (phase 1) or rows (phase 2),
+ * with the current c_k and the given iteration number; other segments, c_k
+ * and the phase bookkeeping are left untouched.  Segments are independent
+ * within a phase, so the listed segments get exactly their full-phase
+ * result.  Used to check large runs on a sample of segments. */
+int oracle_phase_subset(oracle_t *o, int phase, uint32_t iter,
+                        const uint32_t *segs, uint64_t n)
+{
+    int64_t *cnt = malloc(o->K * sizeof(int64_t));
+    int32_t *znew = malloc(o->T * sizeof(int32_t) + 1);
+    if (!cnt || !znew) { free(cnt); free(znew); return -1; }
+    uint64_t accepted = 0;
+    for (uint64_t k = 0; k < n; ++k) {
+        if (phase == PH_WORD && segs[k] < o->V)
+            word_column(o, segs[k], iter, NULL, &accepted, cnt, znew);
+        else if (phase == PH_DOC && segs[k] < o->D)
+            doc_row(o, segs[k], iter, NULL, &accepted, cnt, znew);
+    }
+    free(cnt); free(znew);
     return 0;
 }
 

@@ -1,0 +1,187 @@
+"""Python binding of the MI355X WarpLDA library (include/warplda.h).
+
+Argument marshalling only: every step of the sweep runs in the HIP kernels of
+``libwarplda_hip.so``.  PyTorch provides the device workspace and the stream.
+There is no CPU fallback: if the library is not built, loading fails.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libwarplda_hip.so")
+
+WLDA_OK = 0
+STATUS = {0: "ok", -1: "invalid argument", -2: "workspace too small or misaligned",
+          -3: "HIP runtime error", -4: "call out of order", -5: "unsupported by this build"}
+
+
+class WldaError(RuntimeError):
+    def __init__(self, fn, code):
+        super().__init__(f"{fn} failed: {STATUS.get(code, code)} ({code})")
+        self.code = code
+
+
+class Params(C.Structure):
+    _fields_ = [("V", C.c_uint32), ("D", C.c_uint32), ("K", C.c_uint32), ("M", C.c_uint32),
+                ("alpha", C.c_double), ("beta", C.c_double), ("seed", C.c_uint64)]
+
+
+# Every symbol declared in include/warplda.h (checked by the CPU tests).
+EXPORTS = [
+    "wlda_workspace_bytes", "wlda_create", "wlda_init", "wlda_word_phase", "wlda_doc_phase",
+    "wlda_iterate", "wlda_log_likelihood", "wlda_copy_assignments",
+    "wlda_copy_assignments_csc", "wlda_copy_topic_counts", "wlda_accepted", "wlda_iteration",
+    "wlda_state_bytes", "wlda_save_state", "wlda_load_state", "wlda_set_assignments",
+    "wlda_destroy", "wlda_strerror",
+]
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libwarplda_hip.so (raises if it is missing: no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is not built; run __graft_entry__.build()")
+    L = C.CDLL(path)
+    vp, u32, u64, i32 = C.c_void_p, C.c_uint32, C.c_uint64, C.c_int
+    P = C.POINTER(Params)
+    sig = {
+        "wlda_workspace_bytes": [P, vp, vp, u64, C.POINTER(u64)],
+        "wlda_create": [P, vp, vp, u64, vp, u64, vp, C.POINTER(vp)],
+        "wlda_init": [vp], "wlda_word_phase": [vp], "wlda_doc_phase": [vp],
+        "wlda_iterate": [vp, u32],
+        "wlda_log_likelihood": [vp, C.POINTER(C.c_double)],
+        "wlda_copy_assignments": [vp, vp, vp],
+        "wlda_copy_assignments_csc": [vp, vp, vp],
+        "wlda_copy_topic_counts": [vp, vp],
+        "wlda_accepted": [vp, i32, C.POINTER(u64)],
+        "wlda_iteration": [vp, C.POINTER(u32)],
+        "wlda_state_bytes": [vp, C.POINTER(u64)],
+        "wlda_save_state": [vp, vp, u64], "wlda_load_state": [vp, vp, u64],
+        "wlda_set_assignments": [vp, vp, vp],
+        "wlda_destroy": [vp],
+    }
+    for name, args in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = i32
+    L.wlda_strerror.argtypes = [i32]
+    L.wlda_strerror.restype = C.c_char_p
+    _lib = L
+    return L
+
+
+def _check(fn, rc):
+    if rc != WLDA_OK:
+        raise WldaError(fn, rc)
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+class Sampler:
+    """One WarpLDA sampler on one GPU (mirrors the wlda_* calls)."""
+
+    def __init__(self, word_ids, doc_ids, V, D, K, M, alpha, beta, seed=1, device="cuda:0",
+                 stream=None):
+        import torch
+        L = load_library()
+        self.word_ids = np.ascontiguousarray(word_ids, dtype=np.uint32)
+        self.doc_ids = np.ascontiguousarray(doc_ids, dtype=np.uint32)
+        self.T = int(self.word_ids.shape[0])
+        self.V, self.D, self.K, self.M = V, D, K, M
+        self.params = Params(V, D, K, M, float(alpha), float(beta), int(seed))
+        nbytes = C.c_uint64(0)
+        _check("wlda_workspace_bytes",
+               L.wlda_workspace_bytes(C.byref(self.params), _ptr(self.word_ids),
+                                      _ptr(self.doc_ids), self.T, C.byref(nbytes)))
+        self.device = torch.device(device)
+        self.workspace = torch.empty(int(nbytes.value), dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = C.c_void_p(0)
+        _check("wlda_create",
+               L.wlda_create(C.byref(self.params), _ptr(self.word_ids), _ptr(self.doc_ids),
+                             self.T, C.c_void_p(self.workspace.data_ptr()), int(nbytes.value),
+                             C.c_void_p(self.stream.cuda_stream), C.byref(h)))
+        self.h = h
+
+    @property
+    def workspace_bytes(self) -> int:
+        return int(self.workspace.numel())
+
+    def close(self):
+        if getattr(self, "h", None):
+            load_library().wlda_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def init(self):
+        _check("wlda_init", load_library().wlda_init(self.h))
+
+    def word_phase(self):
+        _check("wlda_word_phase", load_library().wlda_word_phase(self.h))
+
+    def doc_phase(self):
+        _check("wlda_doc_phase", load_library().wlda_doc_phase(self.h))
+
+    def iterate(self, n=1):
+        _check("wlda_iterate", load_library().wlda_iterate(self.h, n))
+
+    def log_likelihood(self) -> float:
+        v = C.c_double(0)
+        _check("wlda_log_likelihood", load_library().wlda_log_likelihood(self.h, C.byref(v)))
+        return v.value
+
+    def assignments(self, csc=False):
+        z = np.empty(self.T, dtype=np.int32)
+        p = np.empty((self.M, self.T), dtype=np.int32)
+        fn = "wlda_copy_assignments_csc" if csc else "wlda_copy_assignments"
+        _check(fn, getattr(load_library(), fn)(self.h, _ptr(z), _ptr(p)))
+        return z, p
+
+    def topic_counts(self):
+        ck = np.empty(self.K, dtype=np.int64)
+        _check("wlda_copy_topic_counts", load_library().wlda_copy_topic_counts(self.h, _ptr(ck)))
+        return ck
+
+    def accepted(self, phase: int) -> int:
+        v = C.c_uint64(0)
+        _check("wlda_accepted", load_library().wlda_accepted(self.h, phase, C.byref(v)))
+        return int(v.value)
+
+    @property
+    def iteration(self) -> int:
+        v = C.c_uint32(0)
+        _check("wlda_iteration", load_library().wlda_iteration(self.h, C.byref(v)))
+        return int(v.value)
+
+    def save_state(self) -> bytes:
+        n = C.c_uint64(0)
+        _check("wlda_state_bytes", load_library().wlda_state_bytes(self.h, C.byref(n)))
+        buf = np.empty(int(n.value), dtype=np.uint8)
+        _check("wlda_save_state", load_library().wlda_save_state(self.h, _ptr(buf), int(n.value)))
+        return buf.tobytes()
+
+    def load_state(self, blob: bytes):
+        buf = np.frombuffer(blob, dtype=np.uint8).copy()
+        _check("wlda_load_state", load_library().wlda_load_state(self.h, _ptr(buf), len(buf)))
+
+    def set_assignments(self, z, props=None):
+        zz = np.ascontiguousarray(z, dtype=np.int32)
+        pp = None if props is None else np.ascontiguousarray(props, dtype=np.int32)
+        _check("wlda_set_assignments",
+               load_library().wlda_set_assignments(self.h, _ptr(zz),
+                                                   None if pp is None else _ptr(pp)))

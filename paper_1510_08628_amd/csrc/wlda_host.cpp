@@ -1,0 +1,553 @@
+// Host runtime of the WarpLDA sampler: input validation, the token layout
+// (Section 5.2), segment binning by length, workspace carving and the phase
+// schedule (Section 4.4, Algorithm 2).  Implements include/warplda.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/warplda.h"
+#include "wlda_internal.h"
+
+using namespace wlda;
+
+namespace {
+
+constexpr uint64_t ALIGN = 256;
+inline uint64_t align_up(uint64_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
+
+struct PhasePlan {
+    std::vector<uint32_t> wave_ids, block_ids, long_ids, long_prefix;
+    uint32_t wave_cut[9] = {}, block_cut[9] = {};
+    // device copies (inside the workspace)
+    uint32_t *d_wave_ids = nullptr, *d_wave_cut = nullptr, *d_block_ids = nullptr,
+             *d_block_cut = nullptr, *d_long_ids = nullptr, *d_long_prefix = nullptr,
+             *d_tables = nullptr;
+};
+
+// Split a length-sorted-by-id list into 8 contiguous shares of ~equal tokens
+// (one per XCD).
+void xcd_cuts(const std::vector<uint32_t> &ids, const std::vector<uint64_t> &len, uint32_t cut[9]) {
+    uint64_t total = 0;
+    for (uint32_t s : ids) total += len[s];
+    uint64_t run = 0;
+    uint32_t x = 1;
+    cut[0] = 0;
+    for (uint32_t i = 0; i < ids.size() && x < 8; ++i) {
+        run += len[ids[i]];
+        while (x < 8 && run * 8 >= total * x) cut[x++] = i + 1;
+    }
+    while (x < 8) cut[x++] = (uint32_t)ids.size();
+    cut[8] = (uint32_t)ids.size();
+}
+
+void build_plan(const std::vector<uint64_t> &len, uint32_t block_max, PhasePlan &pl) {
+    pl.wave_ids.clear();
+    pl.block_ids.clear();
+    pl.long_ids.clear();
+    pl.long_prefix.assign(1, 0);
+    for (uint32_t s = 0; s < len.size(); ++s) {
+        const uint64_t L = len[s];
+        if (L == 0) continue;
+        if (L <= Tuning::WAVE_MAX)
+            pl.wave_ids.push_back(s);
+        else if (L <= block_max)
+            pl.block_ids.push_back(s);
+        else {
+            pl.long_ids.push_back(s);
+            pl.long_prefix.push_back((uint32_t)(pl.long_prefix.back() + L));
+        }
+    }
+    xcd_cuts(pl.wave_ids, len, pl.wave_cut);
+    xcd_cuts(pl.block_ids, len, pl.block_cut);
+}
+
+struct Sizes {
+    uint64_t recs, colptr, rowptr, rowpos, ck, misc;
+    uint64_t plan_word, plan_doc;
+    uint64_t total;
+};
+
+uint64_t plan_bytes(const PhasePlan &pl, uint32_t K) {
+    return align_up(4ull * pl.wave_ids.size() + 4) + align_up(9 * 4) +
+           align_up(4ull * pl.block_ids.size() + 4) + align_up(9 * 4) +
+           align_up(4ull * pl.long_ids.size() + 4) + align_up(4ull * pl.long_prefix.size()) +
+           align_up(4ull * pl.long_ids.size() * K + 4);
+}
+
+Sizes compute_sizes(const wlda_params &p, uint64_t T, const PhasePlan &w, const PhasePlan &d) {
+    Sizes s;
+    s.recs = align_up(T * 8ull * record_words(p.M) + 16);
+    s.colptr = align_up(4ull * (p.V + 1));
+    s.rowptr = align_up(4ull * (p.D + 1));
+    s.rowpos = align_up(4ull * T + 4);
+    s.ck = 2 * align_up(4ull * p.K);
+    s.misc = ALIGN;
+    s.plan_word = plan_bytes(w, p.K);
+    s.plan_doc = plan_bytes(d, p.K);
+    s.total = s.recs + s.colptr + s.rowptr + s.rowpos + s.ck + s.misc + s.plan_word + s.plan_doc;
+    return s;
+}
+
+wlda_status validate(const wlda_params *p, const uint32_t *word_ids, const uint32_t *doc_ids,
+                     uint64_t T) {
+    if (!p) return WLDA_E_INVALID;
+    if (p->K < 1 || p->K > MAX_K || p->M < 1 || p->M > 4 || p->V < 1 || p->D < 1)
+        return WLDA_E_INVALID;
+    if (!(p->alpha > 0) || !(p->beta > 0)) return WLDA_E_INVALID;
+    if (T >= (1ull << 32)) return WLDA_E_INVALID;
+    if (T > 0 && (!word_ids || !doc_ids)) return WLDA_E_INVALID;
+    for (uint64_t i = 0; i < T; ++i)
+        if (word_ids[i] >= p->V || doc_ids[i] >= p->D) return WLDA_E_INVALID;
+    return WLDA_OK;
+}
+
+void lengths(const wlda_params &p, const uint32_t *word_ids, const uint32_t *doc_ids, uint64_t T,
+             std::vector<uint64_t> &lw, std::vector<uint64_t> &ld) {
+    lw.assign(p.V, 0);
+    ld.assign(p.D, 0);
+    for (uint64_t i = 0; i < T; ++i) {
+        lw[word_ids[i]]++;
+        ld[doc_ids[i]]++;
+    }
+}
+
+}  // namespace
+
+struct wlda_sampler_s {
+    wlda_params p{};
+    uint64_t T = 0;
+    hipStream_t st = nullptr;
+    int nw = 1;
+    uint64_t *recs = nullptr;
+    uint32_t *colptr = nullptr, *rowptr = nullptr, *rowpos = nullptr;
+    uint32_t *ck[2] = {nullptr, nullptr};
+    int cur = 0;
+    unsigned long long *acc = nullptr;   // [0] word phase, [1] doc phase
+    double *ll = nullptr;
+    PhasePlan word, doc;
+    std::vector<uint32_t> inv;           // input index -> canonical position
+    uint32_t iter = 0;
+    int next_phase = 0;                  // 0: not initialised, 1: word, 2: doc
+    bool broken = false;
+    float a = 0, b = 0, alpha_bar = 0, beta_k = 0, beta_bar = 0;
+};
+
+namespace {
+
+wlda_status hip_ok(wlda_sampler s, hipError_t e) {
+    if (e == hipSuccess) return WLDA_OK;
+    if (e == hipErrorNotSupported) return WLDA_E_UNSUPPORTED;
+    if (s) s->broken = true;
+    return WLDA_E_HIP;
+}
+
+#define WLDA_TRY(s, expr)                                   \
+    do {                                                    \
+        wlda_status _st = hip_ok((s), (expr));              \
+        if (_st != WLDA_OK) return _st;                     \
+    } while (0)
+
+uint8_t *carve(uint8_t *&cur, uint64_t bytes) {
+    uint8_t *p = cur;
+    cur += align_up(bytes);
+    return p;
+}
+
+hipError_t upload(void *dst, const void *src, uint64_t bytes, hipStream_t st) {
+    if (bytes == 0) return hipSuccess;
+    return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st);
+}
+
+hipError_t place_plan(PhasePlan &pl, uint8_t *&cur, uint32_t K, hipStream_t st) {
+    pl.d_wave_ids = (uint32_t *)carve(cur, 4ull * pl.wave_ids.size() + 4);
+    pl.d_wave_cut = (uint32_t *)carve(cur, 9 * 4);
+    pl.d_block_ids = (uint32_t *)carve(cur, 4ull * pl.block_ids.size() + 4);
+    pl.d_block_cut = (uint32_t *)carve(cur, 9 * 4);
+    pl.d_long_ids = (uint32_t *)carve(cur, 4ull * pl.long_ids.size() + 4);
+    pl.d_long_prefix = (uint32_t *)carve(cur, 4ull * pl.long_prefix.size());
+    pl.d_tables = (uint32_t *)carve(cur, 4ull * pl.long_ids.size() * K + 4);
+    hipError_t e;
+    if ((e = upload(pl.d_wave_ids, pl.wave_ids.data(), 4ull * pl.wave_ids.size(), st))) return e;
+    if ((e = upload(pl.d_wave_cut, pl.wave_cut, 9 * 4, st))) return e;
+    if ((e = upload(pl.d_block_ids, pl.block_ids.data(), 4ull * pl.block_ids.size(), st))) return e;
+    if ((e = upload(pl.d_block_cut, pl.block_cut, 9 * 4, st))) return e;
+    if ((e = upload(pl.d_long_ids, pl.long_ids.data(), 4ull * pl.long_ids.size(), st))) return e;
+    if ((e = upload(pl.d_long_prefix, pl.long_prefix.data(), 4ull * pl.long_prefix.size(), st)))
+        return e;
+    return launch_fill_u32(pl.d_tables, 0, (uint64_t)pl.long_ids.size() * K, st);
+}
+
+// One phase: every segment of the phase's plan, c_k of the new Z into the
+// other buffer, then swap.
+wlda_status run_phase(wlda_sampler s, uint32_t phase, uint32_t iter, bool draw_only) {
+    PhasePlan &pl = phase == PH_WORD ? s->word : s->doc;
+    PhaseArgs a;
+    a.recs = s->recs;
+    a.segptr = phase == PH_WORD ? s->colptr : s->rowptr;
+    a.rowpos = phase == PH_WORD ? nullptr : s->rowpos;
+    a.K = s->p.K;
+    a.iter = iter;
+    a.seed_lo = (uint32_t)s->p.seed;
+    a.seed_hi = (uint32_t)(s->p.seed >> 32);
+    a.ck = s->ck[s->cur];
+    a.ck_next = s->ck[1 - s->cur];
+    a.prior = phase == PH_WORD ? s->b : s->a;
+    a.mass = phase == PH_WORD ? s->beta_k : s->alpha_bar;
+    a.beta_bar = s->beta_bar;
+    a.accepted = s->acc + (phase == PH_WORD ? 0 : 1);
+    a.draw_only = draw_only ? 1 : 0;
+    WLDA_TRY(s, launch_fill_u32(a.ck_next, 0, s->p.K, s->st));
+    WLDA_TRY(s, launch_fill_u32((uint32_t *)a.accepted, 0, 2, s->st));
+    SegList wl{pl.d_wave_ids, (uint32_t)pl.wave_ids.size(), pl.d_wave_cut};
+    SegList bl{pl.d_block_ids, (uint32_t)pl.block_ids.size(), pl.d_block_cut};
+    LongList ll;
+    ll.ids = pl.d_long_ids;
+    ll.prefix = pl.d_long_prefix;
+    ll.n = (uint32_t)pl.long_ids.size();
+    ll.total = pl.long_prefix.back();
+    ll.tables = pl.d_tables;
+    WLDA_TRY(s, launch_wave_segments(a, phase, s->p.M, wl, s->st));
+    WLDA_TRY(s, launch_block_segments(a, phase, s->p.M, bl, s->st));
+    WLDA_TRY(s, launch_long_segments(a, phase, s->p.M, ll, s->st));
+    s->cur = 1 - s->cur;
+    return WLDA_OK;
+}
+
+inline uint32_t get_field(const uint64_t *rec, int f) {
+    return (uint32_t)(rec[f / 3] >> (FIELD_BITS * (f % 3))) & FIELD_MASK;
+}
+
+inline void set_field(uint64_t *rec, int f, uint32_t v) {
+    const int sh = FIELD_BITS * (f % 3);
+    rec[f / 3] = (rec[f / 3] & ~((uint64_t)FIELD_MASK << sh)) | ((uint64_t)v << sh);
+}
+
+wlda_status download_records(wlda_sampler s, std::vector<uint64_t> &h) {
+    h.resize(s->T * s->nw + 1);
+    if (s->T) WLDA_TRY(s, hipMemcpyAsync(h.data(), s->recs, s->T * 8ull * s->nw, hipMemcpyDeviceToHost, s->st));
+    WLDA_TRY(s, hipStreamSynchronize(s->st));
+    return WLDA_OK;
+}
+
+wlda_status upload_records_and_recount(wlda_sampler s, const std::vector<uint64_t> &h) {
+    if (s->T) WLDA_TRY(s, hipMemcpyAsync(s->recs, h.data(), s->T * 8ull * s->nw, hipMemcpyHostToDevice, s->st));
+    WLDA_TRY(s, launch_fill_u32(s->ck[s->cur], 0, s->p.K, s->st));
+    WLDA_TRY(s, launch_histogram_z(s->recs, (uint32_t)s->T, s->p.M, s->p.K, s->ck[s->cur], s->st));
+    WLDA_TRY(s, hipStreamSynchronize(s->st));
+    return WLDA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *wlda_strerror(wlda_status e) {
+    switch (e) {
+        case WLDA_OK: return "ok";
+        case WLDA_E_INVALID: return "invalid argument";
+        case WLDA_E_WORKSPACE: return "workspace too small or misaligned";
+        case WLDA_E_HIP: return "HIP runtime error";
+        case WLDA_E_STATE: return "call out of order";
+        case WLDA_E_UNSUPPORTED: return "unsupported by this build";
+    }
+    return "unknown status";
+}
+
+wlda_status wlda_workspace_bytes(const wlda_params *p, const uint32_t *word_ids,
+                                 const uint32_t *doc_ids, uint64_t n_tokens, uint64_t *bytes) {
+    if (!bytes) return WLDA_E_INVALID;
+    wlda_status v = validate(p, word_ids, doc_ids, n_tokens);
+    if (v != WLDA_OK) return v;
+    std::vector<uint64_t> lw, ld;
+    lengths(*p, word_ids, doc_ids, n_tokens, lw, ld);
+    PhasePlan w, d;
+    build_plan(lw, block_max_tokens(p->M), w);
+    build_plan(ld, block_max_tokens(p->M), d);
+    *bytes = compute_sizes(*p, n_tokens, w, d).total;
+    return WLDA_OK;
+}
+
+wlda_status wlda_create(const wlda_params *p, const uint32_t *word_ids, const uint32_t *doc_ids,
+                        uint64_t T, void *dev_workspace, uint64_t workspace_bytes,
+                        void *hip_stream, wlda_sampler *out) {
+    if (!out) return WLDA_E_INVALID;
+    *out = nullptr;
+    wlda_status v = validate(p, word_ids, doc_ids, T);
+    if (v != WLDA_OK) return v;
+    if (!dev_workspace || ((uintptr_t)dev_workspace % ALIGN) != 0) return WLDA_E_WORKSPACE;
+    wlda_sampler s = new (std::nothrow) wlda_sampler_s();
+    if (!s) return WLDA_E_INVALID;
+    s->p = *p;
+    s->T = T;
+    s->st = (hipStream_t)hip_stream;
+    s->nw = record_words(p->M);
+    s->a = (float)p->alpha;
+    s->b = (float)p->beta;
+    s->alpha_bar = (float)p->K * s->a;
+    s->beta_k = (float)p->K * s->b;
+    s->beta_bar = (float)p->V * s->b;
+
+    // ---- layout: stable order by (word, doc, input index) -------------------
+    std::vector<uint64_t> lw, ld;
+    lengths(*p, word_ids, doc_ids, T, lw, ld);
+    build_plan(lw, block_max_tokens(p->M), s->word);
+    build_plan(ld, block_max_tokens(p->M), s->doc);
+    const Sizes sz = compute_sizes(*p, T, s->word, s->doc);
+    if (workspace_bytes < sz.total) {
+        delete s;
+        return WLDA_E_WORKSPACE;
+    }
+    std::vector<uint32_t> colptr(p->V + 1), rowptr(p->D + 1);
+    colptr[0] = rowptr[0] = 0;
+    for (uint32_t w = 0; w < p->V; ++w) colptr[w + 1] = colptr[w] + (uint32_t)lw[w];
+    for (uint32_t d = 0; d < p->D; ++d) rowptr[d + 1] = rowptr[d] + (uint32_t)ld[d];
+    std::vector<uint32_t> rowpos, doc_csc;
+    try {
+        std::vector<uint32_t> by_doc(T), cursor(rowptr.begin(), rowptr.end() - 1);
+        for (uint64_t i = 0; i < T; ++i) by_doc[cursor[doc_ids[i]]++] = (uint32_t)i;
+        s->inv.resize(T);
+        doc_csc.resize(T);
+        std::vector<uint32_t> wc(colptr.begin(), colptr.end() - 1);
+        for (uint64_t j = 0; j < T; ++j) {
+            const uint32_t i = by_doc[j];
+            const uint32_t t = wc[word_ids[i]]++;
+            s->inv[i] = t;
+            doc_csc[t] = doc_ids[i];
+        }
+        by_doc.clear();
+        by_doc.shrink_to_fit();
+        rowpos.resize(T);
+        std::copy(rowptr.begin(), rowptr.end() - 1, cursor.begin());
+        for (uint64_t t = 0; t < T; ++t) rowpos[cursor[doc_csc[t]]++] = (uint32_t)t;
+    } catch (const std::bad_alloc &) {
+        delete s;
+        return WLDA_E_INVALID;
+    }
+    doc_csc.clear();
+    doc_csc.shrink_to_fit();
+
+    // ---- workspace ----------------------------------------------------------
+    uint8_t *cur = (uint8_t *)dev_workspace;
+    s->recs = (uint64_t *)carve(cur, T * 8ull * s->nw + 16);
+    s->colptr = (uint32_t *)carve(cur, 4ull * (p->V + 1));
+    s->rowptr = (uint32_t *)carve(cur, 4ull * (p->D + 1));
+    s->rowpos = (uint32_t *)carve(cur, 4ull * T + 4);
+    s->ck[0] = (uint32_t *)carve(cur, 4ull * p->K);
+    s->ck[1] = (uint32_t *)carve(cur, 4ull * p->K);
+    uint8_t *misc = carve(cur, ALIGN);
+    s->acc = (unsigned long long *)misc;
+    s->ll = (double *)(misc + 16);
+    wlda_status st = WLDA_OK;
+    hipError_t e = hipSuccess;
+    if (!e) e = upload(s->colptr, colptr.data(), 4ull * (p->V + 1), s->st);
+    if (!e) e = upload(s->rowptr, rowptr.data(), 4ull * (p->D + 1), s->st);
+    if (!e) e = upload(s->rowpos, rowpos.data(), 4ull * T, s->st);
+    if (!e) e = place_plan(s->word, cur, p->K, s->st);
+    if (!e) e = place_plan(s->doc, cur, p->K, s->st);
+    if (!e) e = launch_fill_u32(s->ck[0], 0, 2ull * align_up(4ull * p->K) / 4, s->st);
+    if (!e) e = hipStreamSynchronize(s->st);
+    if (e) {
+        st = hip_ok(s, e);
+        delete s;
+        return st;
+    }
+    *out = s;
+    return WLDA_OK;
+}
+
+wlda_status wlda_init(wlda_sampler s) {
+    if (!s) return WLDA_E_INVALID;
+    if (s->broken) return WLDA_E_HIP;
+    WLDA_TRY(s, launch_init_z(s->recs, (uint32_t)s->T, s->p.M, s->p.K, (uint32_t)s->p.seed,
+                              (uint32_t)(s->p.seed >> 32), s->st));
+    // first doc proposals from the initial Z; c_k of Z lands in the other buffer
+    wlda_status st = run_phase(s, PH_DOC, 0, true);
+    if (st != WLDA_OK) return st;
+    s->iter = 0;
+    s->next_phase = PH_WORD;
+    return WLDA_OK;
+}
+
+wlda_status wlda_word_phase(wlda_sampler s) {
+    if (!s) return WLDA_E_INVALID;
+    if (s->broken) return WLDA_E_HIP;
+    if (s->next_phase != PH_WORD) return WLDA_E_STATE;
+    wlda_status st = run_phase(s, PH_WORD, s->iter + 1, false);
+    if (st != WLDA_OK) return st;
+    s->next_phase = PH_DOC;
+    return WLDA_OK;
+}
+
+wlda_status wlda_doc_phase(wlda_sampler s) {
+    if (!s) return WLDA_E_INVALID;
+    if (s->broken) return WLDA_E_HIP;
+    if (s->next_phase != PH_DOC) return WLDA_E_STATE;
+    wlda_status st = run_phase(s, PH_DOC, s->iter + 1, false);
+    if (st != WLDA_OK) return st;
+    s->iter += 1;
+    s->next_phase = PH_WORD;
+    return WLDA_OK;
+}
+
+wlda_status wlda_iterate(wlda_sampler s, uint32_t n) {
+    for (uint32_t k = 0; k < n; ++k) {
+        wlda_status st = wlda_word_phase(s);
+        if (st != WLDA_OK) return st;
+        st = wlda_doc_phase(s);
+        if (st != WLDA_OK) return st;
+    }
+    return WLDA_OK;
+}
+
+wlda_status wlda_log_likelihood(wlda_sampler s, double *ll) {
+    if (!s || !ll) return WLDA_E_INVALID;
+    if (s->broken) return WLDA_E_HIP;
+    if (s->next_phase == 0) return WLDA_E_STATE;
+    const uint32_t K = s->p.K;
+    WLDA_TRY(s, launch_fill_u32((uint32_t *)s->ll, 0, 2, s->st));
+    WLDA_TRY(s, launch_ll_segments(s->recs, s->p.M, s->rowptr, s->rowpos, s->p.D, K, s->p.alpha,
+                                   (double)K * s->p.alpha, 1, s->ll, s->st));
+    WLDA_TRY(s, launch_ll_segments(s->recs, s->p.M, s->colptr, nullptr, s->p.V, K, s->p.beta, 0.0, 0,
+                                   s->ll, s->st));
+    WLDA_TRY(s, launch_ll_topics(s->ck[s->cur], K, (double)s->p.V * s->p.beta, s->ll, s->st));
+    WLDA_TRY(s, hipMemcpyAsync(ll, s->ll, sizeof(double), hipMemcpyDeviceToHost, s->st));
+    WLDA_TRY(s, hipStreamSynchronize(s->st));
+    return WLDA_OK;
+}
+
+static wlda_status copy_out(wlda_sampler s, int32_t *z, int32_t *props, bool input_order) {
+    if (!s || !z) return WLDA_E_INVALID;
+    if (s->broken) return WLDA_E_HIP;
+    std::vector<uint64_t> h;
+    wlda_status st = download_records(s, h);
+    if (st != WLDA_OK) return st;
+    const uint64_t T = s->T;
+    const int nw = s->nw;
+    for (uint64_t i = 0; i < T; ++i) {
+        const uint64_t t = input_order ? s->inv[i] : i;
+        const uint64_t *rec = &h[t * nw];
+        z[i] = (int32_t)get_field(rec, 0);
+        if (props)
+            for (uint32_t m = 1; m <= s->p.M; ++m) props[(m - 1) * T + i] = (int32_t)get_field(rec, m);
+    }
+    return WLDA_OK;
+}
+
+wlda_status wlda_copy_assignments(wlda_sampler s, int32_t *z, int32_t *props) {
+    return copy_out(s, z, props, true);
+}
+
+wlda_status wlda_copy_assignments_csc(wlda_sampler s, int32_t *z, int32_t *props) {
+    return copy_out(s, z, props, false);
+}
+
+wlda_status wlda_copy_topic_counts(wlda_sampler s, int64_t *ck) {
+    if (!s || !ck) return WLDA_E_INVALID;
+    if (s->broken) return WLDA_E_HIP;
+    std::vector<uint32_t> h(s->p.K);
+    WLDA_TRY(s, hipMemcpyAsync(h.data(), s->ck[s->cur], 4ull * s->p.K, hipMemcpyDeviceToHost, s->st));
+    WLDA_TRY(s, hipStreamSynchronize(s->st));
+    for (uint32_t k = 0; k < s->p.K; ++k) ck[k] = h[k];
+    return WLDA_OK;
+}
+
+wlda_status wlda_accepted(wlda_sampler s, int phase, uint64_t *count) {
+    if (!s || !count || (phase != 1 && phase != 2)) return WLDA_E_INVALID;
+    if (s->broken) return WLDA_E_HIP;
+    unsigned long long h = 0;
+    WLDA_TRY(s, hipMemcpyAsync(&h, s->acc + (phase - 1), 8, hipMemcpyDeviceToHost, s->st));
+    WLDA_TRY(s, hipStreamSynchronize(s->st));
+    *count = h;
+    return WLDA_OK;
+}
+
+wlda_status wlda_iteration(wlda_sampler s, uint32_t *iteration) {
+    if (!s || !iteration) return WLDA_E_INVALID;
+    *iteration = s->iter;
+    return WLDA_OK;
+}
+
+wlda_status wlda_state_bytes(wlda_sampler s, uint64_t *bytes) {
+    if (!s || !bytes) return WLDA_E_INVALID;
+    *bytes = 16 + 4ull * (1 + s->p.M) * s->T;
+    return WLDA_OK;
+}
+
+wlda_status wlda_save_state(wlda_sampler s, void *host_buf, uint64_t bytes) {
+    uint64_t need = 0;
+    wlda_state_bytes(s, &need);
+    if (!s || !host_buf || bytes < need) return WLDA_E_INVALID;
+    if (s->next_phase == 0) return WLDA_E_STATE;
+    uint8_t *p = (uint8_t *)host_buf;
+    const uint64_t hdr[2] = {s->iter, (uint64_t)s->next_phase};
+    std::memcpy(p, hdr, 16);
+    int32_t *z = (int32_t *)(p + 16);
+    return copy_out(s, z, z + s->T, false);
+}
+
+wlda_status wlda_load_state(wlda_sampler s, const void *host_buf, uint64_t bytes) {
+    uint64_t need = 0;
+    wlda_state_bytes(s, &need);
+    if (!s || !host_buf || bytes < need) return WLDA_E_INVALID;
+    if (s->broken) return WLDA_E_HIP;
+    const uint8_t *p = (const uint8_t *)host_buf;
+    uint64_t hdr[2];
+    std::memcpy(hdr, p, 16);
+    if (hdr[1] != PH_WORD && hdr[1] != PH_DOC) return WLDA_E_INVALID;
+    const int32_t *z = (const int32_t *)(p + 16);
+    const int32_t *props = z + s->T;
+    const uint64_t T = s->T;
+    std::vector<uint64_t> h(T * s->nw + 1, 0);
+    for (uint64_t t = 0; t < T; ++t) {
+        if ((uint32_t)z[t] >= s->p.K) return WLDA_E_INVALID;
+        set_field(&h[t * s->nw], 0, (uint32_t)z[t]);
+        for (uint32_t m = 1; m <= s->p.M; ++m) {
+            const uint32_t v = (uint32_t)props[(m - 1) * T + t];
+            if (v >= s->p.K) return WLDA_E_INVALID;
+            set_field(&h[t * s->nw], m, v);
+        }
+    }
+    wlda_status st = upload_records_and_recount(s, h);
+    if (st != WLDA_OK) return st;
+    s->iter = (uint32_t)hdr[0];
+    s->next_phase = (int)hdr[1];
+    return WLDA_OK;
+}
+
+wlda_status wlda_set_assignments(wlda_sampler s, const int32_t *z, const int32_t *props) {
+    if (!s || !z) return WLDA_E_INVALID;
+    if (s->broken) return WLDA_E_HIP;
+    if (!props && s->next_phase == 0) return WLDA_E_STATE;
+    std::vector<uint64_t> h;
+    wlda_status st = download_records(s, h);
+    if (st != WLDA_OK) return st;
+    const uint64_t T = s->T;
+    for (uint64_t i = 0; i < T; ++i) {
+        const uint64_t t = s->inv[i];
+        if ((uint32_t)z[i] >= s->p.K) return WLDA_E_INVALID;
+        set_field(&h[t * s->nw], 0, (uint32_t)z[i]);
+        if (props)
+            for (uint32_t m = 1; m <= s->p.M; ++m) {
+                const uint32_t v = (uint32_t)props[(m - 1) * T + i];
+                if (v >= s->p.K) return WLDA_E_INVALID;
+                set_field(&h[t * s->nw], m, v);
+            }
+    }
+    st = upload_records_and_recount(s, h);
+    if (st != WLDA_OK) return st;
+    s->next_phase = PH_WORD;
+    return WLDA_OK;
+}
+
+wlda_status wlda_destroy(wlda_sampler s) {
+    if (!s) return WLDA_E_INVALID;
+    if (!s->broken) (void)hipStreamSynchronize(s->st);
+    delete s;
+    return WLDA_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,93 @@
+// Internal interface between the host runtime (wlda_host.cpp) and the gfx950
+// kernels (wlda_kernels.hip).  Not part of the public ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace wlda {
+
+enum Phase : uint32_t { PH_INIT = 0, PH_WORD = 1, PH_DOC = 2 };
+
+// Topics are packed three to a 64-bit word, 21 bits each: field 0 is z, field
+// i (1..M) is the i-th pending proposal.  M <= 2 -> one word, M <= 5 -> two.
+constexpr uint32_t FIELD_BITS = 21;
+constexpr uint32_t FIELD_MASK = (1u << FIELD_BITS) - 1;
+constexpr uint32_t MAX_K = FIELD_MASK;   // topics are < 2^21 - 1
+
+inline int record_words(uint32_t M) { return (int)((M + 1 + 2) / 3); }
+
+// Segment = one column (word phase) or one row (doc phase).  Tokens of
+// segment s are the canonical positions segptr[s] .. segptr[s+1]-1 (word
+// phase) or rowpos[segptr[s] .. segptr[s+1]-1] (doc phase).
+struct SegList {
+    const uint32_t *ids = nullptr;   // segment ids, ascending
+    uint32_t n = 0;
+    const uint32_t *xcd_cut = nullptr;   // 9 list offsets: XCD x owns [cut[x], cut[x+1])
+};
+
+struct LongList {
+    const uint32_t *ids = nullptr;     // long segment ids, ascending
+    const uint32_t *prefix = nullptr;  // n+1 virtual token offsets
+    uint32_t n = 0;
+    uint32_t total = 0;                // prefix[n]
+    uint32_t *tables = nullptr;        // n x K counts (global)
+};
+
+struct PhaseArgs {
+    uint64_t *recs = nullptr;
+    const uint32_t *segptr = nullptr;
+    const uint32_t *rowpos = nullptr;  // doc phase indirection, null in word phase
+    uint32_t K = 0, iter = 0, seed_lo = 0, seed_hi = 0;
+    const uint32_t *ck = nullptr;      // c_k at the start of the phase
+    uint32_t *ck_next = nullptr;       // histogram of the phase's new Z
+    float prior = 0.f;                 // beta (word phase) or alpha (doc phase)
+    float mass = 0.f;                  // K beta or K alpha
+    float beta_bar = 0.f;              // V beta
+    unsigned long long *accepted = nullptr;
+    uint32_t draw_only = 0;            // initial proposal draw (no MH)
+};
+
+struct Tuning {
+    // wave kernel: segments of at most 64 * TPT_WAVE tokens
+    static constexpr int TPT_WAVE = 8;
+    static constexpr uint32_t WAVE_MAX = 64 * TPT_WAVE;
+    static constexpr uint32_t WAVE_CAP = 2 * WAVE_MAX;       // hash capacity bound
+    // block kernel: segments of at most 256 * TPT_BLOCK tokens
+    static constexpr int TPT_BLOCK = 16;
+    static constexpr uint32_t BLOCK_MAX = 256 * TPT_BLOCK;
+    static constexpr uint32_t BLOCK_CAP = 2 * BLOCK_MAX;
+    static constexpr uint32_t CK_LDS_MAX = 4096;             // block c_k histogram in LDS
+    static constexpr uint32_t LONG_CHUNK = 32768;            // tokens per histogram block
+};
+
+inline uint32_t block_max_tokens(uint32_t M) {
+    return M <= 2 ? Tuning::BLOCK_MAX : Tuning::BLOCK_MAX / 2;
+}
+
+// ---- launchers (all enqueue on `st`, return hipError_t of the launch) ----
+hipError_t launch_fill_u32(uint32_t *p, uint32_t v, uint64_t n, hipStream_t st);
+hipError_t launch_init_z(uint64_t *recs, uint32_t T, uint32_t M, uint32_t K,
+                         uint32_t seed_lo, uint32_t seed_hi, hipStream_t st);
+hipError_t launch_wave_segments(const PhaseArgs &a, uint32_t phase, uint32_t M,
+                                const SegList &l, hipStream_t st);
+hipError_t launch_block_segments(const PhaseArgs &a, uint32_t phase, uint32_t M,
+                                 const SegList &l, hipStream_t st);
+hipError_t launch_long_segments(const PhaseArgs &a, uint32_t phase, uint32_t M,
+                                const LongList &l, hipStream_t st);
+hipError_t launch_unpack(const uint64_t *recs, uint32_t T, uint32_t M,
+                         int32_t *z_out, int32_t *props_out, hipStream_t st);
+hipError_t launch_pack(uint64_t *recs, uint32_t T, uint32_t M, const int32_t *z_in,
+                       const int32_t *props_in, hipStream_t st);
+hipError_t launch_histogram_z(const uint64_t *recs, uint32_t T, uint32_t M, uint32_t K,
+                              uint32_t *ck, hipStream_t st);
+// LL: adds the document, word and topic parts into *out (binary64).
+// Per segment: sum over nonzero counts c of lgamma(prior + c) - lgamma(prior),
+// plus lgamma(prior_total) - lgamma(prior_total + L) when length_term != 0.
+hipError_t launch_ll_segments(const uint64_t *recs, uint32_t M, const uint32_t *segptr,
+                              const uint32_t *rowpos, uint32_t n_seg, uint32_t K,
+                              double prior, double prior_total, int length_term,
+                              double *out, hipStream_t st);
+hipError_t launch_ll_topics(const uint32_t *ck, uint32_t K, double beta_bar, double *out,
+                            hipStream_t st);
+
+}  // namespace wlda

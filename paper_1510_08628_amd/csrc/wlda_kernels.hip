@@ -1,0 +1,756 @@
+// gfx950 kernels of the WarpLDA sweep.
+//
+// Paper: Chen, Li, Zhu, Chen, "WarpLDA: a Cache Efficient O(1) Algorithm for
+// Latent Dirichlet Allocation" (arXiv:1510.08628).
+//
+// Data: one packed record per token in canonical column-major order (tokens
+// sorted by word, then document, then input index; Section 5.2 stores Y the
+// same way): 21-bit fields, field 0 = z, fields 1..M = pending proposals.
+// The word phase streams columns (coalesced); the document phase reaches each
+// row through `rowpos` (the CSC positions of the row, ascending), i.e. the
+// pointer array P_CSR of Section 5.2.
+//
+// A "segment" is a column (word phase) or a row (document phase).  Segments
+// are binned by length on the host:
+//   * wave kernel   - one 64-lane wavefront per segment (<= 512 tokens);
+//   * block kernel  - one 256-thread workgroup per segment (<= 4096 tokens);
+//   * long path     - segments split over many workgroups (intra-word
+//                     parallelism, Section 5.4): histogram -> MH -> draw.
+// Per-segment counts (c_w or c_d) live in LDS, dense when K fits and otherwise
+// in an open-addressed table with linear probing and an AND hash whose
+// capacity is the power of two >= 2L (Section 5.4, "sparse vectors as hash
+// tables").  c_k is an exact integer histogram of the phase's new Z, kept in
+// LDS per workgroup and added to global memory once per workgroup.
+//
+// Arithmetic that decides the chain (must match any implementation of the
+// same definition bit for bit; compiled without FP contraction):
+//   accept  iff  U * den < num,
+//     num = (cnt[c] + prior) * (ck[s] + beta_bar),
+//     den = (cnt[s] + prior) * (ck[c] + beta_bar)            (Eq. 7)
+//   count part iff U * (L + mass) < L, then the topic of a uniformly chosen
+//   token of the (updated) segment, else a uniform topic       (Eq. 6, Sec. 4.3)
+//   U(r) = (r >> 8) * 2^-24,  Dice(r, n) = (r * n) >> 32.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "wlda_internal.h"
+
+namespace wlda {
+
+// --------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds, each two
+// 32x32 -> 64-bit products mixed into the other lanes, with the Weyl key
+// increments between rounds.
+// --------------------------------------------------------------------------
+__device__ __forceinline__ uint4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                        uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int round = 0; round < 10; ++round) {
+        const uint32_t hi_a = __umulhi(0xD2511F53u, c0), lo_a = 0xD2511F53u * c0;
+        const uint32_t hi_b = __umulhi(0xCD9E8D57u, c2), lo_b = 0xCD9E8D57u * c2;
+        const uint32_t n0 = hi_b ^ c1 ^ k0;
+        const uint32_t n2 = hi_a ^ c3 ^ k1;
+        c0 = n0;
+        c1 = lo_b;
+        c2 = n2;
+        c3 = lo_a;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return make_uint4(c0, c1, c2, c3);
+}
+
+__device__ __forceinline__ float unif24(uint32_t r) { return (float)(r >> 8) * 0x1p-24f; }
+__device__ __forceinline__ uint32_t dice(uint32_t r, uint32_t n) { return __umulhi(r, n); }
+
+__device__ __forceinline__ bool mh_accept(float u, uint32_t cnt_c, uint32_t cnt_s, float prior,
+                                          uint32_t ck_s, uint32_t ck_c, float beta_bar) {
+    const float num = ((float)cnt_c + prior) * ((float)ck_s + beta_bar);
+    const float den = ((float)cnt_s + prior) * ((float)ck_c + beta_bar);
+    return u * den < num;
+}
+
+__device__ __forceinline__ bool take_count_part(float u, uint32_t L, float mass) {
+    return u * ((float)L + mass) < (float)L;
+}
+
+// --------------------------------------------------------------------------
+// Packed records
+// --------------------------------------------------------------------------
+template <int NW>
+struct Rec {
+    uint64_t w[NW];
+};
+
+template <int NW>
+__device__ __forceinline__ Rec<NW> ld_rec(const uint64_t *recs, uint32_t pos) {
+    Rec<NW> r;
+    if constexpr (NW == 1) {
+        r.w[0] = recs[pos];
+    } else {
+        const uint4 v = reinterpret_cast<const uint4 *>(recs)[pos];
+        r.w[0] = ((uint64_t)v.y << 32) | v.x;
+        r.w[1] = ((uint64_t)v.w << 32) | v.z;
+    }
+    return r;
+}
+
+template <int NW>
+__device__ __forceinline__ void st_rec(uint64_t *recs, uint32_t pos, const Rec<NW> &r) {
+    if constexpr (NW == 1) {
+        recs[pos] = r.w[0];
+    } else {
+        reinterpret_cast<uint4 *>(recs)[pos] =
+            make_uint4((uint32_t)r.w[0], (uint32_t)(r.w[0] >> 32), (uint32_t)r.w[1],
+                       (uint32_t)(r.w[1] >> 32));
+    }
+}
+
+template <int NW>
+__device__ __forceinline__ uint32_t fld(const Rec<NW> &r, int f) {
+    return (uint32_t)(r.w[f / 3] >> (FIELD_BITS * (f % 3))) & FIELD_MASK;
+}
+
+template <int NW>
+__device__ __forceinline__ void set_fld(Rec<NW> &r, int f, uint32_t v) {
+    const int sh = FIELD_BITS * (f % 3);
+    r.w[f / 3] = (r.w[f / 3] & ~((uint64_t)FIELD_MASK << sh)) | ((uint64_t)v << sh);
+}
+
+// --------------------------------------------------------------------------
+// LDS count tables
+// --------------------------------------------------------------------------
+constexpr uint32_t EMPTY_KEY = 0xFFFFFFFFu;
+
+__device__ __forceinline__ void tab_insert(uint32_t *key, uint32_t *cnt, uint32_t mask, bool dense,
+                                           uint32_t k) {
+    if (dense) {
+        atomicAdd(&cnt[k], 1u);
+        return;
+    }
+    uint32_t h = k & mask;
+    while (true) {
+        const uint32_t old = atomicCAS(&key[h], EMPTY_KEY, k);
+        if (old == EMPTY_KEY || old == k) {
+            atomicAdd(&cnt[h], 1u);
+            return;
+        }
+        h = (h + 1) & mask;
+    }
+}
+
+__device__ __forceinline__ uint32_t tab_get(const uint32_t *key, const uint32_t *cnt, uint32_t mask,
+                                            bool dense, uint32_t k) {
+    if (dense) return cnt[k];
+    uint32_t h = k & mask;
+    while (true) {
+        const uint32_t kk = key[h];
+        if (kk == k) return cnt[h];
+        if (kk == EMPTY_KEY) return 0u;
+        h = (h + 1) & mask;
+    }
+}
+
+__device__ __forceinline__ uint32_t pow2_at_least(uint32_t x) {
+    return x <= 1 ? 1u : 1u << (32 - __clz(x - 1));
+}
+
+template <int GROUP>
+__device__ __forceinline__ void group_sync() {
+    if constexpr (GROUP == 64) {
+        // one wavefront: LDS operations of a wavefront complete in order, so
+        // a compiler-level wavefront fence is all that is needed.
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    } else {
+        __syncthreads();
+    }
+}
+
+__device__ __forceinline__ void add_accepted(unsigned long long *dst, unsigned long long v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    if ((threadIdx.x & 63) == 0 && v) atomicAdd(dst, v);
+}
+
+// --------------------------------------------------------------------------
+// Segment kernel: GROUP threads (a wavefront or the workgroup) own one segment
+// of at most GROUP*TPT tokens at a time; segments of an XCD's share of the
+// list are taken in ascending order so that the rows visited at the same time
+// are neighbours (their tokens share cache lines of each column, Section 5.2).
+// --------------------------------------------------------------------------
+template <int PHASE, int M, int NW, int GROUP, int TPT>
+__global__ __launch_bounds__(256) void seg_kernel(PhaseArgs a, SegList l, uint32_t cap_max,
+                                                  uint32_t dense_u, uint32_t ck_lds_u) {
+    extern __shared__ uint32_t lds[];
+    constexpr int GPB = 256 / GROUP;
+    const bool dense = dense_u != 0, ck_lds = ck_lds_u != 0;
+    const uint32_t g = threadIdx.x / GROUP, lane = threadIdx.x % GROUP;
+    const uint32_t K = a.K;
+    const uint32_t ck_words = ck_lds ? K : 0;
+    const uint32_t tab_words = dense ? K : 2 * cap_max;
+    uint32_t *ckh = lds;
+    uint32_t *gbase = lds + ck_words + g * (tab_words + GROUP * TPT);
+    uint32_t *tkey = gbase;
+    uint32_t *tcnt = dense ? gbase : gbase + cap_max;
+    uint32_t *zarr = gbase + tab_words;
+
+    for (uint32_t i = threadIdx.x; i < ck_words; i += 256) ckh[i] = 0;
+    if (dense)
+        for (uint32_t i = lane; i < K; i += GROUP) tcnt[i] = 0;
+    __syncthreads();
+
+    const uint32_t xcd = blockIdx.x & 7, nbx = gridDim.x >> 3, bj = blockIdx.x >> 3;
+    const uint32_t lo = l.xcd_cut[xcd], hi = l.xcd_cut[xcd + 1];
+    const uint32_t ngx = nbx * GPB;
+    const float prior = a.prior, mass = a.mass, beta_bar = a.beta_bar;
+    const uint32_t ph = (uint32_t)PHASE << 16;
+    unsigned long long acc = 0;
+
+    for (uint32_t li = lo + bj * GPB + g; li < hi; li += ngx) {
+        const uint32_t s_id = l.ids[li];
+        const uint32_t beg = a.segptr[s_id];
+        const uint32_t L = a.segptr[s_id + 1] - beg;
+        uint32_t pos[TPT];
+        Rec<NW> rec[TPT];
+#pragma unroll
+        for (int r = 0; r < TPT; ++r) {
+            const uint32_t n = r * GROUP + lane;
+            if (n < L) {
+                pos[r] = PHASE == PH_DOC ? a.rowpos[beg + n] : beg + n;
+                rec[r] = ld_rec<NW>(a.recs, pos[r]);
+            }
+        }
+        uint32_t znew[TPT];
+        uint32_t r2[TPT][M];
+        uint32_t coins = 0;   // bit r*M + i: proposal i of token r takes the count part
+        if (!a.draw_only) {
+            uint32_t mask = 0;
+            if (!dense) {
+                const uint32_t cap = pow2_at_least(2 * L);
+                mask = cap - 1;
+                for (uint32_t i = lane; i < cap; i += GROUP) {
+                    tkey[i] = EMPTY_KEY;
+                    tcnt[i] = 0;
+                }
+                group_sync<GROUP>();
+            }
+#pragma unroll
+            for (int r = 0; r < TPT; ++r)
+                if (r * GROUP + lane < L) tab_insert(tkey, tcnt, mask, dense, fld(rec[r], 0));
+            group_sync<GROUP>();
+#pragma unroll
+            for (int r = 0; r < TPT; ++r) {
+                if (r * GROUP + lane < L) {
+                    uint32_t s = fld(rec[r], 0);
+#pragma unroll
+                    for (int i = 1; i <= M; ++i) {
+                        const uint4 R = philox(pos[r], a.iter, ph | i, 0, a.seed_lo, a.seed_hi);
+                        const uint32_t c = fld(rec[r], i);
+                        const uint32_t cc = tab_get(tkey, tcnt, mask, dense, c);
+                        const uint32_t cs = tab_get(tkey, tcnt, mask, dense, s);
+                        if (mh_accept(unif24(R.x), cc, cs, prior, a.ck[s], a.ck[c], beta_bar)) {
+                            s = c;
+                            ++acc;
+                        }
+                        if (take_count_part(unif24(R.y), L, mass)) coins |= 1u << (r * M + i - 1);
+                        r2[r][i - 1] = R.z;
+                    }
+                    znew[r] = s;
+                }
+            }
+            group_sync<GROUP>();
+            if (dense) {
+#pragma unroll
+                for (int r = 0; r < TPT; ++r)
+                    if (r * GROUP + lane < L) tcnt[fld(rec[r], 0)] = 0;
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < TPT; ++r) {
+                if (r * GROUP + lane < L) {
+                    znew[r] = fld(rec[r], 0);
+#pragma unroll
+                    for (int i = 1; i <= M; ++i) {
+                        const uint4 R = philox(pos[r], a.iter, ph | i, 0, a.seed_lo, a.seed_hi);
+                        if (take_count_part(unif24(R.y), L, mass)) coins |= 1u << (r * M + i - 1);
+                        r2[r][i - 1] = R.z;
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < TPT; ++r)
+            if (r * GROUP + lane < L) zarr[r * GROUP + lane] = znew[r];
+        group_sync<GROUP>();
+#pragma unroll
+        for (int r = 0; r < TPT; ++r) {
+            if (r * GROUP + lane < L) {
+                Rec<NW> out;
+#pragma unroll
+                for (int w = 0; w < NW; ++w) out.w[w] = 0;
+                set_fld(out, 0, znew[r]);
+#pragma unroll
+                for (int i = 1; i <= M; ++i) {
+                    const uint32_t rr = r2[r][i - 1];
+                    const uint32_t p = (coins >> (r * M + i - 1)) & 1u ? zarr[dice(rr, L)] : dice(rr, K);
+                    set_fld(out, i, p);
+                }
+                st_rec<NW>(a.recs, pos[r], out);
+                if (ck_lds)
+                    atomicAdd(&ckh[znew[r]], 1u);
+                else
+                    atomicAdd(&a.ck_next[znew[r]], 1u);
+            }
+        }
+        group_sync<GROUP>();
+    }
+    add_accepted(a.accepted, acc);
+    __syncthreads();
+    if (ck_lds) {
+        for (uint32_t k = threadIdx.x; k < K; k += 256) {
+            const uint32_t v = ckh[k];
+            if (v) atomicAdd(&a.ck_next[k], v);
+        }
+    }
+}
+
+// --------------------------------------------------------------------------
+// Long segments (intra-word parallelism, Section 5.4): the tokens of all long
+// segments form one virtual index space [0, total); prefix[j] is where long
+// segment j starts in it.
+// --------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t find_long(const uint32_t *prefix, uint32_t n, uint32_t v) {
+    uint32_t lo = 0, hi = n;   // largest j with prefix[j] <= v
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (prefix[mid] <= v)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+template <int PHASE, int NW>
+__global__ __launch_bounds__(256) void long_hist_kernel(PhaseArgs a, LongList l, uint32_t lds_hist) {
+    extern __shared__ uint32_t hist[];
+    const uint32_t K = a.K;
+    uint32_t v0 = blockIdx.x * Tuning::LONG_CHUNK;
+    const uint32_t v1 = min(l.total, v0 + Tuning::LONG_CHUNK);
+    if (v0 >= v1) return;
+    uint32_t j = find_long(l.prefix, l.n, v0);
+    while (v0 < v1) {
+        const uint32_t pend = min(v1, l.prefix[j + 1]);
+        const uint32_t s_id = l.ids[j];
+        const uint32_t beg = a.segptr[s_id];
+        uint32_t *gt = l.tables + (size_t)j * K;
+        if (lds_hist) {
+            for (uint32_t k = threadIdx.x; k < K; k += 256) hist[k] = 0;
+            __syncthreads();
+        }
+        for (uint32_t v = v0 + threadIdx.x; v < pend; v += 256) {
+            const uint32_t n = v - l.prefix[j];
+            const uint32_t pos = PHASE == PH_DOC ? a.rowpos[beg + n] : beg + n;
+            const uint32_t z = fld(ld_rec<NW>(a.recs, pos), 0);
+            if (lds_hist)
+                atomicAdd(&hist[z], 1u);
+            else
+                atomicAdd(&gt[z], 1u);
+        }
+        if (lds_hist) {
+            __syncthreads();
+            for (uint32_t k = threadIdx.x; k < K; k += 256) {
+                const uint32_t c = hist[k];
+                if (c) atomicAdd(&gt[k], c);
+            }
+            __syncthreads();
+        }
+        v0 = pend;
+        ++j;
+    }
+}
+
+template <int PHASE, int M, int NW>
+__global__ __launch_bounds__(256) void long_mh_kernel(PhaseArgs a, LongList l) {
+    const uint32_t K = a.K;
+    const uint32_t ph = (uint32_t)PHASE << 16;
+    unsigned long long acc = 0;
+    for (uint32_t v = blockIdx.x * 256 + threadIdx.x; v < l.total; v += gridDim.x * 256) {
+        const uint32_t j = find_long(l.prefix, l.n, v);
+        const uint32_t s_id = l.ids[j];
+        const uint32_t beg = a.segptr[s_id];
+        const uint32_t n = v - l.prefix[j];
+        const uint32_t pos = PHASE == PH_DOC ? a.rowpos[beg + n] : beg + n;
+        const uint32_t *gt = l.tables + (size_t)j * K;
+        Rec<NW> rec = ld_rec<NW>(a.recs, pos);
+        uint32_t s = fld(rec, 0);
+#pragma unroll
+        for (int i = 1; i <= M; ++i) {
+            const uint4 R = philox(pos, a.iter, ph | i, 0, a.seed_lo, a.seed_hi);
+            const uint32_t c = fld(rec, i);
+            if (mh_accept(unif24(R.x), gt[c], gt[s], a.prior, a.ck[s], a.ck[c], a.beta_bar)) {
+                s = c;
+                ++acc;
+            }
+        }
+        set_fld(rec, 0, s);
+        st_rec<NW>(a.recs, pos, rec);
+    }
+    add_accepted(a.accepted, acc);
+}
+
+template <int PHASE, int M, int NW>
+__global__ __launch_bounds__(256) void long_draw_kernel(PhaseArgs a, LongList l, uint32_t ck_lds_u,
+                                                        uint32_t zero_tables) {
+    extern __shared__ uint32_t ckh[];
+    const bool ck_lds = ck_lds_u != 0;
+    const uint32_t K = a.K;
+    const uint32_t ph = (uint32_t)PHASE << 16;
+    if (ck_lds) {
+        for (uint32_t k = threadIdx.x; k < K; k += 256) ckh[k] = 0;
+        __syncthreads();
+    }
+    for (uint32_t v = blockIdx.x * 256 + threadIdx.x; v < l.total; v += gridDim.x * 256) {
+        const uint32_t j = find_long(l.prefix, l.n, v);
+        const uint32_t s_id = l.ids[j];
+        const uint32_t beg = a.segptr[s_id];
+        const uint32_t L = a.segptr[s_id + 1] - beg;
+        const uint32_t n = v - l.prefix[j];
+        const uint32_t pos = PHASE == PH_DOC ? a.rowpos[beg + n] : beg + n;
+        Rec<NW> rec = ld_rec<NW>(a.recs, pos);
+        const uint32_t z = fld(rec, 0);
+#pragma unroll
+        for (int i = 1; i <= M; ++i) {
+            const uint4 R = philox(pos, a.iter, ph | i, 0, a.seed_lo, a.seed_hi);
+            uint32_t p;
+            if (take_count_part(unif24(R.y), L, a.mass)) {
+                const uint32_t jn = dice(R.z, L);
+                const uint32_t jpos = PHASE == PH_DOC ? a.rowpos[beg + jn] : beg + jn;
+                p = fld(ld_rec<NW>(a.recs, jpos), 0);
+            } else {
+                p = dice(R.z, K);
+            }
+            set_fld(rec, i, p);
+        }
+        st_rec<NW>(a.recs, pos, rec);
+        if (ck_lds)
+            atomicAdd(&ckh[z], 1u);
+        else
+            atomicAdd(&a.ck_next[z], 1u);
+    }
+    if (zero_tables) {
+        const size_t nt = (size_t)l.n * K;
+        for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < nt; i += (size_t)gridDim.x * 256)
+            l.tables[i] = 0;
+    }
+    if (ck_lds) {
+        __syncthreads();
+        for (uint32_t k = threadIdx.x; k < K; k += 256) {
+            const uint32_t c = ckh[k];
+            if (c) atomicAdd(&a.ck_next[k], c);
+        }
+    }
+}
+
+// --------------------------------------------------------------------------
+// Small kernels
+// --------------------------------------------------------------------------
+__global__ void fill_u32_kernel(uint32_t *p, uint32_t v, uint64_t n) {
+    for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (uint64_t)gridDim.x * 256)
+        p[i] = v;
+}
+
+// z = Dice(K) with the INIT counter (t, 0, 0, 0); proposals cleared.
+template <int NW>
+__global__ void init_z_kernel(uint64_t *recs, uint32_t T, uint32_t K, uint32_t k0, uint32_t k1) {
+    for (uint32_t t = blockIdx.x * 256 + threadIdx.x; t < T; t += gridDim.x * 256) {
+        const uint4 R = philox(t, 0, (uint32_t)PH_INIT << 16, 0, k0, k1);
+        Rec<NW> r;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) r.w[w] = 0;
+        set_fld(r, 0, dice(R.z, K));
+        st_rec<NW>(recs, t, r);
+    }
+}
+
+template <int NW>
+__global__ void unpack_kernel(const uint64_t *recs, uint32_t T, uint32_t M, int32_t *z,
+                              int32_t *props) {
+    for (uint32_t t = blockIdx.x * 256 + threadIdx.x; t < T; t += gridDim.x * 256) {
+        const Rec<NW> r = ld_rec<NW>(recs, t);
+        z[t] = (int32_t)fld(r, 0);
+        if (props)
+            for (uint32_t i = 1; i <= M; ++i) props[(size_t)(i - 1) * T + t] = (int32_t)fld(r, i);
+    }
+}
+
+template <int NW>
+__global__ void pack_kernel(uint64_t *recs, uint32_t T, uint32_t M, const int32_t *z,
+                            const int32_t *props) {
+    for (uint32_t t = blockIdx.x * 256 + threadIdx.x; t < T; t += gridDim.x * 256) {
+        Rec<NW> r;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) r.w[w] = 0;
+        set_fld(r, 0, (uint32_t)z[t]);
+        for (uint32_t i = 1; i <= M; ++i) set_fld(r, i, (uint32_t)props[(size_t)(i - 1) * T + t]);
+        st_rec<NW>(recs, t, r);
+    }
+}
+
+template <int NW>
+__global__ void histogram_z_kernel(const uint64_t *recs, uint32_t T, uint32_t *ck) {
+    for (uint32_t t = blockIdx.x * 256 + threadIdx.x; t < T; t += gridDim.x * 256)
+        atomicAdd(&ck[fld(ld_rec<NW>(recs, t), 0)], 1u);
+}
+
+// --------------------------------------------------------------------------
+// Log joint likelihood (Section 6.1), binary64.  One workgroup per segment,
+// dense LDS counts (K <= LL_DENSE_MAX).
+// --------------------------------------------------------------------------
+constexpr uint32_t LL_DENSE_MAX = 16384;
+
+__device__ double block_sum(double v) {
+    __shared__ double part[4];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double s = 0;
+    if (threadIdx.x == 0) s = part[0] + part[1] + part[2] + part[3];
+    __syncthreads();
+    return s;
+}
+
+template <int NW>
+__global__ __launch_bounds__(256) void ll_seg_kernel(const uint64_t *recs, const uint32_t *segptr,
+                                                     const uint32_t *rowpos, uint32_t n_seg,
+                                                     uint32_t K, double prior, double prior_total,
+                                                     int length_term, double *out) {
+    extern __shared__ uint32_t cnt[];
+    const double lg_prior = lgamma(prior), lg_total = lgamma(prior_total);
+    double acc = 0;
+    for (uint32_t s = blockIdx.x; s < n_seg; s += gridDim.x) {
+        const uint32_t beg = segptr[s], L = segptr[s + 1] - beg;
+        if (L == 0) continue;
+        for (uint32_t k = threadIdx.x; k < K; k += 256) cnt[k] = 0;
+        __syncthreads();
+        for (uint32_t n = threadIdx.x; n < L; n += 256) {
+            const uint32_t pos = rowpos ? rowpos[beg + n] : beg + n;
+            atomicAdd(&cnt[fld(ld_rec<NW>(recs, pos), 0)], 1u);
+        }
+        __syncthreads();
+        for (uint32_t k = threadIdx.x; k < K; k += 256) {
+            const uint32_t c = cnt[k];
+            if (c) acc += lgamma(prior + (double)c) - lg_prior;
+        }
+        if (length_term && threadIdx.x == 0) acc += lg_total - lgamma(prior_total + (double)L);
+        __syncthreads();
+    }
+    const double s = block_sum(acc);
+    if (threadIdx.x == 0) atomicAdd(out, s);
+}
+
+__global__ void ll_topics_kernel(const uint32_t *ck, uint32_t K, double beta_bar, double *out) {
+    const double lg = lgamma(beta_bar);
+    double acc = 0;
+    for (uint32_t k = blockIdx.x * 256 + threadIdx.x; k < K; k += gridDim.x * 256)
+        if (ck[k]) acc += lg - lgamma(beta_bar + (double)ck[k]);
+    const double s = block_sum(acc);
+    if (threadIdx.x == 0) atomicAdd(out, s);
+}
+
+// --------------------------------------------------------------------------
+// Launchers
+// --------------------------------------------------------------------------
+static int grid_for(uint64_t n, int cap = 8192) {
+    uint64_t b = (n + 255) / 256;
+    if (b < 1) b = 1;
+    if (b > (uint64_t)cap) b = cap;
+    return (int)b;
+}
+
+hipError_t launch_fill_u32(uint32_t *p, uint32_t v, uint64_t n, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(fill_u32_kernel, dim3(grid_for(n)), dim3(256), 0, st, p, v, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_init_z(uint64_t *recs, uint32_t T, uint32_t M, uint32_t K, uint32_t k0,
+                         uint32_t k1, hipStream_t st) {
+    if (T == 0) return hipSuccess;
+    if (record_words(M) == 1)
+        hipLaunchKernelGGL(init_z_kernel<1>, dim3(grid_for(T)), dim3(256), 0, st, recs, T, K, k0, k1);
+    else
+        hipLaunchKernelGGL(init_z_kernel<2>, dim3(grid_for(T)), dim3(256), 0, st, recs, T, K, k0, k1);
+    return hipGetLastError();
+}
+
+template <typename Kern>
+static hipError_t launch_dyn(Kern k, dim3 grid, size_t lds, hipStream_t st) {
+    (void)k; (void)grid; (void)st;
+    if (lds > 65536) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+template <int PHASE, int M, int NW, int GROUP, int TPT>
+static hipError_t run_seg(const PhaseArgs &a, const SegList &l, uint32_t cap_bound, hipStream_t st) {
+    if (l.n == 0) return hipSuccess;
+    const bool dense = a.K <= cap_bound;
+    const bool ck_lds = a.K <= Tuning::CK_LDS_MAX;
+    const uint32_t cap_max = dense ? 0 : cap_bound;
+    const uint32_t tab_words = dense ? a.K : 2 * cap_max;
+    constexpr int GPB = 256 / GROUP;
+    const size_t lds = 4ull * ((ck_lds ? a.K : 0) + GPB * (tab_words + GROUP * TPT));
+    auto kern = seg_kernel<PHASE, M, NW, GROUP, TPT>;
+    hipError_t e = launch_dyn(kern, dim3(1), lds, st);
+    if (e != hipSuccess) return e;
+    // Blocks are assigned to XCDs round robin; use a multiple of 8 and
+    // enough groups to keep every CU busy, never more than the list needs.
+    uint32_t blocks = (l.n + GPB - 1) / GPB;
+    blocks = blocks < 2048 ? blocks : 2048;
+    blocks = (blocks + 7) / 8 * 8;
+    hipLaunchKernelGGL(kern, dim3(blocks), dim3(256), lds, st, a, l, cap_max, (uint32_t)dense,
+                       (uint32_t)ck_lds);
+    return hipGetLastError();
+}
+
+template <int PHASE, int M>
+static hipError_t wave_dispatch(const PhaseArgs &a, const SegList &l, hipStream_t st) {
+    constexpr int NW = (M + 3) / 3;
+    return run_seg<PHASE, M, NW, 64, Tuning::TPT_WAVE>(a, l, Tuning::WAVE_CAP, st);
+}
+
+template <int PHASE, int M>
+static hipError_t block_dispatch(const PhaseArgs &a, const SegList &l, hipStream_t st) {
+    constexpr int NW = (M + 3) / 3;
+    constexpr int TPT = M <= 2 ? Tuning::TPT_BLOCK : Tuning::TPT_BLOCK / 2;
+    return run_seg<PHASE, M, NW, 256, TPT>(a, l, 2 * 256 * TPT, st);
+}
+
+#define WLDA_DISPATCH_M(FN, PHASE, ...)                                 \
+    switch (M) {                                                        \
+        case 1: return FN<PHASE, 1>(__VA_ARGS__);                       \
+        case 2: return FN<PHASE, 2>(__VA_ARGS__);                       \
+        case 3: return FN<PHASE, 3>(__VA_ARGS__);                       \
+        case 4: return FN<PHASE, 4>(__VA_ARGS__);                       \
+        default: return hipErrorInvalidValue;                           \
+    }
+
+hipError_t launch_wave_segments(const PhaseArgs &a, uint32_t phase, uint32_t M, const SegList &l,
+                                hipStream_t st) {
+    if (phase == PH_WORD) {
+        WLDA_DISPATCH_M(wave_dispatch, PH_WORD, a, l, st)
+    }
+    WLDA_DISPATCH_M(wave_dispatch, PH_DOC, a, l, st)
+}
+
+hipError_t launch_block_segments(const PhaseArgs &a, uint32_t phase, uint32_t M, const SegList &l,
+                                 hipStream_t st) {
+    if (phase == PH_WORD) {
+        WLDA_DISPATCH_M(block_dispatch, PH_WORD, a, l, st)
+    }
+    WLDA_DISPATCH_M(block_dispatch, PH_DOC, a, l, st)
+}
+
+template <int PHASE, int M>
+static hipError_t long_dispatch(const PhaseArgs &a, const LongList &l, hipStream_t st) {
+    constexpr int NW = (M + 3) / 3;
+    if (l.n == 0) return hipSuccess;
+    const bool lds_hist = a.K <= 16384;
+    const bool ck_lds = a.K <= Tuning::CK_LDS_MAX;
+    hipError_t e;
+    if (!a.draw_only) {
+        const uint32_t hb = (l.total + Tuning::LONG_CHUNK - 1) / Tuning::LONG_CHUNK;
+        const size_t lds = lds_hist ? 4ull * a.K : 0;
+        e = launch_dyn(long_hist_kernel<PHASE, NW>, dim3(1), lds, st);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((long_hist_kernel<PHASE, NW>), dim3(hb), dim3(256), lds, st, a, l,
+                           (uint32_t)lds_hist);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        hipLaunchKernelGGL((long_mh_kernel<PHASE, M, NW>), dim3(grid_for(l.total, 4096)), dim3(256), 0,
+                           st, a, l);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    const size_t lds = ck_lds ? 4ull * a.K : 0;
+    e = launch_dyn(long_draw_kernel<PHASE, M, NW>, dim3(1), lds, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((long_draw_kernel<PHASE, M, NW>), dim3(grid_for(l.total, 2048)), dim3(256), lds,
+                       st, a, l, (uint32_t)ck_lds, (uint32_t)(a.draw_only ? 0 : 1));
+    return hipGetLastError();
+}
+
+hipError_t launch_long_segments(const PhaseArgs &a, uint32_t phase, uint32_t M, const LongList &l,
+                                hipStream_t st) {
+    if (phase == PH_WORD) {
+        WLDA_DISPATCH_M(long_dispatch, PH_WORD, a, l, st)
+    }
+    WLDA_DISPATCH_M(long_dispatch, PH_DOC, a, l, st)
+}
+
+hipError_t launch_unpack(const uint64_t *recs, uint32_t T, uint32_t M, int32_t *z, int32_t *props,
+                         hipStream_t st) {
+    if (T == 0) return hipSuccess;
+    if (record_words(M) == 1)
+        hipLaunchKernelGGL(unpack_kernel<1>, dim3(grid_for(T)), dim3(256), 0, st, recs, T, M, z, props);
+    else
+        hipLaunchKernelGGL(unpack_kernel<2>, dim3(grid_for(T)), dim3(256), 0, st, recs, T, M, z, props);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack(uint64_t *recs, uint32_t T, uint32_t M, const int32_t *z, const int32_t *props,
+                       hipStream_t st) {
+    if (T == 0) return hipSuccess;
+    if (record_words(M) == 1)
+        hipLaunchKernelGGL(pack_kernel<1>, dim3(grid_for(T)), dim3(256), 0, st, recs, T, M, z, props);
+    else
+        hipLaunchKernelGGL(pack_kernel<2>, dim3(grid_for(T)), dim3(256), 0, st, recs, T, M, z, props);
+    return hipGetLastError();
+}
+
+hipError_t launch_histogram_z(const uint64_t *recs, uint32_t T, uint32_t M, uint32_t K, uint32_t *ck,
+                              hipStream_t st) {
+    (void)K;
+    if (T == 0) return hipSuccess;
+    if (record_words(M) == 1)
+        hipLaunchKernelGGL(histogram_z_kernel<1>, dim3(grid_for(T)), dim3(256), 0, st, recs, T, ck);
+    else
+        hipLaunchKernelGGL(histogram_z_kernel<2>, dim3(grid_for(T)), dim3(256), 0, st, recs, T, ck);
+    return hipGetLastError();
+}
+
+hipError_t launch_ll_segments(const uint64_t *recs, uint32_t M, const uint32_t *segptr,
+                              const uint32_t *rowpos, uint32_t n_seg, uint32_t K, double prior,
+                              double prior_total, int length_term, double *out, hipStream_t st) {
+    if (n_seg == 0) return hipSuccess;
+    if (K > LL_DENSE_MAX) return hipErrorNotSupported;
+    const size_t lds = 4ull * K;
+    const int blocks = n_seg < 4096 ? (int)n_seg : 4096;
+    hipError_t e;
+    if (record_words(M) == 1) {
+        e = launch_dyn(ll_seg_kernel<1>, dim3(1), lds, st);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(ll_seg_kernel<1>, dim3(blocks), dim3(256), lds, st, recs, segptr, rowpos,
+                           n_seg, K, prior, prior_total, length_term, out);
+    } else {
+        e = launch_dyn(ll_seg_kernel<2>, dim3(1), lds, st);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(ll_seg_kernel<2>, dim3(blocks), dim3(256), lds, st, recs, segptr, rowpos,
+                           n_seg, K, prior, prior_total, length_term, out);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_ll_topics(const uint32_t *ck, uint32_t K, double beta_bar, double *out,
+                            hipStream_t st) {
+    hipLaunchKernelGGL(ll_topics_kernel, dim3(grid_for(K, 256)), dim3(256), 0, st, ck, K, beta_bar,
+                       out);
+    return hipGetLastError();
+}
+
+}  // namespace wlda

@@ -1,0 +1,217 @@
+"""Parity of the HIP path with the CPU oracle (bit-exact assignments).
+
+Every case drives the library through its C ABI (via the ctypes binding) and
+the oracle with the same corpus, parameters and seed, then compares z, the
+pending proposals, c_k and the acceptance counts element by element after each
+phase.  LL must agree within 1e-6 relative (binary64 accumulation in a
+different order, device vs host lgamma).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+LL_RTOL = 1e-6
+
+
+@pytest.fixture(scope="module")
+def W():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1510_08628_amd as W
+    W.load_library()
+    return W
+
+
+def make_pair(W, c, K, M, alpha, beta, seed=1):
+    s = W.Sampler(c.word_ids, c.doc_ids, c.V, c.D, K, M, alpha, beta, seed=seed)
+    o = oracle.Oracle(c.word_ids, c.doc_ids, c.V, c.D, K, M, alpha, beta, seed=seed)
+    return s, o
+
+
+def assert_same(s, o, where=""):
+    zs, ps = s.assignments()
+    zo, po = o.assignments()
+    if not np.array_equal(zs, zo):
+        bad = np.nonzero(zs != zo)[0]
+        raise AssertionError(f"{where}: z differs at {bad.size} tokens, first {bad[:5]}")
+    if not np.array_equal(ps, po):
+        bad = np.nonzero((ps != po).any(0))[0]
+        raise AssertionError(f"{where}: proposals differ at {bad.size} tokens, first {bad[:5]}")
+    assert np.array_equal(s.topic_counts(), o.topic_counts()), where
+
+
+def mixed_corpus(seed, V=300, D=220, s=1.2, giant_docs=2):
+    """Zipf words (a few columns longer than one workgroup's share), lognormal
+    documents plus a few giant ones, some empty documents and unused words."""
+    rng = np.random.default_rng(seed)
+    lens = np.maximum(1, rng.lognormal(np.log(250) - 0.5, 1.0, D).astype(int))
+    lens[:giant_docs] = 6000           # longer than one workgroup (doc long path)
+    lens[giant_docs:giant_docs + 5] = 1500   # workgroup path
+    lens[-3:] = 0                      # empty documents
+    T = int(lens.sum())
+    w = np.arange(1, V + 1, dtype=float) ** -s
+    w[-7:] = 0                         # words that never occur
+    w /= w.sum()
+    words = rng.choice(V, size=T, p=w).astype(np.uint32)
+    docs = np.repeat(np.arange(D, dtype=np.uint32), lens)
+    perm = rng.permutation(T)          # input order is arbitrary
+    return synth.Corpus(words[perm], docs[perm], V, D)
+
+
+def test_tiny_lda_corpus_50_iterations(W):
+    wl = synth.WORKLOADS["tiny-lda-k16"]
+    c = wl.make()
+    s, o = make_pair(W, c, wl.K, wl.M, wl.alpha, wl.beta, seed=1)
+    s.init()
+    o.init()
+    assert_same(s, o, "init")
+    s.word_phase()
+    o.word_phase()
+    assert_same(s, o, "word phase 1")
+    assert s.accepted(1) == o.accepted(1)
+    s.doc_phase()
+    o.doc_phase()
+    assert_same(s, o, "doc phase 1")
+    assert s.accepted(2) == o.accepted(2)
+    for it in (10, 50):
+        n = it - o.iteration
+        s.iterate(n)
+        o.iterate(n)
+        assert_same(s, o, f"iteration {it}")
+        assert s.iteration == o.iteration == it
+    ll_s, ll_o = s.log_likelihood(), o.log_likelihood()
+    assert abs(ll_s - ll_o) <= LL_RTOL * abs(ll_o), (ll_s, ll_o)
+
+
+@pytest.mark.parametrize("K,M", [(7, 1), (1000, 2), (5000, 3), (20000, 4), (300000, 2)])
+def test_all_paths_bit_exact(W, K, M):
+    c = mixed_corpus(K + M)
+    alpha, beta = 50.0 / K, 0.01
+    s, o = make_pair(W, c, K, M, alpha, beta, seed=K * 7 + M)
+    s.init()
+    o.init()
+    assert_same(s, o, "init")
+    for it in range(3):
+        s.word_phase()
+        o.word_phase()
+        assert_same(s, o, f"word phase {it + 1}")
+        assert s.accepted(1) == o.accepted(1)
+        s.doc_phase()
+        o.doc_phase()
+        assert_same(s, o, f"doc phase {it + 1}")
+        assert s.accepted(2) == o.accepted(2)
+    if K <= 16384:
+        ll_s, ll_o = s.log_likelihood(), o.log_likelihood()
+        assert abs(ll_s - ll_o) <= LL_RTOL * abs(ll_o), (ll_s, ll_o)
+
+
+@pytest.mark.parametrize("case", ["one_token", "one_doc_one_word", "k1", "all_same_cell",
+                                  "empty_rows_cols", "ragged_tail"])
+def test_edge_cases(W, case):
+    rng = np.random.default_rng(3)
+    if case == "one_token":
+        c = synth.Corpus(np.array([4], np.uint32), np.array([2], np.uint32), 5, 3)
+        K, M = 3, 2
+    elif case == "one_doc_one_word":
+        c = synth.Corpus(np.zeros(777, np.uint32), np.zeros(777, np.uint32), 1, 1)
+        K, M = 5, 2
+    elif case == "k1":
+        c = synth.random_corpus(5000, 40, 30, seed=5)
+        K, M = 1, 2
+    elif case == "all_same_cell":      # one column and one row, both long
+        c = synth.Corpus(np.full(12000, 3, np.uint32), np.full(12000, 1, np.uint32), 4, 2)
+        K, M = 50, 2
+    elif case == "empty_rows_cols":
+        w = rng.integers(0, 10, 3000).astype(np.uint32) * 10      # 90% of words unused
+        d = rng.integers(0, 20, 3000).astype(np.uint32) * 5       # 80% of docs empty
+        c = synth.Corpus(w, d, 100, 100)
+        K, M = 64, 2
+    else:                              # lengths straddling every bin boundary
+        lens = [511, 512, 513, 4095, 4096, 4097, 1, 2, 63, 64, 65]
+        d = np.repeat(np.arange(len(lens), dtype=np.uint32), lens)
+        w = np.concatenate([np.full(L, i, np.uint32) for i, L in enumerate(lens)])
+        w = w[rng.permutation(len(w))]
+        c = synth.Corpus(w, d, len(lens), len(lens))
+        K, M = 200, 2
+    s, o = make_pair(W, c, K, M, 0.3, 0.02, seed=11)
+    s.init()
+    o.init()
+    assert_same(s, o, "init")
+    for it in range(2):
+        s.word_phase()
+        o.word_phase()
+        assert_same(s, o, f"{case} word {it}")
+        s.doc_phase()
+        o.doc_phase()
+        assert_same(s, o, f"{case} doc {it}")
+    ll_s, ll_o = s.log_likelihood(), o.log_likelihood()
+    assert abs(ll_s - ll_o) <= LL_RTOL * abs(ll_o) + 1e-9, (ll_s, ll_o)
+
+
+def test_wright_fisher_case_accepts_everything(W):
+    """D = V = 1, alpha = beta: both Eq. (7) ratios are exactly 1."""
+    c = synth.Corpus(np.zeros(3000, np.uint32), np.zeros(3000, np.uint32), 1, 1)
+    s = W.Sampler(c.word_ids, c.doc_ids, 1, 1, 4, 2, 1.0, 1.0, seed=3)
+    s.init()
+    for _ in range(3):
+        s.word_phase()
+        assert s.accepted(1) == 2 * 3000
+        s.doc_phase()
+        assert s.accepted(2) == 2 * 3000
+
+
+def test_checkpoint_resume_and_order_errors(W):
+    c = mixed_corpus(9, V=120, D=90, giant_docs=1)
+    K, M = 100, 2
+    a = W.Sampler(c.word_ids, c.doc_ids, c.V, c.D, K, M, 0.5, 0.01, seed=4)
+    with pytest.raises(W.WldaError) as e:
+        a.word_phase()
+    assert e.value.code == -4
+    a.init()
+    with pytest.raises(W.WldaError):
+        a.doc_phase()
+    a.iterate(2)
+    a.word_phase()
+    blob = a.save_state()
+    a.doc_phase()
+    a.iterate(2)
+    b = W.Sampler(c.word_ids, c.doc_ids, c.V, c.D, K, M, 0.5, 0.01, seed=4)
+    b.load_state(blob)
+    b.doc_phase()
+    b.iterate(2)
+    za, pa = a.assignments()
+    zb, pb = b.assignments()
+    assert np.array_equal(za, zb) and np.array_equal(pa, pb)
+    assert a.iteration == b.iteration == 5
+
+
+def test_set_assignments_matches_oracle(W):
+    c = mixed_corpus(9, V=120, D=90, giant_docs=1)
+    K, M = 100, 2
+    s, o = make_pair(W, c, K, M, 0.5, 0.01, seed=4)
+    s.init()
+    o.init()
+    zo, po = o.assignments()
+    rng = np.random.default_rng(0)
+    z2 = ((zo + rng.integers(0, 3, zo.shape)) % K).astype(np.int32)
+    p2 = ((po + 1) % K).astype(np.int32)
+    s.set_assignments(z2, p2)
+    _, _, _, inv = o.layout()
+    zc = np.empty_like(z2)
+    zc[inv] = z2
+    pc = np.empty_like(p2)
+    pc[:, inv] = p2
+    o.set_csc_state(zc, pc)
+    assert_same(s, o, "after set")
+    for _ in range(2):
+        s.word_phase()
+        o.word_phase()
+        assert_same(s, o, "word after set")
+        s.doc_phase()
+        o.doc_phase()
+        assert_same(s, o, "doc after set")
