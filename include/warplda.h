@@ -138,6 +138,22 @@ wlda_status wlda_load_state(wlda_sampler s, const void *host_buf, uint64_t bytes
  * the next call must be a word phase.  For tests and warm starts. */
 wlda_status wlda_set_assignments(wlda_sampler s, const int32_t *z, const int32_t *props);
 
+/* Per-kernel timing.  wlda_profile(s, 1) clears the counters and starts
+ * recording a HIP event pair around every kernel the sampler launches (on its
+ * stream); wlda_profile(s, 0) stops.  wlda_profile_read() synchronises and
+ * returns one entry per kernel kind: total milliseconds over the recorded
+ * launches, the launch count and the tokens one launch processes. */
+typedef struct {
+    const char *name;            /* static string, e.g. "doc_wave"           */
+    uint64_t launches;
+    uint64_t tokens_per_launch;
+    double total_ms;
+} wlda_kernel_stat;
+
+wlda_status wlda_profile(wlda_sampler s, int enable);
+wlda_status wlda_profile_read(wlda_sampler s, wlda_kernel_stat *out, uint32_t max_entries,
+                              uint32_t *n_entries);
+
 /* Releases host-side state; the workspace is the caller's to free. */
 wlda_status wlda_destroy(wlda_sampler s);
 

@@ -36,8 +36,13 @@ EXPORTS = [
     "wlda_iterate", "wlda_log_likelihood", "wlda_copy_assignments",
     "wlda_copy_assignments_csc", "wlda_copy_topic_counts", "wlda_accepted", "wlda_iteration",
     "wlda_state_bytes", "wlda_save_state", "wlda_load_state", "wlda_set_assignments",
-    "wlda_destroy", "wlda_strerror",
+    "wlda_destroy", "wlda_strerror", "wlda_profile", "wlda_profile_read",
 ]
+
+
+class KernelStat(C.Structure):
+    _fields_ = [("name", C.c_char_p), ("launches", C.c_uint64),
+                ("tokens_per_launch", C.c_uint64), ("total_ms", C.c_double)]
 
 _lib = None
 
@@ -67,6 +72,8 @@ def load_library(path: str = LIB_PATH):
         "wlda_save_state": [vp, vp, u64], "wlda_load_state": [vp, vp, u64],
         "wlda_set_assignments": [vp, vp, vp],
         "wlda_destroy": [vp],
+        "wlda_profile": [vp, i32],
+        "wlda_profile_read": [vp, C.POINTER(KernelStat), u32, C.POINTER(u32)],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -178,6 +185,17 @@ class Sampler:
     def load_state(self, blob: bytes):
         buf = np.frombuffer(blob, dtype=np.uint8).copy()
         _check("wlda_load_state", load_library().wlda_load_state(self.h, _ptr(buf), len(buf)))
+
+    def profile(self, enable: bool):
+        _check("wlda_profile", load_library().wlda_profile(self.h, int(enable)))
+
+    def profile_read(self):
+        """{kernel kind: (launches, tokens per launch, total ms)}"""
+        arr = (KernelStat * 32)()
+        n = C.c_uint32(0)
+        _check("wlda_profile_read", load_library().wlda_profile_read(self.h, arr, 32, C.byref(n)))
+        return {arr[i].name.decode(): (int(arr[i].launches), int(arr[i].tokens_per_launch),
+                                       float(arr[i].total_ms)) for i in range(n.value)}
 
     def set_assignments(self, z, props=None):
         zz = np.ascontiguousarray(z, dtype=np.int32)

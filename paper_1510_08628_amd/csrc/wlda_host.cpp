@@ -21,11 +21,14 @@ inline uint64_t align_up(uint64_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
 
 struct PhasePlan {
     std::vector<uint32_t> wave_ids, block_ids, long_ids, long_prefix;
-    uint32_t wave_cut[9] = {}, block_cut[9] = {};
+    std::vector<uint32_t> chunk_seg, chunk_start;
+    uint32_t wave_cut[9] = {}, block_cut[9] = {}, chunk_cut[9] = {};
     // device copies (inside the workspace)
     uint32_t *d_wave_ids = nullptr, *d_wave_cut = nullptr, *d_block_ids = nullptr,
              *d_block_cut = nullptr, *d_long_ids = nullptr, *d_long_prefix = nullptr,
-             *d_tables = nullptr;
+             *d_tables = nullptr, *d_chunk_seg = nullptr, *d_chunk_start = nullptr,
+             *d_chunk_cut = nullptr;
+    void *d_zc = nullptr;
 };
 
 // Split a length-sorted-by-id list into 8 contiguous shares of ~equal tokens
@@ -63,6 +66,61 @@ void build_plan(const std::vector<uint64_t> &len, uint32_t block_max, PhasePlan 
     }
     xcd_cuts(pl.wave_ids, len, pl.wave_cut);
     xcd_cuts(pl.block_ids, len, pl.block_cut);
+    // Long segments whose compact z fits comfortably in one XCD's L2 go whole
+    // to one XCD: longest first, each to the XCD with the fewest tokens so far
+    // (the greedy balanced partition of the paper's Section 5.3, over the
+    // eight XCDs).  Larger ("huge") segments are dealt chunk by chunk to all
+    // XCDs: their random-positioning reads miss L2 anyway, and one XCD alone
+    // would be the straggler.
+    const size_t n = pl.long_ids.size();
+    const uint64_t huge_tokens = 1u << 20;
+    std::vector<uint32_t> order, owner(n, 8);
+    uint64_t load[8] = {};
+    std::vector<std::vector<std::pair<uint32_t, uint32_t>>> chunks(8);
+    uint32_t rr = 0;
+    for (uint32_t j = 0; j < n; ++j) {
+        const uint64_t L = len[pl.long_ids[j]];
+        if (L < huge_tokens) {
+            order.push_back(j);
+            continue;
+        }
+        for (uint64_t n0 = 0; n0 < L; n0 += Tuning::LONG_CHUNK, rr = (rr + 1) & 7) {
+            chunks[rr].push_back({j, (uint32_t)n0});
+            load[rr] += std::min<uint64_t>(Tuning::LONG_CHUNK, L - n0);
+        }
+    }
+    std::stable_sort(order.begin(), order.end(), [&](uint32_t x, uint32_t y) {
+        return len[pl.long_ids[x]] > len[pl.long_ids[y]];
+    });
+    for (uint32_t j : order) {
+        int best = 0;
+        for (int x = 1; x < 8; ++x)
+            if (load[x] < load[best]) best = x;
+        owner[j] = best;
+        load[best] += len[pl.long_ids[j]];
+    }
+    pl.chunk_seg.clear();
+    pl.chunk_start.clear();
+    for (int x = 0; x < 8; ++x) {
+        pl.chunk_cut[x] = (uint32_t)pl.chunk_seg.size();
+        for (auto &c : chunks[x]) {
+            pl.chunk_seg.push_back(c.first);
+            pl.chunk_start.push_back(c.second);
+        }
+        for (uint32_t j = 0; j < n; ++j) {
+            if (owner[j] != (uint32_t)x) continue;
+            const uint64_t L = len[pl.long_ids[j]];
+            for (uint64_t n0 = 0; n0 < L; n0 += Tuning::LONG_CHUNK) {
+                pl.chunk_seg.push_back(j);
+                pl.chunk_start.push_back((uint32_t)n0);
+            }
+        }
+    }
+    pl.chunk_cut[8] = (uint32_t)pl.chunk_seg.size();
+}
+
+inline uint64_t zc_bytes(const PhasePlan &pl, uint32_t K) {
+    return (uint64_t)pl.long_prefix.back() * (K <= 65535 ? 2 : 4) + 4;
 }
 
 struct Sizes {
@@ -75,7 +133,8 @@ uint64_t plan_bytes(const PhasePlan &pl, uint32_t K) {
     return align_up(4ull * pl.wave_ids.size() + 4) + align_up(9 * 4) +
            align_up(4ull * pl.block_ids.size() + 4) + align_up(9 * 4) +
            align_up(4ull * pl.long_ids.size() + 4) + align_up(4ull * pl.long_prefix.size()) +
-           align_up(4ull * pl.long_ids.size() * K + 4);
+           align_up(4ull * pl.long_ids.size() * K + 4) + 2 * align_up(4ull * pl.chunk_seg.size() + 4) +
+           align_up(9 * 4) + align_up(zc_bytes(pl, K));
 }
 
 Sizes compute_sizes(const wlda_params &p, uint64_t T, const PhasePlan &w, const PhasePlan &d) {
@@ -115,6 +174,20 @@ void lengths(const wlda_params &p, const uint32_t *word_ids, const uint32_t *doc
     }
 }
 
+enum Slot {
+    S_WORD_WAVE, S_WORD_BLOCK, S_WORD_LONG_HIST, S_WORD_LONG_MH, S_WORD_LONG_DRAW,
+    S_DOC_WAVE, S_DOC_BLOCK, S_DOC_LONG_HIST, S_DOC_LONG_MH, S_DOC_LONG_DRAW, KSLOTS
+};
+const char *const SLOT_NAMES[KSLOTS] = {
+    "word_wave", "word_block", "word_long_hist", "word_long_mh", "word_long_draw",
+    "doc_wave", "doc_block", "doc_long_hist", "doc_long_mh", "doc_long_draw"};
+
+uint64_t list_tokens(const std::vector<uint32_t> &ids, const std::vector<uint64_t> &len) {
+    uint64_t t = 0;
+    for (uint32_t s : ids) t += len[s];
+    return t;
+}
+
 }  // namespace
 
 struct wlda_sampler_s {
@@ -134,6 +207,12 @@ struct wlda_sampler_s {
     int next_phase = 0;                  // 0: not initialised, 1: word, 2: doc
     bool broken = false;
     float a = 0, b = 0, alpha_bar = 0, beta_k = 0, beta_bar = 0;
+    // profiling: event pairs per kernel kind
+    bool prof = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pairs[KSLOTS];
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_used = 0;
+    uint64_t slot_tokens[KSLOTS] = {};
 };
 
 namespace {
@@ -170,7 +249,14 @@ hipError_t place_plan(PhasePlan &pl, uint8_t *&cur, uint32_t K, hipStream_t st) 
     pl.d_long_ids = (uint32_t *)carve(cur, 4ull * pl.long_ids.size() + 4);
     pl.d_long_prefix = (uint32_t *)carve(cur, 4ull * pl.long_prefix.size());
     pl.d_tables = (uint32_t *)carve(cur, 4ull * pl.long_ids.size() * K + 4);
+    pl.d_chunk_seg = (uint32_t *)carve(cur, 4ull * pl.chunk_seg.size() + 4);
+    pl.d_chunk_start = (uint32_t *)carve(cur, 4ull * pl.chunk_seg.size() + 4);
+    pl.d_chunk_cut = (uint32_t *)carve(cur, 9 * 4);
+    pl.d_zc = carve(cur, zc_bytes(pl, K));
     hipError_t e;
+    if ((e = upload(pl.d_chunk_seg, pl.chunk_seg.data(), 4ull * pl.chunk_seg.size(), st))) return e;
+    if ((e = upload(pl.d_chunk_start, pl.chunk_start.data(), 4ull * pl.chunk_start.size(), st))) return e;
+    if ((e = upload(pl.d_chunk_cut, pl.chunk_cut, 9 * 4, st))) return e;
     if ((e = upload(pl.d_wave_ids, pl.wave_ids.data(), 4ull * pl.wave_ids.size(), st))) return e;
     if ((e = upload(pl.d_wave_cut, pl.wave_cut, 9 * 4, st))) return e;
     if ((e = upload(pl.d_block_ids, pl.block_ids.data(), 4ull * pl.block_ids.size(), st))) return e;
@@ -179,6 +265,31 @@ hipError_t place_plan(PhasePlan &pl, uint8_t *&cur, uint32_t K, hipStream_t st) 
     if ((e = upload(pl.d_long_prefix, pl.long_prefix.data(), 4ull * pl.long_prefix.size(), st)))
         return e;
     return launch_fill_u32(pl.d_tables, 0, (uint64_t)pl.long_ids.size() * K, st);
+}
+
+hipError_t take_event(wlda_sampler s, hipEvent_t *e) {
+    if (s->ev_used == s->ev_pool.size()) {
+        hipEvent_t ne;
+        hipError_t err = hipEventCreate(&ne);
+        if (err != hipSuccess) return err;
+        s->ev_pool.push_back(ne);
+    }
+    *e = s->ev_pool[s->ev_used++];
+    return hipSuccess;
+}
+
+// Records an event pair around `launch` when profiling is on.
+template <typename F>
+hipError_t timed(wlda_sampler s, int slot, F &&launch) {
+    if (!s->prof) return launch();
+    hipEvent_t a, b;
+    hipError_t e;
+    if ((e = take_event(s, &a)) || (e = take_event(s, &b))) return e;
+    if ((e = hipEventRecord(a, s->st))) return e;
+    if ((e = launch())) return e;
+    if ((e = hipEventRecord(b, s->st))) return e;
+    s->ev_pairs[slot].push_back({a, b});
+    return hipSuccess;
 }
 
 // One phase: every segment of the phase's plan, c_k of the new Z into the
@@ -210,9 +321,27 @@ wlda_status run_phase(wlda_sampler s, uint32_t phase, uint32_t iter, bool draw_o
     ll.n = (uint32_t)pl.long_ids.size();
     ll.total = pl.long_prefix.back();
     ll.tables = pl.d_tables;
-    WLDA_TRY(s, launch_wave_segments(a, phase, s->p.M, wl, s->st));
-    WLDA_TRY(s, launch_block_segments(a, phase, s->p.M, bl, s->st));
-    WLDA_TRY(s, launch_long_segments(a, phase, s->p.M, ll, s->st));
+    ll.chunk_seg = pl.d_chunk_seg;
+    ll.chunk_start = pl.d_chunk_start;
+    ll.n_chunks = (uint32_t)pl.chunk_seg.size();
+    ll.chunk_cut = pl.d_chunk_cut;
+    ll.zc = pl.d_zc;
+    const int base = phase == PH_WORD ? S_WORD_WAVE : S_DOC_WAVE;
+    const bool prof = s->prof && !draw_only;
+    if (prof) {
+        WLDA_TRY(s, timed(s, base + 0, [&] { return launch_wave_segments(a, phase, s->p.M, wl, s->st); }));
+        WLDA_TRY(s, timed(s, base + 1, [&] { return launch_block_segments(a, phase, s->p.M, bl, s->st); }));
+        if (ll.n) {
+            hipEvent_t ev[4];
+            for (int i = 0; i < 4; ++i) WLDA_TRY(s, take_event(s, &ev[i]));
+            WLDA_TRY(s, launch_long_segments(a, phase, s->p.M, ll, s->st, ev));
+            for (int i = 0; i < 3; ++i) s->ev_pairs[base + 2 + i].push_back({ev[i], ev[i + 1]});
+        }
+    } else {
+        WLDA_TRY(s, launch_wave_segments(a, phase, s->p.M, wl, s->st));
+        WLDA_TRY(s, launch_block_segments(a, phase, s->p.M, bl, s->st));
+        WLDA_TRY(s, launch_long_segments(a, phase, s->p.M, ll, s->st));
+    }
     s->cur = 1 - s->cur;
     return WLDA_OK;
 }
@@ -296,6 +425,14 @@ wlda_status wlda_create(const wlda_params *p, const uint32_t *word_ids, const ui
     lengths(*p, word_ids, doc_ids, T, lw, ld);
     build_plan(lw, block_max_tokens(p->M), s->word);
     build_plan(ld, block_max_tokens(p->M), s->doc);
+    s->slot_tokens[S_WORD_WAVE] = list_tokens(s->word.wave_ids, lw);
+    s->slot_tokens[S_WORD_BLOCK] = list_tokens(s->word.block_ids, lw);
+    s->slot_tokens[S_WORD_LONG_HIST] = s->slot_tokens[S_WORD_LONG_MH] =
+        s->slot_tokens[S_WORD_LONG_DRAW] = s->word.long_prefix.back();
+    s->slot_tokens[S_DOC_WAVE] = list_tokens(s->doc.wave_ids, ld);
+    s->slot_tokens[S_DOC_BLOCK] = list_tokens(s->doc.block_ids, ld);
+    s->slot_tokens[S_DOC_LONG_HIST] = s->slot_tokens[S_DOC_LONG_MH] =
+        s->slot_tokens[S_DOC_LONG_DRAW] = s->doc.long_prefix.back();
     const Sizes sz = compute_sizes(*p, T, s->word, s->doc);
     if (workspace_bytes < sz.total) {
         delete s;
@@ -543,9 +680,46 @@ wlda_status wlda_set_assignments(wlda_sampler s, const int32_t *z, const int32_t
     return WLDA_OK;
 }
 
+wlda_status wlda_profile(wlda_sampler s, int enable) {
+    if (!s) return WLDA_E_INVALID;
+    if (s->broken) return WLDA_E_HIP;
+    if (enable) {
+        WLDA_TRY(s, hipStreamSynchronize(s->st));
+        for (auto &v : s->ev_pairs) v.clear();
+        s->ev_used = 0;
+    }
+    s->prof = enable != 0;
+    return WLDA_OK;
+}
+
+wlda_status wlda_profile_read(wlda_sampler s, wlda_kernel_stat *out, uint32_t max_entries,
+                              uint32_t *n_entries) {
+    if (!s || !n_entries || (!out && max_entries)) return WLDA_E_INVALID;
+    if (s->broken) return WLDA_E_HIP;
+    WLDA_TRY(s, hipStreamSynchronize(s->st));
+    uint32_t n = 0;
+    for (int k = 0; k < KSLOTS; ++k) {
+        if (n >= max_entries) break;
+        double tot = 0;
+        for (auto &pr : s->ev_pairs[k]) {
+            float ms = 0;
+            WLDA_TRY(s, hipEventElapsedTime(&ms, pr.first, pr.second));
+            tot += ms;
+        }
+        out[n].name = SLOT_NAMES[k];
+        out[n].launches = s->ev_pairs[k].size();
+        out[n].tokens_per_launch = s->slot_tokens[k];
+        out[n].total_ms = tot;
+        ++n;
+    }
+    *n_entries = n;
+    return WLDA_OK;
+}
+
 wlda_status wlda_destroy(wlda_sampler s) {
     if (!s) return WLDA_E_INVALID;
     if (!s->broken) (void)hipStreamSynchronize(s->st);
+    for (hipEvent_t e : s->ev_pool) (void)hipEventDestroy(e);
     delete s;
     return WLDA_OK;
 }

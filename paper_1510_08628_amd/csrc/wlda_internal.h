@@ -25,12 +25,20 @@ struct SegList {
     const uint32_t *xcd_cut = nullptr;   // 9 list offsets: XCD x owns [cut[x], cut[x+1])
 };
 
+// Segments longer than one workgroup's share ("long") are cut into chunks of
+// LONG_CHUNK tokens; every long segment is owned by one XCD (greedy balance by
+// tokens) and its chunks are listed contiguously in that XCD's share.
 struct LongList {
     const uint32_t *ids = nullptr;     // long segment ids, ascending
-    const uint32_t *prefix = nullptr;  // n+1 virtual token offsets
+    const uint32_t *prefix = nullptr;  // n+1 offsets of each segment in the compact z array
     uint32_t n = 0;
     uint32_t total = 0;                // prefix[n]
+    const uint32_t *chunk_seg = nullptr;    // per chunk: index j into ids
+    const uint32_t *chunk_start = nullptr;  // per chunk: first token within the segment
+    uint32_t n_chunks = 0;
+    const uint32_t *chunk_cut = nullptr;    // 9 chunk-list offsets, one share per XCD
     uint32_t *tables = nullptr;        // n x K counts (global)
+    void *zc = nullptr;                // total compact topics (u16 if K <= 65535, else u32)
 };
 
 struct PhaseArgs {
@@ -57,7 +65,7 @@ struct Tuning {
     static constexpr uint32_t BLOCK_MAX = 256 * TPT_BLOCK;
     static constexpr uint32_t BLOCK_CAP = 2 * BLOCK_MAX;
     static constexpr uint32_t CK_LDS_MAX = 4096;             // block c_k histogram in LDS
-    static constexpr uint32_t LONG_CHUNK = 32768;            // tokens per histogram block
+    static constexpr uint32_t LONG_CHUNK = 4096;             // tokens per long-path chunk
 };
 
 inline uint32_t block_max_tokens(uint32_t M) {
@@ -72,8 +80,10 @@ hipError_t launch_wave_segments(const PhaseArgs &a, uint32_t phase, uint32_t M,
                                 const SegList &l, hipStream_t st);
 hipError_t launch_block_segments(const PhaseArgs &a, uint32_t phase, uint32_t M,
                                  const SegList &l, hipStream_t st);
+// Records ev[0..3] (if non-null) before the histogram, MH and draw kernels and
+// after the draw kernel, so that the host can time each of them.
 hipError_t launch_long_segments(const PhaseArgs &a, uint32_t phase, uint32_t M,
-                                const LongList &l, hipStream_t st);
+                                const LongList &l, hipStream_t st, hipEvent_t *ev = nullptr);
 hipError_t launch_unpack(const uint64_t *recs, uint32_t T, uint32_t M,
                          int32_t *z_out, int32_t *props_out, hipStream_t st);
 hipError_t launch_pack(uint64_t *recs, uint32_t T, uint32_t M, const int32_t *z_in,

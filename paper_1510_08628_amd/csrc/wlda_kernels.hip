@@ -317,41 +317,37 @@ __global__ __launch_bounds__(256) void seg_kernel(PhaseArgs a, SegList l, uint32
 }
 
 // --------------------------------------------------------------------------
-// Long segments (intra-word parallelism, Section 5.4): the tokens of all long
-// segments form one virtual index space [0, total); prefix[j] is where long
-// segment j starts in it.
+// Long segments (intra-word parallelism, Section 5.4).  Three passes over the
+// chunks of all long segments:
+//   hist - c_w (or c_d) of each long segment from the phase-start Z, summed
+//          into a global table per segment;
+//   mh   - the table staged in LDS, M MH steps per token, z written back into
+//          the record and into a compact per-segment z array;
+//   draw - proposals by random positioning over the compact array (the
+//          segment's updated assignments), records written, c_k accumulated.
+// Each XCD owns whole segments, so a segment's compact array is read from
+// that XCD's L2.
 // --------------------------------------------------------------------------
-__device__ __forceinline__ uint32_t find_long(const uint32_t *prefix, uint32_t n, uint32_t v) {
-    uint32_t lo = 0, hi = n;   // largest j with prefix[j] <= v
-    while (hi - lo > 1) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if (prefix[mid] <= v)
-            lo = mid;
-        else
-            hi = mid;
-    }
-    return lo;
-}
+#define WLDA_FOR_CHUNKS(l)                                                        \
+    const uint32_t xcd_ = blockIdx.x & 7, nbx_ = gridDim.x >> 3;                 \
+    for (uint32_t ci = (l).chunk_cut[xcd_] + (blockIdx.x >> 3); ci < (l).chunk_cut[xcd_ + 1]; \
+         ci += nbx_)
 
 template <int PHASE, int NW>
 __global__ __launch_bounds__(256) void long_hist_kernel(PhaseArgs a, LongList l, uint32_t lds_hist) {
     extern __shared__ uint32_t hist[];
     const uint32_t K = a.K;
-    uint32_t v0 = blockIdx.x * Tuning::LONG_CHUNK;
-    const uint32_t v1 = min(l.total, v0 + Tuning::LONG_CHUNK);
-    if (v0 >= v1) return;
-    uint32_t j = find_long(l.prefix, l.n, v0);
-    while (v0 < v1) {
-        const uint32_t pend = min(v1, l.prefix[j + 1]);
+    WLDA_FOR_CHUNKS(l) {
+        const uint32_t j = l.chunk_seg[ci], n0 = l.chunk_start[ci];
         const uint32_t s_id = l.ids[j];
-        const uint32_t beg = a.segptr[s_id];
+        const uint32_t beg = a.segptr[s_id], L = a.segptr[s_id + 1] - beg;
+        const uint32_t n1 = min(L, n0 + Tuning::LONG_CHUNK);
         uint32_t *gt = l.tables + (size_t)j * K;
         if (lds_hist) {
             for (uint32_t k = threadIdx.x; k < K; k += 256) hist[k] = 0;
             __syncthreads();
         }
-        for (uint32_t v = v0 + threadIdx.x; v < pend; v += 256) {
-            const uint32_t n = v - l.prefix[j];
+        for (uint32_t n = n0 + threadIdx.x; n < n1; n += 256) {
             const uint32_t pos = PHASE == PH_DOC ? a.rowpos[beg + n] : beg + n;
             const uint32_t z = fld(ld_rec<NW>(a.recs, pos), 0);
             if (lds_hist)
@@ -367,78 +363,92 @@ __global__ __launch_bounds__(256) void long_hist_kernel(PhaseArgs a, LongList l,
             }
             __syncthreads();
         }
-        v0 = pend;
-        ++j;
     }
 }
 
-template <int PHASE, int M, int NW>
-__global__ __launch_bounds__(256) void long_mh_kernel(PhaseArgs a, LongList l) {
+template <int PHASE, int M, int NW, typename ZT>
+__global__ __launch_bounds__(256) void long_mh_kernel(PhaseArgs a, LongList l, uint32_t lds_tab) {
+    extern __shared__ uint32_t tab[];
     const uint32_t K = a.K;
     const uint32_t ph = (uint32_t)PHASE << 16;
+    ZT *zc = reinterpret_cast<ZT *>(l.zc);
     unsigned long long acc = 0;
-    for (uint32_t v = blockIdx.x * 256 + threadIdx.x; v < l.total; v += gridDim.x * 256) {
-        const uint32_t j = find_long(l.prefix, l.n, v);
+    WLDA_FOR_CHUNKS(l) {
+        const uint32_t j = l.chunk_seg[ci], n0 = l.chunk_start[ci];
         const uint32_t s_id = l.ids[j];
-        const uint32_t beg = a.segptr[s_id];
-        const uint32_t n = v - l.prefix[j];
-        const uint32_t pos = PHASE == PH_DOC ? a.rowpos[beg + n] : beg + n;
+        const uint32_t beg = a.segptr[s_id], L = a.segptr[s_id + 1] - beg;
+        const uint32_t n1 = min(L, n0 + Tuning::LONG_CHUNK);
+        const uint32_t zbase = l.prefix[j];
         const uint32_t *gt = l.tables + (size_t)j * K;
-        Rec<NW> rec = ld_rec<NW>(a.recs, pos);
-        uint32_t s = fld(rec, 0);
-#pragma unroll
-        for (int i = 1; i <= M; ++i) {
-            const uint4 R = philox(pos, a.iter, ph | i, 0, a.seed_lo, a.seed_hi);
-            const uint32_t c = fld(rec, i);
-            if (mh_accept(unif24(R.x), gt[c], gt[s], a.prior, a.ck[s], a.ck[c], a.beta_bar)) {
-                s = c;
-                ++acc;
+        if (a.draw_only) {     // initial draw: only publish z for random positioning
+            for (uint32_t n = n0 + threadIdx.x; n < n1; n += 256) {
+                const uint32_t pos = PHASE == PH_DOC ? a.rowpos[beg + n] : beg + n;
+                zc[zbase + n] = (ZT)fld(ld_rec<NW>(a.recs, pos), 0);
             }
+            continue;
         }
-        set_fld(rec, 0, s);
-        st_rec<NW>(a.recs, pos, rec);
+        if (lds_tab) {
+            for (uint32_t k = threadIdx.x; k < K; k += 256) tab[k] = gt[k];
+            __syncthreads();
+        }
+        const uint32_t *ct = lds_tab ? tab : gt;
+        for (uint32_t n = n0 + threadIdx.x; n < n1; n += 256) {
+            const uint32_t pos = PHASE == PH_DOC ? a.rowpos[beg + n] : beg + n;
+            Rec<NW> rec = ld_rec<NW>(a.recs, pos);
+            uint32_t s = fld(rec, 0);
+#pragma unroll
+            for (int i = 1; i <= M; ++i) {
+                const uint4 R = philox(pos, a.iter, ph | i, 0, a.seed_lo, a.seed_hi);
+                const uint32_t c = fld(rec, i);
+                if (mh_accept(unif24(R.x), ct[c], ct[s], a.prior, a.ck[s], a.ck[c], a.beta_bar)) {
+                    s = c;
+                    ++acc;
+                }
+            }
+            set_fld(rec, 0, s);
+            st_rec<NW>(a.recs, pos, rec);
+            zc[zbase + n] = (ZT)s;
+        }
+        if (lds_tab) __syncthreads();
     }
     add_accepted(a.accepted, acc);
 }
 
-template <int PHASE, int M, int NW>
+template <int PHASE, int M, int NW, typename ZT>
 __global__ __launch_bounds__(256) void long_draw_kernel(PhaseArgs a, LongList l, uint32_t ck_lds_u,
                                                         uint32_t zero_tables) {
     extern __shared__ uint32_t ckh[];
     const bool ck_lds = ck_lds_u != 0;
     const uint32_t K = a.K;
     const uint32_t ph = (uint32_t)PHASE << 16;
+    const ZT *zc = reinterpret_cast<const ZT *>(l.zc);
     if (ck_lds) {
         for (uint32_t k = threadIdx.x; k < K; k += 256) ckh[k] = 0;
         __syncthreads();
     }
-    for (uint32_t v = blockIdx.x * 256 + threadIdx.x; v < l.total; v += gridDim.x * 256) {
-        const uint32_t j = find_long(l.prefix, l.n, v);
+    WLDA_FOR_CHUNKS(l) {
+        const uint32_t j = l.chunk_seg[ci], n0 = l.chunk_start[ci];
         const uint32_t s_id = l.ids[j];
-        const uint32_t beg = a.segptr[s_id];
-        const uint32_t L = a.segptr[s_id + 1] - beg;
-        const uint32_t n = v - l.prefix[j];
-        const uint32_t pos = PHASE == PH_DOC ? a.rowpos[beg + n] : beg + n;
-        Rec<NW> rec = ld_rec<NW>(a.recs, pos);
-        const uint32_t z = fld(rec, 0);
+        const uint32_t beg = a.segptr[s_id], L = a.segptr[s_id + 1] - beg;
+        const uint32_t n1 = min(L, n0 + Tuning::LONG_CHUNK);
+        const ZT *zs = zc + l.prefix[j];
+        for (uint32_t n = n0 + threadIdx.x; n < n1; n += 256) {
+            const uint32_t pos = PHASE == PH_DOC ? a.rowpos[beg + n] : beg + n;
+            Rec<NW> rec = ld_rec<NW>(a.recs, pos);
+            const uint32_t z = fld(rec, 0);
 #pragma unroll
-        for (int i = 1; i <= M; ++i) {
-            const uint4 R = philox(pos, a.iter, ph | i, 0, a.seed_lo, a.seed_hi);
-            uint32_t p;
-            if (take_count_part(unif24(R.y), L, a.mass)) {
-                const uint32_t jn = dice(R.z, L);
-                const uint32_t jpos = PHASE == PH_DOC ? a.rowpos[beg + jn] : beg + jn;
-                p = fld(ld_rec<NW>(a.recs, jpos), 0);
-            } else {
-                p = dice(R.z, K);
+            for (int i = 1; i <= M; ++i) {
+                const uint4 R = philox(pos, a.iter, ph | i, 0, a.seed_lo, a.seed_hi);
+                const uint32_t p =
+                    take_count_part(unif24(R.y), L, a.mass) ? (uint32_t)zs[dice(R.z, L)] : dice(R.z, K);
+                set_fld(rec, i, p);
             }
-            set_fld(rec, i, p);
+            st_rec<NW>(a.recs, pos, rec);
+            if (ck_lds)
+                atomicAdd(&ckh[z], 1u);
+            else
+                atomicAdd(&a.ck_next[z], 1u);
         }
-        st_rec<NW>(a.recs, pos, rec);
-        if (ck_lds)
-            atomicAdd(&ckh[z], 1u);
-        else
-            atomicAdd(&a.ck_next[z], 1u);
     }
     if (zero_tables) {
         const size_t nt = (size_t)l.n * K;
@@ -658,39 +668,58 @@ hipError_t launch_block_segments(const PhaseArgs &a, uint32_t phase, uint32_t M,
     WLDA_DISPATCH_M(block_dispatch, PH_DOC, a, l, st)
 }
 
-template <int PHASE, int M>
-static hipError_t long_dispatch(const PhaseArgs &a, const LongList &l, hipStream_t st) {
+template <int PHASE, int M, typename ZT>
+static hipError_t long_dispatch_z(const PhaseArgs &a, const LongList &l, hipStream_t st,
+                                  hipEvent_t *ev) {
     constexpr int NW = (M + 3) / 3;
-    if (l.n == 0) return hipSuccess;
-    const bool lds_hist = a.K <= 16384;
+    const bool lds_tab = a.K <= 16384;
     const bool ck_lds = a.K <= Tuning::CK_LDS_MAX;
+    uint32_t blocks = l.n_chunks < 2048 ? l.n_chunks : 2048;
+    blocks = (blocks + 7) / 8 * 8;
     hipError_t e;
+    if (ev && (e = hipEventRecord(ev[0], st)) != hipSuccess) return e;
     if (!a.draw_only) {
-        const uint32_t hb = (l.total + Tuning::LONG_CHUNK - 1) / Tuning::LONG_CHUNK;
-        const size_t lds = lds_hist ? 4ull * a.K : 0;
+        const size_t lds = lds_tab ? 4ull * a.K : 0;
         e = launch_dyn(long_hist_kernel<PHASE, NW>, dim3(1), lds, st);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL((long_hist_kernel<PHASE, NW>), dim3(hb), dim3(256), lds, st, a, l,
-                           (uint32_t)lds_hist);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-        hipLaunchKernelGGL((long_mh_kernel<PHASE, M, NW>), dim3(grid_for(l.total, 4096)), dim3(256), 0,
-                           st, a, l);
+        hipLaunchKernelGGL((long_hist_kernel<PHASE, NW>), dim3(blocks), dim3(256), lds, st, a, l,
+                           (uint32_t)lds_tab);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
+    if (ev && (e = hipEventRecord(ev[1], st)) != hipSuccess) return e;
+    {
+        const size_t lds = lds_tab && !a.draw_only ? 4ull * a.K : 0;
+        e = launch_dyn(long_mh_kernel<PHASE, M, NW, ZT>, dim3(1), lds, st);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((long_mh_kernel<PHASE, M, NW, ZT>), dim3(blocks), dim3(256), lds, st, a, l,
+                           (uint32_t)(lds_tab && !a.draw_only));
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    if (ev && (e = hipEventRecord(ev[2], st)) != hipSuccess) return e;
     const size_t lds = ck_lds ? 4ull * a.K : 0;
-    e = launch_dyn(long_draw_kernel<PHASE, M, NW>, dim3(1), lds, st);
+    e = launch_dyn(long_draw_kernel<PHASE, M, NW, ZT>, dim3(1), lds, st);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((long_draw_kernel<PHASE, M, NW>), dim3(grid_for(l.total, 2048)), dim3(256), lds,
-                       st, a, l, (uint32_t)ck_lds, (uint32_t)(a.draw_only ? 0 : 1));
-    return hipGetLastError();
+    hipLaunchKernelGGL((long_draw_kernel<PHASE, M, NW, ZT>), dim3(blocks), dim3(256), lds, st, a, l,
+                       (uint32_t)ck_lds, (uint32_t)(a.draw_only ? 0 : 1));
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (ev) return hipEventRecord(ev[3], st);
+    return hipSuccess;
+}
+
+template <int PHASE, int M>
+static hipError_t long_dispatch(const PhaseArgs &a, const LongList &l, hipStream_t st,
+                                hipEvent_t *ev) {
+    if (l.n == 0) return hipSuccess;
+    if (a.K <= 65535) return long_dispatch_z<PHASE, M, uint16_t>(a, l, st, ev);
+    return long_dispatch_z<PHASE, M, uint32_t>(a, l, st, ev);
 }
 
 hipError_t launch_long_segments(const PhaseArgs &a, uint32_t phase, uint32_t M, const LongList &l,
-                                hipStream_t st) {
+                                hipStream_t st, hipEvent_t *ev) {
     if (phase == PH_WORD) {
-        WLDA_DISPATCH_M(long_dispatch, PH_WORD, a, l, st)
+        WLDA_DISPATCH_M(long_dispatch, PH_WORD, a, l, st, ev)
     }
-    WLDA_DISPATCH_M(long_dispatch, PH_DOC, a, l, st)
+    WLDA_DISPATCH_M(long_dispatch, PH_DOC, a, l, st, ev)
 }
 
 hipError_t launch_unpack(const uint64_t *recs, uint32_t T, uint32_t M, int32_t *z, int32_t *props,
