@@ -154,6 +154,48 @@ wlda_status wlda_profile(wlda_sampler s, int enable);
 wlda_status wlda_profile_read(wlda_sampler s, wlda_kernel_stat *out, uint32_t max_entries,
                               uint32_t *n_entries);
 
+/* ------------------------------------------------------------------------ */
+/* Fold-in of new documents against a frozen model                          */
+/* ------------------------------------------------------------------------ */
+/* A model freezes a trained sampler's assignments: the word-topic counts
+ * C_w, the topic totals c_k and each word's trained column (for random
+ * positioning), all held fixed while new documents run the MCEM E-step of
+ * Eq. (5) (the same delayed-update MH chain as training, Section 4.2-4.4, with
+ * only c_d changing).  C_w is stored dense (V x K uint32): V*K <= 2^33.
+ * Model arrays: the training corpus (host, any order) and its assignments z
+ * in the same order (e.g. from wlda_copy_assignments). */
+typedef struct wlda_model_s *wlda_model;
+
+wlda_status wlda_model_workspace_bytes(const wlda_params *p, uint64_t n_tokens, uint64_t *bytes);
+wlda_status wlda_model_create(const wlda_params *p, const uint32_t *word_ids,
+                              const uint32_t *doc_ids, const int32_t *z, uint64_t n_tokens,
+                              void *dev_workspace, uint64_t workspace_bytes, void *hip_stream,
+                              wlda_model *out);
+wlda_status wlda_model_destroy(wlda_model m);
+
+/* Fold-in of a batch of documents (host arrays): document d is
+ * words[docptr[d] .. docptr[d+1]) (at most 8192 tokens), with request id
+ * req_ids[d] keying its random stream (counter: token-in-document, sweep,
+ * phase << 16 | step, request id).  Runs the initialisation and `sweeps`
+ * sweeps.  Plain mode (learned_weights == NULL): z starts at Dice(K).
+ * Learned mode: learned_weights (n_docs x K, each in [1, 2^24), row sums
+ * < 2^32) define an independence proposal q(k) = w_k / sum(w); z starts at a
+ * draw from q and every sweep adds `learned_steps` MH steps with q after the
+ * word-proposal steps, accepted with the exact ratio
+ * (C_dt+a)(C_wt+b)(C_s+bbar) w_s / ((C_ds+a)(C_ws+b)(C_t+bbar) w_t).
+ * If hoptr != NULL, heldout_out[d] receives the held-out log likelihood of
+ * ho_words[hoptr[d] .. hoptr[d+1]) given the document's final assignments
+ * (theta, phi of Eq. (4) with alpha' = alpha + 1, beta' = beta + 1).
+ * z_out gets the final assignments (docptr order).  Synchronises. */
+wlda_status wlda_foldin_batch_bytes(wlda_model m, uint32_t n_docs, uint64_t n_tokens, int learned,
+                                    uint64_t n_heldout, uint64_t *bytes);
+wlda_status wlda_foldin_batch(wlda_model m, uint32_t n_docs, const uint64_t *docptr,
+                              const uint32_t *words, const uint32_t *req_ids,
+                              const uint32_t *learned_weights, uint32_t learned_steps,
+                              uint32_t sweeps, const uint64_t *hoptr, const uint32_t *ho_words,
+                              void *dev_workspace, uint64_t workspace_bytes, int32_t *z_out,
+                              double *heldout_out);
+
 /* Releases host-side state; the workspace is the caller's to free. */
 wlda_status wlda_destroy(wlda_sampler s);
 

@@ -87,6 +87,12 @@ def lib():
         L.oracle_philox4x32_10.argtypes = [vp, vp, vp]
         L.oracle_phase_subset.argtypes = [vp, C.c_int, u32, vp, u64]
         L.oracle_phase_subset.restype = C.c_int
+        L.oracle_foldin.argtypes = [u32, u32, u32, C.c_double, C.c_double, u64, vp, vp, vp,
+                                    u32, vp, vp, vp, u32, u32, vp, u32, vp, vp]
+        L.oracle_foldin.restype = C.c_int
+        L.oracle_heldout_ll.argtypes = [u32, u32, C.c_double, C.c_double, vp, vp, vp, u32, vp, vp,
+                                        vp, vp]
+        L.oracle_heldout_ll.restype = C.c_double
         _lib = L
     return _lib
 
@@ -108,6 +114,48 @@ def log_joint(word_ids, doc_ids, z, V, D, K, alpha, beta) -> float:
     d = np.ascontiguousarray(doc_ids, dtype=np.uint32)
     zz = np.ascontiguousarray(z, dtype=np.int32)
     return lib().oracle_log_joint(len(w), V, D, K, alpha, beta, _ptr(w), _ptr(d), _ptr(zz))
+
+
+class FrozenModel:
+    """A trained model as the oracle's fold-in sees it: the canonical column
+    layout of the training corpus, its assignments and c_k."""
+
+    def __init__(self, word_ids, doc_ids, z, V, D, K, M, alpha, beta, seed=1):
+        o = Oracle(word_ids, doc_ids, V, D, K, M, alpha, beta, seed)
+        colptr, _, _, inv = o.layout()
+        zc = np.empty(len(z), np.int32)
+        zc[inv] = np.asarray(z, np.int32)
+        self.colptr = colptr
+        self.z_csc = zc
+        self.ck = np.bincount(zc, minlength=K).astype(np.int64)
+        self.V, self.K, self.M, self.alpha, self.beta, self.seed = V, K, M, alpha, beta, seed
+
+    def foldin(self, docptr, words, req_ids, sweeps, weights=None, learned_steps=0,
+               first_sweep=0, z=None, pd=None):
+        docptr = np.ascontiguousarray(docptr, np.uint64)
+        words = np.ascontiguousarray(words, np.uint32)
+        req = np.ascontiguousarray(req_ids, np.uint32)
+        T = int(docptr[-1])
+        z = np.zeros(T, np.int32) if z is None else np.ascontiguousarray(z, np.int32).copy()
+        pd = np.zeros(self.M * T, np.int32) if pd is None else np.ascontiguousarray(pd, np.int32).copy()
+        w = None if weights is None else np.ascontiguousarray(weights, np.uint32)
+        rc = lib().oracle_foldin(self.V, self.K, self.M, self.alpha, self.beta, self.seed,
+                                 _ptr(self.colptr), _ptr(self.z_csc), _ptr(self.ck),
+                                 len(req), _ptr(docptr), _ptr(words), _ptr(req), first_sweep,
+                                 sweeps, None if w is None else _ptr(w), learned_steps,
+                                 _ptr(z), _ptr(pd))
+        if rc != 0:
+            raise RuntimeError("oracle_foldin failed")
+        return z, pd
+
+    def heldout_ll(self, docptr, z, hoptr, ho_words) -> float:
+        docptr = np.ascontiguousarray(docptr, np.uint64)
+        hoptr = np.ascontiguousarray(hoptr, np.uint64)
+        z = np.ascontiguousarray(z, np.int32)
+        how = np.ascontiguousarray(ho_words, np.uint32)
+        return lib().oracle_heldout_ll(self.V, self.K, self.alpha, self.beta, _ptr(self.colptr),
+                                       _ptr(self.z_csc), _ptr(self.ck), len(docptr) - 1,
+                                       _ptr(docptr), _ptr(z), _ptr(hoptr), _ptr(how))
 
 
 class Oracle:

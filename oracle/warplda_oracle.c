@@ -651,3 +651,194 @@ int oracle_frozen_chain(const oracle_t *o, uint32_t t, uint32_t rounds,
     free(cw); free(cd);
     return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Fold-in of new documents (MCEM E-step of Eq. (5) with the word-topic     */
+/* counts C_w and the topic totals c_k held at a trained model's values).   */
+/* Each new document runs its own delayed-update chain, sweep by sweep:     */
+/*   word step - its pending doc proposals are judged with pi_doc of Eq. (7)*/
+/*               using the frozen C_w and c_k; M word proposals are drawn   */
+/*               by random positioning over the trained column of the word  */
+/*               (mixing weight L_w / (L_w + K beta));                      */
+/*   doc step  - c_d is rebuilt from the document, the word proposals are   */
+/*               judged with pi_word, then (learned mode) LS further steps  */
+/*               with an independence proposal q given as integer weights,  */
+/*               and M doc proposals are drawn from the updated document.   */
+/* Randomness: counter (token-in-doc, sweep, phase << 16 | step, request).  */
+/* Learned weights: q(k) = w_k / sum(w); a draw takes u = Dice(sum(w)) and  */
+/* the first k whose running sum exceeds u.  The learned MH ratio is        */
+/* (C_dt+a)(C_wt+b)(C_s+bbar) w_s / ((C_ds+a)(C_ws+b)(C_t+bbar) w_t),       */
+/* multiplied left to right in binary32.                                    */
+/* ------------------------------------------------------------------------ */
+enum { PH_F_INIT = 5, PH_F_WORD = 6, PH_F_DOC = 8, PH_F_LEARN = 9 };
+
+typedef struct {
+    uint32_t V, K, M;
+    double alpha, beta;
+    uint64_t seed;
+    const uint64_t *colptr;   /* V+1: trained columns */
+    const int32_t *z_csc;     /* trained assignments, canonical column order */
+    const int64_t *ck;        /* K: topic totals of the trained Z */
+} oracle_model;
+
+static uint32_t learned_draw(const uint32_t *w, uint32_t K, uint64_t total, uint32_t r)
+{
+    uint64_t u = ((uint64_t)r * total) >> 32, run = 0;
+    for (uint32_t k = 0; k < K; ++k) {
+        run += w[k];
+        if (run > u) return k;
+    }
+    return K - 1;
+}
+
+/* One document.  z (L) in/out state, pd (M x L) pending doc proposals.
+ * first_sweep == 0 initialises (z from Dice(K) or from q, then the first doc
+ * proposals) and continues with sweeps 1..last_sweep. */
+static int fold_doc(const oracle_model *m, uint32_t req, const uint32_t *words, uint32_t L,
+                    uint32_t first_sweep, uint32_t last_sweep, const uint32_t *qw,
+                    uint32_t learned_steps, int32_t *z, int32_t *pd)
+{
+    const uint32_t K = m->K, M = m->M;
+    const float a = (float)m->alpha, b = (float)m->beta;
+    const float alpha_bar = (float)K * a, beta_k = (float)K * b, beta_bar = (float)m->V * b;
+    uint64_t qtot = 0;
+    if (qw) for (uint32_t k = 0; k < K; ++k) qtot += qw[k];
+    int64_t *cw_c = NULL;
+    int64_t *cd = calloc(K, sizeof(int64_t));
+    int32_t *pw = malloc((size_t)M * L * sizeof(int32_t) + 1);
+    if (!cd || !pw) { free(cd); free(pw); return -1; }
+    uint32_t r[4];
+    if (first_sweep == 0) {
+        for (uint32_t n = 0; n < L; ++n) {
+            rng_call(m->seed, n, 0, PH_F_INIT, 0, req, r);
+            z[n] = qw ? (int32_t)learned_draw(qw, K, qtot, r[2]) : (int32_t)dice(r[2], K);
+        }
+        for (uint32_t n = 0; n < L; ++n)
+            for (uint32_t i = 1; i <= M; ++i) {
+                rng_call(m->seed, n, 0, PH_F_DOC, i, req, r);
+                pd[(size_t)(i - 1) * L + n] = take_count_part(unif24(r[1]), L, alpha_bar)
+                                                  ? z[dice(r[2], L)] : (int32_t)dice(r[2], K);
+            }
+        first_sweep = 1;
+    }
+    (void)cw_c;
+    for (uint32_t s = first_sweep; s <= last_sweep; ++s) {
+        /* word step: frozen C_w, c_k */
+        for (uint32_t n = 0; n < L; ++n) {
+            uint32_t w = words[n];
+            uint64_t cb = m->colptr[w], Lw = m->colptr[w + 1] - cb;
+            int32_t x = z[n];
+            for (uint32_t i = 1; i <= M; ++i) {
+                rng_call(m->seed, n, s, PH_F_WORD, i, req, r);
+                int32_t c = pd[(size_t)(i - 1) * L + n];
+                int64_t cwc = 0, cwx = 0;
+                for (uint64_t j = 0; j < Lw; ++j) {
+                    cwc += m->z_csc[cb + j] == c;
+                    cwx += m->z_csc[cb + j] == x;
+                }
+                if (mh_accept(unif24(r[0]), cwc, cwx, b, m->ck[x], m->ck[c], beta_bar)) x = c;
+                pw[(size_t)(i - 1) * L + n] =
+                    Lw && take_count_part(unif24(r[1]), Lw, beta_k)
+                        ? m->z_csc[cb + dice(r[2], (uint32_t)Lw)] : (int32_t)dice(r[2], K);
+            }
+            z[n] = x;
+        }
+        /* doc step: c_d rebuilt, word proposals, learned steps, doc proposals */
+        memset(cd, 0, K * sizeof(int64_t));
+        for (uint32_t n = 0; n < L; ++n) cd[z[n]]++;
+        int32_t *znew = malloc((size_t)L * sizeof(int32_t) + 1);
+        if (!znew) { free(cd); free(pw); return -1; }
+        for (uint32_t n = 0; n < L; ++n) {
+            int32_t x = z[n];
+            for (uint32_t i = 1; i <= M; ++i) {
+                rng_call(m->seed, n, s, PH_F_DOC, i, req, r);
+                int32_t c = pw[(size_t)(i - 1) * L + n];
+                if (mh_accept(unif24(r[0]), cd[c], cd[x], a, m->ck[x], m->ck[c], beta_bar)) x = c;
+            }
+            if (qw) {
+                uint32_t w = words[n];
+                uint64_t cb = m->colptr[w], Lw = m->colptr[w + 1] - cb;
+                for (uint32_t j = 1; j <= learned_steps; ++j) {
+                    rng_call(m->seed, n, s, PH_F_LEARN, j, req, r);
+                    int32_t t = (int32_t)learned_draw(qw, K, qtot, r[2]);
+                    int64_t cwt = 0, cwx = 0;
+                    for (uint64_t q = 0; q < Lw; ++q) {
+                        cwt += m->z_csc[cb + q] == t;
+                        cwx += m->z_csc[cb + q] == x;
+                    }
+                    float num = ((float)cd[t] + a) * ((float)cwt + b) * ((float)m->ck[x] + beta_bar) *
+                                (float)qw[x];
+                    float den = ((float)cd[x] + a) * ((float)cwx + b) * ((float)m->ck[t] + beta_bar) *
+                                (float)qw[t];
+                    if (unif24(r[0]) * den < num) x = t;
+                }
+            }
+            znew[n] = x;
+        }
+        memcpy(z, znew, (size_t)L * sizeof(int32_t));
+        free(znew);
+        for (uint32_t n = 0; n < L; ++n)
+            for (uint32_t i = 1; i <= M; ++i) {
+                rng_call(m->seed, n, s, PH_F_DOC, i, req, r);
+                pd[(size_t)(i - 1) * L + n] = take_count_part(unif24(r[1]), L, alpha_bar)
+                                                  ? z[dice(r[2], L)] : (int32_t)dice(r[2], K);
+            }
+    }
+    free(cd);
+    free(pw);
+    return 0;
+}
+
+/* Fold-in of a batch.  docptr (n_docs+1) indexes words, z and pd (pd is
+ * M x total, proposal-major with stride `total`, sliced per document as
+ * M x L_d contiguous runs at M*docptr[d]).  qw: n_docs x K weights or NULL. */
+int oracle_foldin(uint32_t V, uint32_t K, uint32_t M, double alpha, double beta, uint64_t seed,
+                  const uint64_t *colptr, const int32_t *z_csc, const int64_t *ck,
+                  uint32_t n_docs, const uint64_t *docptr, const uint32_t *words,
+                  const uint32_t *req_ids, uint32_t first_sweep, uint32_t last_sweep,
+                  const uint32_t *qw, uint32_t learned_steps, int32_t *z, int32_t *pd)
+{
+    oracle_model m = { V, K, M, alpha, beta, seed, colptr, z_csc, ck };
+    for (uint32_t d = 0; d < n_docs; ++d) {
+        uint64_t beg = docptr[d];
+        uint32_t L = (uint32_t)(docptr[d + 1] - beg);
+        if (L == 0) continue;
+        int rc = fold_doc(&m, req_ids[d], words + beg, L, first_sweep, last_sweep,
+                          qw ? qw + (size_t)d * K : NULL, learned_steps, z + beg,
+                          pd + (size_t)M * beg);
+        if (rc) return rc;
+    }
+    return 0;
+}
+
+/* Held-out log likelihood by document completion: for each document, theta
+ * from its folded-in assignments (Eq. (4) with alpha' = alpha + 1), phi from
+ * the trained counts (beta' = beta + 1), and sum over its held-out tokens of
+ * log sum_k theta_dk phi_wk.  Returns the total (binary64). */
+double oracle_heldout_ll(uint32_t V, uint32_t K, double alpha, double beta,
+                         const uint64_t *colptr, const int32_t *z_csc, const int64_t *ck,
+                         uint32_t n_docs, const uint64_t *docptr, const int32_t *z,
+                         const uint64_t *hoptr, const uint32_t *ho_words)
+{
+    double *theta = malloc(K * sizeof(double));
+    int64_t *cw = malloc(K * sizeof(int64_t));
+    if (!theta || !cw) { free(theta); free(cw); return NAN; }
+    double total = 0;
+    for (uint32_t d = 0; d < n_docs; ++d) {
+        uint64_t beg = docptr[d], L = docptr[d + 1] - beg;
+        for (uint32_t k = 0; k < K; ++k) theta[k] = alpha;
+        for (uint64_t n = 0; n < L; ++n) theta[z[beg + n]] += 1.0;
+        for (uint32_t k = 0; k < K; ++k) theta[k] /= (double)L + K * alpha;
+        for (uint64_t h = hoptr[d]; h < hoptr[d + 1]; ++h) {
+            uint32_t w = ho_words[h];
+            memset(cw, 0, K * sizeof(int64_t));
+            for (uint64_t j = colptr[w]; j < colptr[w + 1]; ++j) cw[z_csc[j]]++;
+            double p = 0;
+            for (uint32_t k = 0; k < K; ++k)
+                p += theta[k] * ((double)cw[k] + beta) / ((double)ck[k] + V * beta);
+            total += log(p);
+        }
+    }
+    free(theta); free(cw);
+    return total;
+}

@@ -37,6 +37,8 @@ EXPORTS = [
     "wlda_copy_assignments_csc", "wlda_copy_topic_counts", "wlda_accepted", "wlda_iteration",
     "wlda_state_bytes", "wlda_save_state", "wlda_load_state", "wlda_set_assignments",
     "wlda_destroy", "wlda_strerror", "wlda_profile", "wlda_profile_read",
+    "wlda_model_workspace_bytes", "wlda_model_create", "wlda_model_destroy",
+    "wlda_foldin_batch_bytes", "wlda_foldin_batch",
 ]
 
 
@@ -73,6 +75,11 @@ def load_library(path: str = LIB_PATH):
         "wlda_set_assignments": [vp, vp, vp],
         "wlda_destroy": [vp],
         "wlda_profile": [vp, i32],
+        "wlda_model_workspace_bytes": [P, u64, C.POINTER(u64)],
+        "wlda_model_create": [P, vp, vp, vp, u64, vp, u64, vp, C.POINTER(vp)],
+        "wlda_model_destroy": [vp],
+        "wlda_foldin_batch_bytes": [vp, u32, u64, i32, u64, C.POINTER(u64)],
+        "wlda_foldin_batch": [vp, u32, vp, vp, vp, vp, u32, u32, vp, vp, vp, u64, vp, vp],
         "wlda_profile_read": [vp, C.POINTER(KernelStat), u32, C.POINTER(u32)],
     }
     for name, args in sig.items():
@@ -203,3 +210,70 @@ class Sampler:
         _check("wlda_set_assignments",
                load_library().wlda_set_assignments(self.h, _ptr(zz),
                                                    None if pp is None else _ptr(pp)))
+
+
+class Model:
+    """A frozen model on the GPU (wlda_model_create): trained corpus + z."""
+
+    def __init__(self, word_ids, doc_ids, z, V, D, K, M, alpha, beta, seed=1, device="cuda:0",
+                 stream=None):
+        import torch
+        L = load_library()
+        self.params = Params(V, D, K, M, float(alpha), float(beta), int(seed))
+        self.K, self.M, self.V = K, M, V
+        w = np.ascontiguousarray(word_ids, dtype=np.uint32)
+        d = np.ascontiguousarray(doc_ids, dtype=np.uint32)
+        zz = np.ascontiguousarray(z, dtype=np.int32)
+        n = C.c_uint64(0)
+        _check("wlda_model_workspace_bytes",
+               L.wlda_model_workspace_bytes(C.byref(self.params), len(w), C.byref(n)))
+        self.device = torch.device(device)
+        self.workspace = torch.empty(int(n.value), dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = C.c_void_p(0)
+        _check("wlda_model_create",
+               L.wlda_model_create(C.byref(self.params), _ptr(w), _ptr(d), _ptr(zz), len(w),
+                                   C.c_void_p(self.workspace.data_ptr()), int(n.value),
+                                   C.c_void_p(self.stream.cuda_stream), C.byref(h)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            load_library().wlda_model_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def foldin(self, docptr, words, req_ids, sweeps, weights=None, learned_steps=0,
+               hoptr=None, ho_words=None):
+        """Batch fold-in; returns (z, heldout_ll per doc or None)."""
+        import torch
+        L = load_library()
+        docptr = np.ascontiguousarray(docptr, np.uint64)
+        words = np.ascontiguousarray(words, np.uint32)
+        req = np.ascontiguousarray(req_ids, np.uint32)
+        nd = len(req)
+        T = int(docptr[-1])
+        w = None if weights is None else np.ascontiguousarray(weights, np.uint32)
+        hp = None if hoptr is None else np.ascontiguousarray(hoptr, np.uint64)
+        hw = None if ho_words is None else np.ascontiguousarray(ho_words, np.uint32)
+        n_ho = 0 if hp is None else int(hp[-1])
+        nb = C.c_uint64(0)
+        _check("wlda_foldin_batch_bytes",
+               L.wlda_foldin_batch_bytes(self.h, nd, T, int(w is not None), n_ho, C.byref(nb)))
+        ws = torch.empty(int(nb.value), dtype=torch.uint8, device=self.device)
+        z = np.empty(T, np.int32)
+        ho = np.empty(nd, np.float64) if hp is not None else None
+        _check("wlda_foldin_batch",
+               L.wlda_foldin_batch(self.h, nd, _ptr(docptr), _ptr(words), _ptr(req),
+                                   None if w is None else _ptr(w), learned_steps, sweeps,
+                                   None if hp is None else _ptr(hp),
+                                   None if hw is None else _ptr(hw),
+                                   C.c_void_p(ws.data_ptr()), int(nb.value), _ptr(z),
+                                   None if ho is None else _ptr(ho)))
+        del ws
+        return z, ho

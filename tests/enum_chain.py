@@ -127,3 +127,78 @@ def mcem_conditional(cd_row, cw_row, ck, alpha, beta, bbar):
     """q(z = k) of Eq. (5) with frozen counts (token included)."""
     q = (cd_row + alpha) * (cw_row + beta) / (ck + bbar)
     return q / q.sum()
+
+
+# --------------------------------------------------------------------------
+# Fold-in: one new document, C_w and c_k frozen at a trained model's values.
+# --------------------------------------------------------------------------
+def fold_sweep_matrix(words, K, M, alpha, beta, V, cwk, ck, learned=None, learned_steps=0):
+    """K^L x K^L matrix of one fold-in sweep (word step, then doc step with
+    optional learned independence steps); the pending doc proposals were drawn
+    from the document's current assignments."""
+    L = len(words)
+    states = list(itertools.product(range(K), repeat=L))
+    bbar = V * beta
+    cwk = np.asarray(cwk, dtype=np.float64)
+    ck = np.asarray(ck, dtype=np.float64)
+    index = {s: i for i, s in enumerate(states)}
+    # word step
+    Pw = np.zeros((len(states), len(states)))
+    for si, z in enumerate(states):
+        cd = np.bincount(z, minlength=K).astype(np.float64)
+        qd = (cd + alpha) / (L + K * alpha)
+        per = []
+        for t in range(L):
+            cw = cwk[words[t]]
+
+            def acc(s, c, cw=cw):
+                return min(1.0, (cw[c] + beta) * (ck[s] + bbar) / ((cw[s] + beta) * (ck[c] + bbar)))
+            per.append(_mh_outcome(z[t], qd, acc, K, M))
+        for sj, z2 in enumerate(states):
+            pr = 1.0
+            for t in range(L):
+                pr *= per[t][z2[t]]
+            Pw[si, sj] = pr
+    # doc step
+    Pd = np.zeros((len(states), len(states)))
+    for si, z in enumerate(states):
+        cd = np.bincount(z, minlength=K).astype(np.float64)
+        per = []
+        for t in range(L):
+            cw = cwk[words[t]]
+            qw = (cw + beta) / (cw.sum() + K * beta)
+
+            def acc(s, c, cd=cd):
+                return min(1.0, (cd[c] + alpha) * (ck[s] + bbar) / ((cd[s] + alpha) * (ck[c] + bbar)))
+            dist = _mh_outcome(z[t], qw, acc, K, M)
+            if learned is not None and learned_steps:
+                q = np.asarray(learned, np.float64) / np.sum(learned)
+                p = (cd + alpha) * (cw + beta) / (ck + bbar)
+
+                def accl(s, c, p=p, q=q):
+                    return min(1.0, p[c] * q[s] / (p[s] * q[c]))
+                for _ in range(learned_steps):
+                    nd = np.zeros(K)
+                    for s0 in range(K):
+                        nd += dist[s0] * _mh_outcome(s0, q, accl, K, 1)
+                    dist = nd
+            per.append(dist)
+        for sj, z2 in enumerate(states):
+            pr = 1.0
+            for t in range(L):
+                pr *= per[t][z2[t]]
+            Pd[si, sj] = pr
+    return states, Pw @ Pd
+
+
+def fold_distribution(words, K, M, alpha, beta, V, cwk, ck, sweeps, learned=None, learned_steps=0):
+    L = len(words)
+    states, P = fold_sweep_matrix(words, K, M, alpha, beta, V, cwk, ck, learned, learned_steps)
+    if learned is None:
+        pi = np.full(len(states), 1.0 / len(states))
+    else:
+        q = np.asarray(learned, np.float64) / np.sum(learned)
+        pi = np.array([np.prod([q[k] for k in s]) for s in states])
+    for _ in range(sweeps):
+        pi = pi @ P
+    return states, pi
