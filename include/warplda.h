@@ -196,6 +196,60 @@ wlda_status wlda_foldin_batch(wlda_model m, uint32_t n_docs, const uint64_t *doc
                               void *dev_workspace, uint64_t workspace_bytes, int32_t *z_out,
                               double *heldout_out);
 
+/* ------------------------------------------------------------------------ */
+/* Encoder for the learned fold-in proposal                                 */
+/* ------------------------------------------------------------------------ */
+/* An MLP from a hashed bag of words to a distribution over the K topics,
+ * trained on (document, theta_d) pairs that a sampler produced, with
+ * theta_d = (C_dk + alpha) / (L_d + K alpha) (Eq. (4) with alpha' = alpha+1):
+ *   x: bucket b(w) = ((w * 0x9E3779B1 mod 2^32) * buckets) >> 32 of each
+ *      distinct bucket of the document, value = count / L (binary32);
+ *   a1 = b1 + sum x_n W1[b_n]; h1 = relu(a1); a2 = h1 W2 + b2; h2 = relu(a2);
+ *   z = h2 W3 + b3; q = softmax(z); loss = -(1/B) sum_b sum_k theta log q.
+ * W1: buckets x hidden, W2: hidden x hidden, W3: hidden x K (row-major; the
+ * row index is the input unit), biases b1, b2 (hidden), b3 (K).  Matrix
+ * products use bf16 operands (weights, h1, h2 and the back-propagated
+ * signals rounded to nearest even) with fp32 accumulation on the matrix
+ * cores; training is Adam on fp32 master weights.
+ * Weight arrays are passed as 6 host pointers in the order W1, b1, W2, b2,
+ * W3, b3.  Batches are CSR on the device: rowptr (B+1 uint32) into idx
+ * (uint32 buckets) and val (float); theta and probs are B x K float, device.
+ * forward/proposal/train_step enqueue on the encoder's stream; gradients and
+ * train_step with loss != NULL synchronise. */
+typedef struct {
+    uint32_t buckets;     /* hashed vocabulary size (input dimension)        */
+    uint32_t hidden;      /* width of both hidden layers (<= 4096)           */
+    uint32_t K;           /* topics (output dimension)                       */
+    uint32_t max_batch;   /* rows per call (<= 65536)                        */
+    float lr, beta1, beta2, eps;   /* Adam                                  */
+} wlda_encoder_params;
+
+typedef struct wlda_encoder_s *wlda_encoder;
+
+wlda_status wlda_encoder_workspace_bytes(const wlda_encoder_params *p, uint64_t *bytes);
+wlda_status wlda_encoder_create(const wlda_encoder_params *p, void *dev_workspace,
+                                uint64_t workspace_bytes, void *hip_stream, wlda_encoder *out);
+wlda_status wlda_encoder_destroy(wlda_encoder e);
+wlda_status wlda_encoder_set_weights(wlda_encoder e, const float *const *host_weights);
+wlda_status wlda_encoder_get_weights(wlda_encoder e, float *const *host_weights);
+/* Host helper: the sparse input of one document (idx ascending, nnz <= L). */
+wlda_status wlda_encoder_features(uint32_t buckets, const uint32_t *words, uint32_t L,
+                                  uint32_t *idx, float *val, uint32_t *nnz);
+wlda_status wlda_encoder_forward(wlda_encoder e, uint32_t B, const uint32_t *rowptr,
+                                 const uint32_t *idx, const float *val, float *probs);
+/* Integer proposal weights w_k = 1 + floor(2^20 ((1-eps) q_k + eps/K)) as
+ * per-row running sums (B x K uint32, device), for the learned fold-in
+ * proposal; requires K (2^20 + 1) < 2^32. */
+wlda_status wlda_encoder_proposal(wlda_encoder e, uint32_t B, const float *probs, float eps,
+                                  uint32_t *cdf);
+/* Loss and gradients without an update (host outputs, NULL entries skipped). */
+wlda_status wlda_encoder_gradients(wlda_encoder e, uint32_t B, const uint32_t *rowptr,
+                                   const uint32_t *idx, const float *val, const float *theta,
+                                   float *loss, float *const *host_grads);
+wlda_status wlda_encoder_train_step(wlda_encoder e, uint32_t B, const uint32_t *rowptr,
+                                    const uint32_t *idx, const float *val, const float *theta,
+                                    float *loss);
+
 /* Releases host-side state; the workspace is the caller's to free. */
 wlda_status wlda_destroy(wlda_sampler s);
 

@@ -39,7 +39,17 @@ EXPORTS = [
     "wlda_destroy", "wlda_strerror", "wlda_profile", "wlda_profile_read",
     "wlda_model_workspace_bytes", "wlda_model_create", "wlda_model_destroy",
     "wlda_foldin_batch_bytes", "wlda_foldin_batch",
+    "wlda_encoder_workspace_bytes", "wlda_encoder_create", "wlda_encoder_destroy",
+    "wlda_encoder_set_weights", "wlda_encoder_get_weights", "wlda_encoder_features",
+    "wlda_encoder_forward", "wlda_encoder_proposal", "wlda_encoder_gradients",
+    "wlda_encoder_train_step",
 ]
+
+
+class EncoderParams(C.Structure):
+    _fields_ = [("buckets", C.c_uint32), ("hidden", C.c_uint32), ("K", C.c_uint32),
+                ("max_batch", C.c_uint32), ("lr", C.c_float), ("beta1", C.c_float),
+                ("beta2", C.c_float), ("eps", C.c_float)]
 
 
 class KernelStat(C.Structure):
@@ -80,6 +90,16 @@ def load_library(path: str = LIB_PATH):
         "wlda_model_destroy": [vp],
         "wlda_foldin_batch_bytes": [vp, u32, u64, i32, u64, C.POINTER(u64)],
         "wlda_foldin_batch": [vp, u32, vp, vp, vp, vp, u32, u32, vp, vp, vp, u64, vp, vp],
+        "wlda_encoder_workspace_bytes": [C.POINTER(EncoderParams), C.POINTER(u64)],
+        "wlda_encoder_create": [C.POINTER(EncoderParams), vp, u64, vp, C.POINTER(vp)],
+        "wlda_encoder_destroy": [vp],
+        "wlda_encoder_set_weights": [vp, vp],
+        "wlda_encoder_get_weights": [vp, vp],
+        "wlda_encoder_features": [u32, vp, u32, vp, vp, C.POINTER(u32)],
+        "wlda_encoder_forward": [vp, u32, vp, vp, vp, vp],
+        "wlda_encoder_proposal": [vp, u32, vp, C.c_float, vp],
+        "wlda_encoder_gradients": [vp, u32, vp, vp, vp, vp, C.POINTER(C.c_float), vp],
+        "wlda_encoder_train_step": [vp, u32, vp, vp, vp, vp, C.POINTER(C.c_float)],
         "wlda_profile_read": [vp, C.POINTER(KernelStat), u32, C.POINTER(u32)],
     }
     for name, args in sig.items():
@@ -277,3 +297,122 @@ class Model:
                                    None if ho is None else _ptr(ho)))
         del ws
         return z, ho
+
+
+def encoder_features(buckets: int, words) -> tuple:
+    """Sparse hashed bag of words of one document (library host helper)."""
+    w = np.ascontiguousarray(words, np.uint32)
+    idx = np.empty(max(1, len(w)), np.uint32)
+    val = np.empty(max(1, len(w)), np.float32)
+    n = C.c_uint32(0)
+    _check("wlda_encoder_features",
+           load_library().wlda_encoder_features(buckets, _ptr(w), len(w), _ptr(idx), _ptr(val),
+                                                C.byref(n)))
+    return idx[:n.value].copy(), val[:n.value].copy()
+
+
+def batch_features(buckets: int, docs) -> tuple:
+    """CSR (rowptr, idx, val) of a list of documents (word-id arrays)."""
+    rows, idxs, vals = [0], [], []
+    for words in docs:
+        i, v = encoder_features(buckets, words)
+        idxs.append(i)
+        vals.append(v)
+        rows.append(rows[-1] + len(i))
+    return (np.array(rows, np.uint32),
+            np.concatenate(idxs) if idxs else np.zeros(0, np.uint32),
+            np.concatenate(vals) if vals else np.zeros(0, np.float32))
+
+
+class Encoder:
+    """The learned-proposal MLP on the GPU (wlda_encoder_*)."""
+
+    NAMES = ("W1", "b1", "W2", "b2", "W3", "b3")
+
+    def __init__(self, buckets, hidden, K, max_batch=256, lr=1e-3, beta1=0.9, beta2=0.999,
+                 eps=1e-8, device="cuda:0", stream=None):
+        import torch
+        L = load_library()
+        self.p = EncoderParams(buckets, hidden, K, max_batch, lr, beta1, beta2, eps)
+        self.buckets, self.hidden, self.K, self.max_batch = buckets, hidden, K, max_batch
+        n = C.c_uint64(0)
+        _check("wlda_encoder_workspace_bytes",
+               L.wlda_encoder_workspace_bytes(C.byref(self.p), C.byref(n)))
+        self.device = torch.device(device)
+        self.workspace = torch.empty(int(n.value), dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = C.c_void_p(0)
+        _check("wlda_encoder_create",
+               L.wlda_encoder_create(C.byref(self.p), C.c_void_p(self.workspace.data_ptr()),
+                                     int(n.value), C.c_void_p(self.stream.cuda_stream),
+                                     C.byref(h)))
+        self.h = h
+
+    def shapes(self):
+        H, Hd, K = self.buckets, self.hidden, self.K
+        return [(H, Hd), (Hd,), (Hd, Hd), (Hd,), (Hd, K), (K,)]
+
+    def close(self):
+        if getattr(self, "h", None):
+            load_library().wlda_encoder_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_weights(self, ws):
+        arrs = [np.ascontiguousarray(w, np.float32) for w in ws]
+        ptrs = (C.c_void_p * 6)(*[a.ctypes.data for a in arrs])
+        _check("wlda_encoder_set_weights", load_library().wlda_encoder_set_weights(self.h, ptrs))
+
+    def get_weights(self):
+        arrs = [np.empty(s, np.float32) for s in self.shapes()]
+        ptrs = (C.c_void_p * 6)(*[a.ctypes.data for a in arrs])
+        _check("wlda_encoder_get_weights", load_library().wlda_encoder_get_weights(self.h, ptrs))
+        return arrs
+
+    @staticmethod
+    def _dev(t):
+        return C.c_void_p(t.data_ptr())
+
+    def forward(self, rowptr, idx, val):
+        """rowptr/idx/val: torch tensors on the device; returns probs (B x K)."""
+        import torch
+        B = rowptr.numel() - 1
+        probs = torch.empty((B, self.K), dtype=torch.float32, device=self.device)
+        _check("wlda_encoder_forward",
+               load_library().wlda_encoder_forward(self.h, B, self._dev(rowptr), self._dev(idx),
+                                                   self._dev(val), self._dev(probs)))
+        return probs
+
+    def proposal(self, probs, eps=0.01):
+        import torch
+        B = probs.shape[0]
+        cdf = torch.empty((B, self.K), dtype=torch.int32, device=self.device)
+        _check("wlda_encoder_proposal",
+               load_library().wlda_encoder_proposal(self.h, B, self._dev(probs), eps,
+                                                    self._dev(cdf)))
+        return cdf
+
+    def gradients(self, rowptr, idx, val, theta):
+        B = rowptr.numel() - 1
+        grads = [np.empty(s, np.float32) for s in self.shapes()]
+        ptrs = (C.c_void_p * 6)(*[g.ctypes.data for g in grads])
+        loss = C.c_float(0)
+        _check("wlda_encoder_gradients",
+               load_library().wlda_encoder_gradients(self.h, B, self._dev(rowptr), self._dev(idx),
+                                                     self._dev(val), self._dev(theta),
+                                                     C.byref(loss), ptrs))
+        return float(loss.value), grads
+
+    def train_step(self, rowptr, idx, val, theta, want_loss=True):
+        B = rowptr.numel() - 1
+        loss = C.c_float(0)
+        _check("wlda_encoder_train_step",
+               load_library().wlda_encoder_train_step(self.h, B, self._dev(rowptr), self._dev(idx),
+                                                      self._dev(val), self._dev(theta),
+                                                      C.byref(loss) if want_loss else None))
+        return float(loss.value) if want_loss else None

@@ -8,7 +8,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libwarplda_hip.so")
-SOURCES = ["wlda_kernels.hip", "wlda_host.cpp", "wlda_foldin.hip"]
+SOURCES = ["wlda_kernels.hip", "wlda_host.cpp", "wlda_foldin.hip", "wlda_encoder.hip",
+           "wlda_server.cpp"]
 
 # No FP contraction: the MH decisions are binary32 expressions that must round
 # exactly as written.  Packed-FP32 instructions are disabled.

@@ -152,3 +152,17 @@ def doc_prefix(c: Corpus, n_docs: int) -> Corpus:
     n = int(np.searchsorted(c.doc_ids, n_docs, side="left"))
     tz = None if c.true_z is None else c.true_z[:n]
     return Corpus(c.word_ids[:n], c.doc_ids[:n], c.V, n_docs, tz)
+
+
+def encoder_init_weights(buckets: int, hidden: int, K: int, seed: int):
+    """Seeded He-style initial weights of the proposal encoder (float32):
+    [W1 (buckets x hidden), b1, W2 (hidden x hidden), b2, W3 (hidden x K), b3]."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return [
+        (rng.standard_normal((buckets, hidden)) * np.sqrt(2.0 / 32)).astype(np.float32),
+        np.zeros(hidden, np.float32),
+        (rng.standard_normal((hidden, hidden)) * np.sqrt(2.0 / hidden)).astype(np.float32),
+        np.zeros(hidden, np.float32),
+        (rng.standard_normal((hidden, K)) * np.sqrt(1.0 / hidden)).astype(np.float32),
+        np.zeros(K, np.float32),
+    ]

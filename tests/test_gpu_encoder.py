@@ -1,0 +1,93 @@
+"""The HIP encoder against the binary64 oracle: gradients, forward output,
+input features, proposal weights, and a training run that lowers the loss."""
+import numpy as np
+import pytest
+
+from oracle import encoder as E
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def W():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1510_08628_amd as W
+    W.load_library()
+    return W
+
+
+def batch(buckets, K, B, seed, vocab=20000):
+    rng = np.random.default_rng(seed)
+    docs = [rng.integers(0, vocab, int(n)) for n in rng.integers(1, 400, B)]
+    theta = rng.dirichlet(np.full(K, 0.2), size=B)
+    return docs, theta
+
+
+def to_dev(*arrs):
+    import torch
+    return [torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0") for a in arrs]
+
+
+def test_features_equal_oracle(W):
+    rng = np.random.default_rng(1)
+    for n in (1, 2, 17, 4000):
+        words = rng.integers(0, 100000, n).astype(np.uint32)
+        i1, v1 = W.encoder_features(100000, words)
+        i2, v2 = E.features(100000, words)
+        assert np.array_equal(i1, i2) and np.array_equal(v1, v2)
+
+
+@pytest.mark.parametrize("buckets,hidden,K,B", [(3000, 200, 70, 37), (5000, 512, 1000, 64)])
+def test_gradients_match_oracle(W, buckets, hidden, K, B):
+    enc = W.Encoder(buckets, hidden, K, max_batch=B)
+    ws = synth.encoder_init_weights(buckets, hidden, K, 3)
+    ws[1][:] = 0.05
+    ws[3][:] = 0.02
+    ws[5][:] = np.linspace(-0.1, 0.1, K, dtype=np.float32)
+    enc.set_weights(ws)
+    docs, theta = batch(buckets, K, B, 7)
+    rowptr, idx, val = E.batch_features(buckets, docs)
+    loss_o, q_o, g_o = E.forward_backward(ws, rowptr, idx, val, theta, round=True)
+    d_rp, d_idx, d_val, d_th = to_dev(rowptr, idx, val, theta.astype(np.float32))
+    loss_g, g_g = enc.gradients(d_rp, d_idx, d_val, d_th)
+    assert abs(loss_g - loss_o) <= 1e-4 * abs(loss_o), (loss_g, loss_o)
+    q_g = enc.forward(d_rp, d_idx, d_val).cpu().numpy()
+    assert np.abs(q_g - q_o).max() <= 1e-4
+    for name, gg, go in zip(W.Encoder.NAMES, g_g, g_o):
+        err = np.linalg.norm(gg - go) / max(np.linalg.norm(go), 1e-30)
+        assert err < 5e-3, (name, err)
+    # sparse first layer: rows no document touches get no gradient
+    untouched = np.setdiff1d(np.arange(buckets), idx)
+    assert np.all(g_g[0][untouched] == 0)
+
+
+def test_training_lowers_loss(W):
+    buckets, hidden, K, B = 4000, 256, 50, 128
+    enc = W.Encoder(buckets, hidden, K, max_batch=B, lr=3e-3)
+    enc.set_weights(synth.encoder_init_weights(buckets, hidden, K, 5))
+    docs, theta = batch(buckets, K, B, 9, vocab=3000)
+    rowptr, idx, val = E.batch_features(buckets, docs)
+    d = to_dev(rowptr, idx, val, theta.astype(np.float32))
+    # soft cross-entropy is bounded below by the entropy of the targets: the
+    # KL gap to the targets must shrink
+    ent = float(-(theta * np.log(theta)).sum(1).mean())
+    first = enc.train_step(*d)
+    for _ in range(60):
+        last = enc.train_step(*d)
+    assert last - ent < 0.5 * (first - ent), (first, last, ent)
+
+
+def test_proposal_weights(W):
+    import torch
+    K, B = 1000, 5
+    enc = W.Encoder(64, 64, K, max_batch=B)
+    rng = np.random.default_rng(2)
+    p = rng.dirichlet(np.full(K, 0.1), size=B).astype(np.float32)
+    cdf = enc.proposal(torch.from_numpy(p).to("cuda:0"), eps=0.01).cpu().numpy().astype(np.int64)
+    e = np.float32(0.01)
+    q = ((np.float32(1) - e) * p + e / np.float32(K)).astype(np.float32)
+    w = 1 + np.floor(q * np.float32(1 << 20)).astype(np.int64)
+    assert np.array_equal(cdf, np.cumsum(w, axis=1))
