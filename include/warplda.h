@@ -250,6 +250,54 @@ wlda_status wlda_encoder_train_step(wlda_encoder e, uint32_t B, const uint32_t *
                                     const uint32_t *idx, const float *val, const float *theta,
                                     float *loss);
 
+/* ------------------------------------------------------------------------ */
+/* Continuous-batching fold-in server                                       */
+/* ------------------------------------------------------------------------ */
+/* Requests (new documents, at most 8192 tokens) wait in arrival order and
+ * are admitted while a document slot and a contiguous range of the device
+ * token pool are free.  Each wlda_server_step() admits what fits, runs the
+ * encoder for the newly admitted documents (learned mode, on the encoder's
+ * stream, overlapped with the sweep of the documents already in flight),
+ * runs ONE fold-in sweep for every admitted document in one ragged launch,
+ * and retires documents that have had their initialisation and `sweeps`
+ * sweeps (their z and held-out log likelihood are kept for the caller).
+ * A request uses the learned proposal if the server has an encoder or the
+ * request brings its own weights; otherwise the plain chain.  Results do not
+ * depend on the other requests in flight.  Times are seconds on the server's
+ * monotonic clock (wlda_server_now).  step synchronises the server stream. */
+typedef struct {
+    uint32_t max_docs;       /* document slots                                 */
+    uint64_t pool_tokens;    /* device token pool (words, z, proposals)        */
+    uint64_t pool_heldout;   /* device pool of held-out tokens                 */
+    uint32_t sweeps;         /* sweeps per document (after initialisation)     */
+    uint32_t learned_steps;  /* learned MH steps per sweep                     */
+    float eps;               /* uniform share of the learned proposal (0, 1]   */
+} wlda_server_params;
+
+typedef struct {
+    uint32_t req_id, n_tokens, n_heldout, sweeps, learned;
+    double arrival_s, admit_s, done_s;   /* server clock                       */
+    double heldout_ll;                   /* sum over the held-out tokens       */
+} wlda_result;
+
+typedef struct wlda_server_s *wlda_server;
+
+wlda_status wlda_server_workspace_bytes(wlda_model m, wlda_encoder enc_or_null,
+                                        const wlda_server_params *sp, uint64_t *bytes);
+wlda_status wlda_server_create(wlda_model m, wlda_encoder enc_or_null,
+                               const wlda_server_params *sp, void *dev_workspace,
+                               uint64_t workspace_bytes, void *hip_stream, wlda_server *out);
+wlda_status wlda_server_now(wlda_server s, double *seconds);
+/* weights: K learned proposal weights (as in wlda_foldin_batch) or NULL. */
+wlda_status wlda_server_submit(wlda_server s, uint32_t req_id, const uint32_t *words, uint32_t L,
+                               const uint32_t *heldout_words, uint32_t n_heldout,
+                               double arrival_s, const uint32_t *weights);
+wlda_status wlda_server_step(wlda_server s, uint32_t *n_active, uint32_t *n_pending);
+wlda_status wlda_server_poll(wlda_server s, wlda_result *out, uint32_t max_results,
+                             uint32_t *n_results);
+wlda_status wlda_server_take_z(wlda_server s, uint32_t req_id, int32_t *z, uint32_t L);
+wlda_status wlda_server_destroy(wlda_server s);
+
 /* Releases host-side state; the workspace is the caller's to free. */
 wlda_status wlda_destroy(wlda_sampler s);
 

@@ -43,7 +43,21 @@ EXPORTS = [
     "wlda_encoder_set_weights", "wlda_encoder_get_weights", "wlda_encoder_features",
     "wlda_encoder_forward", "wlda_encoder_proposal", "wlda_encoder_gradients",
     "wlda_encoder_train_step",
+    "wlda_server_workspace_bytes", "wlda_server_create", "wlda_server_now", "wlda_server_submit",
+    "wlda_server_step", "wlda_server_poll", "wlda_server_take_z", "wlda_server_destroy",
 ]
+
+
+class ServerParams(C.Structure):
+    _fields_ = [("max_docs", C.c_uint32), ("pool_tokens", C.c_uint64),
+                ("pool_heldout", C.c_uint64), ("sweeps", C.c_uint32),
+                ("learned_steps", C.c_uint32), ("eps", C.c_float)]
+
+
+class Result(C.Structure):
+    _fields_ = [("req_id", C.c_uint32), ("n_tokens", C.c_uint32), ("n_heldout", C.c_uint32),
+                ("sweeps", C.c_uint32), ("learned", C.c_uint32), ("arrival_s", C.c_double),
+                ("admit_s", C.c_double), ("done_s", C.c_double), ("heldout_ll", C.c_double)]
 
 
 class EncoderParams(C.Structure):
@@ -100,6 +114,14 @@ def load_library(path: str = LIB_PATH):
         "wlda_encoder_proposal": [vp, u32, vp, C.c_float, vp],
         "wlda_encoder_gradients": [vp, u32, vp, vp, vp, vp, C.POINTER(C.c_float), vp],
         "wlda_encoder_train_step": [vp, u32, vp, vp, vp, vp, C.POINTER(C.c_float)],
+        "wlda_server_workspace_bytes": [vp, vp, C.POINTER(ServerParams), C.POINTER(u64)],
+        "wlda_server_create": [vp, vp, C.POINTER(ServerParams), vp, u64, vp, C.POINTER(vp)],
+        "wlda_server_now": [vp, C.POINTER(C.c_double)],
+        "wlda_server_submit": [vp, u32, vp, u32, vp, u32, C.c_double, vp],
+        "wlda_server_step": [vp, C.POINTER(u32), C.POINTER(u32)],
+        "wlda_server_poll": [vp, C.POINTER(Result), u32, C.POINTER(u32)],
+        "wlda_server_take_z": [vp, u32, vp, u32],
+        "wlda_server_destroy": [vp],
         "wlda_profile_read": [vp, C.POINTER(KernelStat), u32, C.POINTER(u32)],
     }
     for name, args in sig.items():
@@ -416,3 +438,72 @@ class Encoder:
                                                       self._dev(val), self._dev(theta),
                                                       C.byref(loss) if want_loss else None))
         return float(loss.value) if want_loss else None
+
+
+class Server:
+    """Continuous-batching fold-in server (wlda_server_*)."""
+
+    def __init__(self, model, encoder=None, max_docs=256, pool_tokens=1 << 20,
+                 pool_heldout=1 << 20, sweeps=10, learned_steps=2, eps=0.01, stream=None):
+        import torch
+        L = load_library()
+        self.model, self.encoder = model, encoder
+        self.sp = ServerParams(max_docs, pool_tokens, pool_heldout, sweeps, learned_steps, eps)
+        n = C.c_uint64(0)
+        eh = encoder.h if encoder is not None else None
+        _check("wlda_server_workspace_bytes",
+               L.wlda_server_workspace_bytes(model.h, eh, C.byref(self.sp), C.byref(n)))
+        self.workspace = torch.empty(int(n.value), dtype=torch.uint8, device=model.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(model.device)
+        h = C.c_void_p(0)
+        _check("wlda_server_create",
+               L.wlda_server_create(model.h, eh, C.byref(self.sp),
+                                    C.c_void_p(self.workspace.data_ptr()), int(n.value),
+                                    C.c_void_p(self.stream.cuda_stream), C.byref(h)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            load_library().wlda_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def now(self) -> float:
+        t = C.c_double(0)
+        _check("wlda_server_now", load_library().wlda_server_now(self.h, C.byref(t)))
+        return t.value
+
+    def submit(self, req_id, words, heldout=None, arrival=None, weights=None):
+        w = np.ascontiguousarray(words, np.uint32)
+        ho = np.ascontiguousarray(heldout if heldout is not None else [], np.uint32)
+        wt = None if weights is None else np.ascontiguousarray(weights, np.uint32)
+        t = self.now() if arrival is None else float(arrival)
+        _check("wlda_server_submit",
+               load_library().wlda_server_submit(self.h, req_id, _ptr(w), len(w),
+                                                 _ptr(ho) if len(ho) else None, len(ho), t,
+                                                 None if wt is None else _ptr(wt)))
+
+    def step(self):
+        a, p = C.c_uint32(0), C.c_uint32(0)
+        _check("wlda_server_step", load_library().wlda_server_step(self.h, C.byref(a), C.byref(p)))
+        return int(a.value), int(p.value)
+
+    def poll(self, max_results=4096):
+        arr = (Result * max_results)()
+        n = C.c_uint32(0)
+        _check("wlda_server_poll", load_library().wlda_server_poll(self.h, arr, max_results,
+                                                                   C.byref(n)))
+        return [dict(req_id=r.req_id, n_tokens=r.n_tokens, n_heldout=r.n_heldout,
+                     sweeps=r.sweeps, learned=bool(r.learned), arrival_s=r.arrival_s,
+                     admit_s=r.admit_s, done_s=r.done_s, heldout_ll=r.heldout_ll)
+                for r in arr[:n.value]]
+
+    def take_z(self, req_id, L):
+        z = np.empty(L, np.int32)
+        _check("wlda_server_take_z", load_library().wlda_server_take_z(self.h, req_id, _ptr(z), L))
+        return z

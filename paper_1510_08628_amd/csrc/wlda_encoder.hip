@@ -233,6 +233,8 @@ __global__ __launch_bounds__(256) void probs_to_cdf_kernel(int K, const float *p
 
 using namespace wlda;
 
+struct wlda_encoder_s;
+
 // ============================================================================
 // Host side
 // ============================================================================
@@ -249,6 +251,13 @@ struct wlda_encoder_s {
     uint16_t *h1b = nullptr, *h2b = nullptr, *g3b = nullptr, *g2b = nullptr;
     uint64_t steps = 0;
 };
+
+namespace wlda {
+uint32_t wlda_encoder_get_k(wlda_encoder e) { return e->p.K; }
+uint32_t wlda_encoder_get_buckets(wlda_encoder e) { return e->p.buckets; }
+uint32_t wlda_encoder_get_max_batch(wlda_encoder e) { return e->p.max_batch; }
+void *wlda_encoder_get_stream(wlda_encoder e) { return (void *)e->st; }
+}  // namespace wlda
 
 namespace {
 constexpr uint64_t EALIGN = 256;

@@ -25,7 +25,7 @@
 #include <vector>
 
 #include "../../include/warplda.h"
-#include "wlda_internal.h"
+#include "wlda_fold.h"
 
 namespace wlda {
 
@@ -60,34 +60,6 @@ __device__ __forceinline__ bool faccept(float u, uint32_t cnt_c, uint32_t cnt_s,
     return u * den < num;
 }
 
-struct FoldModel {
-    const uint32_t *colptr;   // V+1
-    const void *zcsc;         // trained z, canonical column order (u16 if K <= 65535)
-    const uint32_t *cwk;      // V x K frozen word-topic counts
-    const uint32_t *ck;       // K
-    uint32_t V, K, M, zc16;
-    float a, b, alpha_bar, beta_k, beta_bar;
-    uint32_t seed_lo, seed_hi;
-};
-
-struct FoldBatch {
-    uint32_t n;               // documents in this launch
-    const uint32_t *slots;    // slot id of each document
-    const uint32_t *off;      // per slot: first token in the pool
-    const uint32_t *len;      // per slot: tokens
-    const uint32_t *req;      // per slot: request id
-    uint32_t *sweep;          // per slot: next sweep (0 = initialise)
-    const uint32_t *words;    // pool
-    uint32_t *z;              // pool
-    uint32_t *pd;             // pool, M x cap (proposal-major)
-    uint32_t *pw;             // pool, M x cap
-    uint32_t cap;
-    const uint32_t *qcdf;     // per slot K running sums of the learned weights (or null)
-    uint32_t learned_steps;
-    uint32_t max_sweep;       // run only documents with sweep <= max_sweep
-};
-
-constexpr uint32_t FOLD_MAX_TOKENS = 8192;
 
 __device__ __forceinline__ uint32_t cdf_draw(const uint32_t *cdf, uint32_t K, uint32_t r) {
     const uint32_t total = cdf[K - 1];
@@ -114,7 +86,8 @@ __global__ __launch_bounds__(256) void fold_sweep_kernel(FoldModel m, FoldBatch 
     uint32_t *zs = lds;                 // L
     uint32_t *cd = lds + FOLD_MAX_TOKENS;   // K
     const ZT *zc = reinterpret_cast<const ZT *>(m.zcsc);
-    const uint32_t *qcdf = b.qcdf ? b.qcdf + (size_t)slot * K : nullptr;
+    const uint32_t *qcdf =
+        b.qcdf && (!b.use_q || b.use_q[slot]) ? b.qcdf + (size_t)slot * K : nullptr;
     const uint32_t cap = b.cap;
 
     if (s == 0) {
