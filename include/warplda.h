@@ -113,6 +113,12 @@ wlda_status wlda_log_likelihood(wlda_sampler s, double *ll);
  * Synchronises. */
 wlda_status wlda_copy_assignments(wlda_sampler s, int32_t *z, int32_t *props);
 
+/* theta_hat of Eq. (4) with alpha' = alpha + 1 for documents d0 .. d0+nd-1:
+ * theta[(d - d0) * K + k] = (C_dk + alpha) / (L_d + K alpha), binary32, written
+ * to DEVICE memory (nd x K floats).  Enqueued on the sampler's stream;
+ * requires K <= 16384. */
+wlda_status wlda_theta(wlda_sampler s, uint32_t d0, uint32_t nd, float *theta);
+
 /* Copies z and the proposals in the canonical column-major order (same
  * shapes as above).  Synchronises. */
 wlda_status wlda_copy_assignments_csc(wlda_sampler s, int32_t *z, int32_t *props);
@@ -235,6 +241,11 @@ wlda_status wlda_encoder_get_weights(wlda_encoder e, float *const *host_weights)
 /* Host helper: the sparse input of one document (idx ascending, nnz <= L). */
 wlda_status wlda_encoder_features(uint32_t buckets, const uint32_t *words, uint32_t L,
                                   uint32_t *idx, float *val, uint32_t *nnz);
+/* Host helper: CSR inputs of n_docs documents (document d = words[docptr[d]
+ * .. docptr[d+1])); rowptr has n_docs+1 entries, idx/val docptr[n_docs]. */
+wlda_status wlda_encoder_features_batch(uint32_t buckets, uint32_t n_docs, const uint64_t *docptr,
+                                        const uint32_t *words, uint32_t *rowptr, uint32_t *idx,
+                                        float *val);
 wlda_status wlda_encoder_forward(wlda_encoder e, uint32_t B, const uint32_t *rowptr,
                                  const uint32_t *idx, const float *val, float *probs);
 /* Integer proposal weights w_k = 1 + floor(2^20 ((1-eps) q_k + eps/K)) as

@@ -42,7 +42,7 @@ EXPORTS = [
     "wlda_encoder_workspace_bytes", "wlda_encoder_create", "wlda_encoder_destroy",
     "wlda_encoder_set_weights", "wlda_encoder_get_weights", "wlda_encoder_features",
     "wlda_encoder_forward", "wlda_encoder_proposal", "wlda_encoder_gradients",
-    "wlda_encoder_train_step",
+    "wlda_encoder_train_step", "wlda_theta", "wlda_encoder_features_batch",
     "wlda_server_workspace_bytes", "wlda_server_create", "wlda_server_now", "wlda_server_submit",
     "wlda_server_step", "wlda_server_poll", "wlda_server_take_z", "wlda_server_destroy",
 ]
@@ -114,6 +114,8 @@ def load_library(path: str = LIB_PATH):
         "wlda_encoder_proposal": [vp, u32, vp, C.c_float, vp],
         "wlda_encoder_gradients": [vp, u32, vp, vp, vp, vp, C.POINTER(C.c_float), vp],
         "wlda_encoder_train_step": [vp, u32, vp, vp, vp, vp, C.POINTER(C.c_float)],
+        "wlda_theta": [vp, u32, u32, vp],
+        "wlda_encoder_features_batch": [u32, u32, vp, vp, vp, vp, vp],
         "wlda_server_workspace_bytes": [vp, vp, C.POINTER(ServerParams), C.POINTER(u64)],
         "wlda_server_create": [vp, vp, C.POINTER(ServerParams), vp, u64, vp, C.POINTER(vp)],
         "wlda_server_now": [vp, C.POINTER(C.c_double)],
@@ -246,6 +248,14 @@ class Sampler:
         return {arr[i].name.decode(): (int(arr[i].launches), int(arr[i].tokens_per_launch),
                                        float(arr[i].total_ms)) for i in range(n.value)}
 
+    def theta(self, d0, nd, out=None):
+        """theta_hat rows of documents d0..d0+nd-1 as a device tensor (nd x K)."""
+        import torch
+        if out is None:
+            out = torch.empty((nd, self.K), dtype=torch.float32, device=self.device)
+        _check("wlda_theta", load_library().wlda_theta(self.h, d0, nd, C.c_void_p(out.data_ptr())))
+        return out
+
     def set_assignments(self, z, props=None):
         zz = np.ascontiguousarray(z, dtype=np.int32)
         pp = None if props is None else np.ascontiguousarray(props, dtype=np.int32)
@@ -331,6 +341,20 @@ def encoder_features(buckets: int, words) -> tuple:
            load_library().wlda_encoder_features(buckets, _ptr(w), len(w), _ptr(idx), _ptr(val),
                                                 C.byref(n)))
     return idx[:n.value].copy(), val[:n.value].copy()
+
+
+def features_csr(buckets: int, docptr, words) -> tuple:
+    """CSR (rowptr, idx, val) of documents words[docptr[d]:docptr[d+1]]."""
+    dp = np.ascontiguousarray(docptr, np.uint64)
+    w = np.ascontiguousarray(words, np.uint32)
+    n = len(dp) - 1
+    rowptr = np.empty(n + 1, np.uint32)
+    idx = np.empty(max(1, len(w)), np.uint32)
+    val = np.empty(max(1, len(w)), np.float32)
+    _check("wlda_encoder_features_batch",
+           load_library().wlda_encoder_features_batch(buckets, n, _ptr(dp), _ptr(w), _ptr(rowptr),
+                                                      _ptr(idx), _ptr(val)))
+    return rowptr, idx[:rowptr[-1]].copy(), val[:rowptr[-1]].copy()
 
 
 def batch_features(buckets: int, docs) -> tuple:

@@ -467,6 +467,24 @@ wlda_status wlda_encoder_features(uint32_t buckets, const uint32_t *words, uint3
     return WLDA_OK;
 }
 
+wlda_status wlda_encoder_features_batch(uint32_t buckets, uint32_t n_docs, const uint64_t *docptr,
+                                        const uint32_t *words, uint32_t *rowptr, uint32_t *idx, float *val) {
+    if (!docptr || !rowptr || buckets == 0) return WLDA_E_INVALID;
+    uint64_t k = 0;
+    rowptr[0] = 0;
+    for (uint32_t d = 0; d < n_docs; ++d) {
+        const uint64_t L = docptr[d + 1] - docptr[d];
+        uint32_t nnz = 0;
+        if (L >= (1ull << 32)) return WLDA_E_INVALID;
+        wlda_status st = wlda_encoder_features(buckets, words + docptr[d], (uint32_t)L, idx + k, val + k, &nnz);
+        if (st != WLDA_OK) return st;
+        k += nnz;
+        if (k >= (1ull << 32)) return WLDA_E_INVALID;
+        rowptr[d + 1] = (uint32_t)k;
+    }
+    return WLDA_OK;
+}
+
 wlda_status wlda_encoder_forward(wlda_encoder e, uint32_t B, const uint32_t *rowptr, const uint32_t *idx,
                                  const float *val, float *probs) {
     if (!e || !rowptr || !probs || B > e->p.max_batch) return WLDA_E_INVALID;

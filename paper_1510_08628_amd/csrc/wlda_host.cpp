@@ -556,6 +556,15 @@ wlda_status wlda_log_likelihood(wlda_sampler s, double *ll) {
     return WLDA_OK;
 }
 
+wlda_status wlda_theta(wlda_sampler s, uint32_t d0, uint32_t nd, float *theta) {
+    if (!s || !theta || (uint64_t)d0 + nd > s->p.D) return WLDA_E_INVALID;
+    if (s->broken) return WLDA_E_HIP;
+    if (s->next_phase == 0) return WLDA_E_STATE;
+    WLDA_TRY(s, launch_theta(s->recs, s->p.M, s->rowptr, s->rowpos, d0, nd, s->p.K, (float)s->p.alpha, theta,
+                             s->st));
+    return WLDA_OK;
+}
+
 static wlda_status copy_out(wlda_sampler s, int32_t *z, int32_t *props, bool input_order) {
     if (!s || !z) return WLDA_E_INVALID;
     if (s->broken) return WLDA_E_HIP;

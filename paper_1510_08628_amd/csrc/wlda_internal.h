@@ -97,6 +97,8 @@ hipError_t launch_ll_segments(const uint64_t *recs, uint32_t M, const uint32_t *
                               const uint32_t *rowpos, uint32_t n_seg, uint32_t K,
                               double prior, double prior_total, int length_term,
                               double *out, hipStream_t st);
+hipError_t launch_theta(const uint64_t *recs, uint32_t M, const uint32_t *rowptr, const uint32_t *rowpos,
+                        uint32_t d0, uint32_t nd, uint32_t K, float alpha, float *out, hipStream_t st);
 hipError_t launch_ll_topics(const uint32_t *ck, uint32_t K, double beta_bar, double *out,
                             hipStream_t st);
 

@@ -562,6 +562,27 @@ __global__ __launch_bounds__(256) void ll_seg_kernel(const uint64_t *recs, const
     if (threadIdx.x == 0) atomicAdd(out, s);
 }
 
+// theta_hat of Eq. (4) (alpha' = alpha + 1): out[d - d0][k] =
+// (C_dk + alpha) / (L_d + K alpha) for documents d0 .. d0 + nd - 1.
+template <int NW>
+__global__ __launch_bounds__(256) void theta_kernel(const uint64_t *recs, const uint32_t *rowptr,
+                                                    const uint32_t *rowpos, uint32_t d0, uint32_t nd,
+                                                    uint32_t K, float alpha, float *out) {
+    extern __shared__ uint32_t cnt[];
+    for (uint32_t d = d0 + blockIdx.x; d < d0 + nd; d += gridDim.x) {
+        const uint32_t beg = rowptr[d], L = rowptr[d + 1] - beg;
+        for (uint32_t k = threadIdx.x; k < K; k += 256) cnt[k] = 0;
+        __syncthreads();
+        for (uint32_t n = threadIdx.x; n < L; n += 256)
+            atomicAdd(&cnt[fld(ld_rec<NW>(recs, rowpos[beg + n]), 0)], 1u);
+        __syncthreads();
+        const float den = (float)L + (float)K * alpha;
+        for (uint32_t k = threadIdx.x; k < K; k += 256)
+            out[(size_t)(d - d0) * K + k] = ((float)cnt[k] + alpha) / den;
+        __syncthreads();
+    }
+}
+
 __global__ void ll_topics_kernel(const uint32_t *ck, uint32_t K, double beta_bar, double *out) {
     const double lg = lgamma(beta_bar);
     double acc = 0;
@@ -771,6 +792,25 @@ hipError_t launch_ll_segments(const uint64_t *recs, uint32_t M, const uint32_t *
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(ll_seg_kernel<2>, dim3(blocks), dim3(256), lds, st, recs, segptr, rowpos,
                            n_seg, K, prior, prior_total, length_term, out);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_theta(const uint64_t *recs, uint32_t M, const uint32_t *rowptr, const uint32_t *rowpos,
+                        uint32_t d0, uint32_t nd, uint32_t K, float alpha, float *out, hipStream_t st) {
+    if (nd == 0) return hipSuccess;
+    if (K > LL_DENSE_MAX) return hipErrorNotSupported;
+    const size_t lds = 4ull * K;
+    const int blocks = nd < 8192 ? (int)nd : 8192;
+    hipError_t e;
+    if (record_words(M) == 1) {
+        if ((e = launch_dyn(theta_kernel<1>, dim3(1), lds, st))) return e;
+        hipLaunchKernelGGL(theta_kernel<1>, dim3(blocks), dim3(256), lds, st, recs, rowptr, rowpos, d0, nd, K,
+                           alpha, out);
+    } else {
+        if ((e = launch_dyn(theta_kernel<2>, dim3(1), lds, st))) return e;
+        hipLaunchKernelGGL(theta_kernel<2>, dim3(blocks), dim3(256), lds, st, recs, rowptr, rowpos, d0, nd, K,
+                           alpha, out);
     }
     return hipGetLastError();
 }

@@ -147,6 +147,12 @@ WORKLOADS = {
 }
 
 
+WORKLOADS["nytimes-shape-topical-k1e3"] = Workload(
+    "nytimes-shape-topical-k1e3", K=1000, M=2, alpha=0.05, beta=0.01, iters=100,
+    make=lambda: topical_zipf_corpus(300_000, 100_000, 1000, 1.0, 330.0, 0.8, 0.05, 2.0,
+                                     CORPUS_SEED_BASE + 11))
+
+
 def doc_prefix(c: Corpus, n_docs: int) -> Corpus:
     """The tokens of documents [0, n_docs) (the generators emit docs in order)."""
     n = int(np.searchsorted(c.doc_ids, n_docs, side="left"))
@@ -154,15 +160,103 @@ def doc_prefix(c: Corpus, n_docs: int) -> Corpus:
     return Corpus(c.word_ids[:n], c.doc_ids[:n], c.V, n_docs, tz)
 
 
-def encoder_init_weights(buckets: int, hidden: int, K: int, seed: int):
+def encoder_init_weights(buckets: int, hidden: int, K: int, seed: int, w1_std: float = 0.25):
     """Seeded He-style initial weights of the proposal encoder (float32):
-    [W1 (buckets x hidden), b1, W2 (hidden x hidden), b2, W3 (hidden x K), b3]."""
+    [W1 (buckets x hidden), b1, W2 (hidden x hidden), b2, W3 (hidden x K), b3].
+    The first layer averages ~L rows (features tf/L), so its scale is set
+    separately (w1_std)."""
     rng = np.random.Generator(np.random.PCG64(seed))
     return [
-        (rng.standard_normal((buckets, hidden)) * np.sqrt(2.0 / 32)).astype(np.float32),
+        (rng.standard_normal((buckets, hidden)) * w1_std).astype(np.float32),
         np.zeros(hidden, np.float32),
         (rng.standard_normal((hidden, hidden)) * np.sqrt(2.0 / hidden)).astype(np.float32),
         np.zeros(hidden, np.float32),
         (rng.standard_normal((hidden, K)) * np.sqrt(1.0 / hidden)).astype(np.float32),
         np.zeros(K, np.float32),
     ]
+
+
+def docs_from_model(word_ids, z, V: int, K: int, alpha: float, beta: float, n_docs: int,
+                    seed: int, mean_len_log: float = 5.76, sigma: float = 0.89,
+                    lo: int = 20, hi: int = 5000):
+    """New documents drawn from a fitted model: theta ~ Dir(alpha), z ~ theta,
+    w ~ phi_z with phi_k proportional to C_wk + beta (the counts of the given
+    assignments).  Lengths round(lognormal(mean_len_log, sigma)) clipped to
+    [lo, hi] (median ~316 for the defaults).  Each document's tokens are split
+    50/50 at random into an observed part and a held-out part.
+    Returns (docptr, words, hoptr, held_out_words), uint64/uint32 arrays."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    cw = np.bincount(np.asarray(word_ids, np.int64) * K + np.asarray(z, np.int64),
+                     minlength=V * K).reshape(V, K)
+    lens = np.clip(np.rint(rng.lognormal(mean_len_log, sigma, n_docs)), lo, hi).astype(np.int64)
+    theta = rng.dirichlet(np.full(K, alpha), size=n_docs)
+    ctheta = np.cumsum(theta, axis=1)
+    ctheta /= ctheta[:, -1:]
+    T = int(lens.sum())
+    topics = np.empty(T, np.int64)
+    pos = 0
+    for d in range(n_docs):
+        t = np.searchsorted(ctheta[d], rng.random(lens[d]), side="right")
+        topics[pos:pos + lens[d]] = np.minimum(t, K - 1)
+        pos += lens[d]
+    words = np.empty(T, np.uint32)
+    u = rng.random(T)
+    for k in np.unique(topics):
+        m = topics == k
+        cdf = np.cumsum(cw[:, k] + beta)
+        words[m] = np.minimum(np.searchsorted(cdf / cdf[-1], u[m], side="right"), V - 1)
+    obs, held, op, hp = [], [], [0], [0]
+    pos = 0
+    for d in range(n_docs):
+        w = words[pos:pos + lens[d]][rng.permutation(lens[d])]
+        pos += lens[d]
+        h = lens[d] // 2
+        obs.append(w[h:])
+        held.append(w[:h])
+        op.append(op[-1] + len(w) - h)
+        hp.append(hp[-1] + h)
+    return (np.array(op, np.uint64), np.concatenate(obs), np.array(hp, np.uint64),
+            np.concatenate(held))
+
+
+def poisson_arrivals(n: int, rate: float, seed: int):
+    """Arrival times (seconds) of a Poisson process of the given rate."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return np.cumsum(rng.exponential(1.0 / rate, n))
+
+
+def topical_zipf_corpus(D: int, V: int, K: int, s: float, mean_len: float, sigma: float,
+                        alpha: float, tilt: float, seed: int) -> Corpus:
+    """LDA-generated corpus with Zipf-shaped topics: phi_k(w) proportional to
+    r(w)^-s * exp(tilt * e_kw), e_kw ~ N(0, 1), so every topic keeps the
+    Zipf(s) profile of word frequencies but favours its own words; theta_d ~
+    Dir(alpha); lognormal document lengths as in zipf_corpus."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    lengths = _lognormal_lengths(rng, D, mean_len, sigma)
+    T = int(lengths.sum())
+    base = np.arange(1, V + 1, dtype=np.float64) ** (-s)
+    rank_to_word = rng.permutation(V).astype(np.uint32)
+    topics = np.empty(T, np.int32)
+    pos = 0
+    for d0 in range(0, D, 8192):            # topic counts per document, in chunks
+        d1 = min(D, d0 + 8192)
+        theta = rng.dirichlet(np.full(K, alpha), size=d1 - d0)
+        counts = rng.multinomial(lengths[d0:d1], theta)
+        n = int(lengths[d0:d1].sum())
+        topics[pos:pos + n] = np.repeat(np.tile(np.arange(K, dtype=np.int32), d1 - d0),
+                                        counts.ravel())
+        pos += n
+    word_ids = np.empty(T, np.uint32)
+    u = rng.random(T)
+    order = np.argsort(topics, kind="stable")
+    bounds = np.searchsorted(topics[order], np.arange(K + 1))
+    for k in range(K):
+        sel = order[bounds[k]:bounds[k + 1]]
+        if len(sel) == 0:
+            continue
+        phi = base * np.exp(tilt * rng.standard_normal(V))
+        cdf = np.cumsum(phi)
+        r = np.minimum(np.searchsorted(cdf / cdf[-1], u[sel], side="right"), V - 1)
+        word_ids[sel] = rank_to_word[r]
+    doc_ids = np.repeat(np.arange(D, dtype=np.uint32), lengths)
+    return Corpus(word_ids, doc_ids, V, D, topics)
