@@ -294,7 +294,7 @@ static void word_column(oracle_t *o, uint32_t w, uint32_t iter, int64_t *ck_next
 {
     uint64_t beg = o->colptr[w], L = o->colptr[w + 1] - beg;
     if (L == 0) return;
-    memset(cw, 0, o->K * sizeof(int64_t));
+    /* cw is all zero on entry and is returned all zero */
     for (uint64_t n = 0; n < L; ++n) cw[o->z[beg + n]]++;
     for (uint64_t n = 0; n < L; ++n) {
         uint32_t t = (uint32_t)(beg + n);
@@ -311,6 +311,7 @@ static void word_column(oracle_t *o, uint32_t w, uint32_t iter, int64_t *ck_next
         }
         znew[t] = s;
     }
+    for (uint64_t n = 0; n < L; ++n) cw[o->z[beg + n]] = 0;
     for (uint64_t n = 0; n < L; ++n) o->z[beg + n] = znew[beg + n];
     for (uint64_t n = 0; n < L; ++n) {
         uint32_t t = (uint32_t)(beg + n);
@@ -333,7 +334,7 @@ int oracle_word_phase(oracle_t *o)
 {
     if (o->next_phase != PH_WORD) return -4;
     uint32_t iter = o->iter + 1;
-    int64_t *cw = malloc(o->K * sizeof(int64_t));
+    int64_t *cw = calloc(o->K, sizeof(int64_t));
     int64_t *ck_next = calloc(o->K, sizeof(int64_t));
     int32_t *znew = malloc(o->T * sizeof(int32_t) + 1);
     if (!cw || !ck_next || !znew) { free(cw); free(ck_next); free(znew); return -1; }
@@ -357,7 +358,7 @@ static void doc_row(oracle_t *o, uint32_t d, uint32_t iter, int64_t *ck_next,
 {
     uint64_t beg = o->rowptr[d], L = o->rowptr[d + 1] - beg;
     if (L == 0) return;
-    memset(cd, 0, o->K * sizeof(int64_t));
+    /* cd is all zero on entry and is returned all zero */
     for (uint64_t n = 0; n < L; ++n) cd[o->z[o->row[beg + n]]]++;
     for (uint64_t n = 0; n < L; ++n) {
         uint32_t t = o->row[beg + n];
@@ -374,6 +375,7 @@ static void doc_row(oracle_t *o, uint32_t d, uint32_t iter, int64_t *ck_next,
         }
         znew[t] = s;
     }
+    for (uint64_t n = 0; n < L; ++n) cd[o->z[o->row[beg + n]]] = 0;
     for (uint64_t n = 0; n < L; ++n) {
         uint32_t t = o->row[beg + n];
         o->z[t] = znew[t];
@@ -388,7 +390,7 @@ int oracle_doc_phase(oracle_t *o)
 {
     if (o->next_phase != PH_DOC) return -4;
     uint32_t iter = o->iter + 1;
-    int64_t *cd = malloc(o->K * sizeof(int64_t));
+    int64_t *cd = calloc(o->K, sizeof(int64_t));
     int64_t *ck_next = calloc(o->K, sizeof(int64_t));
     int32_t *znew = malloc(o->T * sizeof(int32_t) + 1);
     if (!cd || !ck_next || !znew) { free(cd); free(ck_next); free(znew); return -1; }
@@ -413,7 +415,7 @@ int oracle_doc_phase(oracle_t *o)
 int oracle_phase_subset(oracle_t *o, int phase, uint32_t iter,
                         const uint32_t *segs, uint64_t n)
 {
-    int64_t *cnt = malloc(o->K * sizeof(int64_t));
+    int64_t *cnt = calloc(o->K, sizeof(int64_t));
     int32_t *znew = malloc(o->T * sizeof(int32_t) + 1);
     if (!cnt || !znew) { free(cnt); free(znew); return -1; }
     uint64_t accepted = 0;
@@ -493,19 +495,24 @@ double oracle_log_likelihood(const oracle_t *o)
     for (uint32_t d = 0; d < o->D; ++d) {
         uint64_t beg = o->rowptr[d], L = o->rowptr[d + 1] - beg;
         if (L == 0) continue;
-        memset(cnt, 0, o->K * sizeof(int64_t));
         for (uint64_t n = 0; n < L; ++n) cnt[o->z[o->row[beg + n]]]++;
         ll += lgamma(alpha_bar) - lgamma(alpha_bar + (double)L);
-        for (uint32_t k = 0; k < o->K; ++k)
+        /* each distinct topic of the row once: add, then clear */
+        for (uint64_t n = 0; n < L; ++n) {
+            int32_t k = o->z[o->row[beg + n]];
             if (cnt[k]) ll += lgamma(o->alpha + (double)cnt[k]) - lgamma(o->alpha);
+            cnt[k] = 0;
+        }
     }
     for (uint32_t w = 0; w < o->V; ++w) {
         uint64_t beg = o->colptr[w], L = o->colptr[w + 1] - beg;
         if (L == 0) continue;
-        memset(cnt, 0, o->K * sizeof(int64_t));
         for (uint64_t n = 0; n < L; ++n) cnt[o->z[beg + n]]++;
-        for (uint32_t k = 0; k < o->K; ++k)
+        for (uint64_t n = 0; n < L; ++n) {
+            int32_t k = o->z[beg + n];
             if (cnt[k]) ll += lgamma(o->beta + (double)cnt[k]) - lgamma(o->beta);
+            cnt[k] = 0;
+        }
     }
     memset(cnt, 0, o->K * sizeof(int64_t));
     for (uint64_t t = 0; t < o->T; ++t) cnt[o->z[t]]++;

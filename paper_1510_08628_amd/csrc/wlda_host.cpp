@@ -21,13 +21,15 @@ inline uint64_t align_up(uint64_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
 
 struct PhasePlan {
     std::vector<uint32_t> wave_ids, block_ids, long_ids, long_prefix;
-    std::vector<uint32_t> chunk_seg, chunk_start;
+    std::vector<uint32_t> chunk_seg, chunk_start, tab_cap;
+    std::vector<uint64_t> tab_off;          // n+1 word offsets of the per-segment tables
     uint32_t wave_cut[9] = {}, block_cut[9] = {}, chunk_cut[9] = {};
     // device copies (inside the workspace)
     uint32_t *d_wave_ids = nullptr, *d_wave_cut = nullptr, *d_block_ids = nullptr,
              *d_block_cut = nullptr, *d_long_ids = nullptr, *d_long_prefix = nullptr,
              *d_tables = nullptr, *d_chunk_seg = nullptr, *d_chunk_start = nullptr,
-             *d_chunk_cut = nullptr;
+             *d_chunk_cut = nullptr, *d_tab_cap = nullptr;
+    uint64_t *d_tab_off = nullptr;
     void *d_zc = nullptr;
 };
 
@@ -47,7 +49,13 @@ void xcd_cuts(const std::vector<uint32_t> &ids, const std::vector<uint64_t> &len
     cut[8] = (uint32_t)ids.size();
 }
 
-void build_plan(const std::vector<uint64_t> &len, uint32_t block_max, PhasePlan &pl) {
+uint32_t pow2_ge(uint64_t x) {
+    uint64_t c = 1;
+    while (c < x) c <<= 1;
+    return (uint32_t)c;
+}
+
+void build_plan(const std::vector<uint64_t> &len, uint32_t block_max, uint32_t K, PhasePlan &pl) {
     pl.wave_ids.clear();
     pl.block_ids.clear();
     pl.long_ids.clear();
@@ -117,6 +125,21 @@ void build_plan(const std::vector<uint64_t> &len, uint32_t block_max, PhasePlan 
         }
     }
     pl.chunk_cut[8] = (uint32_t)pl.chunk_seg.size();
+    // global count tables of the long segments: dense K counts when K is
+    // small or the table would reach K slots, else open addressing with the
+    // smallest power of two >= 2L slots (Section 5.4's hash tables)
+    pl.tab_off.assign(1, 0);
+    pl.tab_cap.clear();
+    for (uint32_t j = 0; j < n; ++j) {
+        const uint64_t L = len[pl.long_ids[j]];
+        uint32_t cap = 0;
+        if (K > Tuning::LDS_DENSE_MAX) {
+            const uint32_t c = pow2_ge(std::min<uint64_t>(K, 2 * L));
+            if (c < K) cap = c;
+        }
+        pl.tab_cap.push_back(cap);
+        pl.tab_off.push_back(pl.tab_off.back() + (cap ? 2ull * cap : (uint64_t)K));
+    }
 }
 
 inline uint64_t zc_bytes(const PhasePlan &pl, uint32_t K) {
@@ -133,7 +156,8 @@ uint64_t plan_bytes(const PhasePlan &pl, uint32_t K) {
     return align_up(4ull * pl.wave_ids.size() + 4) + align_up(9 * 4) +
            align_up(4ull * pl.block_ids.size() + 4) + align_up(9 * 4) +
            align_up(4ull * pl.long_ids.size() + 4) + align_up(4ull * pl.long_prefix.size()) +
-           align_up(4ull * pl.long_ids.size() * K + 4) + 2 * align_up(4ull * pl.chunk_seg.size() + 4) +
+           align_up(4ull * pl.tab_off.back() + 4) + align_up(8ull * pl.tab_off.size()) +
+           align_up(4ull * pl.tab_cap.size() + 4) + 2 * align_up(4ull * pl.chunk_seg.size() + 4) +
            align_up(9 * 4) + align_up(zc_bytes(pl, K));
 }
 
@@ -248,7 +272,9 @@ hipError_t place_plan(PhasePlan &pl, uint8_t *&cur, uint32_t K, hipStream_t st) 
     pl.d_block_cut = (uint32_t *)carve(cur, 9 * 4);
     pl.d_long_ids = (uint32_t *)carve(cur, 4ull * pl.long_ids.size() + 4);
     pl.d_long_prefix = (uint32_t *)carve(cur, 4ull * pl.long_prefix.size());
-    pl.d_tables = (uint32_t *)carve(cur, 4ull * pl.long_ids.size() * K + 4);
+    pl.d_tables = (uint32_t *)carve(cur, 4ull * pl.tab_off.back() + 4);
+    pl.d_tab_off = (uint64_t *)carve(cur, 8ull * pl.tab_off.size());
+    pl.d_tab_cap = (uint32_t *)carve(cur, 4ull * pl.tab_cap.size() + 4);
     pl.d_chunk_seg = (uint32_t *)carve(cur, 4ull * pl.chunk_seg.size() + 4);
     pl.d_chunk_start = (uint32_t *)carve(cur, 4ull * pl.chunk_seg.size() + 4);
     pl.d_chunk_cut = (uint32_t *)carve(cur, 9 * 4);
@@ -257,6 +283,8 @@ hipError_t place_plan(PhasePlan &pl, uint8_t *&cur, uint32_t K, hipStream_t st) 
     if ((e = upload(pl.d_chunk_seg, pl.chunk_seg.data(), 4ull * pl.chunk_seg.size(), st))) return e;
     if ((e = upload(pl.d_chunk_start, pl.chunk_start.data(), 4ull * pl.chunk_start.size(), st))) return e;
     if ((e = upload(pl.d_chunk_cut, pl.chunk_cut, 9 * 4, st))) return e;
+    if ((e = upload(pl.d_tab_off, pl.tab_off.data(), 8ull * pl.tab_off.size(), st))) return e;
+    if ((e = upload(pl.d_tab_cap, pl.tab_cap.data(), 4ull * pl.tab_cap.size(), st))) return e;
     if ((e = upload(pl.d_wave_ids, pl.wave_ids.data(), 4ull * pl.wave_ids.size(), st))) return e;
     if ((e = upload(pl.d_wave_cut, pl.wave_cut, 9 * 4, st))) return e;
     if ((e = upload(pl.d_block_ids, pl.block_ids.data(), 4ull * pl.block_ids.size(), st))) return e;
@@ -264,7 +292,8 @@ hipError_t place_plan(PhasePlan &pl, uint8_t *&cur, uint32_t K, hipStream_t st) 
     if ((e = upload(pl.d_long_ids, pl.long_ids.data(), 4ull * pl.long_ids.size(), st))) return e;
     if ((e = upload(pl.d_long_prefix, pl.long_prefix.data(), 4ull * pl.long_prefix.size(), st)))
         return e;
-    return launch_fill_u32(pl.d_tables, 0, (uint64_t)pl.long_ids.size() * K, st);
+    (void)K;
+    return launch_fill_u32(pl.d_tables, 0, pl.tab_off.back(), st);
 }
 
 hipError_t take_event(wlda_sampler s, hipEvent_t *e) {
@@ -292,6 +321,24 @@ hipError_t timed(wlda_sampler s, int slot, F &&launch) {
     return hipSuccess;
 }
 
+LongList long_list(const PhasePlan &pl) {
+    LongList ll;
+    ll.ids = pl.d_long_ids;
+    ll.prefix = pl.d_long_prefix;
+    ll.n = (uint32_t)pl.long_ids.size();
+    ll.total = pl.long_prefix.back();
+    ll.tables = pl.d_tables;
+    ll.chunk_seg = pl.d_chunk_seg;
+    ll.chunk_start = pl.d_chunk_start;
+    ll.n_chunks = (uint32_t)pl.chunk_seg.size();
+    ll.chunk_cut = pl.d_chunk_cut;
+    ll.zc = pl.d_zc;
+    ll.tab_off = pl.d_tab_off;
+    ll.tab_cap = pl.d_tab_cap;
+    ll.table_words = pl.tab_off.back();
+    return ll;
+}
+
 // One phase: every segment of the phase's plan, c_k of the new Z into the
 // other buffer, then swap.
 wlda_status run_phase(wlda_sampler s, uint32_t phase, uint32_t iter, bool draw_only) {
@@ -315,17 +362,7 @@ wlda_status run_phase(wlda_sampler s, uint32_t phase, uint32_t iter, bool draw_o
     WLDA_TRY(s, launch_fill_u32((uint32_t *)a.accepted, 0, 2, s->st));
     SegList wl{pl.d_wave_ids, (uint32_t)pl.wave_ids.size(), pl.d_wave_cut};
     SegList bl{pl.d_block_ids, (uint32_t)pl.block_ids.size(), pl.d_block_cut};
-    LongList ll;
-    ll.ids = pl.d_long_ids;
-    ll.prefix = pl.d_long_prefix;
-    ll.n = (uint32_t)pl.long_ids.size();
-    ll.total = pl.long_prefix.back();
-    ll.tables = pl.d_tables;
-    ll.chunk_seg = pl.d_chunk_seg;
-    ll.chunk_start = pl.d_chunk_start;
-    ll.n_chunks = (uint32_t)pl.chunk_seg.size();
-    ll.chunk_cut = pl.d_chunk_cut;
-    ll.zc = pl.d_zc;
+    LongList ll = long_list(pl);
     const int base = phase == PH_WORD ? S_WORD_WAVE : S_DOC_WAVE;
     const bool prof = s->prof && !draw_only;
     if (prof) {
@@ -394,8 +431,8 @@ wlda_status wlda_workspace_bytes(const wlda_params *p, const uint32_t *word_ids,
     std::vector<uint64_t> lw, ld;
     lengths(*p, word_ids, doc_ids, n_tokens, lw, ld);
     PhasePlan w, d;
-    build_plan(lw, block_max_tokens(p->M), w);
-    build_plan(ld, block_max_tokens(p->M), d);
+    build_plan(lw, block_max_tokens(p->M), p->K, w);
+    build_plan(ld, block_max_tokens(p->M), p->K, d);
     *bytes = compute_sizes(*p, n_tokens, w, d).total;
     return WLDA_OK;
 }
@@ -423,8 +460,8 @@ wlda_status wlda_create(const wlda_params *p, const uint32_t *word_ids, const ui
     // ---- layout: stable order by (word, doc, input index) -------------------
     std::vector<uint64_t> lw, ld;
     lengths(*p, word_ids, doc_ids, T, lw, ld);
-    build_plan(lw, block_max_tokens(p->M), s->word);
-    build_plan(ld, block_max_tokens(p->M), s->doc);
+    build_plan(lw, block_max_tokens(p->M), p->K, s->word);
+    build_plan(ld, block_max_tokens(p->M), p->K, s->doc);
     s->slot_tokens[S_WORD_WAVE] = list_tokens(s->word.wave_ids, lw);
     s->slot_tokens[S_WORD_BLOCK] = list_tokens(s->word.block_ids, lw);
     s->slot_tokens[S_WORD_LONG_HIST] = s->slot_tokens[S_WORD_LONG_MH] =
@@ -546,10 +583,24 @@ wlda_status wlda_log_likelihood(wlda_sampler s, double *ll) {
     if (s->next_phase == 0) return WLDA_E_STATE;
     const uint32_t K = s->p.K;
     WLDA_TRY(s, launch_fill_u32((uint32_t *)s->ll, 0, 2, s->st));
-    WLDA_TRY(s, launch_ll_segments(s->recs, s->p.M, s->rowptr, s->rowpos, s->p.D, K, s->p.alpha,
-                                   (double)K * s->p.alpha, 1, s->ll, s->st));
-    WLDA_TRY(s, launch_ll_segments(s->recs, s->p.M, s->colptr, nullptr, s->p.V, K, s->p.beta, 0.0, 0,
-                                   s->ll, s->st));
+    for (int ph = PH_WORD; ph <= PH_DOC; ++ph) {
+        const PhasePlan &pl = ph == PH_WORD ? s->word : s->doc;
+        const uint32_t *segptr = ph == PH_WORD ? s->colptr : s->rowptr;
+        const uint32_t *rowpos = ph == PH_WORD ? nullptr : s->rowpos;
+        const double prior = ph == PH_WORD ? s->p.beta : s->p.alpha;
+        const double total = ph == PH_WORD ? 0.0 : (double)K * s->p.alpha;
+        const int lt = ph == PH_DOC;
+        WLDA_TRY(s, launch_ll_list(s->recs, s->p.M, segptr, rowpos, pl.d_wave_ids,
+                                   (uint32_t)pl.wave_ids.size(), K, prior, total, lt, s->ll, s->st));
+        WLDA_TRY(s, launch_ll_list(s->recs, s->p.M, segptr, rowpos, pl.d_block_ids,
+                                   (uint32_t)pl.block_ids.size(), K, prior, total, lt, s->ll, s->st));
+        PhaseArgs a;
+        a.recs = s->recs;
+        a.segptr = segptr;
+        a.rowpos = rowpos;
+        a.K = K;
+        WLDA_TRY(s, launch_ll_long(a, ph, s->p.M, long_list(pl), prior, total, lt, s->ll, s->st));
+    }
     WLDA_TRY(s, launch_ll_topics(s->ck[s->cur], K, (double)s->p.V * s->p.beta, s->ll, s->st));
     WLDA_TRY(s, hipMemcpyAsync(ll, s->ll, sizeof(double), hipMemcpyDeviceToHost, s->st));
     WLDA_TRY(s, hipStreamSynchronize(s->st));

@@ -37,7 +37,15 @@ struct LongList {
     const uint32_t *chunk_start = nullptr;  // per chunk: first token within the segment
     uint32_t n_chunks = 0;
     const uint32_t *chunk_cut = nullptr;    // 9 chunk-list offsets, one share per XCD
-    uint32_t *tables = nullptr;        // n x K counts (global)
+    // Per-segment counts in global memory: segment j owns the words
+    // tables[tab_off[j] ..); tab_cap[j] == 0 means dense (K counts), otherwise
+    // an open-addressed table of tab_cap[j] (power of two) slots laid out as
+    // tab_cap keys (topic + 1, 0 = empty) followed by tab_cap counts.  All-zero
+    // words are an empty table.
+    uint32_t *tables = nullptr;
+    const uint64_t *tab_off = nullptr;
+    const uint32_t *tab_cap = nullptr;
+    uint64_t table_words = 0;
     void *zc = nullptr;                // total compact topics (u16 if K <= 65535, else u32)
 };
 
@@ -66,6 +74,7 @@ struct Tuning {
     static constexpr uint32_t BLOCK_CAP = 2 * BLOCK_MAX;
     static constexpr uint32_t CK_LDS_MAX = 4096;             // block c_k histogram in LDS
     static constexpr uint32_t LONG_CHUNK = 4096;             // tokens per long-path chunk
+    static constexpr uint32_t LDS_DENSE_MAX = 16384;         // dense LDS counts up to this K
 };
 
 inline uint32_t block_max_tokens(uint32_t M) {
@@ -93,10 +102,15 @@ hipError_t launch_histogram_z(const uint64_t *recs, uint32_t T, uint32_t M, uint
 // LL: adds the document, word and topic parts into *out (binary64).
 // Per segment: sum over nonzero counts c of lgamma(prior + c) - lgamma(prior),
 // plus lgamma(prior_total) - lgamma(prior_total + L) when length_term != 0.
-hipError_t launch_ll_segments(const uint64_t *recs, uint32_t M, const uint32_t *segptr,
-                              const uint32_t *rowpos, uint32_t n_seg, uint32_t K,
-                              double prior, double prior_total, int length_term,
-                              double *out, hipStream_t st);
+// LL parts over the segments of a list (at most block_max tokens each) and
+// over the long segments (through their global tables, which are left zeroed).
+hipError_t launch_ll_list(const uint64_t *recs, uint32_t M, const uint32_t *segptr,
+                          const uint32_t *rowpos, const uint32_t *ids, uint32_t n, uint32_t K,
+                          double prior, double prior_total, int length_term, double *out,
+                          hipStream_t st);
+hipError_t launch_ll_long(const PhaseArgs &a, uint32_t phase, uint32_t M, const LongList &l,
+                          double prior, double prior_total, int length_term, double *out,
+                          hipStream_t st);
 hipError_t launch_theta(const uint64_t *recs, uint32_t M, const uint32_t *rowptr, const uint32_t *rowpos,
                         uint32_t d0, uint32_t nd, uint32_t K, float alpha, float *out, hipStream_t st);
 hipError_t launch_ll_topics(const uint32_t *ck, uint32_t K, double beta_bar, double *out,

@@ -328,41 +328,79 @@ __global__ __launch_bounds__(256) void seg_kernel(PhaseArgs a, SegList l, uint32
 // Each XCD owns whole segments, so a segment's compact array is read from
 // that XCD's L2.
 // --------------------------------------------------------------------------
+// Global per-segment counts (dense or open-addressed, keys stored as topic+1).
+__device__ __forceinline__ void gtab_add(const LongList &l, uint32_t j, uint32_t K, uint32_t k, uint32_t add) {
+    uint32_t *base = l.tables + l.tab_off[j];
+    const uint32_t cap = l.tab_cap[j];
+    if (cap == 0) {
+        atomicAdd(&base[k], add);
+        return;
+    }
+    const uint32_t mask = cap - 1, key = k + 1;
+    uint32_t h = k & mask;
+    while (true) {
+        const uint32_t old = atomicCAS(&base[h], 0u, key);
+        if (old == 0u || old == key) {
+            atomicAdd(&base[cap + h], add);
+            return;
+        }
+        h = (h + 1) & mask;
+    }
+}
+
+__device__ __forceinline__ uint32_t gtab_get(const uint32_t *base, uint32_t cap, uint32_t k) {
+    if (cap == 0) return base[k];
+    const uint32_t mask = cap - 1, key = k + 1;
+    uint32_t h = k & mask;
+    while (true) {
+        const uint32_t kk = base[h];
+        if (kk == key) return base[cap + h];
+        if (kk == 0u) return 0u;
+        h = (h + 1) & mask;
+    }
+}
+
 #define WLDA_FOR_CHUNKS(l)                                                        \
     const uint32_t xcd_ = blockIdx.x & 7, nbx_ = gridDim.x >> 3;                 \
     for (uint32_t ci = (l).chunk_cut[xcd_] + (blockIdx.x >> 3); ci < (l).chunk_cut[xcd_ + 1]; \
          ci += nbx_)
 
 template <int PHASE, int NW>
-__global__ __launch_bounds__(256) void long_hist_kernel(PhaseArgs a, LongList l, uint32_t lds_hist) {
+__global__ __launch_bounds__(256) void long_hist_kernel(PhaseArgs a, LongList l, uint32_t lds_dense) {
     extern __shared__ uint32_t hist[];
     const uint32_t K = a.K;
+    // LDS: dense K counts, or an open-addressed table of 2 * LONG_CHUNK slots
+    constexpr uint32_t HCAP = 2 * Tuning::LONG_CHUNK;
+    uint32_t *hkey = hist, *hcnt = hist + HCAP;
     WLDA_FOR_CHUNKS(l) {
         const uint32_t j = l.chunk_seg[ci], n0 = l.chunk_start[ci];
         const uint32_t s_id = l.ids[j];
         const uint32_t beg = a.segptr[s_id], L = a.segptr[s_id + 1] - beg;
         const uint32_t n1 = min(L, n0 + Tuning::LONG_CHUNK);
-        uint32_t *gt = l.tables + (size_t)j * K;
-        if (lds_hist) {
+        if (lds_dense) {
             for (uint32_t k = threadIdx.x; k < K; k += 256) hist[k] = 0;
-            __syncthreads();
+        } else {
+            for (uint32_t k = threadIdx.x; k < HCAP; k += 256) hkey[k] = EMPTY_KEY, hcnt[k] = 0;
         }
+        __syncthreads();
         for (uint32_t n = n0 + threadIdx.x; n < n1; n += 256) {
             const uint32_t pos = PHASE == PH_DOC ? a.rowpos[beg + n] : beg + n;
             const uint32_t z = fld(ld_rec<NW>(a.recs, pos), 0);
-            if (lds_hist)
-                atomicAdd(&hist[z], 1u);
-            else
-                atomicAdd(&gt[z], 1u);
+            tab_insert(hkey, lds_dense ? hist : hcnt, HCAP - 1, lds_dense != 0, z);
         }
-        if (lds_hist) {
-            __syncthreads();
+        __syncthreads();
+        if (lds_dense) {
             for (uint32_t k = threadIdx.x; k < K; k += 256) {
                 const uint32_t c = hist[k];
-                if (c) atomicAdd(&gt[k], c);
+                if (c) gtab_add(l, j, K, k, c);
             }
-            __syncthreads();
+        } else {
+            for (uint32_t k = threadIdx.x; k < HCAP; k += 256) {
+                const uint32_t c = hcnt[k];
+                if (c) gtab_add(l, j, K, hkey[k], c);
+            }
         }
+        __syncthreads();
     }
 }
 
@@ -379,7 +417,8 @@ __global__ __launch_bounds__(256) void long_mh_kernel(PhaseArgs a, LongList l, u
         const uint32_t beg = a.segptr[s_id], L = a.segptr[s_id + 1] - beg;
         const uint32_t n1 = min(L, n0 + Tuning::LONG_CHUNK);
         const uint32_t zbase = l.prefix[j];
-        const uint32_t *gt = l.tables + (size_t)j * K;
+        const uint32_t *gt = l.tables + l.tab_off[j];
+        const uint32_t gcap = l.tab_cap[j];
         if (a.draw_only) {     // initial draw: only publish z for random positioning
             for (uint32_t n = n0 + threadIdx.x; n < n1; n += 256) {
                 const uint32_t pos = PHASE == PH_DOC ? a.rowpos[beg + n] : beg + n;
@@ -392,6 +431,7 @@ __global__ __launch_bounds__(256) void long_mh_kernel(PhaseArgs a, LongList l, u
             __syncthreads();
         }
         const uint32_t *ct = lds_tab ? tab : gt;
+        const uint32_t ccap = lds_tab ? 0u : gcap;
         for (uint32_t n = n0 + threadIdx.x; n < n1; n += 256) {
             const uint32_t pos = PHASE == PH_DOC ? a.rowpos[beg + n] : beg + n;
             Rec<NW> rec = ld_rec<NW>(a.recs, pos);
@@ -400,7 +440,8 @@ __global__ __launch_bounds__(256) void long_mh_kernel(PhaseArgs a, LongList l, u
             for (int i = 1; i <= M; ++i) {
                 const uint4 R = philox(pos, a.iter, ph | i, 0, a.seed_lo, a.seed_hi);
                 const uint32_t c = fld(rec, i);
-                if (mh_accept(unif24(R.x), ct[c], ct[s], a.prior, a.ck[s], a.ck[c], a.beta_bar)) {
+                if (mh_accept(unif24(R.x), gtab_get(ct, ccap, c), gtab_get(ct, ccap, s), a.prior, a.ck[s],
+                              a.ck[c], a.beta_bar)) {
                     s = c;
                     ++acc;
                 }
@@ -451,7 +492,7 @@ __global__ __launch_bounds__(256) void long_draw_kernel(PhaseArgs a, LongList l,
         }
     }
     if (zero_tables) {
-        const size_t nt = (size_t)l.n * K;
+        const size_t nt = l.table_words;
         for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < nt; i += (size_t)gridDim.x * 256)
             l.tables[i] = 0;
     }
@@ -519,7 +560,7 @@ __global__ void histogram_z_kernel(const uint64_t *recs, uint32_t T, uint32_t *c
 // Log joint likelihood (Section 6.1), binary64.  One workgroup per segment,
 // dense LDS counts (K <= LL_DENSE_MAX).
 // --------------------------------------------------------------------------
-constexpr uint32_t LL_DENSE_MAX = 16384;
+constexpr uint32_t LL_DENSE_MAX = Tuning::LDS_DENSE_MAX;
 
 __device__ double block_sum(double v) {
     __shared__ double part[4];
@@ -533,33 +574,67 @@ __device__ double block_sum(double v) {
     return s;
 }
 
+// One workgroup per listed segment: counts in LDS (dense for K <=
+// LDS_DENSE_MAX, else an open-addressed table of pow2 >= 2L slots).
 template <int NW>
 __global__ __launch_bounds__(256) void ll_seg_kernel(const uint64_t *recs, const uint32_t *segptr,
-                                                     const uint32_t *rowpos, uint32_t n_seg,
-                                                     uint32_t K, double prior, double prior_total,
+                                                     const uint32_t *rowpos, const uint32_t *ids,
+                                                     uint32_t n_seg, uint32_t K, uint32_t dense_u,
+                                                     double prior, double prior_total,
                                                      int length_term, double *out) {
     extern __shared__ uint32_t cnt[];
+    const bool dense = dense_u != 0;
     const double lg_prior = lgamma(prior), lg_total = lgamma(prior_total);
     double acc = 0;
-    for (uint32_t s = blockIdx.x; s < n_seg; s += gridDim.x) {
+    for (uint32_t li = blockIdx.x; li < n_seg; li += gridDim.x) {
+        const uint32_t s = ids[li];
         const uint32_t beg = segptr[s], L = segptr[s + 1] - beg;
-        if (L == 0) continue;
-        for (uint32_t k = threadIdx.x; k < K; k += 256) cnt[k] = 0;
+        const uint32_t cap = dense ? K : pow2_at_least(2 * L);
+        uint32_t *key = cnt, *c = dense ? cnt : cnt + cap;
+        for (uint32_t k = threadIdx.x; k < cap; k += 256) {
+            c[k] = 0;
+            if (!dense) key[k] = EMPTY_KEY;
+        }
         __syncthreads();
         for (uint32_t n = threadIdx.x; n < L; n += 256) {
             const uint32_t pos = rowpos ? rowpos[beg + n] : beg + n;
-            atomicAdd(&cnt[fld(ld_rec<NW>(recs, pos), 0)], 1u);
+            tab_insert(key, c, cap - 1, dense, fld(ld_rec<NW>(recs, pos), 0));
         }
         __syncthreads();
-        for (uint32_t k = threadIdx.x; k < K; k += 256) {
-            const uint32_t c = cnt[k];
-            if (c) acc += lgamma(prior + (double)c) - lg_prior;
+        for (uint32_t k = threadIdx.x; k < cap; k += 256) {
+            const uint32_t v = c[k];
+            if (v) acc += lgamma(prior + (double)v) - lg_prior;
         }
         if (length_term && threadIdx.x == 0) acc += lg_total - lgamma(prior_total + (double)L);
         __syncthreads();
     }
-    const double s = block_sum(acc);
-    if (threadIdx.x == 0) atomicAdd(out, s);
+    const double sum = block_sum(acc);
+    if (threadIdx.x == 0) atomicAdd(out, sum);
+}
+
+// LL part of the long segments from their global tables (filled by the
+// histogram pass); the tables are zeroed afterwards.
+__global__ __launch_bounds__(256) void ll_tables_kernel(LongList l, const uint32_t *segptr, uint32_t K,
+                                                        double prior, double prior_total,
+                                                        int length_term, double *out) {
+    const double lg_prior = lgamma(prior), lg_total = lgamma(prior_total);
+    double acc = 0;
+    for (uint32_t j = blockIdx.x; j < l.n; j += gridDim.x) {
+        uint32_t *base = l.tables + l.tab_off[j];
+        const uint32_t cap = l.tab_cap[j];
+        const uint32_t nslots = cap ? cap : K;
+        uint32_t *c = cap ? base + cap : base;
+        for (uint32_t k = threadIdx.x; k < nslots; k += 256) {
+            const uint32_t v = c[k];
+            if (v) acc += lgamma(prior + (double)v) - lg_prior;
+        }
+        if (length_term && threadIdx.x == 0) {
+            const uint32_t s = l.ids[j];
+            acc += lg_total - lgamma(prior_total + (double)(segptr[s + 1] - segptr[s]));
+        }
+    }
+    const double sum = block_sum(acc);
+    if (threadIdx.x == 0) atomicAdd(out, sum);
 }
 
 // theta_hat of Eq. (4) (alpha' = alpha + 1): out[d - d0][k] =
@@ -693,14 +768,14 @@ template <int PHASE, int M, typename ZT>
 static hipError_t long_dispatch_z(const PhaseArgs &a, const LongList &l, hipStream_t st,
                                   hipEvent_t *ev) {
     constexpr int NW = (M + 3) / 3;
-    const bool lds_tab = a.K <= 16384;
+    const bool lds_tab = a.K <= Tuning::LDS_DENSE_MAX;
     const bool ck_lds = a.K <= Tuning::CK_LDS_MAX;
     uint32_t blocks = l.n_chunks < 2048 ? l.n_chunks : 2048;
     blocks = (blocks + 7) / 8 * 8;
     hipError_t e;
     if (ev && (e = hipEventRecord(ev[0], st)) != hipSuccess) return e;
     if (!a.draw_only) {
-        const size_t lds = lds_tab ? 4ull * a.K : 0;
+        const size_t lds = lds_tab ? 4ull * a.K : 4ull * 2 * 2 * Tuning::LONG_CHUNK;
         e = launch_dyn(long_hist_kernel<PHASE, NW>, dim3(1), lds, st);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL((long_hist_kernel<PHASE, NW>), dim3(blocks), dim3(256), lds, st, a, l,
@@ -774,26 +849,52 @@ hipError_t launch_histogram_z(const uint64_t *recs, uint32_t T, uint32_t M, uint
     return hipGetLastError();
 }
 
-hipError_t launch_ll_segments(const uint64_t *recs, uint32_t M, const uint32_t *segptr,
-                              const uint32_t *rowpos, uint32_t n_seg, uint32_t K, double prior,
-                              double prior_total, int length_term, double *out, hipStream_t st) {
-    if (n_seg == 0) return hipSuccess;
-    if (K > LL_DENSE_MAX) return hipErrorNotSupported;
-    const size_t lds = 4ull * K;
-    const int blocks = n_seg < 4096 ? (int)n_seg : 4096;
+hipError_t launch_ll_list(const uint64_t *recs, uint32_t M, const uint32_t *segptr, const uint32_t *rowpos,
+                          const uint32_t *ids, uint32_t n, uint32_t K, double prior, double prior_total,
+                          int length_term, double *out, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    const bool dense = K <= Tuning::LDS_DENSE_MAX;
+    const size_t lds = dense ? 4ull * K : 4ull * 2 * 2 * Tuning::BLOCK_MAX;
+    const int blocks = n < 4096 ? (int)n : 4096;
     hipError_t e;
     if (record_words(M) == 1) {
-        e = launch_dyn(ll_seg_kernel<1>, dim3(1), lds, st);
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(ll_seg_kernel<1>, dim3(blocks), dim3(256), lds, st, recs, segptr, rowpos,
-                           n_seg, K, prior, prior_total, length_term, out);
+        if ((e = launch_dyn(ll_seg_kernel<1>, dim3(1), lds, st))) return e;
+        hipLaunchKernelGGL(ll_seg_kernel<1>, dim3(blocks), dim3(256), lds, st, recs, segptr, rowpos, ids, n, K,
+                           (uint32_t)dense, prior, prior_total, length_term, out);
     } else {
-        e = launch_dyn(ll_seg_kernel<2>, dim3(1), lds, st);
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(ll_seg_kernel<2>, dim3(blocks), dim3(256), lds, st, recs, segptr, rowpos,
-                           n_seg, K, prior, prior_total, length_term, out);
+        if ((e = launch_dyn(ll_seg_kernel<2>, dim3(1), lds, st))) return e;
+        hipLaunchKernelGGL(ll_seg_kernel<2>, dim3(blocks), dim3(256), lds, st, recs, segptr, rowpos, ids, n, K,
+                           (uint32_t)dense, prior, prior_total, length_term, out);
     }
     return hipGetLastError();
+}
+
+template <int PHASE, int M>
+static hipError_t ll_long_dispatch(const PhaseArgs &a, const LongList &l, double prior, double prior_total,
+                                   int length_term, double *out, hipStream_t st) {
+    constexpr int NW = (M + 3) / 3;
+    if (l.n == 0) return hipSuccess;
+    const bool lds_dense = a.K <= Tuning::LDS_DENSE_MAX;
+    uint32_t blocks = l.n_chunks < 2048 ? l.n_chunks : 2048;
+    blocks = (blocks + 7) / 8 * 8;
+    const size_t lds = lds_dense ? 4ull * a.K : 4ull * 2 * 2 * Tuning::LONG_CHUNK;
+    hipError_t e = launch_dyn(long_hist_kernel<PHASE, NW>, dim3(1), lds, st);
+    if (e) return e;
+    hipLaunchKernelGGL((long_hist_kernel<PHASE, NW>), dim3(blocks), dim3(256), lds, st, a, l,
+                       (uint32_t)lds_dense);
+    if ((e = hipGetLastError())) return e;
+    hipLaunchKernelGGL(ll_tables_kernel, dim3(l.n < 1024 ? l.n : 1024), dim3(256), 0, st, l, a.segptr, a.K,
+                       prior, prior_total, length_term, out);
+    if ((e = hipGetLastError())) return e;
+    return launch_fill_u32(l.tables, 0, l.table_words, st);
+}
+
+hipError_t launch_ll_long(const PhaseArgs &a, uint32_t phase, uint32_t M, const LongList &l, double prior,
+                          double prior_total, int length_term, double *out, hipStream_t st) {
+    if (phase == PH_WORD) {
+        WLDA_DISPATCH_M(ll_long_dispatch, PH_WORD, a, l, prior, prior_total, length_term, out, st)
+    }
+    WLDA_DISPATCH_M(ll_long_dispatch, PH_DOC, a, l, prior, prior_total, length_term, out, st)
 }
 
 hipError_t launch_theta(const uint64_t *recs, uint32_t M, const uint32_t *rowptr, const uint32_t *rowpos,
