@@ -5,6 +5,8 @@
 
 #include <algorithm>
 #include <cstdint>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -237,6 +239,10 @@ struct wlda_sampler_s {
     std::vector<hipEvent_t> ev_pool;
     size_t ev_used = 0;
     uint64_t slot_tokens[KSLOTS] = {};
+    // launch-shape bounds (grid size of the segment kernels), per phase and
+    // kernel kind: [word wave, word block, doc wave, doc block]; overridable
+    // with WLDA_SEG_BLOCKS="a,b,c,d" for tuning sweeps
+    uint32_t seg_blocks[4] = {1024, 1024, 2048, 2048};
 };
 
 namespace {
@@ -360,13 +366,16 @@ wlda_status run_phase(wlda_sampler s, uint32_t phase, uint32_t iter, bool draw_o
     a.draw_only = draw_only ? 1 : 0;
     WLDA_TRY(s, launch_fill_u32(a.ck_next, 0, s->p.K, s->st));
     WLDA_TRY(s, launch_fill_u32((uint32_t *)a.accepted, 0, 2, s->st));
+    const int kb = phase == PH_WORD ? 0 : 2;
     SegList wl{pl.d_wave_ids, (uint32_t)pl.wave_ids.size(), pl.d_wave_cut};
     SegList bl{pl.d_block_ids, (uint32_t)pl.block_ids.size(), pl.d_block_cut};
     LongList ll = long_list(pl);
     const int base = phase == PH_WORD ? S_WORD_WAVE : S_DOC_WAVE;
     const bool prof = s->prof && !draw_only;
     if (prof) {
+        a.max_blocks = s->seg_blocks[kb];
         WLDA_TRY(s, timed(s, base + 0, [&] { return launch_wave_segments(a, phase, s->p.M, wl, s->st); }));
+        a.max_blocks = s->seg_blocks[kb + 1];
         WLDA_TRY(s, timed(s, base + 1, [&] { return launch_block_segments(a, phase, s->p.M, bl, s->st); }));
         if (ll.n) {
             hipEvent_t ev[4];
@@ -375,7 +384,9 @@ wlda_status run_phase(wlda_sampler s, uint32_t phase, uint32_t iter, bool draw_o
             for (int i = 0; i < 3; ++i) s->ev_pairs[base + 2 + i].push_back({ev[i], ev[i + 1]});
         }
     } else {
+        a.max_blocks = s->seg_blocks[kb];
         WLDA_TRY(s, launch_wave_segments(a, phase, s->p.M, wl, s->st));
+        a.max_blocks = s->seg_blocks[kb + 1];
         WLDA_TRY(s, launch_block_segments(a, phase, s->p.M, bl, s->st));
         WLDA_TRY(s, launch_long_segments(a, phase, s->p.M, ll, s->st));
     }
@@ -456,6 +467,11 @@ wlda_status wlda_create(const wlda_params *p, const uint32_t *word_ids, const ui
     s->alpha_bar = (float)p->K * s->a;
     s->beta_k = (float)p->K * s->b;
     s->beta_bar = (float)p->V * s->b;
+    if (const char *env = std::getenv("WLDA_SEG_BLOCKS")) {
+        unsigned v[4];
+        if (std::sscanf(env, "%u,%u,%u,%u", &v[0], &v[1], &v[2], &v[3]) == 4)
+            for (int i = 0; i < 4; ++i) s->seg_blocks[i] = v[i] < 8 ? 8 : (v[i] > 65536 ? 65536 : v[i]);
+    }
 
     // ---- layout: stable order by (word, doc, input index) -------------------
     std::vector<uint64_t> lw, ld;

@@ -61,6 +61,7 @@ struct PhaseArgs {
     float beta_bar = 0.f;              // V beta
     unsigned long long *accepted = nullptr;
     uint32_t draw_only = 0;            // initial proposal draw (no MH)
+    uint32_t max_blocks = 2048;        // grid bound of the segment kernels (launch shape only)
 };
 
 struct Tuning {

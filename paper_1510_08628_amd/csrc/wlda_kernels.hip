@@ -719,7 +719,8 @@ static hipError_t run_seg(const PhaseArgs &a, const SegList &l, uint32_t cap_bou
     // Blocks are assigned to XCDs round robin; use a multiple of 8 and
     // enough groups to keep every CU busy, never more than the list needs.
     uint32_t blocks = (l.n + GPB - 1) / GPB;
-    blocks = blocks < 2048 ? blocks : 2048;
+    const uint32_t cap_blocks = a.max_blocks >= 8 ? a.max_blocks : 8;
+    blocks = blocks < cap_blocks ? blocks : cap_blocks;
     blocks = (blocks + 7) / 8 * 8;
     hipLaunchKernelGGL(kern, dim3(blocks), dim3(256), lds, st, a, l, cap_max, (uint32_t)dense,
                        (uint32_t)ck_lds);
