@@ -37,7 +37,11 @@
  *   - all acceptance and coin arithmetic is IEEE binary32 with the exact
  *     expressions below, no fused multiply-add, strict "<";
  *   - randomness is Philox4x32-10 (Salmon et al., SC'11), one call per
- *     (token, iteration, phase, step) with the counter layout of rng_call().
+ *     (token, iteration, phase, step) with the counter layout of rng_call();
+ *     the token index is the token's position in the order its phase visits
+ *     it: the canonical column-major (CSC) position at initialisation and in
+ *     the word phase, the canonical row-major (CSR) position, rowptr[d] + n,
+ *     in the doc phase.  Neither depends on how an implementation stores Y.
  *
  * Build: gcc -O2 -std=c99 -ffp-contract=off -fno-fast-math -shared -fPIC
  */
@@ -255,7 +259,7 @@ static void draw_doc_proposals(oracle_t *o, uint32_t d, uint32_t iter)
         uint32_t t = o->row[beg + n];
         for (uint32_t i = 1; i <= o->M; ++i) {
             uint32_t r[4];
-            rng_call(o->seed, t, iter, PH_DOC, i, 0, r);
+            rng_call(o->seed, (uint32_t)(beg + n), iter, PH_DOC, i, 0, r);
             int32_t prop;
             if (take_count_part(unif24(r[1]), L, o->alpha_bar))
                 prop = o->z[o->row[beg + dice(r[2], (uint32_t)L)]];
@@ -365,7 +369,7 @@ static void doc_row(oracle_t *o, uint32_t d, uint32_t iter, int64_t *ck_next,
         int32_t s = o->z[t];
         for (uint32_t i = 1; i <= o->M; ++i) {
             uint32_t r[4];
-            rng_call(o->seed, t, iter, PH_DOC, i, 0, r);
+            rng_call(o->seed, (uint32_t)(beg + n), iter, PH_DOC, i, 0, r);
             int32_t c = o->prop[(uint64_t)(i - 1) * o->T + t];
             if (mh_accept(unif24(r[0]), cd[c], cd[s], o->a, o->ck[s],
                           o->ck[c], o->beta_bar)) {

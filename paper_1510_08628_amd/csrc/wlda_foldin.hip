@@ -25,41 +25,12 @@
 #include <vector>
 
 #include "../../include/warplda.h"
+#include "wlda_device.h"
 #include "wlda_fold.h"
 
 namespace wlda {
 
 enum FoldPhase : uint32_t { PH_F_INIT = 5, PH_F_WORD = 6, PH_F_DOC = 8, PH_F_LEARN = 9 };
-
-__device__ __forceinline__ uint4 fphilox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
-                                         uint32_t k0, uint32_t k1) {
-#pragma unroll
-    for (int round = 0; round < 10; ++round) {
-        const uint32_t hi_a = __umulhi(0xD2511F53u, c0), lo_a = 0xD2511F53u * c0;
-        const uint32_t hi_b = __umulhi(0xCD9E8D57u, c2), lo_b = 0xCD9E8D57u * c2;
-        const uint32_t n0 = hi_b ^ c1 ^ k0, n2 = hi_a ^ c3 ^ k1;
-        c0 = n0;
-        c1 = lo_b;
-        c2 = n2;
-        c3 = lo_a;
-        k0 += 0x9E3779B9u;
-        k1 += 0xBB67AE85u;
-    }
-    return make_uint4(c0, c1, c2, c3);
-}
-
-__device__ __forceinline__ float funif(uint32_t r) { return (float)(r >> 8) * 0x1p-24f; }
-__device__ __forceinline__ uint32_t fdice(uint32_t r, uint32_t n) { return __umulhi(r, n); }
-__device__ __forceinline__ bool fcoin(float u, uint32_t L, float mass) {
-    return u * ((float)L + mass) < (float)L;
-}
-__device__ __forceinline__ bool faccept(float u, uint32_t cnt_c, uint32_t cnt_s, float prior,
-                                        uint32_t ck_s, uint32_t ck_c, float beta_bar) {
-    const float num = ((float)cnt_c + prior) * ((float)ck_s + beta_bar);
-    const float den = ((float)cnt_s + prior) * ((float)ck_c + beta_bar);
-    return u * den < num;
-}
-
 
 __device__ __forceinline__ uint32_t cdf_draw(const uint32_t *cdf, uint32_t K, uint32_t r) {
     const uint32_t total = cdf[K - 1];
@@ -92,8 +63,8 @@ __global__ __launch_bounds__(256) void fold_sweep_kernel(FoldModel m, FoldBatch 
 
     if (s == 0) {
         for (uint32_t n = threadIdx.x; n < L; n += 256) {
-            const uint4 R = fphilox(n, 0, PH_F_INIT << 16, req, m.seed_lo, m.seed_hi);
-            zs[n] = qcdf ? cdf_draw(qcdf, K, R.z) : fdice(R.z, K);
+            const uint4 R = philox(n, 0, PH_F_INIT << 16, req, m.seed_lo, m.seed_hi);
+            zs[n] = qcdf ? cdf_draw(qcdf, K, R.z) : dice(R.z, K);
         }
         __syncthreads();
     } else {
@@ -104,11 +75,11 @@ __global__ __launch_bounds__(256) void fold_sweep_kernel(FoldModel m, FoldBatch 
             const uint32_t *cw = m.cwk + (size_t)w * K;
             uint32_t x = b.z[off + n];
             for (uint32_t i = 1; i <= M; ++i) {
-                const uint4 R = fphilox(n, s, (PH_F_WORD << 16) | i, req, m.seed_lo, m.seed_hi);
+                const uint4 R = philox(n, s, (PH_F_WORD << 16) | i, req, m.seed_lo, m.seed_hi);
                 const uint32_t c = b.pd[(size_t)(i - 1) * cap + off + n];
-                if (faccept(funif(R.x), cw[c], cw[x], m.b, m.ck[x], m.ck[c], m.beta_bar)) x = c;
+                if (mh_accept(unif24(R.x), cw[c], cw[x], m.b, m.ck[x], m.ck[c], m.beta_bar)) x = c;
                 b.pw[(size_t)(i - 1) * cap + off + n] =
-                    fcoin(funif(R.y), Lw, m.beta_k) ? (uint32_t)zc[cb + fdice(R.z, Lw)] : fdice(R.z, K);
+                    take_count_part(unif24(R.y), Lw, m.beta_k) ? (uint32_t)zc[cb + dice(R.z, Lw)] : dice(R.z, K);
             }
             zs[n] = x;
         }
@@ -121,15 +92,15 @@ __global__ __launch_bounds__(256) void fold_sweep_kernel(FoldModel m, FoldBatch 
         for (uint32_t n = threadIdx.x; n < L; n += 256) {
             uint32_t x = zs[n];
             for (uint32_t i = 1; i <= M; ++i) {
-                const uint4 R = fphilox(n, s, (PH_F_DOC << 16) | i, req, m.seed_lo, m.seed_hi);
+                const uint4 R = philox(n, s, (PH_F_DOC << 16) | i, req, m.seed_lo, m.seed_hi);
                 const uint32_t c = b.pw[(size_t)(i - 1) * cap + off + n];
-                if (faccept(funif(R.x), cd[c], cd[x], m.a, m.ck[x], m.ck[c], m.beta_bar)) x = c;
+                if (mh_accept(unif24(R.x), cd[c], cd[x], m.a, m.ck[x], m.ck[c], m.beta_bar)) x = c;
             }
             if (qcdf) {
                 const uint32_t w = b.words[off + n];
                 const uint32_t *cw = m.cwk + (size_t)w * K;
                 for (uint32_t j = 1; j <= b.learned_steps; ++j) {
-                    const uint4 R = fphilox(n, s, (PH_F_LEARN << 16) | j, req, m.seed_lo, m.seed_hi);
+                    const uint4 R = philox(n, s, (PH_F_LEARN << 16) | j, req, m.seed_lo, m.seed_hi);
                     const uint32_t t = cdf_draw(qcdf, K, R.z);
                     const float wx = (float)(qcdf[x] - (x ? qcdf[x - 1] : 0u));
                     const float wt = (float)(qcdf[t] - (t ? qcdf[t - 1] : 0u));
@@ -137,7 +108,7 @@ __global__ __launch_bounds__(256) void fold_sweep_kernel(FoldModel m, FoldBatch 
                                       ((float)m.ck[x] + m.beta_bar) * wx;
                     const float den = ((float)cd[x] + m.a) * ((float)cw[x] + m.b) *
                                       ((float)m.ck[t] + m.beta_bar) * wt;
-                    if (funif(R.x) * den < num) x = t;
+                    if (unif24(R.x) * den < num) x = t;
                 }
             }
             zs[n] = x;
@@ -147,9 +118,9 @@ __global__ __launch_bounds__(256) void fold_sweep_kernel(FoldModel m, FoldBatch 
     // doc proposals from the updated document; publish z
     for (uint32_t n = threadIdx.x; n < L; n += 256) {
         for (uint32_t i = 1; i <= M; ++i) {
-            const uint4 R = fphilox(n, s, (PH_F_DOC << 16) | i, req, m.seed_lo, m.seed_hi);
+            const uint4 R = philox(n, s, (PH_F_DOC << 16) | i, req, m.seed_lo, m.seed_hi);
             b.pd[(size_t)(i - 1) * cap + off + n] =
-                fcoin(funif(R.y), L, m.alpha_bar) ? zs[fdice(R.z, L)] : fdice(R.z, K);
+                take_count_part(unif24(R.y), L, m.alpha_bar) ? zs[dice(R.z, L)] : dice(R.z, K);
         }
         b.z[off + n] = zs[n];
     }

@@ -1,6 +1,7 @@
-// Host runtime of the WarpLDA sampler: input validation, the token layout
-// (Section 5.2), segment binning by length, workspace carving and the phase
-// schedule (Section 4.4, Algorithm 2).  Implements include/warplda.h.
+// Host runtime of the WarpLDA sampler: input validation, the canonical token
+// orders and the blocked record layout (Section 5.2), segment binning by
+// length, workspace carving and the phase schedule (Section 4.4, Algorithm 2).
+// Implements include/warplda.h.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -144,12 +145,62 @@ void build_plan(const std::vector<uint64_t> &len, uint32_t block_max, uint32_t K
     }
 }
 
+// ---- record layout ---------------------------------------------------------
+// Y is stored once (Section 5.2), by default in plain CSC order.  The
+// alternative built here blocks it by documents: documents, in the doc
+// phase's visiting order (each bin's
+// list, XCD share by XCD share), are cut into blocks of about `block_tokens`
+// tokens; a block never spans two bins or two XCD shares, and a long row is a
+// block of its own.  Inside a block the tokens are ordered by (word rank,
+// document, input index), the word rank being the word phase's visiting order
+// (bins and shares again).  So a doc-phase window gathers inside one or two
+// blocks that fit its XCD's L2, and one XCD's words occupy one contiguous run
+// of every block.  mem[t] receives the record position of CSC token t.
+void build_layout(const PhasePlan &wp, const PhasePlan &dp, const std::vector<uint64_t> &ld,
+                  const std::vector<uint32_t> &colptr, const std::vector<uint32_t> &doc_csc,
+                  uint64_t block_tokens, std::vector<uint32_t> &mem) {
+    std::vector<uint32_t> block_of(ld.size(), 0);
+    std::vector<uint64_t> start;   // block sizes, then running record offsets
+    auto cut = [&](const std::vector<uint32_t> &ids, uint32_t b, uint32_t e, bool own) {
+        uint64_t run = block_tokens;
+        for (uint32_t i = b; i < e; ++i) {
+            const uint32_t d = ids[i];
+            if (own || run >= block_tokens) {
+                start.push_back(0);
+                run = 0;
+            }
+            block_of[d] = (uint32_t)start.size() - 1;
+            start.back() += ld[d];
+            run += ld[d];
+        }
+    };
+    for (int x = 0; x < 8; ++x) cut(dp.wave_ids, dp.wave_cut[x], dp.wave_cut[x + 1], false);
+    for (int x = 0; x < 8; ++x) cut(dp.block_ids, dp.block_cut[x], dp.block_cut[x + 1], false);
+    cut(dp.long_ids, 0, (uint32_t)dp.long_ids.size(), true);
+    uint64_t off = 0;
+    for (uint64_t &v : start) {
+        const uint64_t n = v;
+        v = off;
+        off += n;
+    }
+    std::vector<uint32_t> words(wp.wave_ids);
+    words.insert(words.end(), wp.block_ids.begin(), wp.block_ids.end());
+    std::vector<char> seen(wp.long_ids.size(), 0);
+    for (uint32_t j : wp.chunk_seg)
+        if (!seen[j]) {
+            seen[j] = 1;
+            words.push_back(wp.long_ids[j]);
+        }
+    for (uint32_t w : words)
+        for (uint32_t t = colptr[w]; t < colptr[w + 1]; ++t) mem[t] = (uint32_t)start[block_of[doc_csc[t]]]++;
+}
+
 inline uint64_t zc_bytes(const PhasePlan &pl, uint32_t K) {
     return (uint64_t)pl.long_prefix.back() * (K <= 65535 ? 2 : 4) + 4;
 }
 
 struct Sizes {
-    uint64_t recs, colptr, rowptr, rowpos, ck, misc;
+    uint64_t recs, colptr, rowptr, colidx, rowidx, ck, misc;
     uint64_t plan_word, plan_doc;
     uint64_t total;
 };
@@ -168,12 +219,13 @@ Sizes compute_sizes(const wlda_params &p, uint64_t T, const PhasePlan &w, const 
     s.recs = align_up(T * 8ull * record_words(p.M) + 16);
     s.colptr = align_up(4ull * (p.V + 1));
     s.rowptr = align_up(4ull * (p.D + 1));
-    s.rowpos = align_up(4ull * T + 4);
+    s.colidx = align_up(4ull * T + 4);
+    s.rowidx = align_up(4ull * T + 4);
     s.ck = 2 * align_up(4ull * p.K);
     s.misc = ALIGN;
     s.plan_word = plan_bytes(w, p.K);
     s.plan_doc = plan_bytes(d, p.K);
-    s.total = s.recs + s.colptr + s.rowptr + s.rowpos + s.ck + s.misc + s.plan_word + s.plan_doc;
+    s.total = s.recs + s.colptr + s.rowptr + s.colidx + s.rowidx + s.ck + s.misc + s.plan_word + s.plan_doc;
     return s;
 }
 
@@ -222,13 +274,16 @@ struct wlda_sampler_s {
     hipStream_t st = nullptr;
     int nw = 1;
     uint64_t *recs = nullptr;
-    uint32_t *colptr = nullptr, *rowptr = nullptr, *rowpos = nullptr;
+    uint32_t *colptr = nullptr, *rowptr = nullptr;
+    uint32_t *colidx = nullptr, *rowidx = nullptr;   // canonical position -> record
     uint32_t *ck[2] = {nullptr, nullptr};
     int cur = 0;
     unsigned long long *acc = nullptr;   // [0] word phase, [1] doc phase
     double *ll = nullptr;
     PhasePlan word, doc;
-    std::vector<uint32_t> inv;           // input index -> canonical position
+    std::vector<uint32_t> inv;           // input index -> record position
+    std::vector<uint32_t> mem;           // canonical CSC position -> record position
+    bool blocked = false;                // records blocked by documents (else CSC order)
     uint32_t iter = 0;
     int next_phase = 0;                  // 0: not initialised, 1: word, 2: doc
     bool broken = false;
@@ -352,7 +407,7 @@ wlda_status run_phase(wlda_sampler s, uint32_t phase, uint32_t iter, bool draw_o
     PhaseArgs a;
     a.recs = s->recs;
     a.segptr = phase == PH_WORD ? s->colptr : s->rowptr;
-    a.rowpos = phase == PH_WORD ? nullptr : s->rowpos;
+    a.idx = phase == PH_WORD ? s->colidx : s->rowidx;
     a.K = s->p.K;
     a.iter = iter;
     a.seed_lo = (uint32_t)s->p.seed;
@@ -495,37 +550,50 @@ wlda_status wlda_create(const wlda_params *p, const uint32_t *word_ids, const ui
     colptr[0] = rowptr[0] = 0;
     for (uint32_t w = 0; w < p->V; ++w) colptr[w + 1] = colptr[w] + (uint32_t)lw[w];
     for (uint32_t d = 0; d < p->D; ++d) rowptr[d + 1] = rowptr[d] + (uint32_t)ld[d];
-    std::vector<uint32_t> rowpos, doc_csc;
+    // canonical CSC position t of input token i: stable order by (word, doc,
+    // input index); canonical CSR position: rows in ascending CSC position
+    std::vector<uint32_t> rowidx;
     try {
-        std::vector<uint32_t> by_doc(T), cursor(rowptr.begin(), rowptr.end() - 1);
-        for (uint64_t i = 0; i < T; ++i) by_doc[cursor[doc_ids[i]]++] = (uint32_t)i;
-        s->inv.resize(T);
-        doc_csc.resize(T);
-        std::vector<uint32_t> wc(colptr.begin(), colptr.end() - 1);
-        for (uint64_t j = 0; j < T; ++j) {
-            const uint32_t i = by_doc[j];
-            const uint32_t t = wc[word_ids[i]]++;
-            s->inv[i] = t;
-            doc_csc[t] = doc_ids[i];
+        std::vector<uint32_t> doc_csc(T);
+        {
+            std::vector<uint32_t> by_doc(T), cursor(rowptr.begin(), rowptr.end() - 1);
+            for (uint64_t i = 0; i < T; ++i) by_doc[cursor[doc_ids[i]]++] = (uint32_t)i;
+            s->inv.resize(T);
+            std::vector<uint32_t> wc(colptr.begin(), colptr.end() - 1);
+            for (uint64_t j = 0; j < T; ++j) {
+                const uint32_t i = by_doc[j];
+                const uint32_t t = wc[word_ids[i]]++;
+                s->inv[i] = t;
+                doc_csc[t] = doc_ids[i];
+            }
         }
-        by_doc.clear();
-        by_doc.shrink_to_fit();
-        rowpos.resize(T);
-        std::copy(rowptr.begin(), rowptr.end() - 1, cursor.begin());
-        for (uint64_t t = 0; t < T; ++t) rowpos[cursor[doc_csc[t]]++] = (uint32_t)t;
+        // record layout: plain CSC order (colidx is the identity), or blocked
+        // by documents when WLDA_DOC_BLOCK_KIB gives a block size
+        s->mem.resize(T);
+        uint64_t block_kib = 0;
+        if (const char *env = std::getenv("WLDA_DOC_BLOCK_KIB")) block_kib = std::strtoull(env, nullptr, 10);
+        s->blocked = block_kib >= 16 && block_kib <= (1ull << 20);
+        if (s->blocked) {
+            build_layout(s->word, s->doc, ld, colptr, doc_csc, (block_kib << 10) / (8ull * s->nw), s->mem);
+            for (uint64_t i = 0; i < T; ++i) s->inv[i] = s->mem[s->inv[i]];
+        } else {
+            for (uint64_t t = 0; t < T; ++t) s->mem[t] = (uint32_t)t;
+        }
+        rowidx.resize(T);
+        std::vector<uint32_t> cursor(rowptr.begin(), rowptr.end() - 1);
+        for (uint64_t t = 0; t < T; ++t) rowidx[cursor[doc_csc[t]]++] = s->mem[t];
     } catch (const std::bad_alloc &) {
         delete s;
         return WLDA_E_INVALID;
     }
-    doc_csc.clear();
-    doc_csc.shrink_to_fit();
 
     // ---- workspace ----------------------------------------------------------
     uint8_t *cur = (uint8_t *)dev_workspace;
     s->recs = (uint64_t *)carve(cur, T * 8ull * s->nw + 16);
     s->colptr = (uint32_t *)carve(cur, 4ull * (p->V + 1));
     s->rowptr = (uint32_t *)carve(cur, 4ull * (p->D + 1));
-    s->rowpos = (uint32_t *)carve(cur, 4ull * T + 4);
+    s->colidx = (uint32_t *)carve(cur, 4ull * T + 4);
+    s->rowidx = (uint32_t *)carve(cur, 4ull * T + 4);
     s->ck[0] = (uint32_t *)carve(cur, 4ull * p->K);
     s->ck[1] = (uint32_t *)carve(cur, 4ull * p->K);
     uint8_t *misc = carve(cur, ALIGN);
@@ -535,7 +603,9 @@ wlda_status wlda_create(const wlda_params *p, const uint32_t *word_ids, const ui
     hipError_t e = hipSuccess;
     if (!e) e = upload(s->colptr, colptr.data(), 4ull * (p->V + 1), s->st);
     if (!e) e = upload(s->rowptr, rowptr.data(), 4ull * (p->D + 1), s->st);
-    if (!e) e = upload(s->rowpos, rowpos.data(), 4ull * T, s->st);
+    if (!e && s->blocked) e = upload(s->colidx, s->mem.data(), 4ull * T, s->st);
+    if (!s->blocked) s->colidx = nullptr;   // identity: kernels use the CSC position
+    if (!e) e = upload(s->rowidx, rowidx.data(), 4ull * T, s->st);
     if (!e) e = place_plan(s->word, cur, p->K, s->st);
     if (!e) e = place_plan(s->doc, cur, p->K, s->st);
     if (!e) e = launch_fill_u32(s->ck[0], 0, 2ull * align_up(4ull * p->K) / 4, s->st);
@@ -552,7 +622,7 @@ wlda_status wlda_create(const wlda_params *p, const uint32_t *word_ids, const ui
 wlda_status wlda_init(wlda_sampler s) {
     if (!s) return WLDA_E_INVALID;
     if (s->broken) return WLDA_E_HIP;
-    WLDA_TRY(s, launch_init_z(s->recs, (uint32_t)s->T, s->p.M, s->p.K, (uint32_t)s->p.seed,
+    WLDA_TRY(s, launch_init_z(s->recs, s->colidx, (uint32_t)s->T, s->p.M, s->p.K, (uint32_t)s->p.seed,
                               (uint32_t)(s->p.seed >> 32), s->st));
     // first doc proposals from the initial Z; c_k of Z lands in the other buffer
     wlda_status st = run_phase(s, PH_DOC, 0, true);
@@ -602,18 +672,18 @@ wlda_status wlda_log_likelihood(wlda_sampler s, double *ll) {
     for (int ph = PH_WORD; ph <= PH_DOC; ++ph) {
         const PhasePlan &pl = ph == PH_WORD ? s->word : s->doc;
         const uint32_t *segptr = ph == PH_WORD ? s->colptr : s->rowptr;
-        const uint32_t *rowpos = ph == PH_WORD ? nullptr : s->rowpos;
+        const uint32_t *idx = ph == PH_WORD ? s->colidx : s->rowidx;
         const double prior = ph == PH_WORD ? s->p.beta : s->p.alpha;
         const double total = ph == PH_WORD ? 0.0 : (double)K * s->p.alpha;
         const int lt = ph == PH_DOC;
-        WLDA_TRY(s, launch_ll_list(s->recs, s->p.M, segptr, rowpos, pl.d_wave_ids,
+        WLDA_TRY(s, launch_ll_list(s->recs, s->p.M, segptr, idx, pl.d_wave_ids,
                                    (uint32_t)pl.wave_ids.size(), K, prior, total, lt, s->ll, s->st));
-        WLDA_TRY(s, launch_ll_list(s->recs, s->p.M, segptr, rowpos, pl.d_block_ids,
+        WLDA_TRY(s, launch_ll_list(s->recs, s->p.M, segptr, idx, pl.d_block_ids,
                                    (uint32_t)pl.block_ids.size(), K, prior, total, lt, s->ll, s->st));
         PhaseArgs a;
         a.recs = s->recs;
         a.segptr = segptr;
-        a.rowpos = rowpos;
+        a.idx = idx;
         a.K = K;
         WLDA_TRY(s, launch_ll_long(a, ph, s->p.M, long_list(pl), prior, total, lt, s->ll, s->st));
     }
@@ -627,7 +697,7 @@ wlda_status wlda_theta(wlda_sampler s, uint32_t d0, uint32_t nd, float *theta) {
     if (!s || !theta || (uint64_t)d0 + nd > s->p.D) return WLDA_E_INVALID;
     if (s->broken) return WLDA_E_HIP;
     if (s->next_phase == 0) return WLDA_E_STATE;
-    WLDA_TRY(s, launch_theta(s->recs, s->p.M, s->rowptr, s->rowpos, d0, nd, s->p.K, (float)s->p.alpha, theta,
+    WLDA_TRY(s, launch_theta(s->recs, s->p.M, s->rowptr, s->rowidx, d0, nd, s->p.K, (float)s->p.alpha, theta,
                              s->st));
     return WLDA_OK;
 }
@@ -641,7 +711,7 @@ static wlda_status copy_out(wlda_sampler s, int32_t *z, int32_t *props, bool inp
     const uint64_t T = s->T;
     const int nw = s->nw;
     for (uint64_t i = 0; i < T; ++i) {
-        const uint64_t t = input_order ? s->inv[i] : i;
+        const uint64_t t = input_order ? s->inv[i] : s->mem[i];
         const uint64_t *rec = &h[t * nw];
         z[i] = (int32_t)get_field(rec, 0);
         if (props)
@@ -716,12 +786,13 @@ wlda_status wlda_load_state(wlda_sampler s, const void *host_buf, uint64_t bytes
     const uint64_t T = s->T;
     std::vector<uint64_t> h(T * s->nw + 1, 0);
     for (uint64_t t = 0; t < T; ++t) {
+        uint64_t *rec = &h[(uint64_t)s->mem[t] * s->nw];
         if ((uint32_t)z[t] >= s->p.K) return WLDA_E_INVALID;
-        set_field(&h[t * s->nw], 0, (uint32_t)z[t]);
+        set_field(rec, 0, (uint32_t)z[t]);
         for (uint32_t m = 1; m <= s->p.M; ++m) {
             const uint32_t v = (uint32_t)props[(m - 1) * T + t];
             if (v >= s->p.K) return WLDA_E_INVALID;
-            set_field(&h[t * s->nw], m, v);
+            set_field(rec, m, v);
         }
     }
     wlda_status st = upload_records_and_recount(s, h);

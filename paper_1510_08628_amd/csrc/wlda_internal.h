@@ -16,9 +16,11 @@ constexpr uint32_t MAX_K = FIELD_MASK;   // topics are < 2^21 - 1
 
 inline int record_words(uint32_t M) { return (int)((M + 1 + 2) / 3); }
 
-// Segment = one column (word phase) or one row (doc phase).  Tokens of
-// segment s are the canonical positions segptr[s] .. segptr[s+1]-1 (word
-// phase) or rowpos[segptr[s] .. segptr[s+1]-1] (doc phase).
+// Segment = one column (word phase) or one row (doc phase).  The n-th token
+// of segment s has the canonical position segptr[s] + n of its phase (CSC in
+// the word phase, CSR in the doc phase; the RNG counter uses it) and its
+// record at recs[idx[segptr[s] + n]] (idx = colidx or rowidx: the record
+// layout is blocked by documents, see the host runtime).
 struct SegList {
     const uint32_t *ids = nullptr;   // segment ids, ascending
     uint32_t n = 0;
@@ -52,7 +54,7 @@ struct LongList {
 struct PhaseArgs {
     uint64_t *recs = nullptr;
     const uint32_t *segptr = nullptr;
-    const uint32_t *rowpos = nullptr;  // doc phase indirection, null in word phase
+    const uint32_t *idx = nullptr;     // record position of each canonical position
     uint32_t K = 0, iter = 0, seed_lo = 0, seed_hi = 0;
     const uint32_t *ck = nullptr;      // c_k at the start of the phase
     uint32_t *ck_next = nullptr;       // histogram of the phase's new Z
@@ -84,7 +86,7 @@ inline uint32_t block_max_tokens(uint32_t M) {
 
 // ---- launchers (all enqueue on `st`, return hipError_t of the launch) ----
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, uint64_t n, hipStream_t st);
-hipError_t launch_init_z(uint64_t *recs, uint32_t T, uint32_t M, uint32_t K,
+hipError_t launch_init_z(uint64_t *recs, const uint32_t *colidx, uint32_t T, uint32_t M, uint32_t K,
                          uint32_t seed_lo, uint32_t seed_hi, hipStream_t st);
 hipError_t launch_wave_segments(const PhaseArgs &a, uint32_t phase, uint32_t M,
                                 const SegList &l, hipStream_t st);
@@ -94,10 +96,6 @@ hipError_t launch_block_segments(const PhaseArgs &a, uint32_t phase, uint32_t M,
 // after the draw kernel, so that the host can time each of them.
 hipError_t launch_long_segments(const PhaseArgs &a, uint32_t phase, uint32_t M,
                                 const LongList &l, hipStream_t st, hipEvent_t *ev = nullptr);
-hipError_t launch_unpack(const uint64_t *recs, uint32_t T, uint32_t M,
-                         int32_t *z_out, int32_t *props_out, hipStream_t st);
-hipError_t launch_pack(uint64_t *recs, uint32_t T, uint32_t M, const int32_t *z_in,
-                       const int32_t *props_in, hipStream_t st);
 hipError_t launch_histogram_z(const uint64_t *recs, uint32_t T, uint32_t M, uint32_t K,
                               uint32_t *ck, hipStream_t st);
 // LL: adds the document, word and topic parts into *out (binary64).
@@ -106,13 +104,13 @@ hipError_t launch_histogram_z(const uint64_t *recs, uint32_t T, uint32_t M, uint
 // LL parts over the segments of a list (at most block_max tokens each) and
 // over the long segments (through their global tables, which are left zeroed).
 hipError_t launch_ll_list(const uint64_t *recs, uint32_t M, const uint32_t *segptr,
-                          const uint32_t *rowpos, const uint32_t *ids, uint32_t n, uint32_t K,
+                          const uint32_t *idx, const uint32_t *ids, uint32_t n, uint32_t K,
                           double prior, double prior_total, int length_term, double *out,
                           hipStream_t st);
 hipError_t launch_ll_long(const PhaseArgs &a, uint32_t phase, uint32_t M, const LongList &l,
                           double prior, double prior_total, int length_term, double *out,
                           hipStream_t st);
-hipError_t launch_theta(const uint64_t *recs, uint32_t M, const uint32_t *rowptr, const uint32_t *rowpos,
+hipError_t launch_theta(const uint64_t *recs, uint32_t M, const uint32_t *rowptr, const uint32_t *rowidx,
                         uint32_t d0, uint32_t nd, uint32_t K, float alpha, float *out, hipStream_t st);
 hipError_t launch_ll_topics(const uint32_t *ck, uint32_t K, double beta_bar, double *out,
                             hipStream_t st);

@@ -3,12 +3,16 @@
 // Paper: Chen, Li, Zhu, Chen, "WarpLDA: a Cache Efficient O(1) Algorithm for
 // Latent Dirichlet Allocation" (arXiv:1510.08628).
 //
-// Data: one packed record per token in canonical column-major order (tokens
-// sorted by word, then document, then input index; Section 5.2 stores Y the
-// same way): 21-bit fields, field 0 = z, fields 1..M = pending proposals.
-// The word phase streams columns (coalesced); the document phase reaches each
-// row through `rowpos` (the CSC positions of the row, ascending), i.e. the
-// pointer array P_CSR of Section 5.2.
+// Data: one packed record per token, 21-bit fields, field 0 = z, fields 1..M
+// = pending proposals, stored once (Section 5.2).  Both phases reach their
+// segments through a pointer array into that copy of Y, the role P_CSR plays
+// in Section 5.2: `colidx` (canonical CSC position -> record; null when the
+// records are in CSC order, so the word phase streams its columns) and
+// `rowidx` (canonical CSR position -> record).  The host may instead block
+// the records by documents (column-major inside each block), which keeps a
+// document window's gathers inside L2 at the price of word-phase gathers.
+// The RNG counter of a token is its canonical position in the phase's order,
+// independent of the layout.
 //
 // A "segment" is a column (word phase) or a row (document phase).  Segments
 // are binned by length on the host:
@@ -33,46 +37,10 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "wlda_device.h"
 #include "wlda_internal.h"
 
 namespace wlda {
-
-// --------------------------------------------------------------------------
-// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds, each two
-// 32x32 -> 64-bit products mixed into the other lanes, with the Weyl key
-// increments between rounds.
-// --------------------------------------------------------------------------
-__device__ __forceinline__ uint4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
-                                        uint32_t k0, uint32_t k1) {
-#pragma unroll
-    for (int round = 0; round < 10; ++round) {
-        const uint32_t hi_a = __umulhi(0xD2511F53u, c0), lo_a = 0xD2511F53u * c0;
-        const uint32_t hi_b = __umulhi(0xCD9E8D57u, c2), lo_b = 0xCD9E8D57u * c2;
-        const uint32_t n0 = hi_b ^ c1 ^ k0;
-        const uint32_t n2 = hi_a ^ c3 ^ k1;
-        c0 = n0;
-        c1 = lo_b;
-        c2 = n2;
-        c3 = lo_a;
-        k0 += 0x9E3779B9u;
-        k1 += 0xBB67AE85u;
-    }
-    return make_uint4(c0, c1, c2, c3);
-}
-
-__device__ __forceinline__ float unif24(uint32_t r) { return (float)(r >> 8) * 0x1p-24f; }
-__device__ __forceinline__ uint32_t dice(uint32_t r, uint32_t n) { return __umulhi(r, n); }
-
-__device__ __forceinline__ bool mh_accept(float u, uint32_t cnt_c, uint32_t cnt_s, float prior,
-                                          uint32_t ck_s, uint32_t ck_c, float beta_bar) {
-    const float num = ((float)cnt_c + prior) * ((float)ck_s + beta_bar);
-    const float den = ((float)cnt_s + prior) * ((float)ck_c + beta_bar);
-    return u * den < num;
-}
-
-__device__ __forceinline__ bool take_count_part(float u, uint32_t L, float mass) {
-    return u * ((float)L + mass) < (float)L;
-}
 
 // --------------------------------------------------------------------------
 // Packed records
@@ -188,15 +156,22 @@ __global__ __launch_bounds__(256) void seg_kernel(PhaseArgs a, SegList l, uint32
     const bool dense = dense_u != 0, ck_lds = ck_lds_u != 0;
     const uint32_t g = threadIdx.x / GROUP, lane = threadIdx.x % GROUP;
     const uint32_t K = a.K;
-    const uint32_t ck_words = ck_lds ? K : 0;
+    // LDS: [c_k histogram of the new Z | c_k + beta_bar as binary32] when
+    // K <= CK_LDS_MAX, then per group [count table | new z of the segment]
+    const uint32_t ck_words = ck_lds ? 2 * K : 0;
     const uint32_t tab_words = dense ? K : 2 * cap_max;
     uint32_t *ckh = lds;
+    float *ckb = reinterpret_cast<float *>(lds + K);
     uint32_t *gbase = lds + ck_words + g * (tab_words + GROUP * TPT);
     uint32_t *tkey = gbase;
     uint32_t *tcnt = dense ? gbase : gbase + cap_max;
     uint32_t *zarr = gbase + tab_words;
 
-    for (uint32_t i = threadIdx.x; i < ck_words; i += 256) ckh[i] = 0;
+    if (ck_lds)
+        for (uint32_t i = threadIdx.x; i < K; i += 256) {
+            ckh[i] = 0;
+            ckb[i] = (float)a.ck[i] + a.beta_bar;
+        }
     if (dense)
         for (uint32_t i = lane; i < K; i += GROUP) tcnt[i] = 0;
     __syncthreads();
@@ -218,7 +193,7 @@ __global__ __launch_bounds__(256) void seg_kernel(PhaseArgs a, SegList l, uint32
         for (int r = 0; r < TPT; ++r) {
             const uint32_t n = r * GROUP + lane;
             if (n < L) {
-                pos[r] = PHASE == PH_DOC ? a.rowpos[beg + n] : beg + n;
+                pos[r] = a.idx ? a.idx[beg + n] : beg + n;
                 rec[r] = ld_rec<NW>(a.recs, pos[r]);
             }
         }
@@ -246,11 +221,13 @@ __global__ __launch_bounds__(256) void seg_kernel(PhaseArgs a, SegList l, uint32
                     uint32_t s = fld(rec[r], 0);
 #pragma unroll
                     for (int i = 1; i <= M; ++i) {
-                        const uint4 R = philox(pos[r], a.iter, ph | i, 0, a.seed_lo, a.seed_hi);
+                        const uint4 R = philox(beg + r * GROUP + lane, a.iter, ph | i, 0, a.seed_lo, a.seed_hi);
                         const uint32_t c = fld(rec[r], i);
                         const uint32_t cc = tab_get(tkey, tcnt, mask, dense, c);
                         const uint32_t cs = tab_get(tkey, tcnt, mask, dense, s);
-                        if (mh_accept(unif24(R.x), cc, cs, prior, a.ck[s], a.ck[c], beta_bar)) {
+                        const bool ok = ck_lds ? mh_accept_b(unif24(R.x), cc, cs, prior, ckb[s], ckb[c])
+                                               : mh_accept(unif24(R.x), cc, cs, prior, a.ck[s], a.ck[c], beta_bar);
+                        if (ok) {
                             s = c;
                             ++acc;
                         }
@@ -273,7 +250,7 @@ __global__ __launch_bounds__(256) void seg_kernel(PhaseArgs a, SegList l, uint32
                     znew[r] = fld(rec[r], 0);
 #pragma unroll
                     for (int i = 1; i <= M; ++i) {
-                        const uint4 R = philox(pos[r], a.iter, ph | i, 0, a.seed_lo, a.seed_hi);
+                        const uint4 R = philox(beg + r * GROUP + lane, a.iter, ph | i, 0, a.seed_lo, a.seed_hi);
                         if (take_count_part(unif24(R.y), L, mass)) coins |= 1u << (r * M + i - 1);
                         r2[r][i - 1] = R.z;
                     }
@@ -360,6 +337,9 @@ __device__ __forceinline__ uint32_t gtab_get(const uint32_t *base, uint32_t cap,
     }
 }
 
+// tokens per thread whose loads are issued together in the long kernels
+constexpr int LONG_BATCH = 8;
+
 #define WLDA_FOR_CHUNKS(l)                                                        \
     const uint32_t xcd_ = blockIdx.x & 7, nbx_ = gridDim.x >> 3;                 \
     for (uint32_t ci = (l).chunk_cut[xcd_] + (blockIdx.x >> 3); ci < (l).chunk_cut[xcd_ + 1]; \
@@ -383,10 +363,17 @@ __global__ __launch_bounds__(256) void long_hist_kernel(PhaseArgs a, LongList l,
             for (uint32_t k = threadIdx.x; k < HCAP; k += 256) hkey[k] = EMPTY_KEY, hcnt[k] = 0;
         }
         __syncthreads();
-        for (uint32_t n = n0 + threadIdx.x; n < n1; n += 256) {
-            const uint32_t pos = PHASE == PH_DOC ? a.rowpos[beg + n] : beg + n;
-            const uint32_t z = fld(ld_rec<NW>(a.recs, pos), 0);
-            tab_insert(hkey, lds_dense ? hist : hcnt, HCAP - 1, lds_dense != 0, z);
+        // LONG_BATCH tokens per thread in flight: all loads, then the inserts
+        for (uint32_t nb = n0 + threadIdx.x; nb < n1; nb += 256 * LONG_BATCH) {
+            uint32_t z[LONG_BATCH];
+#pragma unroll
+            for (int u = 0; u < LONG_BATCH; ++u) {
+                const uint32_t n = nb + u * 256;
+                if (n < n1) z[u] = fld(ld_rec<NW>(a.recs, a.idx ? a.idx[beg + n] : beg + n), 0);
+            }
+#pragma unroll
+            for (int u = 0; u < LONG_BATCH; ++u)
+                if (nb + u * 256 < n1) tab_insert(hkey, lds_dense ? hist : hcnt, HCAP - 1, lds_dense != 0, z[u]);
         }
         __syncthreads();
         if (lds_dense) {
@@ -405,9 +392,17 @@ __global__ __launch_bounds__(256) void long_hist_kernel(PhaseArgs a, LongList l,
 }
 
 template <int PHASE, int M, int NW, typename ZT>
-__global__ __launch_bounds__(256) void long_mh_kernel(PhaseArgs a, LongList l, uint32_t lds_tab) {
+__global__ __launch_bounds__(256) void long_mh_kernel(PhaseArgs a, LongList l, uint32_t lds_tab,
+                                                      uint32_t ck_lds_u) {
+    // LDS: [the segment's count table (lds_tab) | c_k + beta_bar (ck_lds)]
     extern __shared__ uint32_t tab[];
     const uint32_t K = a.K;
+    const bool ck_lds = ck_lds_u != 0;
+    float *ckb = reinterpret_cast<float *>(tab + (lds_tab ? K : 0));
+    if (ck_lds) {
+        for (uint32_t k = threadIdx.x; k < K; k += 256) ckb[k] = (float)a.ck[k] + a.beta_bar;
+        __syncthreads();
+    }
     const uint32_t ph = (uint32_t)PHASE << 16;
     ZT *zc = reinterpret_cast<ZT *>(l.zc);
     unsigned long long acc = 0;
@@ -421,7 +416,7 @@ __global__ __launch_bounds__(256) void long_mh_kernel(PhaseArgs a, LongList l, u
         const uint32_t gcap = l.tab_cap[j];
         if (a.draw_only) {     // initial draw: only publish z for random positioning
             for (uint32_t n = n0 + threadIdx.x; n < n1; n += 256) {
-                const uint32_t pos = PHASE == PH_DOC ? a.rowpos[beg + n] : beg + n;
+                const uint32_t pos = a.idx ? a.idx[beg + n] : beg + n;
                 zc[zbase + n] = (ZT)fld(ld_rec<NW>(a.recs, pos), 0);
             }
             continue;
@@ -432,23 +427,38 @@ __global__ __launch_bounds__(256) void long_mh_kernel(PhaseArgs a, LongList l, u
         }
         const uint32_t *ct = lds_tab ? tab : gt;
         const uint32_t ccap = lds_tab ? 0u : gcap;
-        for (uint32_t n = n0 + threadIdx.x; n < n1; n += 256) {
-            const uint32_t pos = PHASE == PH_DOC ? a.rowpos[beg + n] : beg + n;
-            Rec<NW> rec = ld_rec<NW>(a.recs, pos);
-            uint32_t s = fld(rec, 0);
+        for (uint32_t nb = n0 + threadIdx.x; nb < n1; nb += 256 * LONG_BATCH) {
+            uint32_t pos[LONG_BATCH];
+            Rec<NW> rec[LONG_BATCH];
 #pragma unroll
-            for (int i = 1; i <= M; ++i) {
-                const uint4 R = philox(pos, a.iter, ph | i, 0, a.seed_lo, a.seed_hi);
-                const uint32_t c = fld(rec, i);
-                if (mh_accept(unif24(R.x), gtab_get(ct, ccap, c), gtab_get(ct, ccap, s), a.prior, a.ck[s],
-                              a.ck[c], a.beta_bar)) {
-                    s = c;
-                    ++acc;
+            for (int u = 0; u < LONG_BATCH; ++u) {
+                const uint32_t n = nb + u * 256;
+                if (n < n1) {
+                    pos[u] = a.idx ? a.idx[beg + n] : beg + n;
+                    rec[u] = ld_rec<NW>(a.recs, pos[u]);
                 }
             }
-            set_fld(rec, 0, s);
-            st_rec<NW>(a.recs, pos, rec);
-            zc[zbase + n] = (ZT)s;
+#pragma unroll
+            for (int u = 0; u < LONG_BATCH; ++u) {
+                const uint32_t n = nb + u * 256;
+                if (n >= n1) continue;
+                uint32_t s = fld(rec[u], 0);
+#pragma unroll
+                for (int i = 1; i <= M; ++i) {
+                    const uint4 R = philox(beg + n, a.iter, ph | i, 0, a.seed_lo, a.seed_hi);
+                    const uint32_t c = fld(rec[u], i);
+                    const uint32_t cc = gtab_get(ct, ccap, c), cs = gtab_get(ct, ccap, s);
+                    const bool ok = ck_lds ? mh_accept_b(unif24(R.x), cc, cs, a.prior, ckb[s], ckb[c])
+                                           : mh_accept(unif24(R.x), cc, cs, a.prior, a.ck[s], a.ck[c], a.beta_bar);
+                    if (ok) {
+                        s = c;
+                        ++acc;
+                    }
+                }
+                set_fld(rec[u], 0, s);
+                st_rec<NW>(a.recs, pos[u], rec[u]);
+                zc[zbase + n] = (ZT)s;
+            }
         }
         if (lds_tab) __syncthreads();
     }
@@ -473,22 +483,41 @@ __global__ __launch_bounds__(256) void long_draw_kernel(PhaseArgs a, LongList l,
         const uint32_t beg = a.segptr[s_id], L = a.segptr[s_id + 1] - beg;
         const uint32_t n1 = min(L, n0 + Tuning::LONG_CHUNK);
         const ZT *zs = zc + l.prefix[j];
-        for (uint32_t n = n0 + threadIdx.x; n < n1; n += 256) {
-            const uint32_t pos = PHASE == PH_DOC ? a.rowpos[beg + n] : beg + n;
-            Rec<NW> rec = ld_rec<NW>(a.recs, pos);
-            const uint32_t z = fld(rec, 0);
+        for (uint32_t nb = n0 + threadIdx.x; nb < n1; nb += 256 * LONG_BATCH) {
+            uint32_t pos[LONG_BATCH];
+            Rec<NW> rec[LONG_BATCH];
 #pragma unroll
-            for (int i = 1; i <= M; ++i) {
-                const uint4 R = philox(pos, a.iter, ph | i, 0, a.seed_lo, a.seed_hi);
-                const uint32_t p =
-                    take_count_part(unif24(R.y), L, a.mass) ? (uint32_t)zs[dice(R.z, L)] : dice(R.z, K);
-                set_fld(rec, i, p);
+            for (int u = 0; u < LONG_BATCH; ++u) {
+                const uint32_t n = nb + u * 256;
+                if (n < n1) {
+                    pos[u] = a.idx ? a.idx[beg + n] : beg + n;
+                    rec[u] = ld_rec<NW>(a.recs, pos[u]);
+                }
             }
-            st_rec<NW>(a.recs, pos, rec);
-            if (ck_lds)
-                atomicAdd(&ckh[z], 1u);
-            else
-                atomicAdd(&a.ck_next[z], 1u);
+            // all random-positioning reads of the batch are issued before
+            // any record is written back
+#pragma unroll
+            for (int u = 0; u < LONG_BATCH; ++u) {
+                const uint32_t n = nb + u * 256;
+                if (n >= n1) continue;
+#pragma unroll
+                for (int i = 1; i <= M; ++i) {
+                    const uint4 R = philox(beg + n, a.iter, ph | i, 0, a.seed_lo, a.seed_hi);
+                    const uint32_t p =
+                        take_count_part(unif24(R.y), L, a.mass) ? (uint32_t)zs[dice(R.z, L)] : dice(R.z, K);
+                    set_fld(rec[u], i, p);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < LONG_BATCH; ++u) {
+                if (nb + u * 256 >= n1) continue;
+                st_rec<NW>(a.recs, pos[u], rec[u]);
+                const uint32_t z = fld(rec[u], 0);
+                if (ck_lds)
+                    atomicAdd(&ckh[z], 1u);
+                else
+                    atomicAdd(&a.ck_next[z], 1u);
+            }
         }
     }
     if (zero_tables) {
@@ -513,40 +542,18 @@ __global__ void fill_u32_kernel(uint32_t *p, uint32_t v, uint64_t n) {
         p[i] = v;
 }
 
-// z = Dice(K) with the INIT counter (t, 0, 0, 0); proposals cleared.
+// z = Dice(K) with the INIT counter (t, 0, 0, 0), t the canonical CSC
+// position; proposals cleared.
 template <int NW>
-__global__ void init_z_kernel(uint64_t *recs, uint32_t T, uint32_t K, uint32_t k0, uint32_t k1) {
+__global__ void init_z_kernel(uint64_t *recs, const uint32_t *colidx, uint32_t T, uint32_t K, uint32_t k0,
+                              uint32_t k1) {
     for (uint32_t t = blockIdx.x * 256 + threadIdx.x; t < T; t += gridDim.x * 256) {
         const uint4 R = philox(t, 0, (uint32_t)PH_INIT << 16, 0, k0, k1);
         Rec<NW> r;
 #pragma unroll
         for (int w = 0; w < NW; ++w) r.w[w] = 0;
         set_fld(r, 0, dice(R.z, K));
-        st_rec<NW>(recs, t, r);
-    }
-}
-
-template <int NW>
-__global__ void unpack_kernel(const uint64_t *recs, uint32_t T, uint32_t M, int32_t *z,
-                              int32_t *props) {
-    for (uint32_t t = blockIdx.x * 256 + threadIdx.x; t < T; t += gridDim.x * 256) {
-        const Rec<NW> r = ld_rec<NW>(recs, t);
-        z[t] = (int32_t)fld(r, 0);
-        if (props)
-            for (uint32_t i = 1; i <= M; ++i) props[(size_t)(i - 1) * T + t] = (int32_t)fld(r, i);
-    }
-}
-
-template <int NW>
-__global__ void pack_kernel(uint64_t *recs, uint32_t T, uint32_t M, const int32_t *z,
-                            const int32_t *props) {
-    for (uint32_t t = blockIdx.x * 256 + threadIdx.x; t < T; t += gridDim.x * 256) {
-        Rec<NW> r;
-#pragma unroll
-        for (int w = 0; w < NW; ++w) r.w[w] = 0;
-        set_fld(r, 0, (uint32_t)z[t]);
-        for (uint32_t i = 1; i <= M; ++i) set_fld(r, i, (uint32_t)props[(size_t)(i - 1) * T + t]);
-        st_rec<NW>(recs, t, r);
+        st_rec<NW>(recs, colidx ? colidx[t] : t, r);
     }
 }
 
@@ -578,7 +585,7 @@ __device__ double block_sum(double v) {
 // LDS_DENSE_MAX, else an open-addressed table of pow2 >= 2L slots).
 template <int NW>
 __global__ __launch_bounds__(256) void ll_seg_kernel(const uint64_t *recs, const uint32_t *segptr,
-                                                     const uint32_t *rowpos, const uint32_t *ids,
+                                                     const uint32_t *idx, const uint32_t *ids,
                                                      uint32_t n_seg, uint32_t K, uint32_t dense_u,
                                                      double prior, double prior_total,
                                                      int length_term, double *out) {
@@ -597,8 +604,7 @@ __global__ __launch_bounds__(256) void ll_seg_kernel(const uint64_t *recs, const
         }
         __syncthreads();
         for (uint32_t n = threadIdx.x; n < L; n += 256) {
-            const uint32_t pos = rowpos ? rowpos[beg + n] : beg + n;
-            tab_insert(key, c, cap - 1, dense, fld(ld_rec<NW>(recs, pos), 0));
+            tab_insert(key, c, cap - 1, dense, fld(ld_rec<NW>(recs, idx ? idx[beg + n] : beg + n), 0));
         }
         __syncthreads();
         for (uint32_t k = threadIdx.x; k < cap; k += 256) {
@@ -641,7 +647,7 @@ __global__ __launch_bounds__(256) void ll_tables_kernel(LongList l, const uint32
 // (C_dk + alpha) / (L_d + K alpha) for documents d0 .. d0 + nd - 1.
 template <int NW>
 __global__ __launch_bounds__(256) void theta_kernel(const uint64_t *recs, const uint32_t *rowptr,
-                                                    const uint32_t *rowpos, uint32_t d0, uint32_t nd,
+                                                    const uint32_t *rowidx, uint32_t d0, uint32_t nd,
                                                     uint32_t K, float alpha, float *out) {
     extern __shared__ uint32_t cnt[];
     for (uint32_t d = d0 + blockIdx.x; d < d0 + nd; d += gridDim.x) {
@@ -649,7 +655,7 @@ __global__ __launch_bounds__(256) void theta_kernel(const uint64_t *recs, const 
         for (uint32_t k = threadIdx.x; k < K; k += 256) cnt[k] = 0;
         __syncthreads();
         for (uint32_t n = threadIdx.x; n < L; n += 256)
-            atomicAdd(&cnt[fld(ld_rec<NW>(recs, rowpos[beg + n]), 0)], 1u);
+            atomicAdd(&cnt[fld(ld_rec<NW>(recs, rowidx[beg + n]), 0)], 1u);
         __syncthreads();
         const float den = (float)L + (float)K * alpha;
         for (uint32_t k = threadIdx.x; k < K; k += 256)
@@ -683,13 +689,13 @@ hipError_t launch_fill_u32(uint32_t *p, uint32_t v, uint64_t n, hipStream_t st) 
     return hipGetLastError();
 }
 
-hipError_t launch_init_z(uint64_t *recs, uint32_t T, uint32_t M, uint32_t K, uint32_t k0,
-                         uint32_t k1, hipStream_t st) {
+hipError_t launch_init_z(uint64_t *recs, const uint32_t *colidx, uint32_t T, uint32_t M, uint32_t K,
+                         uint32_t k0, uint32_t k1, hipStream_t st) {
     if (T == 0) return hipSuccess;
     if (record_words(M) == 1)
-        hipLaunchKernelGGL(init_z_kernel<1>, dim3(grid_for(T)), dim3(256), 0, st, recs, T, K, k0, k1);
+        hipLaunchKernelGGL(init_z_kernel<1>, dim3(grid_for(T)), dim3(256), 0, st, recs, colidx, T, K, k0, k1);
     else
-        hipLaunchKernelGGL(init_z_kernel<2>, dim3(grid_for(T)), dim3(256), 0, st, recs, T, K, k0, k1);
+        hipLaunchKernelGGL(init_z_kernel<2>, dim3(grid_for(T)), dim3(256), 0, st, recs, colidx, T, K, k0, k1);
     return hipGetLastError();
 }
 
@@ -712,7 +718,7 @@ static hipError_t run_seg(const PhaseArgs &a, const SegList &l, uint32_t cap_bou
     const uint32_t cap_max = dense ? 0 : cap_bound;
     const uint32_t tab_words = dense ? a.K : 2 * cap_max;
     constexpr int GPB = 256 / GROUP;
-    const size_t lds = 4ull * ((ck_lds ? a.K : 0) + GPB * (tab_words + GROUP * TPT));
+    const size_t lds = 4ull * ((ck_lds ? 2 * a.K : 0) + GPB * (tab_words + GROUP * TPT));
     auto kern = seg_kernel<PHASE, M, NW, GROUP, TPT>;
     hipError_t e = launch_dyn(kern, dim3(1), lds, st);
     if (e != hipSuccess) return e;
@@ -785,11 +791,12 @@ static hipError_t long_dispatch_z(const PhaseArgs &a, const LongList &l, hipStre
     }
     if (ev && (e = hipEventRecord(ev[1], st)) != hipSuccess) return e;
     {
-        const size_t lds = lds_tab && !a.draw_only ? 4ull * a.K : 0;
+        const bool mh_tab = lds_tab && !a.draw_only, mh_ck = ck_lds && !a.draw_only;
+        const size_t lds = 4ull * ((mh_tab ? a.K : 0) + (mh_ck ? a.K : 0));
         e = launch_dyn(long_mh_kernel<PHASE, M, NW, ZT>, dim3(1), lds, st);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL((long_mh_kernel<PHASE, M, NW, ZT>), dim3(blocks), dim3(256), lds, st, a, l,
-                           (uint32_t)(lds_tab && !a.draw_only));
+                           (uint32_t)mh_tab, (uint32_t)mh_ck);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     if (ev && (e = hipEventRecord(ev[2], st)) != hipSuccess) return e;
@@ -819,26 +826,6 @@ hipError_t launch_long_segments(const PhaseArgs &a, uint32_t phase, uint32_t M, 
     WLDA_DISPATCH_M(long_dispatch, PH_DOC, a, l, st, ev)
 }
 
-hipError_t launch_unpack(const uint64_t *recs, uint32_t T, uint32_t M, int32_t *z, int32_t *props,
-                         hipStream_t st) {
-    if (T == 0) return hipSuccess;
-    if (record_words(M) == 1)
-        hipLaunchKernelGGL(unpack_kernel<1>, dim3(grid_for(T)), dim3(256), 0, st, recs, T, M, z, props);
-    else
-        hipLaunchKernelGGL(unpack_kernel<2>, dim3(grid_for(T)), dim3(256), 0, st, recs, T, M, z, props);
-    return hipGetLastError();
-}
-
-hipError_t launch_pack(uint64_t *recs, uint32_t T, uint32_t M, const int32_t *z, const int32_t *props,
-                       hipStream_t st) {
-    if (T == 0) return hipSuccess;
-    if (record_words(M) == 1)
-        hipLaunchKernelGGL(pack_kernel<1>, dim3(grid_for(T)), dim3(256), 0, st, recs, T, M, z, props);
-    else
-        hipLaunchKernelGGL(pack_kernel<2>, dim3(grid_for(T)), dim3(256), 0, st, recs, T, M, z, props);
-    return hipGetLastError();
-}
-
 hipError_t launch_histogram_z(const uint64_t *recs, uint32_t T, uint32_t M, uint32_t K, uint32_t *ck,
                               hipStream_t st) {
     (void)K;
@@ -850,7 +837,7 @@ hipError_t launch_histogram_z(const uint64_t *recs, uint32_t T, uint32_t M, uint
     return hipGetLastError();
 }
 
-hipError_t launch_ll_list(const uint64_t *recs, uint32_t M, const uint32_t *segptr, const uint32_t *rowpos,
+hipError_t launch_ll_list(const uint64_t *recs, uint32_t M, const uint32_t *segptr, const uint32_t *idx,
                           const uint32_t *ids, uint32_t n, uint32_t K, double prior, double prior_total,
                           int length_term, double *out, hipStream_t st) {
     if (n == 0) return hipSuccess;
@@ -860,11 +847,11 @@ hipError_t launch_ll_list(const uint64_t *recs, uint32_t M, const uint32_t *segp
     hipError_t e;
     if (record_words(M) == 1) {
         if ((e = launch_dyn(ll_seg_kernel<1>, dim3(1), lds, st))) return e;
-        hipLaunchKernelGGL(ll_seg_kernel<1>, dim3(blocks), dim3(256), lds, st, recs, segptr, rowpos, ids, n, K,
+        hipLaunchKernelGGL(ll_seg_kernel<1>, dim3(blocks), dim3(256), lds, st, recs, segptr, idx, ids, n, K,
                            (uint32_t)dense, prior, prior_total, length_term, out);
     } else {
         if ((e = launch_dyn(ll_seg_kernel<2>, dim3(1), lds, st))) return e;
-        hipLaunchKernelGGL(ll_seg_kernel<2>, dim3(blocks), dim3(256), lds, st, recs, segptr, rowpos, ids, n, K,
+        hipLaunchKernelGGL(ll_seg_kernel<2>, dim3(blocks), dim3(256), lds, st, recs, segptr, idx, ids, n, K,
                            (uint32_t)dense, prior, prior_total, length_term, out);
     }
     return hipGetLastError();
@@ -898,7 +885,7 @@ hipError_t launch_ll_long(const PhaseArgs &a, uint32_t phase, uint32_t M, const 
     WLDA_DISPATCH_M(ll_long_dispatch, PH_DOC, a, l, prior, prior_total, length_term, out, st)
 }
 
-hipError_t launch_theta(const uint64_t *recs, uint32_t M, const uint32_t *rowptr, const uint32_t *rowpos,
+hipError_t launch_theta(const uint64_t *recs, uint32_t M, const uint32_t *rowptr, const uint32_t *idx,
                         uint32_t d0, uint32_t nd, uint32_t K, float alpha, float *out, hipStream_t st) {
     if (nd == 0) return hipSuccess;
     if (K > LL_DENSE_MAX) return hipErrorNotSupported;
@@ -907,11 +894,11 @@ hipError_t launch_theta(const uint64_t *recs, uint32_t M, const uint32_t *rowptr
     hipError_t e;
     if (record_words(M) == 1) {
         if ((e = launch_dyn(theta_kernel<1>, dim3(1), lds, st))) return e;
-        hipLaunchKernelGGL(theta_kernel<1>, dim3(blocks), dim3(256), lds, st, recs, rowptr, rowpos, d0, nd, K,
+        hipLaunchKernelGGL(theta_kernel<1>, dim3(blocks), dim3(256), lds, st, recs, rowptr, idx, d0, nd, K,
                            alpha, out);
     } else {
         if ((e = launch_dyn(theta_kernel<2>, dim3(1), lds, st))) return e;
-        hipLaunchKernelGGL(theta_kernel<2>, dim3(blocks), dim3(256), lds, st, recs, rowptr, rowpos, d0, nd, K,
+        hipLaunchKernelGGL(theta_kernel<2>, dim3(blocks), dim3(256), lds, st, recs, rowptr, idx, d0, nd, K,
                            alpha, out);
     }
     return hipGetLastError();
