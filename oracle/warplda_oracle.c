@@ -32,8 +32,11 @@
  *   - counts include the token's own assignment (Eq. 5 has no "not dn");
  *   - proposals are drawn from the counts *after* this phase's updates;
  *   - both proposals use random positioning (Section 4.3) over the canonical
- *     row/column order; the word-proposal mixing weight is L_w / (L_w + K beta)
- *     (the prior mass of C_wk + beta over K topics);
+ *     row/column order, except that words with L_w > K (Section 5.4's
+ *     intra-word-parallel words, whose proposal the paper draws from a table
+ *     over c_w) take the inverse CDF of the updated c_w; the word-proposal
+ *     mixing weight is L_w / (L_w + K beta) (the prior mass of C_wk + beta
+ *     over K topics);
  *   - all acceptance and coin arithmetic is IEEE binary32 with the exact
  *     expressions below, no fused multiply-add, strict "<";
  *   - randomness is Philox4x32-10 (Salmon et al., SC'11), one call per
@@ -117,6 +120,19 @@ static int mh_accept(float u, int64_t cnt_c, int64_t cnt_s, float prior,
 static int take_count_part(float u, uint64_t L, float prior_mass)
 {
     return u * ((float)L + prior_mass) < (float)L;
+}
+
+/* Smallest topic k with cum[k] > j, cum an inclusive prefix count over
+ * topics 0..K-1 and j < cum[K-1] (binary search). */
+static int32_t cdf_topic(const int64_t *cum, uint32_t K, uint32_t j)
+{
+    uint32_t lo = 0, hi = K - 1;
+    while (lo < hi) {
+        uint32_t mid = (lo + hi) / 2;
+        if (cum[mid] > (int64_t)j) hi = mid;
+        else lo = mid + 1;
+    }
+    return (int32_t)lo;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -317,20 +333,35 @@ static void word_column(oracle_t *o, uint32_t w, uint32_t iter, int64_t *ck_next
     }
     for (uint64_t n = 0; n < L; ++n) cw[o->z[beg + n]] = 0;
     for (uint64_t n = 0; n < L; ++n) o->z[beg + n] = znew[beg + n];
+    /* Words with L_w > K are the intra-word-parallel words of Section 5.4,
+     * whose word proposal the paper draws from a table built over the
+     * column's counts c_w rather than from a token position.  For them the
+     * count part is the inverse CDF of the updated c_w: j = Dice(r, L_w),
+     * and the proposal is the smallest topic k whose inclusive prefix count
+     * C(k) exceeds j.  Each token's topic occupies one unit of [0, L_w), so
+     * the law is that of random positioning. */
+    int by_cdf = L > o->K;
+    if (by_cdf) {
+        for (uint64_t n = 0; n < L; ++n) cw[o->z[beg + n]]++;
+        for (uint32_t k = 1; k < o->K; ++k) cw[k] += cw[k - 1];
+    }
     for (uint64_t n = 0; n < L; ++n) {
         uint32_t t = (uint32_t)(beg + n);
         for (uint32_t i = 1; i <= o->M; ++i) {
             uint32_t r[4];
             rng_call(o->seed, t, iter, PH_WORD, i, 0, r);
             int32_t prop;
-            if (take_count_part(unif24(r[1]), L, o->beta_k))
-                prop = o->z[beg + dice(r[2], (uint32_t)L)];
-            else
+            if (take_count_part(unif24(r[1]), L, o->beta_k)) {
+                uint32_t j = dice(r[2], (uint32_t)L);
+                prop = by_cdf ? cdf_topic(cw, o->K, j) : o->z[beg + j];
+            } else {
                 prop = (int32_t)dice(r[2], o->K);
+            }
             o->prop[(uint64_t)(i - 1) * o->T + t] = prop;
         }
         if (ck_next) ck_next[o->z[t]]++;
     }
+    if (by_cdf) memset(cw, 0, o->K * sizeof(int64_t));
 }
 
 /* Word phase, VisitByColumn with f_c (Section 4.4, Algorithm 2). */

@@ -209,7 +209,7 @@ uint64_t plan_bytes(const PhasePlan &pl, uint32_t K) {
     return align_up(4ull * pl.wave_ids.size() + 4) + align_up(9 * 4) +
            align_up(4ull * pl.block_ids.size() + 4) + align_up(9 * 4) +
            align_up(4ull * pl.long_ids.size() + 4) + align_up(4ull * pl.long_prefix.size()) +
-           align_up(4ull * pl.tab_off.back() + 4) + align_up(8ull * pl.tab_off.size()) +
+           align_up(8ull * pl.tab_off.back() + 4) + align_up(8ull * pl.tab_off.size()) +
            align_up(4ull * pl.tab_cap.size() + 4) + 2 * align_up(4ull * pl.chunk_seg.size() + 4) +
            align_up(9 * 4) + align_up(zc_bytes(pl, K));
 }
@@ -333,7 +333,7 @@ hipError_t place_plan(PhasePlan &pl, uint8_t *&cur, uint32_t K, hipStream_t st) 
     pl.d_block_cut = (uint32_t *)carve(cur, 9 * 4);
     pl.d_long_ids = (uint32_t *)carve(cur, 4ull * pl.long_ids.size() + 4);
     pl.d_long_prefix = (uint32_t *)carve(cur, 4ull * pl.long_prefix.size());
-    pl.d_tables = (uint32_t *)carve(cur, 4ull * pl.tab_off.back() + 4);
+    pl.d_tables = (uint32_t *)carve(cur, 8ull * pl.tab_off.back() + 4);   // old | updated counts
     pl.d_tab_off = (uint64_t *)carve(cur, 8ull * pl.tab_off.size());
     pl.d_tab_cap = (uint32_t *)carve(cur, 4ull * pl.tab_cap.size() + 4);
     pl.d_chunk_seg = (uint32_t *)carve(cur, 4ull * pl.chunk_seg.size() + 4);
@@ -354,7 +354,7 @@ hipError_t place_plan(PhasePlan &pl, uint8_t *&cur, uint32_t K, hipStream_t st) 
     if ((e = upload(pl.d_long_prefix, pl.long_prefix.data(), 4ull * pl.long_prefix.size(), st)))
         return e;
     (void)K;
-    return launch_fill_u32(pl.d_tables, 0, pl.tab_off.back(), st);
+    return launch_fill_u32(pl.d_tables, 0, 2 * pl.tab_off.back(), st);
 }
 
 hipError_t take_event(wlda_sampler s, hipEvent_t *e) {
@@ -397,6 +397,7 @@ LongList long_list(const PhasePlan &pl) {
     ll.tab_off = pl.d_tab_off;
     ll.tab_cap = pl.d_tab_cap;
     ll.table_words = pl.tab_off.back();
+    ll.tables_new = pl.d_tables + pl.tab_off.back();
     return ll;
 }
 

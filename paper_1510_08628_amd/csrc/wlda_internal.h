@@ -49,6 +49,10 @@ struct LongList {
     const uint32_t *tab_cap = nullptr;
     uint64_t table_words = 0;
     void *zc = nullptr;                // total compact topics (u16 if K <= 65535, else u32)
+    // Dense counts of the updated z of every word with L > K (same offsets as
+    // `tables`, which are dense for those words), turned into inclusive
+    // prefix counts for the inverse-CDF word proposals; zeroed before use.
+    uint32_t *tables_new = nullptr;
 };
 
 struct PhaseArgs {
@@ -78,6 +82,7 @@ struct Tuning {
     static constexpr uint32_t CK_LDS_MAX = 4096;             // block c_k histogram in LDS
     static constexpr uint32_t LONG_CHUNK = 4096;             // tokens per long-path chunk
     static constexpr uint32_t LDS_DENSE_MAX = 16384;         // dense LDS counts up to this K
+    static constexpr uint32_t CDF_LDS_MAX = 8192;            // long-word prefix counts in LDS
 };
 
 inline uint32_t block_max_tokens(uint32_t M) {

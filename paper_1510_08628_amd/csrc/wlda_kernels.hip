@@ -136,6 +136,68 @@ __device__ __forceinline__ void group_sync() {
     }
 }
 
+// Inclusive prefix sums of a[0..K) in place by the GROUP threads of a group
+// (each thread a contiguous run of entries); ends with a group barrier.
+template <int GROUP>
+__device__ void group_inclusive_scan(uint32_t *a, uint32_t K, uint32_t lane) {
+    const uint32_t per = (K + GROUP - 1) / GROUP;
+    const uint32_t k0 = min(K, lane * per), k1 = min(K, k0 + per);
+    uint32_t sum = 0;
+    for (uint32_t k = k0; k < k1; ++k) sum += a[k];
+    uint32_t x = sum;
+    const uint32_t wl = lane & 63;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(x, off, 64);
+        if (wl >= (uint32_t)off) x += y;
+    }
+    if constexpr (GROUP > 64) {
+        __shared__ uint32_t wsum[GROUP / 64];
+        if (wl == 63) wsum[lane >> 6] = x;
+        __syncthreads();
+        for (uint32_t w = 0; w < (lane >> 6); ++w) x += wsum[w];
+        __syncthreads();
+    }
+    uint32_t run = x - sum;
+    for (uint32_t k = k0; k < k1; ++k) {
+        run += a[k];
+        a[k] = run;
+    }
+    group_sync<GROUP>();
+}
+
+// Inverse CDF: the smallest topic k with cum[k] > j (cum inclusive prefix
+// counts over topics 0..K-1, j < cum[K-1]).
+__device__ __forceinline__ uint32_t cdf_find(const uint32_t *cum, uint32_t K, uint32_t j) {
+    uint32_t lo = 0, hi = K - 1;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (cum[mid] > j)
+            hi = mid;
+        else
+            lo = mid + 1;
+    }
+    return lo;
+}
+
+// N independent inverse-CDF lookups at once, j[d] replaced by its topic: a
+// branch-free binary search whose trip count depends on K only, so the N
+// loads of each step are in flight together.
+template <int N>
+__device__ __forceinline__ void cdf_find_n(const uint32_t *cum, uint32_t K, uint32_t (&j)[N]) {
+    uint32_t base[N];
+#pragma unroll
+    for (int d = 0; d < N; ++d) base[d] = 0;
+    for (uint32_t n = K; n > 1;) {
+        const uint32_t half = n >> 1;
+#pragma unroll
+        for (int d = 0; d < N; ++d) base[d] = cum[base[d] + half] <= j[d] ? base[d] + half : base[d];
+        n -= half;
+    }
+#pragma unroll
+    for (int d = 0; d < N; ++d) j[d] = base[d] + (cum[base[d]] <= j[d] ? 1u : 0u);
+}
+
 __device__ __forceinline__ void add_accepted(unsigned long long *dst, unsigned long long v) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
@@ -148,7 +210,7 @@ __device__ __forceinline__ void add_accepted(unsigned long long *dst, unsigned l
 // list are taken in ascending order so that the rows visited at the same time
 // are neighbours (their tokens share cache lines of each column, Section 5.2).
 // --------------------------------------------------------------------------
-template <int PHASE, int M, int NW, int GROUP, int TPT>
+template <int PHASE, int M, int NW, int GROUP, int TPT, bool CDF>
 __global__ __launch_bounds__(256) void seg_kernel(PhaseArgs a, SegList l, uint32_t cap_max,
                                                   uint32_t dense_u, uint32_t ck_lds_u) {
     extern __shared__ uint32_t lds[];
@@ -187,6 +249,9 @@ __global__ __launch_bounds__(256) void seg_kernel(PhaseArgs a, SegList l, uint32
         const uint32_t s_id = l.ids[li];
         const uint32_t beg = a.segptr[s_id];
         const uint32_t L = a.segptr[s_id + 1] - beg;
+        // word proposals of a column with L > K: inverse CDF of its updated
+        // counts (the table is dense whenever L > K: K < L <= GROUP * TPT)
+        const bool by_cdf = CDF && PHASE == PH_WORD && !a.draw_only && dense && L > K;
         uint32_t pos[TPT];
         Rec<NW> rec[TPT];
 #pragma unroll
@@ -198,7 +263,7 @@ __global__ __launch_bounds__(256) void seg_kernel(PhaseArgs a, SegList l, uint32
             }
         }
         uint32_t znew[TPT];
-        uint32_t r2[TPT][M];
+        uint32_t r2[TPT][M] = {};
         uint32_t coins = 0;   // bit r*M + i: proposal i of token r takes the count part
         if (!a.draw_only) {
             uint32_t mask = 0;
@@ -243,6 +308,14 @@ __global__ __launch_bounds__(256) void seg_kernel(PhaseArgs a, SegList l, uint32
                 for (int r = 0; r < TPT; ++r)
                     if (r * GROUP + lane < L) tcnt[fld(rec[r], 0)] = 0;
             }
+            if (by_cdf) {       // counts of the updated column, then prefix sums
+                group_sync<GROUP>();
+#pragma unroll
+                for (int r = 0; r < TPT; ++r)
+                    if (r * GROUP + lane < L) atomicAdd(&tcnt[znew[r]], 1u);
+                group_sync<GROUP>();
+                group_inclusive_scan<GROUP>(tcnt, K, lane);
+            }
         } else {
 #pragma unroll
             for (int r = 0; r < TPT; ++r) {
@@ -260,6 +333,24 @@ __global__ __launch_bounds__(256) void seg_kernel(PhaseArgs a, SegList l, uint32
 #pragma unroll
         for (int r = 0; r < TPT; ++r)
             if (r * GROUP + lane < L) zarr[r * GROUP + lane] = znew[r];
+        if (by_cdf) {           // count-part draws become topics, CDF_RB tokens at a time
+            constexpr int CDF_RB = TPT < 4 ? TPT : 4;
+#pragma unroll
+            for (int r0 = 0; r0 < TPT; r0 += CDF_RB) {
+                uint32_t jj[CDF_RB * M];
+#pragma unroll
+                for (int q = 0; q < CDF_RB; ++q)
+#pragma unroll
+                    for (int i = 0; i < M; ++i)
+                        jj[q * M + i] = dice(r2[r0 + q][i], L);   // < L: in range for any slot
+                cdf_find_n<CDF_RB * M>(tcnt, K, jj);
+#pragma unroll
+                for (int q = 0; q < CDF_RB; ++q)
+#pragma unroll
+                    for (int i = 0; i < M; ++i)
+                        if ((coins >> ((r0 + q) * M + i)) & 1u) r2[r0 + q][i] = jj[q * M + i];
+            }
+        }
         group_sync<GROUP>();
 #pragma unroll
         for (int r = 0; r < TPT; ++r) {
@@ -271,7 +362,9 @@ __global__ __launch_bounds__(256) void seg_kernel(PhaseArgs a, SegList l, uint32
 #pragma unroll
                 for (int i = 1; i <= M; ++i) {
                     const uint32_t rr = r2[r][i - 1];
-                    const uint32_t p = (coins >> (r * M + i - 1)) & 1u ? zarr[dice(rr, L)] : dice(rr, K);
+                    const uint32_t p = !((coins >> (r * M + i - 1)) & 1u) ? dice(rr, K)
+                                       : by_cdf ? rr                 // resolved above
+                                                : zarr[dice(rr, L)];
                     set_fld(out, i, p);
                 }
                 st_rec<NW>(a.recs, pos[r], out);
@@ -282,6 +375,10 @@ __global__ __launch_bounds__(256) void seg_kernel(PhaseArgs a, SegList l, uint32
             }
         }
         group_sync<GROUP>();
+        if (by_cdf) {           // prefix sums fill the table: clear all of it
+            for (uint32_t k = lane; k < K; k += GROUP) tcnt[k] = 0;
+            group_sync<GROUP>();
+        }
     }
     add_accepted(a.accepted, acc);
     __syncthreads();
@@ -427,7 +524,14 @@ __global__ __launch_bounds__(256) void long_mh_kernel(PhaseArgs a, LongList l, u
         }
         const uint32_t *ct = lds_tab ? tab : gt;
         const uint32_t ccap = lds_tab ? 0u : gcap;
-        for (uint32_t nb = n0 + threadIdx.x; nb < n1; nb += 256 * LONG_BATCH) {
+        // L > K: the word proposals take the inverse CDF of the updated
+        // counts, gathered here instead of the compact z array
+        const bool by_cdf = PHASE == PH_WORD && L > K;
+        constexpr int PER_THREAD = Tuning::LONG_CHUNK / 256;
+        uint32_t zk[PER_THREAD];
+#pragma unroll
+        for (int bt = 0; bt < PER_THREAD / LONG_BATCH; ++bt) {
+            const uint32_t nb = n0 + threadIdx.x + bt * 256 * LONG_BATCH;
             uint32_t pos[LONG_BATCH];
             Rec<NW> rec[LONG_BATCH];
 #pragma unroll
@@ -457,7 +561,28 @@ __global__ __launch_bounds__(256) void long_mh_kernel(PhaseArgs a, LongList l, u
                 }
                 set_fld(rec[u], 0, s);
                 st_rec<NW>(a.recs, pos[u], rec[u]);
-                zc[zbase + n] = (ZT)s;
+                zk[bt * LONG_BATCH + u] = s;
+                if (!by_cdf) zc[zbase + n] = (ZT)s;
+            }
+        }
+        if (by_cdf) {
+            uint32_t *nt = l.tables_new + l.tab_off[j];
+            if (lds_tab) {      // chunk histogram in LDS, then one add per topic
+                __syncthreads();
+                for (uint32_t k = threadIdx.x; k < K; k += 256) tab[k] = 0;
+                __syncthreads();
+#pragma unroll
+                for (int q = 0; q < PER_THREAD; ++q)
+                    if (n0 + threadIdx.x + q * 256 < n1) atomicAdd(&tab[zk[q]], 1u);
+                __syncthreads();
+                for (uint32_t k = threadIdx.x; k < K; k += 256) {
+                    const uint32_t c = tab[k];
+                    if (c) atomicAdd(&nt[k], c);
+                }
+            } else {
+#pragma unroll
+                for (int q = 0; q < PER_THREAD; ++q)
+                    if (n0 + threadIdx.x + q * 256 < n1) atomicAdd(&nt[zk[q]], 1u);
             }
         }
         if (lds_tab) __syncthreads();
@@ -465,12 +590,57 @@ __global__ __launch_bounds__(256) void long_mh_kernel(PhaseArgs a, LongList l, u
     add_accepted(a.accepted, acc);
 }
 
+// Inclusive prefix sums, in place, of the updated counts of every long word
+// with L > K: one workgroup per word, tiles of 4096 topics.
+__global__ __launch_bounds__(256) void long_cdf_kernel(LongList l, const uint32_t *segptr, uint32_t K) {
+    __shared__ uint32_t wsum[4];
+    constexpr int PER = 16;
+    for (uint32_t j = blockIdx.x; j < l.n; j += gridDim.x) {
+        const uint32_t s = l.ids[j];
+        if (segptr[s + 1] - segptr[s] <= K) continue;
+        uint32_t *cnt = l.tables_new + l.tab_off[j];
+        uint32_t carry = 0;
+        for (uint32_t t0 = 0; t0 < K; t0 += 256 * PER) {
+            const uint32_t k0 = t0 + threadIdx.x * PER;
+            uint32_t v[PER], sum = 0;
+#pragma unroll
+            for (int i = 0; i < PER; ++i) {
+                v[i] = k0 + i < K ? cnt[k0 + i] : 0u;
+                sum += v[i];
+            }
+            uint32_t x = sum;
+            const uint32_t wl = threadIdx.x & 63;
+#pragma unroll
+            for (int off = 1; off < 64; off <<= 1) {
+                const uint32_t y = __shfl_up(x, off, 64);
+                if (wl >= (uint32_t)off) x += y;
+            }
+            if (wl == 63) wsum[threadIdx.x >> 6] = x;
+            __syncthreads();
+            uint32_t base = carry;
+            for (uint32_t w = 0; w < (threadIdx.x >> 6); ++w) base += wsum[w];
+            const uint32_t tile = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+            uint32_t run = base + x - sum;
+#pragma unroll
+            for (int i = 0; i < PER; ++i) {
+                run += v[i];
+                if (k0 + i < K) cnt[k0 + i] = run;
+            }
+            carry += tile;
+            __syncthreads();
+        }
+    }
+}
+
 template <int PHASE, int M, int NW, typename ZT>
 __global__ __launch_bounds__(256) void long_draw_kernel(PhaseArgs a, LongList l, uint32_t ck_lds_u,
-                                                        uint32_t zero_tables) {
+                                                        uint32_t zero_tables, uint32_t cdf_lds_u) {
+    // LDS: [c_k histogram of the new Z (ck_lds) | prefix counts of the
+    // current word (cdf_lds, words with L > K)]
     extern __shared__ uint32_t ckh[];
-    const bool ck_lds = ck_lds_u != 0;
+    const bool ck_lds = ck_lds_u != 0, cdf_lds = cdf_lds_u != 0;
     const uint32_t K = a.K;
+    uint32_t *cdfl = ckh + (ck_lds ? K : 0);
     const uint32_t ph = (uint32_t)PHASE << 16;
     const ZT *zc = reinterpret_cast<const ZT *>(l.zc);
     if (ck_lds) {
@@ -483,6 +653,12 @@ __global__ __launch_bounds__(256) void long_draw_kernel(PhaseArgs a, LongList l,
         const uint32_t beg = a.segptr[s_id], L = a.segptr[s_id + 1] - beg;
         const uint32_t n1 = min(L, n0 + Tuning::LONG_CHUNK);
         const ZT *zs = zc + l.prefix[j];
+        const bool by_cdf = PHASE == PH_WORD && L > K;
+        const uint32_t *cum = l.tables_new + l.tab_off[j];
+        if (by_cdf && cdf_lds) {
+            for (uint32_t k = threadIdx.x; k < K; k += 256) cdfl[k] = cum[k];
+            __syncthreads();
+        }
         for (uint32_t nb = n0 + threadIdx.x; nb < n1; nb += 256 * LONG_BATCH) {
             uint32_t pos[LONG_BATCH];
             Rec<NW> rec[LONG_BATCH];
@@ -494,8 +670,10 @@ __global__ __launch_bounds__(256) void long_draw_kernel(PhaseArgs a, LongList l,
                     rec[u] = ld_rec<NW>(a.recs, pos[u]);
                 }
             }
-            // all random-positioning reads of the batch are issued before
-            // any record is written back
+            // all random-positioning reads (or CDF lookups) of the batch are
+            // issued before any record is written back
+            uint32_t jj[LONG_BATCH * M] = {};
+            uint32_t coin = 0;
 #pragma unroll
             for (int u = 0; u < LONG_BATCH; ++u) {
                 const uint32_t n = nb + u * 256;
@@ -503,10 +681,23 @@ __global__ __launch_bounds__(256) void long_draw_kernel(PhaseArgs a, LongList l,
 #pragma unroll
                 for (int i = 1; i <= M; ++i) {
                     const uint4 R = philox(beg + n, a.iter, ph | i, 0, a.seed_lo, a.seed_hi);
-                    const uint32_t p =
-                        take_count_part(unif24(R.y), L, a.mass) ? (uint32_t)zs[dice(R.z, L)] : dice(R.z, K);
-                    set_fld(rec[u], i, p);
+                    if (take_count_part(unif24(R.y), L, a.mass)) {
+                        coin |= 1u << (u * M + i - 1);
+                        jj[u * M + i - 1] = dice(R.z, L);
+                        if (!by_cdf) set_fld(rec[u], i, (uint32_t)zs[jj[u * M + i - 1]]);
+                    } else {
+                        set_fld(rec[u], i, dice(R.z, K));
+                    }
                 }
+            }
+            if (by_cdf) {
+                if (cdf_lds)
+                    cdf_find_n<LONG_BATCH * M>(cdfl, K, jj);
+                else
+                    cdf_find_n<LONG_BATCH * M>(cum, K, jj);
+#pragma unroll
+                for (int d = 0; d < LONG_BATCH * M; ++d)
+                    if ((coin >> d) & 1u) set_fld(rec[d / M], d % M + 1, jj[d]);
             }
 #pragma unroll
             for (int u = 0; u < LONG_BATCH; ++u) {
@@ -519,6 +710,7 @@ __global__ __launch_bounds__(256) void long_draw_kernel(PhaseArgs a, LongList l,
                     atomicAdd(&a.ck_next[z], 1u);
             }
         }
+        if (by_cdf && cdf_lds) __syncthreads();
     }
     if (zero_tables) {
         const size_t nt = l.table_words;
@@ -710,16 +902,15 @@ static hipError_t launch_dyn(Kern k, dim3 grid, size_t lds, hipStream_t st) {
     return hipSuccess;
 }
 
-template <int PHASE, int M, int NW, int GROUP, int TPT>
-static hipError_t run_seg(const PhaseArgs &a, const SegList &l, uint32_t cap_bound, hipStream_t st) {
-    if (l.n == 0) return hipSuccess;
+template <int PHASE, int M, int NW, int GROUP, int TPT, bool CDF>
+static hipError_t run_seg_k(const PhaseArgs &a, const SegList &l, uint32_t cap_bound, hipStream_t st) {
     const bool dense = a.K <= cap_bound;
     const bool ck_lds = a.K <= Tuning::CK_LDS_MAX;
     const uint32_t cap_max = dense ? 0 : cap_bound;
     const uint32_t tab_words = dense ? a.K : 2 * cap_max;
     constexpr int GPB = 256 / GROUP;
     const size_t lds = 4ull * ((ck_lds ? 2 * a.K : 0) + GPB * (tab_words + GROUP * TPT));
-    auto kern = seg_kernel<PHASE, M, NW, GROUP, TPT>;
+    auto kern = seg_kernel<PHASE, M, NW, GROUP, TPT, CDF>;
     hipError_t e = launch_dyn(kern, dim3(1), lds, st);
     if (e != hipSuccess) return e;
     // Blocks are assigned to XCDs round robin; use a multiple of 8 and
@@ -731,6 +922,19 @@ static hipError_t run_seg(const PhaseArgs &a, const SegList &l, uint32_t cap_bou
     hipLaunchKernelGGL(kern, dim3(blocks), dim3(256), lds, st, a, l, cap_max, (uint32_t)dense,
                        (uint32_t)ck_lds);
     return hipGetLastError();
+}
+
+// The inverse-CDF word proposals (columns with L > K) are compiled in only
+// where the bin can hold such a column, so the other variants keep their
+// register budget.
+template <int PHASE, int M, int NW, int GROUP, int TPT>
+static hipError_t run_seg(const PhaseArgs &a, const SegList &l, uint32_t cap_bound, hipStream_t st) {
+    if (l.n == 0) return hipSuccess;
+    if constexpr (PHASE == PH_WORD) {
+        if (!a.draw_only && a.K < (uint32_t)(GROUP * TPT))
+            return run_seg_k<PHASE, M, NW, GROUP, TPT, true>(a, l, cap_bound, st);
+    }
+    return run_seg_k<PHASE, M, NW, GROUP, TPT, false>(a, l, cap_bound, st);
 }
 
 template <int PHASE, int M>
@@ -790,6 +994,9 @@ static hipError_t long_dispatch_z(const PhaseArgs &a, const LongList &l, hipStre
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     if (ev && (e = hipEventRecord(ev[1], st)) != hipSuccess) return e;
+    if (PHASE == PH_WORD && !a.draw_only) {
+        if ((e = launch_fill_u32(l.tables_new, 0, l.table_words, st)) != hipSuccess) return e;
+    }
     {
         const bool mh_tab = lds_tab && !a.draw_only, mh_ck = ck_lds && !a.draw_only;
         const size_t lds = 4ull * ((mh_tab ? a.K : 0) + (mh_ck ? a.K : 0));
@@ -800,11 +1007,16 @@ static hipError_t long_dispatch_z(const PhaseArgs &a, const LongList &l, hipStre
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     if (ev && (e = hipEventRecord(ev[2], st)) != hipSuccess) return e;
-    const size_t lds = ck_lds ? 4ull * a.K : 0;
+    const bool cdf_lds = PHASE == PH_WORD && a.K <= Tuning::CDF_LDS_MAX;
+    if (PHASE == PH_WORD && !a.draw_only) {
+        hipLaunchKernelGGL(long_cdf_kernel, dim3(l.n < 1024 ? l.n : 1024), dim3(256), 0, st, l, a.segptr, a.K);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    const size_t lds = 4ull * ((ck_lds ? a.K : 0) + (cdf_lds ? a.K : 0));
     e = launch_dyn(long_draw_kernel<PHASE, M, NW, ZT>, dim3(1), lds, st);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((long_draw_kernel<PHASE, M, NW, ZT>), dim3(blocks), dim3(256), lds, st, a, l,
-                       (uint32_t)ck_lds, (uint32_t)(a.draw_only ? 0 : 1));
+                       (uint32_t)ck_lds, (uint32_t)(a.draw_only ? 0 : 1), (uint32_t)cdf_lds);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (ev) return hipEventRecord(ev[3], st);
     return hipSuccess;
