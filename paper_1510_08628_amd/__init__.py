@@ -80,6 +80,10 @@ def load_library(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise ImportError(f"{path} is not built; run __graft_entry__.build()")
+    # torch first: its bundled HIP runtime must be the one this library binds
+    # to, or device pointers and streams from torch would belong to another
+    # runtime instance in the same process
+    import torch  # noqa: F401
     L = C.CDLL(path)
     vp, u32, u64, i32 = C.c_void_p, C.c_uint32, C.c_uint64, C.c_int
     P = C.POINTER(Params)

@@ -22,14 +22,21 @@ namespace {
 constexpr uint64_t ALIGN = 256;
 inline uint64_t align_up(uint64_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
 
+// Segment ids of one bin, in ascending order, cut into eight XCD shares.
+struct BinList {
+    std::vector<uint32_t> ids;
+    uint32_t cut[9] = {};
+    uint32_t *d_ids = nullptr, *d_cut = nullptr;   // device copies
+};
+
 struct PhasePlan {
-    std::vector<uint32_t> wave_ids, block_ids, long_ids, long_prefix;
+    BinList bins[NBINS];
+    std::vector<uint32_t> long_ids, long_prefix;
     std::vector<uint32_t> chunk_seg, chunk_start, tab_cap;
     std::vector<uint64_t> tab_off;          // n+1 word offsets of the per-segment tables
-    uint32_t wave_cut[9] = {}, block_cut[9] = {}, chunk_cut[9] = {};
+    uint32_t chunk_cut[9] = {};
     // device copies (inside the workspace)
-    uint32_t *d_wave_ids = nullptr, *d_wave_cut = nullptr, *d_block_ids = nullptr,
-             *d_block_cut = nullptr, *d_long_ids = nullptr, *d_long_prefix = nullptr,
+    uint32_t *d_long_ids = nullptr, *d_long_prefix = nullptr,
              *d_tables = nullptr, *d_chunk_seg = nullptr, *d_chunk_start = nullptr,
              *d_chunk_cut = nullptr, *d_tab_cap = nullptr;
     uint64_t *d_tab_off = nullptr;
@@ -58,25 +65,25 @@ uint32_t pow2_ge(uint64_t x) {
     return (uint32_t)c;
 }
 
-void build_plan(const std::vector<uint64_t> &len, uint32_t block_max, uint32_t K, PhasePlan &pl) {
-    pl.wave_ids.clear();
-    pl.block_ids.clear();
+// Each segment goes to the first bin that holds its length (wave, block,
+// wide), else to the long path.
+void build_plan(const std::vector<uint64_t> &len, uint32_t M, uint32_t K, PhasePlan &pl) {
+    for (BinList &b : pl.bins) b.ids.clear();
     pl.long_ids.clear();
     pl.long_prefix.assign(1, 0);
     for (uint32_t s = 0; s < len.size(); ++s) {
         const uint64_t L = len[s];
         if (L == 0) continue;
-        if (L <= Tuning::WAVE_MAX)
-            pl.wave_ids.push_back(s);
-        else if (L <= block_max)
-            pl.block_ids.push_back(s);
-        else {
+        int bin = 0;
+        while (bin < NBINS && L > bin_max_tokens(bin, M)) ++bin;
+        if (bin < NBINS) {
+            pl.bins[bin].ids.push_back(s);
+        } else {
             pl.long_ids.push_back(s);
             pl.long_prefix.push_back((uint32_t)(pl.long_prefix.back() + L));
         }
     }
-    xcd_cuts(pl.wave_ids, len, pl.wave_cut);
-    xcd_cuts(pl.block_ids, len, pl.block_cut);
+    for (BinList &b : pl.bins) xcd_cuts(b.ids, len, b.cut);
     // Long segments whose compact z fits comfortably in one XCD's L2 go whole
     // to one XCD: longest first, each to the XCD with the fewest tokens so far
     // (the greedy balanced partition of the paper's Section 5.3, over the
@@ -174,8 +181,8 @@ void build_layout(const PhasePlan &wp, const PhasePlan &dp, const std::vector<ui
             run += ld[d];
         }
     };
-    for (int x = 0; x < 8; ++x) cut(dp.wave_ids, dp.wave_cut[x], dp.wave_cut[x + 1], false);
-    for (int x = 0; x < 8; ++x) cut(dp.block_ids, dp.block_cut[x], dp.block_cut[x + 1], false);
+    for (const BinList &b : dp.bins)
+        for (int x = 0; x < 8; ++x) cut(b.ids, b.cut[x], b.cut[x + 1], false);
     cut(dp.long_ids, 0, (uint32_t)dp.long_ids.size(), true);
     uint64_t off = 0;
     for (uint64_t &v : start) {
@@ -183,8 +190,8 @@ void build_layout(const PhasePlan &wp, const PhasePlan &dp, const std::vector<ui
         v = off;
         off += n;
     }
-    std::vector<uint32_t> words(wp.wave_ids);
-    words.insert(words.end(), wp.block_ids.begin(), wp.block_ids.end());
+    std::vector<uint32_t> words;
+    for (const BinList &b : wp.bins) words.insert(words.end(), b.ids.begin(), b.ids.end());
     std::vector<char> seen(wp.long_ids.size(), 0);
     for (uint32_t j : wp.chunk_seg)
         if (!seen[j]) {
@@ -206,9 +213,9 @@ struct Sizes {
 };
 
 uint64_t plan_bytes(const PhasePlan &pl, uint32_t K) {
-    return align_up(4ull * pl.wave_ids.size() + 4) + align_up(9 * 4) +
-           align_up(4ull * pl.block_ids.size() + 4) + align_up(9 * 4) +
-           align_up(4ull * pl.long_ids.size() + 4) + align_up(4ull * pl.long_prefix.size()) +
+    uint64_t b = 0;
+    for (const BinList &bl : pl.bins) b += align_up(4ull * bl.ids.size() + 4) + align_up(9 * 4);
+    return b + align_up(4ull * pl.long_ids.size() + 4) + align_up(4ull * pl.long_prefix.size()) +
            align_up(8ull * pl.tab_off.back() + 4) + align_up(8ull * pl.tab_off.size()) +
            align_up(4ull * pl.tab_cap.size() + 4) + 2 * align_up(4ull * pl.chunk_seg.size() + 4) +
            align_up(9 * 4) + align_up(zc_bytes(pl, K));
@@ -253,12 +260,12 @@ void lengths(const wlda_params &p, const uint32_t *word_ids, const uint32_t *doc
 }
 
 enum Slot {
-    S_WORD_WAVE, S_WORD_BLOCK, S_WORD_LONG_HIST, S_WORD_LONG_MH, S_WORD_LONG_DRAW,
-    S_DOC_WAVE, S_DOC_BLOCK, S_DOC_LONG_HIST, S_DOC_LONG_MH, S_DOC_LONG_DRAW, KSLOTS
+    S_WORD_WAVE, S_WORD_BLOCK, S_WORD_WIDE, S_WORD_LONG_HIST, S_WORD_LONG_MH, S_WORD_LONG_DRAW,
+    S_DOC_WAVE, S_DOC_BLOCK, S_DOC_WIDE, S_DOC_LONG_HIST, S_DOC_LONG_MH, S_DOC_LONG_DRAW, KSLOTS
 };
 const char *const SLOT_NAMES[KSLOTS] = {
-    "word_wave", "word_block", "word_long_hist", "word_long_mh", "word_long_draw",
-    "doc_wave", "doc_block", "doc_long_hist", "doc_long_mh", "doc_long_draw"};
+    "word_wave", "word_block", "word_wide", "word_long_hist", "word_long_mh", "word_long_draw",
+    "doc_wave", "doc_block", "doc_wide", "doc_long_hist", "doc_long_mh", "doc_long_draw"};
 
 uint64_t list_tokens(const std::vector<uint32_t> &ids, const std::vector<uint64_t> &len) {
     uint64_t t = 0;
@@ -295,9 +302,9 @@ struct wlda_sampler_s {
     size_t ev_used = 0;
     uint64_t slot_tokens[KSLOTS] = {};
     // launch-shape bounds (grid size of the segment kernels), per phase and
-    // kernel kind: [word wave, word block, doc wave, doc block]; overridable
-    // with WLDA_SEG_BLOCKS="a,b,c,d" for tuning sweeps
-    uint32_t seg_blocks[4] = {1024, 1024, 2048, 2048};
+    // bin: [word wave, block, wide, doc wave, block, wide]; overridable with
+    // WLDA_SEG_BLOCKS="a,b,c,d,e,f" for tuning sweeps
+    uint32_t seg_blocks[2 * NBINS] = {1024, 1024, 1024, 2048, 2048, 2048};
 };
 
 namespace {
@@ -327,10 +334,10 @@ hipError_t upload(void *dst, const void *src, uint64_t bytes, hipStream_t st) {
 }
 
 hipError_t place_plan(PhasePlan &pl, uint8_t *&cur, uint32_t K, hipStream_t st) {
-    pl.d_wave_ids = (uint32_t *)carve(cur, 4ull * pl.wave_ids.size() + 4);
-    pl.d_wave_cut = (uint32_t *)carve(cur, 9 * 4);
-    pl.d_block_ids = (uint32_t *)carve(cur, 4ull * pl.block_ids.size() + 4);
-    pl.d_block_cut = (uint32_t *)carve(cur, 9 * 4);
+    for (BinList &b : pl.bins) {
+        b.d_ids = (uint32_t *)carve(cur, 4ull * b.ids.size() + 4);
+        b.d_cut = (uint32_t *)carve(cur, 9 * 4);
+    }
     pl.d_long_ids = (uint32_t *)carve(cur, 4ull * pl.long_ids.size() + 4);
     pl.d_long_prefix = (uint32_t *)carve(cur, 4ull * pl.long_prefix.size());
     pl.d_tables = (uint32_t *)carve(cur, 8ull * pl.tab_off.back() + 4);   // old | updated counts
@@ -346,10 +353,10 @@ hipError_t place_plan(PhasePlan &pl, uint8_t *&cur, uint32_t K, hipStream_t st) 
     if ((e = upload(pl.d_chunk_cut, pl.chunk_cut, 9 * 4, st))) return e;
     if ((e = upload(pl.d_tab_off, pl.tab_off.data(), 8ull * pl.tab_off.size(), st))) return e;
     if ((e = upload(pl.d_tab_cap, pl.tab_cap.data(), 4ull * pl.tab_cap.size(), st))) return e;
-    if ((e = upload(pl.d_wave_ids, pl.wave_ids.data(), 4ull * pl.wave_ids.size(), st))) return e;
-    if ((e = upload(pl.d_wave_cut, pl.wave_cut, 9 * 4, st))) return e;
-    if ((e = upload(pl.d_block_ids, pl.block_ids.data(), 4ull * pl.block_ids.size(), st))) return e;
-    if ((e = upload(pl.d_block_cut, pl.block_cut, 9 * 4, st))) return e;
+    for (BinList &b : pl.bins) {
+        if ((e = upload(b.d_ids, b.ids.data(), 4ull * b.ids.size(), st))) return e;
+        if ((e = upload(b.d_cut, b.cut, 9 * 4, st))) return e;
+    }
     if ((e = upload(pl.d_long_ids, pl.long_ids.data(), 4ull * pl.long_ids.size(), st))) return e;
     if ((e = upload(pl.d_long_prefix, pl.long_prefix.data(), 4ull * pl.long_prefix.size(), st)))
         return e;
@@ -422,28 +429,31 @@ wlda_status run_phase(wlda_sampler s, uint32_t phase, uint32_t iter, bool draw_o
     a.draw_only = draw_only ? 1 : 0;
     WLDA_TRY(s, launch_fill_u32(a.ck_next, 0, s->p.K, s->st));
     WLDA_TRY(s, launch_fill_u32((uint32_t *)a.accepted, 0, 2, s->st));
-    const int kb = phase == PH_WORD ? 0 : 2;
-    SegList wl{pl.d_wave_ids, (uint32_t)pl.wave_ids.size(), pl.d_wave_cut};
-    SegList bl{pl.d_block_ids, (uint32_t)pl.block_ids.size(), pl.d_block_cut};
+    const int kb = phase == PH_WORD ? 0 : NBINS;
     LongList ll = long_list(pl);
     const int base = phase == PH_WORD ? S_WORD_WAVE : S_DOC_WAVE;
     const bool prof = s->prof && !draw_only;
+    for (int bin = 0; bin < NBINS; ++bin) {
+        const BinList &b = pl.bins[bin];
+        const SegList l{b.d_ids, (uint32_t)b.ids.size(), b.d_cut};
+        a.max_blocks = s->seg_blocks[kb + bin];
+        auto launch = [&] {
+            return bin == BIN_WAVE ? launch_wave_segments(a, phase, s->p.M, l, s->st)
+                                   : launch_block_segments(a, phase, s->p.M, l, bin, s->st);
+        };
+        if (prof)
+            WLDA_TRY(s, timed(s, base + bin, launch));
+        else
+            WLDA_TRY(s, launch());
+    }
     if (prof) {
-        a.max_blocks = s->seg_blocks[kb];
-        WLDA_TRY(s, timed(s, base + 0, [&] { return launch_wave_segments(a, phase, s->p.M, wl, s->st); }));
-        a.max_blocks = s->seg_blocks[kb + 1];
-        WLDA_TRY(s, timed(s, base + 1, [&] { return launch_block_segments(a, phase, s->p.M, bl, s->st); }));
         if (ll.n) {
             hipEvent_t ev[4];
             for (int i = 0; i < 4; ++i) WLDA_TRY(s, take_event(s, &ev[i]));
             WLDA_TRY(s, launch_long_segments(a, phase, s->p.M, ll, s->st, ev));
-            for (int i = 0; i < 3; ++i) s->ev_pairs[base + 2 + i].push_back({ev[i], ev[i + 1]});
+            for (int i = 0; i < 3; ++i) s->ev_pairs[base + NBINS + i].push_back({ev[i], ev[i + 1]});
         }
     } else {
-        a.max_blocks = s->seg_blocks[kb];
-        WLDA_TRY(s, launch_wave_segments(a, phase, s->p.M, wl, s->st));
-        a.max_blocks = s->seg_blocks[kb + 1];
-        WLDA_TRY(s, launch_block_segments(a, phase, s->p.M, bl, s->st));
         WLDA_TRY(s, launch_long_segments(a, phase, s->p.M, ll, s->st));
     }
     s->cur = 1 - s->cur;
@@ -498,8 +508,8 @@ wlda_status wlda_workspace_bytes(const wlda_params *p, const uint32_t *word_ids,
     std::vector<uint64_t> lw, ld;
     lengths(*p, word_ids, doc_ids, n_tokens, lw, ld);
     PhasePlan w, d;
-    build_plan(lw, block_max_tokens(p->M), p->K, w);
-    build_plan(ld, block_max_tokens(p->M), p->K, d);
+    build_plan(lw, p->M, p->K, w);
+    build_plan(ld, p->M, p->K, d);
     *bytes = compute_sizes(*p, n_tokens, w, d).total;
     return WLDA_OK;
 }
@@ -524,22 +534,22 @@ wlda_status wlda_create(const wlda_params *p, const uint32_t *word_ids, const ui
     s->beta_k = (float)p->K * s->b;
     s->beta_bar = (float)p->V * s->b;
     if (const char *env = std::getenv("WLDA_SEG_BLOCKS")) {
-        unsigned v[4];
-        if (std::sscanf(env, "%u,%u,%u,%u", &v[0], &v[1], &v[2], &v[3]) == 4)
-            for (int i = 0; i < 4; ++i) s->seg_blocks[i] = v[i] < 8 ? 8 : (v[i] > 65536 ? 65536 : v[i]);
+        unsigned v[2 * NBINS];
+        if (std::sscanf(env, "%u,%u,%u,%u,%u,%u", &v[0], &v[1], &v[2], &v[3], &v[4], &v[5]) == 2 * NBINS)
+            for (int i = 0; i < 2 * NBINS; ++i) s->seg_blocks[i] = v[i] < 8 ? 8 : (v[i] > 65536 ? 65536 : v[i]);
     }
 
     // ---- layout: stable order by (word, doc, input index) -------------------
     std::vector<uint64_t> lw, ld;
     lengths(*p, word_ids, doc_ids, T, lw, ld);
-    build_plan(lw, block_max_tokens(p->M), p->K, s->word);
-    build_plan(ld, block_max_tokens(p->M), p->K, s->doc);
-    s->slot_tokens[S_WORD_WAVE] = list_tokens(s->word.wave_ids, lw);
-    s->slot_tokens[S_WORD_BLOCK] = list_tokens(s->word.block_ids, lw);
+    build_plan(lw, p->M, p->K, s->word);
+    build_plan(ld, p->M, p->K, s->doc);
+    for (int bin = 0; bin < NBINS; ++bin) {
+        s->slot_tokens[S_WORD_WAVE + bin] = list_tokens(s->word.bins[bin].ids, lw);
+        s->slot_tokens[S_DOC_WAVE + bin] = list_tokens(s->doc.bins[bin].ids, ld);
+    }
     s->slot_tokens[S_WORD_LONG_HIST] = s->slot_tokens[S_WORD_LONG_MH] =
         s->slot_tokens[S_WORD_LONG_DRAW] = s->word.long_prefix.back();
-    s->slot_tokens[S_DOC_WAVE] = list_tokens(s->doc.wave_ids, ld);
-    s->slot_tokens[S_DOC_BLOCK] = list_tokens(s->doc.block_ids, ld);
     s->slot_tokens[S_DOC_LONG_HIST] = s->slot_tokens[S_DOC_LONG_MH] =
         s->slot_tokens[S_DOC_LONG_DRAW] = s->doc.long_prefix.back();
     const Sizes sz = compute_sizes(*p, T, s->word, s->doc);
@@ -677,10 +687,9 @@ wlda_status wlda_log_likelihood(wlda_sampler s, double *ll) {
         const double prior = ph == PH_WORD ? s->p.beta : s->p.alpha;
         const double total = ph == PH_WORD ? 0.0 : (double)K * s->p.alpha;
         const int lt = ph == PH_DOC;
-        WLDA_TRY(s, launch_ll_list(s->recs, s->p.M, segptr, idx, pl.d_wave_ids,
-                                   (uint32_t)pl.wave_ids.size(), K, prior, total, lt, s->ll, s->st));
-        WLDA_TRY(s, launch_ll_list(s->recs, s->p.M, segptr, idx, pl.d_block_ids,
-                                   (uint32_t)pl.block_ids.size(), K, prior, total, lt, s->ll, s->st));
+        for (const BinList &b : pl.bins)
+            WLDA_TRY(s, launch_ll_list(s->recs, s->p.M, segptr, idx, b.d_ids, (uint32_t)b.ids.size(), K,
+                                       prior, total, lt, s->ll, s->st));
         PhaseArgs a;
         a.recs = s->recs;
         a.segptr = segptr;

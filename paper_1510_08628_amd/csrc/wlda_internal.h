@@ -74,19 +74,29 @@ struct Tuning {
     // wave kernel: segments of at most 64 * TPT_WAVE tokens
     static constexpr int TPT_WAVE = 8;
     static constexpr uint32_t WAVE_MAX = 64 * TPT_WAVE;
-    static constexpr uint32_t WAVE_CAP = 2 * WAVE_MAX;       // hash capacity bound
-    // block kernel: segments of at most 256 * TPT_BLOCK tokens
-    static constexpr int TPT_BLOCK = 16;
-    static constexpr uint32_t BLOCK_MAX = 256 * TPT_BLOCK;
-    static constexpr uint32_t BLOCK_CAP = 2 * BLOCK_MAX;
+    // block kernels (one 256-thread workgroup per segment): the narrow one
+    // keeps TPT_BLOCK tokens per thread in registers (high occupancy), the
+    // wide one twice as many; M > 2 halves both (two-word records)
+    static constexpr int TPT_BLOCK = 8;
+    static constexpr int TPT_WIDE = 16;
+    static constexpr uint32_t WIDE_MAX = 256 * TPT_WIDE;     // longest segment below the long path
     static constexpr uint32_t CK_LDS_MAX = 4096;             // block c_k histogram in LDS
     static constexpr uint32_t LONG_CHUNK = 4096;             // tokens per long-path chunk
     static constexpr uint32_t LDS_DENSE_MAX = 16384;         // dense LDS counts up to this K
     static constexpr uint32_t CDF_LDS_MAX = 8192;            // long-word prefix counts in LDS
 };
 
-inline uint32_t block_max_tokens(uint32_t M) {
-    return M <= 2 ? Tuning::BLOCK_MAX : Tuning::BLOCK_MAX / 2;
+// Segment bins below the long path, by length: the wave kernel, the narrow
+// and the wide block kernel.
+enum Bin : int { BIN_WAVE = 0, BIN_BLOCK = 1, BIN_WIDE = 2, NBINS = 3 };
+
+inline uint32_t bin_tpt(int bin, uint32_t M) {
+    const int t = bin == BIN_WAVE ? Tuning::TPT_WAVE : bin == BIN_BLOCK ? Tuning::TPT_BLOCK : Tuning::TPT_WIDE;
+    return bin == BIN_WAVE || M <= 2 ? (uint32_t)t : (uint32_t)t / 2;
+}
+
+inline uint32_t bin_max_tokens(int bin, uint32_t M) {
+    return (bin == BIN_WAVE ? 64u : 256u) * bin_tpt(bin, M);
 }
 
 // ---- launchers (all enqueue on `st`, return hipError_t of the launch) ----
@@ -95,8 +105,9 @@ hipError_t launch_init_z(uint64_t *recs, const uint32_t *colidx, uint32_t T, uin
                          uint32_t seed_lo, uint32_t seed_hi, hipStream_t st);
 hipError_t launch_wave_segments(const PhaseArgs &a, uint32_t phase, uint32_t M,
                                 const SegList &l, hipStream_t st);
+// bin = BIN_BLOCK or BIN_WIDE
 hipError_t launch_block_segments(const PhaseArgs &a, uint32_t phase, uint32_t M,
-                                 const SegList &l, hipStream_t st);
+                                 const SegList &l, int bin, hipStream_t st);
 // Records ev[0..3] (if non-null) before the histogram, MH and draw kernels and
 // after the draw kernel, so that the host can time each of them.
 hipError_t launch_long_segments(const PhaseArgs &a, uint32_t phase, uint32_t M,

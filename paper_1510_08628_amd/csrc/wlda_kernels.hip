@@ -522,8 +522,6 @@ __global__ __launch_bounds__(256) void long_mh_kernel(PhaseArgs a, LongList l, u
             for (uint32_t k = threadIdx.x; k < K; k += 256) tab[k] = gt[k];
             __syncthreads();
         }
-        const uint32_t *ct = lds_tab ? tab : gt;
-        const uint32_t ccap = lds_tab ? 0u : gcap;
         // L > K: the word proposals take the inverse CDF of the updated
         // counts, gathered here instead of the compact z array
         const bool by_cdf = PHASE == PH_WORD && L > K;
@@ -551,7 +549,16 @@ __global__ __launch_bounds__(256) void long_mh_kernel(PhaseArgs a, LongList l, u
                 for (int i = 1; i <= M; ++i) {
                     const uint4 R = philox(beg + n, a.iter, ph | i, 0, a.seed_lo, a.seed_hi);
                     const uint32_t c = fld(rec[u], i);
-                    const uint32_t cc = gtab_get(ct, ccap, c), cs = gtab_get(ct, ccap, s);
+                    // separate paths keep LDS reads as ds_read (a pointer
+                    // selected at run time would force flat loads)
+                    uint32_t cc, cs;
+                    if (lds_tab) {
+                        cc = tab[c];
+                        cs = tab[s];
+                    } else {
+                        cc = gtab_get(gt, gcap, c);
+                        cs = gtab_get(gt, gcap, s);
+                    }
                     const bool ok = ck_lds ? mh_accept_b(unif24(R.x), cc, cs, a.prior, ckb[s], ckb[c])
                                            : mh_accept(unif24(R.x), cc, cs, a.prior, a.ck[s], a.ck[c], a.beta_bar);
                     if (ok) {
@@ -937,17 +944,20 @@ static hipError_t run_seg(const PhaseArgs &a, const SegList &l, uint32_t cap_bou
     return run_seg_k<PHASE, M, NW, GROUP, TPT, false>(a, l, cap_bound, st);
 }
 
+// Hash capacity bound of a bin: the power of two >= 2L for its longest segment.
 template <int PHASE, int M>
 static hipError_t wave_dispatch(const PhaseArgs &a, const SegList &l, hipStream_t st) {
     constexpr int NW = (M + 3) / 3;
-    return run_seg<PHASE, M, NW, 64, Tuning::TPT_WAVE>(a, l, Tuning::WAVE_CAP, st);
+    return run_seg<PHASE, M, NW, 64, Tuning::TPT_WAVE>(a, l, 2 * Tuning::WAVE_MAX, st);
 }
 
 template <int PHASE, int M>
-static hipError_t block_dispatch(const PhaseArgs &a, const SegList &l, hipStream_t st) {
+static hipError_t block_dispatch(const PhaseArgs &a, const SegList &l, int bin, hipStream_t st) {
     constexpr int NW = (M + 3) / 3;
-    constexpr int TPT = M <= 2 ? Tuning::TPT_BLOCK : Tuning::TPT_BLOCK / 2;
-    return run_seg<PHASE, M, NW, 256, TPT>(a, l, 2 * 256 * TPT, st);
+    constexpr int TB = M <= 2 ? Tuning::TPT_BLOCK : Tuning::TPT_BLOCK / 2;
+    constexpr int TW = M <= 2 ? Tuning::TPT_WIDE : Tuning::TPT_WIDE / 2;
+    if (bin == BIN_WIDE) return run_seg<PHASE, M, NW, 256, TW>(a, l, 2 * 256 * TW, st);
+    return run_seg<PHASE, M, NW, 256, TB>(a, l, 2 * 256 * TB, st);
 }
 
 #define WLDA_DISPATCH_M(FN, PHASE, ...)                                 \
@@ -967,12 +977,12 @@ hipError_t launch_wave_segments(const PhaseArgs &a, uint32_t phase, uint32_t M, 
     WLDA_DISPATCH_M(wave_dispatch, PH_DOC, a, l, st)
 }
 
-hipError_t launch_block_segments(const PhaseArgs &a, uint32_t phase, uint32_t M, const SegList &l,
+hipError_t launch_block_segments(const PhaseArgs &a, uint32_t phase, uint32_t M, const SegList &l, int bin,
                                  hipStream_t st) {
     if (phase == PH_WORD) {
-        WLDA_DISPATCH_M(block_dispatch, PH_WORD, a, l, st)
+        WLDA_DISPATCH_M(block_dispatch, PH_WORD, a, l, bin, st)
     }
-    WLDA_DISPATCH_M(block_dispatch, PH_DOC, a, l, st)
+    WLDA_DISPATCH_M(block_dispatch, PH_DOC, a, l, bin, st)
 }
 
 template <int PHASE, int M, typename ZT>
@@ -1054,7 +1064,7 @@ hipError_t launch_ll_list(const uint64_t *recs, uint32_t M, const uint32_t *segp
                           int length_term, double *out, hipStream_t st) {
     if (n == 0) return hipSuccess;
     const bool dense = K <= Tuning::LDS_DENSE_MAX;
-    const size_t lds = dense ? 4ull * K : 4ull * 2 * 2 * Tuning::BLOCK_MAX;
+    const size_t lds = dense ? 4ull * K : 4ull * 2 * 2 * Tuning::WIDE_MAX;
     const int blocks = n < 4096 ? (int)n : 4096;
     hipError_t e;
     if (record_words(M) == 1) {

@@ -111,7 +111,7 @@ def test_all_paths_bit_exact(W, K, M):
 
 
 @pytest.mark.parametrize("case", ["one_token", "one_doc_one_word", "k1", "all_same_cell",
-                                  "empty_rows_cols", "ragged_tail"])
+                                  "empty_rows_cols", "ragged_tail", "ragged_tail_m4"])
 def test_edge_cases(W, case):
     rng = np.random.default_rng(3)
     if case == "one_token":
@@ -132,12 +132,14 @@ def test_edge_cases(W, case):
         c = synth.Corpus(w, d, 100, 100)
         K, M = 64, 2
     else:                              # lengths straddling every bin boundary
-        lens = [511, 512, 513, 4095, 4096, 4097, 1, 2, 63, 64, 65]
+        # wave 512; block 2048 (1024 for M > 2); wide 4096 (2048); long path
+        lens = [511, 512, 513, 1023, 1024, 1025, 2047, 2048, 2049, 4095, 4096, 4097,
+                1, 2, 63, 64, 65]
         d = np.repeat(np.arange(len(lens), dtype=np.uint32), lens)
         w = np.concatenate([np.full(L, i, np.uint32) for i, L in enumerate(lens)])
         w = w[rng.permutation(len(w))]
         c = synth.Corpus(w, d, len(lens), len(lens))
-        K, M = 200, 2
+        K, M = (200, 2) if case == "ragged_tail" else (200, 4)
     s, o = make_pair(W, c, K, M, 0.3, 0.02, seed=11)
     s.init()
     o.init()
