@@ -223,7 +223,7 @@ uint64_t plan_bytes(const PhasePlan &pl, uint32_t K) {
 
 Sizes compute_sizes(const wlda_params &p, uint64_t T, const PhasePlan &w, const PhasePlan &d) {
     Sizes s;
-    s.recs = align_up(T * 8ull * record_words(p.M) + 16);
+    s.recs = align_up(T * (uint64_t)record_bytes(p.M, p.K) + 16);
     s.colptr = align_up(4ull * (p.V + 1));
     s.rowptr = align_up(4ull * (p.D + 1));
     s.colidx = align_up(4ull * T + 4);
@@ -279,7 +279,7 @@ struct wlda_sampler_s {
     wlda_params p{};
     uint64_t T = 0;
     hipStream_t st = nullptr;
-    int nw = 1;
+    int nw = 8;                          // bytes per record
     uint64_t *recs = nullptr;
     uint32_t *colptr = nullptr, *rowptr = nullptr;
     uint32_t *colidx = nullptr, *rowidx = nullptr;   // canonical position -> record
@@ -414,6 +414,7 @@ wlda_status run_phase(wlda_sampler s, uint32_t phase, uint32_t iter, bool draw_o
     PhasePlan &pl = phase == PH_WORD ? s->word : s->doc;
     PhaseArgs a;
     a.recs = s->recs;
+    a.rf = record_format(s->p.M, s->p.K);
     a.segptr = phase == PH_WORD ? s->colptr : s->rowptr;
     a.idx = phase == PH_WORD ? s->colidx : s->rowidx;
     a.K = s->p.K;
@@ -460,24 +461,49 @@ wlda_status run_phase(wlda_sampler s, uint32_t phase, uint32_t iter, bool draw_o
     return WLDA_OK;
 }
 
-inline uint32_t get_field(const uint64_t *rec, int f) {
-    return (uint32_t)(rec[f / 3] >> (FIELD_BITS * (f % 3))) & FIELD_MASK;
+// Host copies of the records: T records of record_bytes(M, K) bytes, as
+// 64-bit words (a 32-bit record format uses half words).
+struct HostRecs {
+    std::vector<uint64_t> w;
+    int rf = 1;
+    uint32_t get(uint64_t i, int f) const {
+        if (rf < 0) {
+            const uint32_t b = (uint32_t)(-rf);
+            const uint32_t r = reinterpret_cast<const uint32_t *>(w.data())[i];
+            return (r >> (b * f)) & ((1u << b) - 1u);
+        }
+        const uint64_t *rec = &w[i * rf];
+        return (uint32_t)(rec[f / 3] >> (FIELD_BITS * (f % 3))) & FIELD_MASK;
+    }
+    void set(uint64_t i, int f, uint32_t v) {
+        if (rf < 0) {
+            const uint32_t b = (uint32_t)(-rf), sh = b * f;
+            uint32_t &r = reinterpret_cast<uint32_t *>(w.data())[i];
+            r = (r & ~(((1u << b) - 1u) << sh)) | (v << sh);
+            return;
+        }
+        uint64_t *rec = &w[i * rf];
+        const int sh = FIELD_BITS * (f % 3);
+        rec[f / 3] = (rec[f / 3] & ~((uint64_t)FIELD_MASK << sh)) | ((uint64_t)v << sh);
+    }
+};
+
+uint64_t record_array_bytes(wlda_sampler s) { return s->T * (uint64_t)record_bytes(s->p.M, s->p.K); }
+
+void host_records(wlda_sampler s, HostRecs &h) {
+    h.rf = record_format(s->p.M, s->p.K);
+    h.w.assign(record_array_bytes(s) / 8 + 1, 0);
 }
 
-inline void set_field(uint64_t *rec, int f, uint32_t v) {
-    const int sh = FIELD_BITS * (f % 3);
-    rec[f / 3] = (rec[f / 3] & ~((uint64_t)FIELD_MASK << sh)) | ((uint64_t)v << sh);
-}
-
-wlda_status download_records(wlda_sampler s, std::vector<uint64_t> &h) {
-    h.resize(s->T * s->nw + 1);
-    if (s->T) WLDA_TRY(s, hipMemcpyAsync(h.data(), s->recs, s->T * 8ull * s->nw, hipMemcpyDeviceToHost, s->st));
+wlda_status download_records(wlda_sampler s, HostRecs &h) {
+    host_records(s, h);
+    if (s->T) WLDA_TRY(s, hipMemcpyAsync(h.w.data(), s->recs, record_array_bytes(s), hipMemcpyDeviceToHost, s->st));
     WLDA_TRY(s, hipStreamSynchronize(s->st));
     return WLDA_OK;
 }
 
-wlda_status upload_records_and_recount(wlda_sampler s, const std::vector<uint64_t> &h) {
-    if (s->T) WLDA_TRY(s, hipMemcpyAsync(s->recs, h.data(), s->T * 8ull * s->nw, hipMemcpyHostToDevice, s->st));
+wlda_status upload_records_and_recount(wlda_sampler s, const HostRecs &h) {
+    if (s->T) WLDA_TRY(s, hipMemcpyAsync(s->recs, h.w.data(), record_array_bytes(s), hipMemcpyHostToDevice, s->st));
     WLDA_TRY(s, launch_fill_u32(s->ck[s->cur], 0, s->p.K, s->st));
     WLDA_TRY(s, launch_histogram_z(s->recs, (uint32_t)s->T, s->p.M, s->p.K, s->ck[s->cur], s->st));
     WLDA_TRY(s, hipStreamSynchronize(s->st));
@@ -527,7 +553,7 @@ wlda_status wlda_create(const wlda_params *p, const uint32_t *word_ids, const ui
     s->p = *p;
     s->T = T;
     s->st = (hipStream_t)hip_stream;
-    s->nw = record_words(p->M);
+    s->nw = (int)record_bytes(p->M, p->K);   // bytes per record
     s->a = (float)p->alpha;
     s->b = (float)p->beta;
     s->alpha_bar = (float)p->K * s->a;
@@ -585,7 +611,7 @@ wlda_status wlda_create(const wlda_params *p, const uint32_t *word_ids, const ui
         if (const char *env = std::getenv("WLDA_DOC_BLOCK_KIB")) block_kib = std::strtoull(env, nullptr, 10);
         s->blocked = block_kib >= 16 && block_kib <= (1ull << 20);
         if (s->blocked) {
-            build_layout(s->word, s->doc, ld, colptr, doc_csc, (block_kib << 10) / (8ull * s->nw), s->mem);
+            build_layout(s->word, s->doc, ld, colptr, doc_csc, (block_kib << 10) / (uint64_t)s->nw, s->mem);
             for (uint64_t i = 0; i < T; ++i) s->inv[i] = s->mem[s->inv[i]];
         } else {
             for (uint64_t t = 0; t < T; ++t) s->mem[t] = (uint32_t)t;
@@ -600,7 +626,7 @@ wlda_status wlda_create(const wlda_params *p, const uint32_t *word_ids, const ui
 
     // ---- workspace ----------------------------------------------------------
     uint8_t *cur = (uint8_t *)dev_workspace;
-    s->recs = (uint64_t *)carve(cur, T * 8ull * s->nw + 16);
+    s->recs = (uint64_t *)carve(cur, T * (uint64_t)s->nw + 16);
     s->colptr = (uint32_t *)carve(cur, 4ull * (p->V + 1));
     s->rowptr = (uint32_t *)carve(cur, 4ull * (p->D + 1));
     s->colidx = (uint32_t *)carve(cur, 4ull * T + 4);
@@ -692,6 +718,7 @@ wlda_status wlda_log_likelihood(wlda_sampler s, double *ll) {
                                        prior, total, lt, s->ll, s->st));
         PhaseArgs a;
         a.recs = s->recs;
+        a.rf = record_format(s->p.M, s->p.K);
         a.segptr = segptr;
         a.idx = idx;
         a.K = K;
@@ -715,17 +742,15 @@ wlda_status wlda_theta(wlda_sampler s, uint32_t d0, uint32_t nd, float *theta) {
 static wlda_status copy_out(wlda_sampler s, int32_t *z, int32_t *props, bool input_order) {
     if (!s || !z) return WLDA_E_INVALID;
     if (s->broken) return WLDA_E_HIP;
-    std::vector<uint64_t> h;
+    HostRecs h;
     wlda_status st = download_records(s, h);
     if (st != WLDA_OK) return st;
     const uint64_t T = s->T;
-    const int nw = s->nw;
     for (uint64_t i = 0; i < T; ++i) {
         const uint64_t t = input_order ? s->inv[i] : s->mem[i];
-        const uint64_t *rec = &h[t * nw];
-        z[i] = (int32_t)get_field(rec, 0);
+        z[i] = (int32_t)h.get(t, 0);
         if (props)
-            for (uint32_t m = 1; m <= s->p.M; ++m) props[(m - 1) * T + i] = (int32_t)get_field(rec, m);
+            for (uint32_t m = 1; m <= s->p.M; ++m) props[(m - 1) * T + i] = (int32_t)h.get(t, m);
     }
     return WLDA_OK;
 }
@@ -794,15 +819,16 @@ wlda_status wlda_load_state(wlda_sampler s, const void *host_buf, uint64_t bytes
     const int32_t *z = (const int32_t *)(p + 16);
     const int32_t *props = z + s->T;
     const uint64_t T = s->T;
-    std::vector<uint64_t> h(T * s->nw + 1, 0);
+    HostRecs h;
+    host_records(s, h);
     for (uint64_t t = 0; t < T; ++t) {
-        uint64_t *rec = &h[(uint64_t)s->mem[t] * s->nw];
+        const uint64_t r = s->mem[t];
         if ((uint32_t)z[t] >= s->p.K) return WLDA_E_INVALID;
-        set_field(rec, 0, (uint32_t)z[t]);
+        h.set(r, 0, (uint32_t)z[t]);
         for (uint32_t m = 1; m <= s->p.M; ++m) {
             const uint32_t v = (uint32_t)props[(m - 1) * T + t];
             if (v >= s->p.K) return WLDA_E_INVALID;
-            set_field(rec, m, v);
+            h.set(r, m, v);
         }
     }
     wlda_status st = upload_records_and_recount(s, h);
@@ -816,19 +842,19 @@ wlda_status wlda_set_assignments(wlda_sampler s, const int32_t *z, const int32_t
     if (!s || !z) return WLDA_E_INVALID;
     if (s->broken) return WLDA_E_HIP;
     if (!props && s->next_phase == 0) return WLDA_E_STATE;
-    std::vector<uint64_t> h;
+    HostRecs h;
     wlda_status st = download_records(s, h);
     if (st != WLDA_OK) return st;
     const uint64_t T = s->T;
     for (uint64_t i = 0; i < T; ++i) {
         const uint64_t t = s->inv[i];
         if ((uint32_t)z[i] >= s->p.K) return WLDA_E_INVALID;
-        set_field(&h[t * s->nw], 0, (uint32_t)z[i]);
+        h.set(t, 0, (uint32_t)z[i]);
         if (props)
             for (uint32_t m = 1; m <= s->p.M; ++m) {
                 const uint32_t v = (uint32_t)props[(m - 1) * T + i];
                 if (v >= s->p.K) return WLDA_E_INVALID;
-                set_field(&h[t * s->nw], m, v);
+                h.set(t, m, v);
             }
     }
     st = upload_records_and_recount(s, h);

@@ -8,13 +8,25 @@ namespace wlda {
 
 enum Phase : uint32_t { PH_INIT = 0, PH_WORD = 1, PH_DOC = 2 };
 
-// Topics are packed three to a 64-bit word, 21 bits each: field 0 is z, field
-// i (1..M) is the i-th pending proposal.  M <= 2 -> one word, M <= 5 -> two.
+// One packed record per token: field 0 is z, field i (1..M) the i-th pending
+// proposal.  When K fits, the 1 + M fields share one 32-bit word, floor(32 /
+// (1 + M)) bits each (K <= 65536 for M = 1, 1024 for M = 2, 256 for M = 3,
+// 64 for M = 4); otherwise topics take 21 bits, three to a 64-bit word (one
+// word for M <= 2, two for M <= 5).  Kernels name the format by RF: 1 or 2
+// 64-bit words, or -b for a 32-bit record of b-bit fields.
 constexpr uint32_t FIELD_BITS = 21;
 constexpr uint32_t FIELD_MASK = (1u << FIELD_BITS) - 1;
 constexpr uint32_t MAX_K = FIELD_MASK;   // topics are < 2^21 - 1
 
-inline int record_words(uint32_t M) { return (int)((M + 1 + 2) / 3); }
+inline uint32_t rec32_bits(uint32_t M) { return 32 / (1 + M); }
+inline bool rec32_fits(uint32_t M, uint32_t K) { return M <= 4 && K <= (1u << rec32_bits(M)); }
+inline int record_format(uint32_t M, uint32_t K) {
+    return rec32_fits(M, K) ? -(int)rec32_bits(M) : (int)((M + 1 + 2) / 3);
+}
+inline uint32_t record_bytes(uint32_t M, uint32_t K) {
+    const int rf = record_format(M, K);
+    return rf < 0 ? 4u : 8u * (uint32_t)rf;
+}
 
 // Segment = one column (word phase) or one row (doc phase).  The n-th token
 // of segment s has the canonical position segptr[s] + n of its phase (CSC in
@@ -68,6 +80,7 @@ struct PhaseArgs {
     unsigned long long *accepted = nullptr;
     uint32_t draw_only = 0;            // initial proposal draw (no MH)
     uint32_t max_blocks = 2048;        // grid bound of the segment kernels (launch shape only)
+    int rf = 1;                        // record format (see record_format)
 };
 
 struct Tuning {

@@ -37,6 +37,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "wlda_device.h"
 #include "wlda_internal.h"
 
@@ -45,15 +47,19 @@ namespace wlda {
 // --------------------------------------------------------------------------
 // Packed records
 // --------------------------------------------------------------------------
-template <int NW>
+// RF = 1 or 2: that many 64-bit words of 21-bit fields; RF = -b: one 32-bit
+// word of b-bit fields.
+template <int RF>
 struct Rec {
-    uint64_t w[NW];
+    uint64_t w[RF > 0 ? RF : 1];
 };
 
-template <int NW>
-__device__ __forceinline__ Rec<NW> ld_rec(const uint64_t *recs, uint32_t pos) {
-    Rec<NW> r;
-    if constexpr (NW == 1) {
+template <int RF>
+__device__ __forceinline__ Rec<RF> ld_rec(const uint64_t *recs, uint32_t pos) {
+    Rec<RF> r;
+    if constexpr (RF < 0) {
+        r.w[0] = reinterpret_cast<const uint32_t *>(recs)[pos];
+    } else if constexpr (RF == 1) {
         r.w[0] = recs[pos];
     } else {
         const uint4 v = reinterpret_cast<const uint4 *>(recs)[pos];
@@ -63,9 +69,11 @@ __device__ __forceinline__ Rec<NW> ld_rec(const uint64_t *recs, uint32_t pos) {
     return r;
 }
 
-template <int NW>
-__device__ __forceinline__ void st_rec(uint64_t *recs, uint32_t pos, const Rec<NW> &r) {
-    if constexpr (NW == 1) {
+template <int RF>
+__device__ __forceinline__ void st_rec(uint64_t *recs, uint32_t pos, const Rec<RF> &r) {
+    if constexpr (RF < 0) {
+        reinterpret_cast<uint32_t *>(recs)[pos] = (uint32_t)r.w[0];
+    } else if constexpr (RF == 1) {
         recs[pos] = r.w[0];
     } else {
         reinterpret_cast<uint4 *>(recs)[pos] =
@@ -74,15 +82,26 @@ __device__ __forceinline__ void st_rec(uint64_t *recs, uint32_t pos, const Rec<N
     }
 }
 
-template <int NW>
-__device__ __forceinline__ uint32_t fld(const Rec<NW> &r, int f) {
-    return (uint32_t)(r.w[f / 3] >> (FIELD_BITS * (f % 3))) & FIELD_MASK;
+template <int RF>
+__device__ __forceinline__ uint32_t fld(const Rec<RF> &r, int f) {
+    if constexpr (RF < 0) {
+        constexpr uint32_t B = (uint32_t)(-RF);
+        return (uint32_t)(r.w[0] >> (B * f)) & ((1u << B) - 1u);
+    } else {
+        return (uint32_t)(r.w[f / 3] >> (FIELD_BITS * (f % 3))) & FIELD_MASK;
+    }
 }
 
-template <int NW>
-__device__ __forceinline__ void set_fld(Rec<NW> &r, int f, uint32_t v) {
-    const int sh = FIELD_BITS * (f % 3);
-    r.w[f / 3] = (r.w[f / 3] & ~((uint64_t)FIELD_MASK << sh)) | ((uint64_t)v << sh);
+template <int RF>
+__device__ __forceinline__ void set_fld(Rec<RF> &r, int f, uint32_t v) {
+    if constexpr (RF < 0) {
+        constexpr uint32_t B = (uint32_t)(-RF);
+        const uint32_t sh = B * f;
+        r.w[0] = (r.w[0] & ~((uint64_t)((1u << B) - 1u) << sh)) | ((uint64_t)v << sh);
+    } else {
+        const int sh = FIELD_BITS * (f % 3);
+        r.w[f / 3] = (r.w[f / 3] & ~((uint64_t)FIELD_MASK << sh)) | ((uint64_t)v << sh);
+    }
 }
 
 // --------------------------------------------------------------------------
@@ -357,7 +376,7 @@ __global__ __launch_bounds__(256) void seg_kernel(PhaseArgs a, SegList l, uint32
             if (r * GROUP + lane < L) {
                 Rec<NW> out;
 #pragma unroll
-                for (int w = 0; w < NW; ++w) out.w[w] = 0;
+                for (int w = 0; w < (NW > 0 ? NW : 1); ++w) out.w[w] = 0;
                 set_fld(out, 0, znew[r]);
 #pragma unroll
                 for (int i = 1; i <= M; ++i) {
@@ -750,7 +769,7 @@ __global__ void init_z_kernel(uint64_t *recs, const uint32_t *colidx, uint32_t T
         const uint4 R = philox(t, 0, (uint32_t)PH_INIT << 16, 0, k0, k1);
         Rec<NW> r;
 #pragma unroll
-        for (int w = 0; w < NW; ++w) r.w[w] = 0;
+        for (int w = 0; w < (NW > 0 ? NW : 1); ++w) r.w[w] = 0;
         set_fld(r, 0, dice(R.z, K));
         st_rec<NW>(recs, colidx ? colidx[t] : t, r);
     }
@@ -882,6 +901,20 @@ static int grid_for(uint64_t n, int cap = 8192) {
     return (int)b;
 }
 
+// Calls f(std::integral_constant<int, RF>) for the record format rf.
+template <typename F>
+static hipError_t with_rf(int rf, F &&f) {
+    switch (rf) {
+        case -16: return f(std::integral_constant<int, -16>{});
+        case -10: return f(std::integral_constant<int, -10>{});
+        case -8: return f(std::integral_constant<int, -8>{});
+        case -6: return f(std::integral_constant<int, -6>{});
+        case 1: return f(std::integral_constant<int, 1>{});
+        case 2: return f(std::integral_constant<int, 2>{});
+        default: return hipErrorInvalidValue;
+    }
+}
+
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, uint64_t n, hipStream_t st) {
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(fill_u32_kernel, dim3(grid_for(n)), dim3(256), 0, st, p, v, n);
@@ -891,11 +924,11 @@ hipError_t launch_fill_u32(uint32_t *p, uint32_t v, uint64_t n, hipStream_t st) 
 hipError_t launch_init_z(uint64_t *recs, const uint32_t *colidx, uint32_t T, uint32_t M, uint32_t K,
                          uint32_t k0, uint32_t k1, hipStream_t st) {
     if (T == 0) return hipSuccess;
-    if (record_words(M) == 1)
-        hipLaunchKernelGGL(init_z_kernel<1>, dim3(grid_for(T)), dim3(256), 0, st, recs, colidx, T, K, k0, k1);
-    else
-        hipLaunchKernelGGL(init_z_kernel<2>, dim3(grid_for(T)), dim3(256), 0, st, recs, colidx, T, K, k0, k1);
-    return hipGetLastError();
+    return with_rf(record_format(M, K), [&](auto c) {
+        hipLaunchKernelGGL(init_z_kernel<decltype(c)::value>, dim3(grid_for(T)), dim3(256), 0, st, recs, colidx, T,
+                           K, k0, k1);
+        return hipGetLastError();
+    });
 }
 
 template <typename Kern>
@@ -944,20 +977,34 @@ static hipError_t run_seg(const PhaseArgs &a, const SegList &l, uint32_t cap_bou
     return run_seg_k<PHASE, M, NW, GROUP, TPT, false>(a, l, cap_bound, st);
 }
 
+// Calls f(std::integral_constant<int, RF>) with the record format of M topics
+// per proposal set: 32-bit when rf < 0 (and M <= 4), else 64-bit words.
+template <int M, typename F>
+static hipError_t with_rf_m(int rf, F &&f) {
+    if constexpr (M <= 4) {
+        if (rf < 0) return f(std::integral_constant<int, -(int)(32 / (1 + M))>{});
+    }
+    return f(std::integral_constant<int, (M + 3) / 3>{});
+}
+
 // Hash capacity bound of a bin: the power of two >= 2L for its longest segment.
 template <int PHASE, int M>
 static hipError_t wave_dispatch(const PhaseArgs &a, const SegList &l, hipStream_t st) {
-    constexpr int NW = (M + 3) / 3;
+    return with_rf_m<M>(a.rf, [&](auto rfc) -> hipError_t {
+    constexpr int NW = decltype(rfc)::value;
     return run_seg<PHASE, M, NW, 64, Tuning::TPT_WAVE>(a, l, 2 * Tuning::WAVE_MAX, st);
+    });
 }
 
 template <int PHASE, int M>
 static hipError_t block_dispatch(const PhaseArgs &a, const SegList &l, int bin, hipStream_t st) {
-    constexpr int NW = (M + 3) / 3;
+    return with_rf_m<M>(a.rf, [&](auto rfc) -> hipError_t {
+    constexpr int NW = decltype(rfc)::value;
     constexpr int TB = M <= 2 ? Tuning::TPT_BLOCK : Tuning::TPT_BLOCK / 2;
     constexpr int TW = M <= 2 ? Tuning::TPT_WIDE : Tuning::TPT_WIDE / 2;
     if (bin == BIN_WIDE) return run_seg<PHASE, M, NW, 256, TW>(a, l, 2 * 256 * TW, st);
     return run_seg<PHASE, M, NW, 256, TB>(a, l, 2 * 256 * TB, st);
+    });
 }
 
 #define WLDA_DISPATCH_M(FN, PHASE, ...)                                 \
@@ -988,7 +1035,8 @@ hipError_t launch_block_segments(const PhaseArgs &a, uint32_t phase, uint32_t M,
 template <int PHASE, int M, typename ZT>
 static hipError_t long_dispatch_z(const PhaseArgs &a, const LongList &l, hipStream_t st,
                                   hipEvent_t *ev) {
-    constexpr int NW = (M + 3) / 3;
+    return with_rf_m<M>(a.rf, [&](auto rfc) -> hipError_t {
+    constexpr int NW = decltype(rfc)::value;
     const bool lds_tab = a.K <= Tuning::LDS_DENSE_MAX;
     const bool ck_lds = a.K <= Tuning::CK_LDS_MAX;
     uint32_t blocks = l.n_chunks < 2048 ? l.n_chunks : 2048;
@@ -1030,6 +1078,7 @@ static hipError_t long_dispatch_z(const PhaseArgs &a, const LongList &l, hipStre
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (ev) return hipEventRecord(ev[3], st);
     return hipSuccess;
+    });
 }
 
 template <int PHASE, int M>
@@ -1050,13 +1099,11 @@ hipError_t launch_long_segments(const PhaseArgs &a, uint32_t phase, uint32_t M, 
 
 hipError_t launch_histogram_z(const uint64_t *recs, uint32_t T, uint32_t M, uint32_t K, uint32_t *ck,
                               hipStream_t st) {
-    (void)K;
     if (T == 0) return hipSuccess;
-    if (record_words(M) == 1)
-        hipLaunchKernelGGL(histogram_z_kernel<1>, dim3(grid_for(T)), dim3(256), 0, st, recs, T, ck);
-    else
-        hipLaunchKernelGGL(histogram_z_kernel<2>, dim3(grid_for(T)), dim3(256), 0, st, recs, T, ck);
-    return hipGetLastError();
+    return with_rf(record_format(M, K), [&](auto c) {
+        hipLaunchKernelGGL(histogram_z_kernel<decltype(c)::value>, dim3(grid_for(T)), dim3(256), 0, st, recs, T, ck);
+        return hipGetLastError();
+    });
 }
 
 hipError_t launch_ll_list(const uint64_t *recs, uint32_t M, const uint32_t *segptr, const uint32_t *idx,
@@ -1066,23 +1113,21 @@ hipError_t launch_ll_list(const uint64_t *recs, uint32_t M, const uint32_t *segp
     const bool dense = K <= Tuning::LDS_DENSE_MAX;
     const size_t lds = dense ? 4ull * K : 4ull * 2 * 2 * Tuning::WIDE_MAX;
     const int blocks = n < 4096 ? (int)n : 4096;
-    hipError_t e;
-    if (record_words(M) == 1) {
-        if ((e = launch_dyn(ll_seg_kernel<1>, dim3(1), lds, st))) return e;
-        hipLaunchKernelGGL(ll_seg_kernel<1>, dim3(blocks), dim3(256), lds, st, recs, segptr, idx, ids, n, K,
+    return with_rf(record_format(M, K), [&](auto c) {
+        constexpr int RF = decltype(c)::value;
+        hipError_t e = launch_dyn(ll_seg_kernel<RF>, dim3(1), lds, st);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(ll_seg_kernel<RF>, dim3(blocks), dim3(256), lds, st, recs, segptr, idx, ids, n, K,
                            (uint32_t)dense, prior, prior_total, length_term, out);
-    } else {
-        if ((e = launch_dyn(ll_seg_kernel<2>, dim3(1), lds, st))) return e;
-        hipLaunchKernelGGL(ll_seg_kernel<2>, dim3(blocks), dim3(256), lds, st, recs, segptr, idx, ids, n, K,
-                           (uint32_t)dense, prior, prior_total, length_term, out);
-    }
-    return hipGetLastError();
+        return hipGetLastError();
+    });
 }
 
 template <int PHASE, int M>
 static hipError_t ll_long_dispatch(const PhaseArgs &a, const LongList &l, double prior, double prior_total,
                                    int length_term, double *out, hipStream_t st) {
-    constexpr int NW = (M + 3) / 3;
+    return with_rf_m<M>(a.rf, [&](auto rfc) -> hipError_t {
+    constexpr int NW = decltype(rfc)::value;
     if (l.n == 0) return hipSuccess;
     const bool lds_dense = a.K <= Tuning::LDS_DENSE_MAX;
     uint32_t blocks = l.n_chunks < 2048 ? l.n_chunks : 2048;
@@ -1097,6 +1142,7 @@ static hipError_t ll_long_dispatch(const PhaseArgs &a, const LongList &l, double
                        prior, prior_total, length_term, out);
     if ((e = hipGetLastError())) return e;
     return launch_fill_u32(l.tables, 0, l.table_words, st);
+    });
 }
 
 hipError_t launch_ll_long(const PhaseArgs &a, uint32_t phase, uint32_t M, const LongList &l, double prior,
@@ -1113,17 +1159,14 @@ hipError_t launch_theta(const uint64_t *recs, uint32_t M, const uint32_t *rowptr
     if (K > LL_DENSE_MAX) return hipErrorNotSupported;
     const size_t lds = 4ull * K;
     const int blocks = nd < 8192 ? (int)nd : 8192;
-    hipError_t e;
-    if (record_words(M) == 1) {
-        if ((e = launch_dyn(theta_kernel<1>, dim3(1), lds, st))) return e;
-        hipLaunchKernelGGL(theta_kernel<1>, dim3(blocks), dim3(256), lds, st, recs, rowptr, idx, d0, nd, K,
+    return with_rf(record_format(M, K), [&](auto c) {
+        constexpr int RF = decltype(c)::value;
+        hipError_t e = launch_dyn(theta_kernel<RF>, dim3(1), lds, st);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(theta_kernel<RF>, dim3(blocks), dim3(256), lds, st, recs, rowptr, idx, d0, nd, K,
                            alpha, out);
-    } else {
-        if ((e = launch_dyn(theta_kernel<2>, dim3(1), lds, st))) return e;
-        hipLaunchKernelGGL(theta_kernel<2>, dim3(blocks), dim3(256), lds, st, recs, rowptr, idx, d0, nd, K,
-                           alpha, out);
-    }
-    return hipGetLastError();
+        return hipGetLastError();
+    });
 }
 
 hipError_t launch_ll_topics(const uint32_t *ck, uint32_t K, double beta_bar, double *out,

@@ -88,8 +88,11 @@ def test_tiny_lda_corpus_50_iterations(W):
     assert abs(ll_s - ll_o) <= LL_RTOL * abs(ll_o), (ll_s, ll_o)
 
 
-@pytest.mark.parametrize("K,M", [(7, 1), (1000, 2), (5000, 3), (20000, 4), (300000, 2),
-                                 (1000000, 2), (2000, 4)])
+# record formats: 32-bit with 16-bit fields (M=1, K<=65536), 10-bit (M=2,
+# K<=1024), 8-bit (M=3, K<=256), 6-bit (M=4, K<=64); else 21-bit fields in one
+# or two 64-bit words
+@pytest.mark.parametrize("K,M", [(7, 1), (65536, 1), (1000, 2), (1024, 2), (1025, 2), (256, 3),
+                                 (5000, 3), (64, 4), (20000, 4), (300000, 2), (1000000, 2), (2000, 4)])
 def test_all_paths_bit_exact(W, K, M):
     c = mixed_corpus(K + M)
     alpha, beta = 50.0 / K, 0.01
