@@ -20,6 +20,9 @@ using namespace wlda;
 namespace {
 
 constexpr uint64_t ALIGN = 256;
+// records per document block: 1 MiB stays resident in an XCD's 4 MiB L2 while
+// that XCD's document window (about 1k rows in flight) gathers from it
+constexpr uint64_t DOC_BLOCK_KIB = 1024;
 inline uint64_t align_up(uint64_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
 
 // Segment ids of one bin, in ascending order, cut into eight XCD shares.
@@ -153,9 +156,8 @@ void build_plan(const std::vector<uint64_t> &len, uint32_t M, uint32_t K, PhaseP
 }
 
 // ---- record layout ---------------------------------------------------------
-// Y is stored once (Section 5.2), by default in plain CSC order.  The
-// alternative built here blocks it by documents: documents, in the doc
-// phase's visiting order (each bin's
+// Y is stored once (Section 5.2), blocked by documents (plain CSC order is
+// the alternative): documents, in the doc phase's visiting order (each bin's
 // list, XCD share by XCD share), are cut into blocks of about `block_tokens`
 // tokens; a block never spans two bins or two XCD shares, and a long row is a
 // block of its own.  Inside a block the tokens are ordered by (word rank,
@@ -304,7 +306,7 @@ struct wlda_sampler_s {
     // launch-shape bounds (grid size of the segment kernels), per phase and
     // bin: [word wave, block, wide, doc wave, block, wide]; overridable with
     // WLDA_SEG_BLOCKS="a,b,c,d,e,f" for tuning sweeps
-    uint32_t seg_blocks[2 * NBINS] = {1024, 1024, 1024, 2048, 2048, 2048};
+    uint32_t seg_blocks[2 * NBINS] = {1024, 1024, 1024, 1024, 1024, 1024};
 };
 
 namespace {
@@ -604,10 +606,11 @@ wlda_status wlda_create(const wlda_params *p, const uint32_t *word_ids, const ui
                 doc_csc[t] = doc_ids[i];
             }
         }
-        // record layout: plain CSC order (colidx is the identity), or blocked
-        // by documents when WLDA_DOC_BLOCK_KIB gives a block size
+        // record layout: blocked by documents, blocks of DOC_BLOCK_KIB of
+        // records (WLDA_DOC_BLOCK_KIB overrides; 0 selects plain CSC order,
+        // where colidx is the identity)
         s->mem.resize(T);
-        uint64_t block_kib = 0;
+        uint64_t block_kib = DOC_BLOCK_KIB;
         if (const char *env = std::getenv("WLDA_DOC_BLOCK_KIB")) block_kib = std::strtoull(env, nullptr, 10);
         s->blocked = block_kib >= 16 && block_kib <= (1ull << 20);
         if (s->blocked) {

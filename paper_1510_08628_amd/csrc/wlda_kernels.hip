@@ -3,16 +3,17 @@
 // Paper: Chen, Li, Zhu, Chen, "WarpLDA: a Cache Efficient O(1) Algorithm for
 // Latent Dirichlet Allocation" (arXiv:1510.08628).
 //
-// Data: one packed record per token, 21-bit fields, field 0 = z, fields 1..M
-// = pending proposals, stored once (Section 5.2).  Both phases reach their
-// segments through a pointer array into that copy of Y, the role P_CSR plays
-// in Section 5.2: `colidx` (canonical CSC position -> record; null when the
-// records are in CSC order, so the word phase streams its columns) and
-// `rowidx` (canonical CSR position -> record).  The host may instead block
-// the records by documents (column-major inside each block), which keeps a
-// document window's gathers inside L2 at the price of word-phase gathers.
-// The RNG counter of a token is its canonical position in the phase's order,
-// independent of the layout.
+// Data: one packed record per token (field 0 = z, fields 1..M = pending
+// proposals), stored once (Section 5.2) and blocked by documents: blocks of
+// consecutive rows of the doc phase's visiting order, column-major inside a
+// block.  Both phases reach their segments through a pointer array into that
+// copy of Y, the role P_CSR plays in Section 5.2: `colidx` (canonical CSC
+// position -> record) in the word phase and `rowidx` (canonical CSR position
+// -> record) in the document phase.  A document window then gathers inside
+// blocks resident in its XCD's L2, and a column reads one run per block.
+// With records in plain CSC order (the alternative) colidx is null and the
+// word phase streams its columns.  The RNG counter of a token is its
+// canonical position in the phase's order, independent of the layout.
 //
 // A "segment" is a column (word phase) or a row (document phase).  Segments
 // are binned by length on the host:

@@ -220,3 +220,25 @@ def test_set_assignments_matches_oracle(W):
         s.doc_phase()
         o.doc_phase()
         assert_same(s, o, "doc after set")
+
+
+@pytest.mark.parametrize("block_kib", ["0", "16", "4096"])
+@pytest.mark.parametrize("K,M", [(1000, 2), (50, 4)])
+def test_record_layouts_bit_exact(W, block_kib, K, M, monkeypatch):
+    """The record layout (plain CSC order, or blocked by documents with tiny
+    or large blocks) changes where records live, never the chain."""
+    monkeypatch.setenv("WLDA_DOC_BLOCK_KIB", block_kib)
+    c = mixed_corpus(K + M + 3)
+    s, o = make_pair(W, c, K, M, 50.0 / K, 0.01, seed=5)
+    s.init()
+    o.init()
+    assert_same(s, o, "init")
+    for it in range(2):
+        s.word_phase()
+        o.word_phase()
+        assert_same(s, o, f"word phase {it + 1}")
+        s.doc_phase()
+        o.doc_phase()
+        assert_same(s, o, f"doc phase {it + 1}")
+    ll_s, ll_o = s.log_likelihood(), o.log_likelihood()
+    assert abs(ll_s - ll_o) <= LL_RTOL * abs(ll_o), (ll_s, ll_o)
