@@ -272,16 +272,20 @@ __global__ __launch_bounds__(256) void seg_kernel(PhaseArgs a, SegList l, uint32
         // word proposals of a column with L > K: inverse CDF of its updated
         // counts (the table is dense whenever L > K: K < L <= GROUP * TPT)
         const bool by_cdf = CDF && PHASE == PH_WORD && !a.draw_only && dense && L > K;
+        // All pointers first, then all records, with no branch around any load:
+        // slots past the segment's end re-read its last token.  Each batch is
+        // then in flight at once instead of one dependent pair per slot.
         uint32_t pos[TPT];
         Rec<NW> rec[TPT];
+        if (a.idx) {
 #pragma unroll
-        for (int r = 0; r < TPT; ++r) {
-            const uint32_t n = r * GROUP + lane;
-            if (n < L) {
-                pos[r] = a.idx ? a.idx[beg + n] : beg + n;
-                rec[r] = ld_rec<NW>(a.recs, pos[r]);
-            }
+            for (int r = 0; r < TPT; ++r) pos[r] = a.idx[beg + min(r * GROUP + lane, L - 1)];
+        } else {
+#pragma unroll
+            for (int r = 0; r < TPT; ++r) pos[r] = beg + min(r * GROUP + lane, L - 1);
         }
+#pragma unroll
+        for (int r = 0; r < TPT; ++r) rec[r] = ld_rec<NW>(a.recs, pos[r]);
         uint32_t znew[TPT];
         uint32_t r2[TPT][M] = {};
         uint32_t coins = 0;   // bit r*M + i: proposal i of token r takes the count part
@@ -457,6 +461,21 @@ __device__ __forceinline__ uint32_t gtab_get(const uint32_t *base, uint32_t cap,
 // tokens per thread whose loads are issued together in the long kernels
 constexpr int LONG_BATCH = 8;
 
+// Record positions of tokens nb, nb + 256, ... of a segment starting at
+// canonical position beg, clamped to the chunk's last token n1 - 1 so that
+// every load is in bounds and the batch issues without per-token branches.
+template <int B>
+__device__ __forceinline__ void load_positions(const uint32_t *idx, uint32_t beg, uint32_t nb, uint32_t n1,
+                                               uint32_t (&pos)[B]) {
+    if (idx) {
+#pragma unroll
+        for (int u = 0; u < B; ++u) pos[u] = idx[beg + min(nb + u * 256, n1 - 1)];
+    } else {
+#pragma unroll
+        for (int u = 0; u < B; ++u) pos[u] = beg + min(nb + u * 256, n1 - 1);
+    }
+}
+
 #define WLDA_FOR_CHUNKS(l)                                                        \
     const uint32_t xcd_ = blockIdx.x & 7, nbx_ = gridDim.x >> 3;                 \
     for (uint32_t ci = (l).chunk_cut[xcd_] + (blockIdx.x >> 3); ci < (l).chunk_cut[xcd_ + 1]; \
@@ -482,12 +501,10 @@ __global__ __launch_bounds__(256) void long_hist_kernel(PhaseArgs a, LongList l,
         __syncthreads();
         // LONG_BATCH tokens per thread in flight: all loads, then the inserts
         for (uint32_t nb = n0 + threadIdx.x; nb < n1; nb += 256 * LONG_BATCH) {
-            uint32_t z[LONG_BATCH];
+            uint32_t pos[LONG_BATCH], z[LONG_BATCH];
+            load_positions<LONG_BATCH>(a.idx, beg, nb, n1, pos);
 #pragma unroll
-            for (int u = 0; u < LONG_BATCH; ++u) {
-                const uint32_t n = nb + u * 256;
-                if (n < n1) z[u] = fld(ld_rec<NW>(a.recs, a.idx ? a.idx[beg + n] : beg + n), 0);
-            }
+            for (int u = 0; u < LONG_BATCH; ++u) z[u] = fld(ld_rec<NW>(a.recs, pos[u]), 0);
 #pragma unroll
             for (int u = 0; u < LONG_BATCH; ++u)
                 if (nb + u * 256 < n1) tab_insert(hkey, lds_dense ? hist : hcnt, HCAP - 1, lds_dense != 0, z[u]);
@@ -552,14 +569,9 @@ __global__ __launch_bounds__(256) void long_mh_kernel(PhaseArgs a, LongList l, u
             const uint32_t nb = n0 + threadIdx.x + bt * 256 * LONG_BATCH;
             uint32_t pos[LONG_BATCH];
             Rec<NW> rec[LONG_BATCH];
+            load_positions<LONG_BATCH>(a.idx, beg, nb, n1, pos);
 #pragma unroll
-            for (int u = 0; u < LONG_BATCH; ++u) {
-                const uint32_t n = nb + u * 256;
-                if (n < n1) {
-                    pos[u] = a.idx ? a.idx[beg + n] : beg + n;
-                    rec[u] = ld_rec<NW>(a.recs, pos[u]);
-                }
-            }
+            for (int u = 0; u < LONG_BATCH; ++u) rec[u] = ld_rec<NW>(a.recs, pos[u]);
 #pragma unroll
             for (int u = 0; u < LONG_BATCH; ++u) {
                 const uint32_t n = nb + u * 256;
@@ -689,14 +701,9 @@ __global__ __launch_bounds__(256) void long_draw_kernel(PhaseArgs a, LongList l,
         for (uint32_t nb = n0 + threadIdx.x; nb < n1; nb += 256 * LONG_BATCH) {
             uint32_t pos[LONG_BATCH];
             Rec<NW> rec[LONG_BATCH];
+            load_positions<LONG_BATCH>(a.idx, beg, nb, n1, pos);
 #pragma unroll
-            for (int u = 0; u < LONG_BATCH; ++u) {
-                const uint32_t n = nb + u * 256;
-                if (n < n1) {
-                    pos[u] = a.idx ? a.idx[beg + n] : beg + n;
-                    rec[u] = ld_rec<NW>(a.recs, pos[u]);
-                }
-            }
+            for (int u = 0; u < LONG_BATCH; ++u) rec[u] = ld_rec<NW>(a.recs, pos[u]);
             // all random-positioning reads (or CDF lookups) of the batch are
             // issued before any record is written back
             uint32_t jj[LONG_BATCH * M] = {};
