@@ -52,7 +52,8 @@ namespace wlda {
 // word of b-bit fields.
 template <int RF>
 struct Rec {
-    uint64_t w[RF > 0 ? RF : 1];
+    using W = std::conditional_t<(RF < 0), uint32_t, uint64_t>;
+    W w[RF > 0 ? RF : 1];
 };
 
 template <int RF>
@@ -73,7 +74,7 @@ __device__ __forceinline__ Rec<RF> ld_rec(const uint64_t *recs, uint32_t pos) {
 template <int RF>
 __device__ __forceinline__ void st_rec(uint64_t *recs, uint32_t pos, const Rec<RF> &r) {
     if constexpr (RF < 0) {
-        reinterpret_cast<uint32_t *>(recs)[pos] = (uint32_t)r.w[0];
+        reinterpret_cast<uint32_t *>(recs)[pos] = r.w[0];
     } else if constexpr (RF == 1) {
         recs[pos] = r.w[0];
     } else {
@@ -87,7 +88,7 @@ template <int RF>
 __device__ __forceinline__ uint32_t fld(const Rec<RF> &r, int f) {
     if constexpr (RF < 0) {
         constexpr uint32_t B = (uint32_t)(-RF);
-        return (uint32_t)(r.w[0] >> (B * f)) & ((1u << B) - 1u);
+        return (r.w[0] >> (B * f)) & ((1u << B) - 1u);
     } else {
         return (uint32_t)(r.w[f / 3] >> (FIELD_BITS * (f % 3))) & FIELD_MASK;
     }
@@ -98,7 +99,7 @@ __device__ __forceinline__ void set_fld(Rec<RF> &r, int f, uint32_t v) {
     if constexpr (RF < 0) {
         constexpr uint32_t B = (uint32_t)(-RF);
         const uint32_t sh = B * f;
-        r.w[0] = (r.w[0] & ~((uint64_t)((1u << B) - 1u) << sh)) | ((uint64_t)v << sh);
+        r.w[0] = (r.w[0] & ~(((1u << B) - 1u) << sh)) | (v << sh);
     } else {
         const int sh = FIELD_BITS * (f % 3);
         r.w[f / 3] = (r.w[f / 3] & ~((uint64_t)FIELD_MASK << sh)) | ((uint64_t)v << sh);
@@ -265,27 +266,32 @@ __global__ __launch_bounds__(256) void seg_kernel(PhaseArgs a, SegList l, uint32
     const uint32_t ph = (uint32_t)PHASE << 16;
     unsigned long long acc = 0;
 
-    for (uint32_t li = lo + bj * GPB + g; li < hi; li += ngx) {
-        const uint32_t s_id = l.ids[li];
-        const uint32_t beg = a.segptr[s_id];
-        const uint32_t L = a.segptr[s_id + 1] - beg;
+    // Segment li's span and records.  All pointers first, then all records,
+    // with no branch around any load (slots past the segment's end re-read its
+    // last token), so each batch is in flight at once.
+    auto fetch = [&](uint32_t lj, uint32_t &fbeg, uint32_t &fL, uint32_t(&fpos)[TPT], Rec<NW>(&frec)[TPT]) {
+        const uint32_t s_id = l.ids[lj];
+        fbeg = a.segptr[s_id];
+        fL = a.segptr[s_id + 1] - fbeg;
+        if (a.idx) {
+#pragma unroll
+            for (int r = 0; r < TPT; ++r) fpos[r] = a.idx[fbeg + min(r * GROUP + lane, fL - 1)];
+        } else {
+#pragma unroll
+            for (int r = 0; r < TPT; ++r) fpos[r] = fbeg + min(r * GROUP + lane, fL - 1);
+        }
+#pragma unroll
+        for (int r = 0; r < TPT; ++r) frec[r] = ld_rec<NW>(a.recs, fpos[r]);
+    };
+    uint32_t li = lo + bj * GPB + g;
+    uint32_t beg = 0, L = 1;
+    uint32_t pos[TPT];
+    Rec<NW> rec[TPT];
+    if (li < hi) fetch(li, beg, L, pos, rec);
+    for (; li < hi; li += ngx) {
         // word proposals of a column with L > K: inverse CDF of its updated
         // counts (the table is dense whenever L > K: K < L <= GROUP * TPT)
         const bool by_cdf = CDF && PHASE == PH_WORD && !a.draw_only && dense && L > K;
-        // All pointers first, then all records, with no branch around any load:
-        // slots past the segment's end re-read its last token.  Each batch is
-        // then in flight at once instead of one dependent pair per slot.
-        uint32_t pos[TPT];
-        Rec<NW> rec[TPT];
-        if (a.idx) {
-#pragma unroll
-            for (int r = 0; r < TPT; ++r) pos[r] = a.idx[beg + min(r * GROUP + lane, L - 1)];
-        } else {
-#pragma unroll
-            for (int r = 0; r < TPT; ++r) pos[r] = beg + min(r * GROUP + lane, L - 1);
-        }
-#pragma unroll
-        for (int r = 0; r < TPT; ++r) rec[r] = ld_rec<NW>(a.recs, pos[r]);
         uint32_t znew[TPT];
         uint32_t r2[TPT][M] = {};
         uint32_t coins = 0;   // bit r*M + i: proposal i of token r takes the count part
@@ -376,6 +382,15 @@ __global__ __launch_bounds__(256) void seg_kernel(PhaseArgs a, SegList l, uint32
             }
         }
         group_sync<GROUP>();
+        // Word phase: the next segment's loads go out before this one's stores
+        // (loads and stores share one in-order counter, so loads issued after
+        // the stores would wait for them).  Measured slower in the doc phase,
+        // whose gathers and scatters compete for the same L2 lines.
+        constexpr bool PREFETCH = PHASE == PH_WORD;
+        uint32_t nbeg = 0, nL = 1;
+        uint32_t npos[TPT];
+        Rec<NW> nrec[TPT];
+        if (PREFETCH && li + ngx < hi) fetch(li + ngx, nbeg, nL, npos, nrec);
 #pragma unroll
         for (int r = 0; r < TPT; ++r) {
             if (r * GROUP + lane < L) {
@@ -402,6 +417,17 @@ __global__ __launch_bounds__(256) void seg_kernel(PhaseArgs a, SegList l, uint32
         if (by_cdf) {           // prefix sums fill the table: clear all of it
             for (uint32_t k = lane; k < K; k += GROUP) tcnt[k] = 0;
             group_sync<GROUP>();
+        }
+        if constexpr (PREFETCH) {
+            beg = nbeg;
+            L = nL;
+#pragma unroll
+            for (int r = 0; r < TPT; ++r) {
+                pos[r] = npos[r];
+                rec[r] = nrec[r];
+            }
+        } else if (li + ngx < hi) {
+            fetch(li + ngx, beg, L, pos, rec);
         }
     }
     add_accepted(a.accepted, acc);
