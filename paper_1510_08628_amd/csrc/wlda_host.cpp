@@ -304,9 +304,9 @@ struct wlda_sampler_s {
     size_t ev_used = 0;
     uint64_t slot_tokens[KSLOTS] = {};
     // launch-shape bounds (grid size of the segment kernels), per phase and
-    // bin: [word wave, block, wide, doc wave, block, wide]; overridable with
-    // WLDA_SEG_BLOCKS="a,b,c,d,e,f" for tuning sweeps
-    uint32_t seg_blocks[2 * NBINS] = {1024, 1024, 1024, 1024, 1024, 1024};
+    // bin: [word wave, block, wide, doc wave, block, wide]; set from the CU
+    // count at create, overridable with WLDA_SEG_BLOCKS="a,b,c,d,e,f"
+    uint32_t seg_blocks[2 * NBINS] = {1024, 1024, 1024, 512, 768, 512};
 };
 
 namespace {
@@ -561,6 +561,20 @@ wlda_status wlda_create(const wlda_params *p, const uint32_t *word_ids, const ui
     s->alpha_bar = (float)p->K * s->a;
     s->beta_k = (float)p->K * s->b;
     s->beta_bar = (float)p->V * s->b;
+    {
+        // Workgroups per CU of each segment kernel.  The word phase streams
+        // and wants every resident slot; the doc phase gathers and scatters
+        // inside L2-resident blocks, and more rows in flight than about two
+        // (rows <= 512) or three (longer rows) workgroups per CU make the L2
+        // write dirty lines back before they fill (measured: 4 per CU costs
+        // the row kernel 20%).  Multiples of the CU count keep every CU of
+        // an XCD equally loaded.
+        static const uint32_t per_cu[2 * NBINS] = {4, 4, 4, 2, 3, 2};
+        int dev = 0, cus = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
+            for (int i = 0; i < 2 * NBINS; ++i) s->seg_blocks[i] = per_cu[i] * (uint32_t)cus;
+    }
     if (const char *env = std::getenv("WLDA_SEG_BLOCKS")) {
         unsigned v[2 * NBINS];
         if (std::sscanf(env, "%u,%u,%u,%u,%u,%u", &v[0], &v[1], &v[2], &v[3], &v[4], &v[5]) == 2 * NBINS)
