@@ -306,7 +306,9 @@ struct wlda_sampler_s {
     // launch-shape bounds (grid size of the segment kernels), per phase and
     // bin: [word wave, block, wide, doc wave, block, wide]; set from the CU
     // count at create, overridable with WLDA_SEG_BLOCKS="a,b,c,d,e,f"
-    uint32_t seg_blocks[2 * NBINS] = {1024, 1024, 1024, 512, 768, 512};
+    uint32_t seg_blocks[2 * NBINS] = {768, 768, 512, 512, 768, 512};
+    // grid bound of the long-segment kernels [word, doc]; WLDA_LONG_BLOCKS="a,b"
+    uint32_t long_blocks[2] = {4096, 2048};
 };
 
 namespace {
@@ -449,6 +451,7 @@ wlda_status run_phase(wlda_sampler s, uint32_t phase, uint32_t iter, bool draw_o
         else
             WLDA_TRY(s, launch());
     }
+    a.max_blocks = s->long_blocks[phase == PH_WORD ? 0 : 1];
     if (prof) {
         if (ll.n) {
             hipEvent_t ev[4];
@@ -562,18 +565,27 @@ wlda_status wlda_create(const wlda_params *p, const uint32_t *word_ids, const ui
     s->beta_k = (float)p->K * s->b;
     s->beta_bar = (float)p->V * s->b;
     {
-        // Workgroups per CU of each segment kernel.  The word phase streams
-        // and wants every resident slot; the doc phase gathers and scatters
-        // inside L2-resident blocks, and more rows in flight than about two
-        // (rows <= 512) or three (longer rows) workgroups per CU make the L2
-        // write dirty lines back before they fill (measured: 4 per CU costs
-        // the row kernel 20%).  Multiples of the CU count keep every CU of
-        // an XCD equally loaded.
-        static const uint32_t per_cu[2 * NBINS] = {4, 4, 4, 2, 3, 2};
+        // Workgroups per CU of each segment kernel, measured at C1: the doc
+        // phase gathers and scatters inside L2-resident blocks, and more rows
+        // in flight than about two (rows <= 512) or three (longer rows)
+        // workgroups per CU make the L2 write dirty lines back before they
+        // fill (4 per CU costs the row kernel 20%); the word phase's column
+        // kernels peak at 2-3.  The long-segment kernels stream chunks and
+        // want many more.  Multiples of the CU count keep every CU of an XCD
+        // equally loaded.
+        static const uint32_t per_cu[2 * NBINS] = {3, 3, 2, 2, 3, 2};
+        static const uint32_t long_per_cu[2] = {16, 8};
         int dev = 0, cus = 0;
         if (hipGetDevice(&dev) == hipSuccess &&
-            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0) {
             for (int i = 0; i < 2 * NBINS; ++i) s->seg_blocks[i] = per_cu[i] * (uint32_t)cus;
+            for (int i = 0; i < 2; ++i) s->long_blocks[i] = long_per_cu[i] * (uint32_t)cus;
+        }
+    }
+    if (const char *env = std::getenv("WLDA_LONG_BLOCKS")) {
+        unsigned v[2];
+        if (std::sscanf(env, "%u,%u", &v[0], &v[1]) == 2)
+            for (int i = 0; i < 2; ++i) s->long_blocks[i] = v[i] < 8 ? 8 : (v[i] > 65536 ? 65536 : v[i]);
     }
     if (const char *env = std::getenv("WLDA_SEG_BLOCKS")) {
         unsigned v[2 * NBINS];

@@ -1073,7 +1073,8 @@ static hipError_t long_dispatch_z(const PhaseArgs &a, const LongList &l, hipStre
     constexpr int NW = decltype(rfc)::value;
     const bool lds_tab = a.K <= Tuning::LDS_DENSE_MAX;
     const bool ck_lds = a.K <= Tuning::CK_LDS_MAX;
-    uint32_t blocks = l.n_chunks < 2048 ? l.n_chunks : 2048;
+    const uint32_t cap_blocks = a.max_blocks >= 8 ? a.max_blocks : 8;
+    uint32_t blocks = l.n_chunks < cap_blocks ? l.n_chunks : cap_blocks;
     blocks = (blocks + 7) / 8 * 8;
     hipError_t e;
     if (ev && (e = hipEventRecord(ev[0], st)) != hipSuccess) return e;
