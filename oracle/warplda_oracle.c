@@ -39,8 +39,10 @@
  *     over K topics);
  *   - all acceptance and coin arithmetic is IEEE binary32 with the exact
  *     expressions below, no fused multiply-add, strict "<";
- *   - randomness is Philox4x32-10 (Salmon et al., SC'11), one call per
- *     (token, iteration, phase, step) with the counter layout of rng_call();
+ *   - randomness is Philox4x32-10 (Salmon et al., SC'11) with the counter
+ *     layout of rng_call(): per (token, iteration, phase), call 0 gives the
+ *     M acceptance uniforms and calls 1..ceil(M/2) the (coin, index) words
+ *     of two proposals each (accept_words, draw_words);
  *     the token index is the token's position in the order its phase visits
  *     it: the canonical column-major (CSC) position at initialisation and in
  *     the word phase, the canonical row-major (CSR) position, rowptr[d] + n,
@@ -92,6 +94,26 @@ static void rng_call(uint64_t seed, uint32_t token, uint32_t iter,
     uint32_t key[2] = { (uint32_t)seed, (uint32_t)(seed >> 32) };
     uint32_t ctr[4] = { token, iter, (phase << 16) | step, stream };
     oracle_philox4x32_10(key, ctr, r);
+}
+
+/* The random words of one token in one phase: call 0 holds the M
+ * acceptance uniforms (word i-1 for step i, M <= 4); call j >= 1 holds the
+ * mixture coin and the index/topic word of proposals 2j-1 (words 0, 1) and
+ * 2j (words 2, 3).  draw_words() returns those of proposal i. */
+static void accept_words(uint64_t seed, uint32_t token, uint32_t iter,
+                         uint32_t phase, uint32_t r[4])
+{
+    rng_call(seed, token, iter, phase, 0, 0, r);
+}
+
+static void draw_words(uint64_t seed, uint32_t token, uint32_t iter,
+                       uint32_t phase, uint32_t i, uint32_t *coin_word,
+                       uint32_t *index_word)
+{
+    uint32_t r[4];
+    rng_call(seed, token, iter, phase, (i + 1) / 2, 0, r);
+    *coin_word = r[2 * ((i - 1) % 2)];
+    *index_word = r[2 * ((i - 1) % 2) + 1];
 }
 
 /* Uniform in [0,1) on the 2^-24 grid. */
@@ -227,7 +249,7 @@ void oracle_destroy(oracle_t *o)
 oracle_t *oracle_create(const oracle_params *p, const uint32_t *word_ids,
                         const uint32_t *doc_ids, uint64_t n_tokens)
 {
-    if (!p || p->K == 0 || p->M == 0 || p->M > 0xFFFF || p->V == 0 ||
+    if (!p || p->K == 0 || p->M == 0 || p->M > 4 || p->V == 0 ||
         p->D == 0 || !(p->alpha > 0) || !(p->beta > 0) ||
         n_tokens >= ((uint64_t)1 << 32))
         return NULL;
@@ -274,13 +296,13 @@ static void draw_doc_proposals(oracle_t *o, uint32_t d, uint32_t iter)
     for (uint64_t n = 0; n < L; ++n) {
         uint32_t t = o->row[beg + n];
         for (uint32_t i = 1; i <= o->M; ++i) {
-            uint32_t r[4];
-            rng_call(o->seed, (uint32_t)(beg + n), iter, PH_DOC, i, 0, r);
+            uint32_t cw_, iw;
+            draw_words(o->seed, (uint32_t)(beg + n), iter, PH_DOC, i, &cw_, &iw);
             int32_t prop;
-            if (take_count_part(unif24(r[1]), L, o->alpha_bar))
-                prop = o->z[o->row[beg + dice(r[2], (uint32_t)L)]];
+            if (take_count_part(unif24(cw_), L, o->alpha_bar))
+                prop = o->z[o->row[beg + dice(iw, (uint32_t)L)]];
             else
-                prop = (int32_t)dice(r[2], o->K);
+                prop = (int32_t)dice(iw, o->K);
             o->prop[(uint64_t)(i - 1) * o->T + t] = prop;
         }
     }
@@ -319,11 +341,11 @@ static void word_column(oracle_t *o, uint32_t w, uint32_t iter, int64_t *ck_next
     for (uint64_t n = 0; n < L; ++n) {
         uint32_t t = (uint32_t)(beg + n);
         int32_t s = o->z[t];
+        uint32_t ra[4];
+        accept_words(o->seed, t, iter, PH_WORD, ra);
         for (uint32_t i = 1; i <= o->M; ++i) {
-            uint32_t r[4];
-            rng_call(o->seed, t, iter, PH_WORD, i, 0, r);
             int32_t c = o->prop[(uint64_t)(i - 1) * o->T + t];
-            if (mh_accept(unif24(r[0]), cw[c], cw[s], o->b, o->ck[s],
+            if (mh_accept(unif24(ra[i - 1]), cw[c], cw[s], o->b, o->ck[s],
                           o->ck[c], o->beta_bar)) {
                 s = c;
                 (*accepted)++;
@@ -348,14 +370,14 @@ static void word_column(oracle_t *o, uint32_t w, uint32_t iter, int64_t *ck_next
     for (uint64_t n = 0; n < L; ++n) {
         uint32_t t = (uint32_t)(beg + n);
         for (uint32_t i = 1; i <= o->M; ++i) {
-            uint32_t r[4];
-            rng_call(o->seed, t, iter, PH_WORD, i, 0, r);
+            uint32_t cw_, iw;
+            draw_words(o->seed, t, iter, PH_WORD, i, &cw_, &iw);
             int32_t prop;
-            if (take_count_part(unif24(r[1]), L, o->beta_k)) {
-                uint32_t j = dice(r[2], (uint32_t)L);
+            if (take_count_part(unif24(cw_), L, o->beta_k)) {
+                uint32_t j = dice(iw, (uint32_t)L);
                 prop = by_cdf ? cdf_topic(cw, o->K, j) : o->z[beg + j];
             } else {
-                prop = (int32_t)dice(r[2], o->K);
+                prop = (int32_t)dice(iw, o->K);
             }
             o->prop[(uint64_t)(i - 1) * o->T + t] = prop;
         }
@@ -398,11 +420,11 @@ static void doc_row(oracle_t *o, uint32_t d, uint32_t iter, int64_t *ck_next,
     for (uint64_t n = 0; n < L; ++n) {
         uint32_t t = o->row[beg + n];
         int32_t s = o->z[t];
+        uint32_t ra[4];
+        accept_words(o->seed, (uint32_t)(beg + n), iter, PH_DOC, ra);
         for (uint32_t i = 1; i <= o->M; ++i) {
-            uint32_t r[4];
-            rng_call(o->seed, (uint32_t)(beg + n), iter, PH_DOC, i, 0, r);
             int32_t c = o->prop[(uint64_t)(i - 1) * o->T + t];
-            if (mh_accept(unif24(r[0]), cd[c], cd[s], o->a, o->ck[s],
+            if (mh_accept(unif24(ra[i - 1]), cd[c], cd[s], o->a, o->ck[s],
                           o->ck[c], o->beta_bar)) {
                 s = c;
                 (*accepted)++;

@@ -35,6 +35,10 @@
 //   count part iff U * (L + mass) < L, then the topic of a uniformly chosen
 //   token of the (updated) segment, else a uniform topic       (Eq. 6, Sec. 4.3)
 //   U(r) = (r >> 8) * 2^-24,  Dice(r, n) = (r * n) >> 32.
+// Random words per (token, iteration, phase): Philox call 0 gives the M
+// acceptance uniforms; call j >= 1 the (coin, index) words of proposals 2j-1
+// and 2j.  The MH pass and the draw pass of the long path each compute only
+// their own calls.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -105,6 +109,16 @@ __device__ __forceinline__ void set_fld(Rec<RF> &r, int f, uint32_t v) {
         r.w[f / 3] = (r.w[f / 3] & ~((uint64_t)FIELD_MASK << sh)) | ((uint64_t)v << sh);
     }
 }
+
+// Word w (0..3) of a Philox output.
+__device__ __forceinline__ uint32_t word4(const uint4 &r, int w) {
+    return w == 0 ? r.x : w == 1 ? r.y : w == 2 ? r.z : r.w;
+}
+
+// The random words of a token in a phase: call 0 (step field 0) holds the M
+// acceptance uniforms, word i-1 for step i; call j >= 1 holds the mixture
+// coin and the index/topic word of proposals 2j-1 (words 0, 1) and 2j
+// (words 2, 3).
 
 // --------------------------------------------------------------------------
 // LDS count tables
@@ -293,8 +307,6 @@ __global__ __launch_bounds__(256) void seg_kernel(PhaseArgs a, SegList l, uint32
         // counts (the table is dense whenever L > K: K < L <= GROUP * TPT)
         const bool by_cdf = CDF && PHASE == PH_WORD && !a.draw_only && dense && L > K;
         uint32_t znew[TPT];
-        uint32_t r2[TPT][M] = {};
-        uint32_t coins = 0;   // bit r*M + i: proposal i of token r takes the count part
         if (!a.draw_only) {
             uint32_t mask = 0;
             if (!dense) {
@@ -314,20 +326,19 @@ __global__ __launch_bounds__(256) void seg_kernel(PhaseArgs a, SegList l, uint32
             for (int r = 0; r < TPT; ++r) {
                 if (r * GROUP + lane < L) {
                     uint32_t s = fld(rec[r], 0);
+                    const uint4 RA = philox(beg + r * GROUP + lane, a.iter, ph, 0, a.seed_lo, a.seed_hi);
 #pragma unroll
                     for (int i = 1; i <= M; ++i) {
-                        const uint4 R = philox(beg + r * GROUP + lane, a.iter, ph | i, 0, a.seed_lo, a.seed_hi);
                         const uint32_t c = fld(rec[r], i);
                         const uint32_t cc = tab_get(tkey, tcnt, mask, dense, c);
                         const uint32_t cs = tab_get(tkey, tcnt, mask, dense, s);
-                        const bool ok = ck_lds ? mh_accept_b(unif24(R.x), cc, cs, prior, ckb[s], ckb[c])
-                                               : mh_accept(unif24(R.x), cc, cs, prior, a.ck[s], a.ck[c], beta_bar);
+                        const float u = unif24(word4(RA, i - 1));
+                        const bool ok = ck_lds ? mh_accept_b(u, cc, cs, prior, ckb[s], ckb[c])
+                                               : mh_accept(u, cc, cs, prior, a.ck[s], a.ck[c], beta_bar);
                         if (ok) {
                             s = c;
                             ++acc;
                         }
-                        if (take_count_part(unif24(R.y), L, mass)) coins |= 1u << (r * M + i - 1);
-                        r2[r][i - 1] = R.z;
                     }
                     znew[r] = s;
                 }
@@ -348,38 +359,12 @@ __global__ __launch_bounds__(256) void seg_kernel(PhaseArgs a, SegList l, uint32
             }
         } else {
 #pragma unroll
-            for (int r = 0; r < TPT; ++r) {
-                if (r * GROUP + lane < L) {
-                    znew[r] = fld(rec[r], 0);
-#pragma unroll
-                    for (int i = 1; i <= M; ++i) {
-                        const uint4 R = philox(beg + r * GROUP + lane, a.iter, ph | i, 0, a.seed_lo, a.seed_hi);
-                        if (take_count_part(unif24(R.y), L, mass)) coins |= 1u << (r * M + i - 1);
-                        r2[r][i - 1] = R.z;
-                    }
-                }
-            }
+            for (int r = 0; r < TPT; ++r) znew[r] = fld(rec[r], 0);
         }
+        if (!by_cdf) {
 #pragma unroll
-        for (int r = 0; r < TPT; ++r)
-            if (r * GROUP + lane < L) zarr[r * GROUP + lane] = znew[r];
-        if (by_cdf) {           // count-part draws become topics, CDF_RB tokens at a time
-            constexpr int CDF_RB = TPT < 4 ? TPT : 4;
-#pragma unroll
-            for (int r0 = 0; r0 < TPT; r0 += CDF_RB) {
-                uint32_t jj[CDF_RB * M];
-#pragma unroll
-                for (int q = 0; q < CDF_RB; ++q)
-#pragma unroll
-                    for (int i = 0; i < M; ++i)
-                        jj[q * M + i] = dice(r2[r0 + q][i], L);   // < L: in range for any slot
-                cdf_find_n<CDF_RB * M>(tcnt, K, jj);
-#pragma unroll
-                for (int q = 0; q < CDF_RB; ++q)
-#pragma unroll
-                    for (int i = 0; i < M; ++i)
-                        if ((coins >> ((r0 + q) * M + i)) & 1u) r2[r0 + q][i] = jj[q * M + i];
-            }
+            for (int r = 0; r < TPT; ++r)
+                if (r * GROUP + lane < L) zarr[r * GROUP + lane] = znew[r];
         }
         group_sync<GROUP>();
         // Word phase: the next segment's loads go out before this one's stores
@@ -391,26 +376,65 @@ __global__ __launch_bounds__(256) void seg_kernel(PhaseArgs a, SegList l, uint32
         uint32_t npos[TPT];
         Rec<NW> nrec[TPT];
         if (PREFETCH && li + ngx < hi) fetch(li + ngx, nbeg, nL, npos, nrec);
+        // Draws, DB tokens at a time: the count part is a token of the updated
+        // segment (random positioning) or, for columns with L > K, the
+        // inverse CDF of their counts, resolved for the whole batch at once.
+        constexpr int DB = TPT < 4 ? TPT : 4;
 #pragma unroll
-        for (int r = 0; r < TPT; ++r) {
-            if (r * GROUP + lane < L) {
-                Rec<NW> out;
+        for (int r0 = 0; r0 < TPT; r0 += DB) {
+            uint32_t pw[DB * M];
+            uint32_t pend = 0;          // bit q*M + i - 1: pw holds an index for the CDF
 #pragma unroll
-                for (int w = 0; w < (NW > 0 ? NW : 1); ++w) out.w[w] = 0;
-                set_fld(out, 0, znew[r]);
+            for (int q = 0; q < DB; ++q) {
+                const uint32_t n = (r0 + q) * GROUP + lane;
 #pragma unroll
-                for (int i = 1; i <= M; ++i) {
-                    const uint32_t rr = r2[r][i - 1];
-                    const uint32_t p = !((coins >> (r * M + i - 1)) & 1u) ? dice(rr, K)
-                                       : by_cdf ? rr                 // resolved above
-                                                : zarr[dice(rr, L)];
-                    set_fld(out, i, p);
+                for (int i = 0; i < M; ++i) pw[q * M + i] = 0;
+                if (n < L) {
+#pragma unroll
+                    for (int j = 1; j <= (M + 1) / 2; ++j) {
+                        const uint4 RB = philox(beg + n, a.iter, ph | j, 0, a.seed_lo, a.seed_hi);
+#pragma unroll
+                        for (int h = 0; h < 2; ++h) {
+                            const int i = 2 * j - 1 + h;
+                            if (i > M) continue;
+                            const uint32_t w = word4(RB, 2 * h + 1);
+                            if (!take_count_part(unif24(word4(RB, 2 * h)), L, mass)) {
+                                pw[q * M + i - 1] = dice(w, K);
+                            } else if (by_cdf) {
+                                pw[q * M + i - 1] = dice(w, L);
+                                pend |= 1u << (q * M + i - 1);
+                            } else {
+                                pw[q * M + i - 1] = zarr[dice(w, L)];
+                            }
+                        }
+                    }
                 }
-                st_rec<NW>(a.recs, pos[r], out);
-                if (ck_lds)
-                    atomicAdd(&ckh[znew[r]], 1u);
-                else
-                    atomicAdd(&a.ck_next[znew[r]], 1u);
+            }
+            if (by_cdf) {
+                uint32_t jj[DB * M];
+#pragma unroll
+                for (int d = 0; d < DB * M; ++d) jj[d] = (pend >> d) & 1u ? pw[d] : 0u;
+                cdf_find_n<DB * M>(tcnt, K, jj);
+#pragma unroll
+                for (int d = 0; d < DB * M; ++d)
+                    if ((pend >> d) & 1u) pw[d] = jj[d];
+            }
+#pragma unroll
+            for (int q = 0; q < DB; ++q) {
+                const int r = r0 + q;
+                if (r * GROUP + lane < L) {
+                    Rec<NW> out;
+#pragma unroll
+                    for (int w = 0; w < (NW > 0 ? NW : 1); ++w) out.w[w] = 0;
+                    set_fld(out, 0, znew[r]);
+#pragma unroll
+                    for (int i = 1; i <= M; ++i) set_fld(out, i, pw[q * M + i - 1]);
+                    st_rec<NW>(a.recs, pos[r], out);
+                    if (ck_lds)
+                        atomicAdd(&ckh[znew[r]], 1u);
+                    else
+                        atomicAdd(&a.ck_next[znew[r]], 1u);
+                }
             }
         }
         group_sync<GROUP>();
@@ -603,9 +627,10 @@ __global__ __launch_bounds__(256) void long_mh_kernel(PhaseArgs a, LongList l, u
                 const uint32_t n = nb + u * 256;
                 if (n >= n1) continue;
                 uint32_t s = fld(rec[u], 0);
+                const uint4 RA = philox(beg + n, a.iter, ph, 0, a.seed_lo, a.seed_hi);
 #pragma unroll
                 for (int i = 1; i <= M; ++i) {
-                    const uint4 R = philox(beg + n, a.iter, ph | i, 0, a.seed_lo, a.seed_hi);
+                    const float uacc = unif24(word4(RA, i - 1));
                     const uint32_t c = fld(rec[u], i);
                     // separate paths keep LDS reads as ds_read (a pointer
                     // selected at run time would force flat loads)
@@ -617,8 +642,8 @@ __global__ __launch_bounds__(256) void long_mh_kernel(PhaseArgs a, LongList l, u
                         cc = gtab_get(gt, gcap, c);
                         cs = gtab_get(gt, gcap, s);
                     }
-                    const bool ok = ck_lds ? mh_accept_b(unif24(R.x), cc, cs, a.prior, ckb[s], ckb[c])
-                                           : mh_accept(unif24(R.x), cc, cs, a.prior, a.ck[s], a.ck[c], a.beta_bar);
+                    const bool ok = ck_lds ? mh_accept_b(uacc, cc, cs, a.prior, ckb[s], ckb[c])
+                                           : mh_accept(uacc, cc, cs, a.prior, a.ck[s], a.ck[c], a.beta_bar);
                     if (ok) {
                         s = c;
                         ++acc;
@@ -739,14 +764,20 @@ __global__ __launch_bounds__(256) void long_draw_kernel(PhaseArgs a, LongList l,
                 const uint32_t n = nb + u * 256;
                 if (n >= n1) continue;
 #pragma unroll
-                for (int i = 1; i <= M; ++i) {
-                    const uint4 R = philox(beg + n, a.iter, ph | i, 0, a.seed_lo, a.seed_hi);
-                    if (take_count_part(unif24(R.y), L, a.mass)) {
-                        coin |= 1u << (u * M + i - 1);
-                        jj[u * M + i - 1] = dice(R.z, L);
-                        if (!by_cdf) set_fld(rec[u], i, (uint32_t)zs[jj[u * M + i - 1]]);
-                    } else {
-                        set_fld(rec[u], i, dice(R.z, K));
+                for (int j = 1; j <= (M + 1) / 2; ++j) {
+                    const uint4 RB = philox(beg + n, a.iter, ph | j, 0, a.seed_lo, a.seed_hi);
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        const int i = 2 * j - 1 + h;
+                        if (i > M) continue;
+                        const uint32_t w = word4(RB, 2 * h + 1);
+                        if (take_count_part(unif24(word4(RB, 2 * h)), L, a.mass)) {
+                            coin |= 1u << (u * M + i - 1);
+                            jj[u * M + i - 1] = dice(w, L);
+                            if (!by_cdf) set_fld(rec[u], i, (uint32_t)zs[jj[u * M + i - 1]]);
+                        } else {
+                            set_fld(rec[u], i, dice(w, K));
+                        }
                     }
                 }
             }

@@ -92,7 +92,7 @@ def test_layout_definition():
 def test_rejects_invalid_inputs():
     w = np.array([0, 1], dtype=np.uint32)
     d = np.array([0, 0], dtype=np.uint32)
-    for kw in [dict(K=0), dict(M=0), dict(alpha=0.0), dict(beta=-1.0)]:
+    for kw in [dict(K=0), dict(M=0), dict(M=5), dict(alpha=0.0), dict(beta=-1.0)]:
         args = dict(V=2, D=1, K=2, M=1, alpha=0.1, beta=0.1)
         args.update(kw)
         with pytest.raises(ValueError):
