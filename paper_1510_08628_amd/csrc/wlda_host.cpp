@@ -306,7 +306,7 @@ struct wlda_sampler_s {
     // launch-shape bounds (grid size of the segment kernels), per phase and
     // bin: [word wave, block, wide, doc wave, block, wide]; set from the CU
     // count at create, overridable with WLDA_SEG_BLOCKS="a,b,c,d,e,f"
-    uint32_t seg_blocks[2 * NBINS] = {768, 768, 512, 512, 768, 512};
+    uint32_t seg_blocks[2 * NBINS] = {768, 1024, 768, 512, 768, 512};
     // grid bound of the long-segment kernels [word, doc]; WLDA_LONG_BLOCKS="a,b"
     uint32_t long_blocks[2] = {4096, 2048};
 };
@@ -573,7 +573,7 @@ wlda_status wlda_create(const wlda_params *p, const uint32_t *word_ids, const ui
         // kernels peak at 2-3.  The long-segment kernels stream chunks and
         // want many more.  Multiples of the CU count keep every CU of an XCD
         // equally loaded.
-        static const uint32_t per_cu[2 * NBINS] = {3, 3, 2, 2, 3, 2};
+        static const uint32_t per_cu[2 * NBINS] = {3, 4, 3, 2, 3, 2};
         static const uint32_t long_per_cu[2] = {16, 8};
         int dev = 0, cus = 0;
         if (hipGetDevice(&dev) == hipSuccess &&
