@@ -84,15 +84,32 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(int M, int N, int Kd, co
 }
 
 // a1[b][j] = b1[j] + sum_n val_n W1b[idx_n][j]; h1b = bf16(relu(a1))
+// One workgroup per document.  Eight features at a time with separate partial
+// sums, so eight row reads of W1 are in flight per thread (a single running
+// sum serialises one dependent load per feature); the partial sums are added
+// in a fixed order, so the result is deterministic.
 __global__ __launch_bounds__(256) void embag_fwd_kernel(int H, const uint32_t *rowptr, const uint32_t *idx,
                                                         const float *val, const uint16_t *W1b,
                                                         const float *b1, float *a1, uint16_t *h1b) {
+    constexpr int U = 8;
     const int b = blockIdx.x;
+    const uint32_t n0 = rowptr[b], n1 = rowptr[b + 1];
     for (int j = threadIdx.x; j < H; j += 256) {
-        float acc = b1[j];
-        for (uint32_t n = rowptr[b]; n < rowptr[b + 1]; ++n) acc += val[n] * from_bf16(W1b[(size_t)idx[n] * H + j]);
-        a1[(size_t)b * H + j] = acc;
-        h1b[(size_t)b * H + j] = to_bf16(acc > 0.f ? acc : 0.f);
+        float acc[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) acc[u] = 0.f;
+        uint32_t n = n0;
+        for (; n + U <= n1; n += U) {
+            float w[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) w[u] = from_bf16(W1b[(size_t)idx[n + u] * H + j]);
+#pragma unroll
+            for (int u = 0; u < U; ++u) acc[u] += val[n + u] * w[u];
+        }
+        for (int u = 0; n < n1; ++n, ++u) acc[u] += val[n] * from_bf16(W1b[(size_t)idx[n] * H + j]);
+        const float sum = b1[j] + (((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7])));
+        a1[(size_t)b * H + j] = sum;
+        h1b[(size_t)b * H + j] = to_bf16(sum > 0.f ? sum : 0.f);
     }
 }
 

@@ -37,6 +37,7 @@ struct FoldBatch {
 };
 
 constexpr uint32_t FOLD_MAX_TOKENS = 8192;
+constexpr uint32_t FOLD_Q_LDS_MAX = 4096;   // learned proposal CDF staged in LDS up to this K
 
 const FoldModel &model_internal(wlda_model m);
 const wlda_params &model_params(wlda_model m);

@@ -56,15 +56,38 @@ __global__ __launch_bounds__(256) void fold_sweep_kernel(FoldModel m, FoldBatch 
     if (s > b.max_sweep || L == 0) return;
     uint32_t *zs = lds;                 // L
     uint32_t *cd = lds + FOLD_MAX_TOKENS;   // K
+    uint32_t *qs = cd + K;              // K: the learned CDF staged in LDS (K <= FOLD_Q_LDS_MAX)
     const ZT *zc = reinterpret_cast<const ZT *>(m.zcsc);
     const uint32_t *qcdf =
         b.qcdf && (!b.use_q || b.use_q[slot]) ? b.qcdf + (size_t)slot * K : nullptr;
     const uint32_t cap = b.cap;
+    const bool q_lds = qcdf && K <= FOLD_Q_LDS_MAX;
+    if (q_lds) {
+        for (uint32_t k = threadIdx.x; k < K; k += 256) qs[k] = qcdf[k];
+        __syncthreads();
+    }
+    // The learned independence steps of one token (Alg. 1 with target Eq. 5
+    // and proposal q): q read from LDS or global memory through a pointer of
+    // known address space.
+    auto learned = [&](const uint32_t *q, uint32_t n, uint32_t x) {
+        const uint32_t w = b.words[off + n];
+        const uint32_t *cw = m.cwk + (size_t)w * K;
+        for (uint32_t j = 1; j <= b.learned_steps; ++j) {
+            const uint4 R = philox(n, s, (PH_F_LEARN << 16) | j, req, m.seed_lo, m.seed_hi);
+            const uint32_t t = cdf_draw(q, K, R.z);
+            const float wx = (float)(q[x] - (x ? q[x - 1] : 0u));
+            const float wt = (float)(q[t] - (t ? q[t - 1] : 0u));
+            const float num = ((float)cd[t] + m.a) * ((float)cw[t] + m.b) * ((float)m.ck[x] + m.beta_bar) * wx;
+            const float den = ((float)cd[x] + m.a) * ((float)cw[x] + m.b) * ((float)m.ck[t] + m.beta_bar) * wt;
+            if (unif24(R.x) * den < num) x = t;
+        }
+        return x;
+    };
 
     if (s == 0) {
         for (uint32_t n = threadIdx.x; n < L; n += 256) {
             const uint4 R = philox(n, 0, PH_F_INIT << 16, req, m.seed_lo, m.seed_hi);
-            zs[n] = qcdf ? cdf_draw(qcdf, K, R.z) : dice(R.z, K);
+            zs[n] = q_lds ? cdf_draw(qs, K, R.z) : qcdf ? cdf_draw(qcdf, K, R.z) : dice(R.z, K);
         }
         __syncthreads();
     } else {
@@ -96,21 +119,10 @@ __global__ __launch_bounds__(256) void fold_sweep_kernel(FoldModel m, FoldBatch 
                 const uint32_t c = b.pw[(size_t)(i - 1) * cap + off + n];
                 if (mh_accept(unif24(R.x), cd[c], cd[x], m.a, m.ck[x], m.ck[c], m.beta_bar)) x = c;
             }
-            if (qcdf) {
-                const uint32_t w = b.words[off + n];
-                const uint32_t *cw = m.cwk + (size_t)w * K;
-                for (uint32_t j = 1; j <= b.learned_steps; ++j) {
-                    const uint4 R = philox(n, s, (PH_F_LEARN << 16) | j, req, m.seed_lo, m.seed_hi);
-                    const uint32_t t = cdf_draw(qcdf, K, R.z);
-                    const float wx = (float)(qcdf[x] - (x ? qcdf[x - 1] : 0u));
-                    const float wt = (float)(qcdf[t] - (t ? qcdf[t - 1] : 0u));
-                    const float num = ((float)cd[t] + m.a) * ((float)cw[t] + m.b) *
-                                      ((float)m.ck[x] + m.beta_bar) * wx;
-                    const float den = ((float)cd[x] + m.a) * ((float)cw[x] + m.b) *
-                                      ((float)m.ck[t] + m.beta_bar) * wt;
-                    if (unif24(R.x) * den < num) x = t;
-                }
-            }
+            if (q_lds)
+                x = learned(qs, n, x);
+            else if (qcdf)
+                x = learned(qcdf, n, x);
             zs[n] = x;
         }
         __syncthreads();
@@ -130,12 +142,16 @@ __global__ __launch_bounds__(256) void fold_sweep_kernel(FoldModel m, FoldBatch 
 // Held-out log likelihood by document completion (binary64): theta from the
 // document's assignments, phi from the frozen counts (Eq. 4, alpha' = alpha+1,
 // beta' = beta+1); out[d] = sum over held-out tokens of log sum_k theta phi.
+// theta_k / (c_k + beta_bar) of one document is staged in LDS (binary64) up to
+// this K; each held-out word then costs one dot product with its row of C_w.
+constexpr uint32_t HELDOUT_LDS_MAX = 8192;
+
 __global__ __launch_bounds__(256) void fold_heldout_kernel(FoldModel m, FoldBatch b,
                                                            const uint32_t *ho_off,
                                                            const uint32_t *ho_len,
                                                            const uint32_t *ho_words, double a,
                                                            double beta, double *out) {
-    extern __shared__ uint32_t cnt[];
+    extern __shared__ uint32_t cnt[];   // K counts, then (K <= HELDOUT_LDS_MAX) K doubles
     __shared__ double part[4];
     const uint32_t K = m.K;
     const uint32_t slot = b.slots[blockIdx.x];
@@ -145,20 +161,33 @@ __global__ __launch_bounds__(256) void fold_heldout_kernel(FoldModel m, FoldBatc
     for (uint32_t n = threadIdx.x; n < L; n += 256) atomicAdd(&cnt[b.z[off + n]], 1u);
     __syncthreads();
     const double denom_d = (double)L + K * a, bbar = m.V * beta;
+    const bool staged = K <= HELDOUT_LDS_MAX;
+    double *tk = reinterpret_cast<double *>(cnt + ((K + 1) & ~1u));   // 8-byte aligned
+    if (staged) {
+        for (uint32_t k = threadIdx.x; k < K; k += 256)
+            tk[k] = ((double)cnt[k] + a) / denom_d / ((double)m.ck[k] + bbar);
+        __syncthreads();
+    }
+    // one wavefront per held-out word: p_h = sum_k theta_k phi_k(w) (Eq. 4),
+    // a wavefront-wide sum, log p_h added by lane 0 in word order
+    const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     double total = 0;
-    for (uint32_t h = 0; h < ho_len[slot]; ++h) {
+    for (uint32_t h = wave; h < ho_len[slot]; h += 4) {
         const uint32_t w = ho_words[ho_off[slot] + h];
         const uint32_t *cw = m.cwk + (size_t)w * K;
         double p = 0;
-        for (uint32_t k = threadIdx.x; k < K; k += 256)
-            p += ((double)cnt[k] + a) / denom_d * (((double)cw[k] + beta) / ((double)m.ck[k] + bbar));
+        if (staged) {
+            for (uint32_t k = lane; k < K; k += 64) p += tk[k] * ((double)cw[k] + beta);
+        } else {
+            for (uint32_t k = lane; k < K; k += 64)
+                p += ((double)cnt[k] + a) / denom_d * (((double)cw[k] + beta) / ((double)m.ck[k] + bbar));
+        }
         for (int o = 32; o > 0; o >>= 1) p += __shfl_down(p, o, 64);
-        if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = p;
-        __syncthreads();
-        if (threadIdx.x == 0) total += log(part[0] + part[1] + part[2] + part[3]);
-        __syncthreads();
+        if (lane == 0) total += log(p);
     }
-    if (threadIdx.x == 0) out[slot] = total;
+    if (lane == 0) part[wave] = total;
+    __syncthreads();
+    if (threadIdx.x == 0) out[slot] = (part[0] + part[1]) + (part[2] + part[3]);
 }
 
 // Frozen counts of a model: C_wk and c_k from the canonical assignments.
@@ -210,7 +239,7 @@ uint64_t model_bytes(const wlda_params &p, uint64_t T) {
 
 hipError_t launch_fold(const FoldModel &m, const FoldBatch &b, hipStream_t st) {
     if (b.n == 0) return hipSuccess;
-    const size_t lds = 4ull * (FOLD_MAX_TOKENS + m.K);
+    const size_t lds = 4ull * (FOLD_MAX_TOKENS + m.K + (b.qcdf && m.K <= FOLD_Q_LDS_MAX ? m.K : 0));
     if (m.zc16) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(fold_sweep_kernel<uint16_t>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -229,7 +258,7 @@ hipError_t launch_heldout(const FoldModel &m, const FoldBatch &b, const uint32_t
                           const uint32_t *ho_len, const uint32_t *ho_words, double alpha, double beta,
                           double *out, hipStream_t st) {
     if (b.n == 0) return hipSuccess;
-    const size_t lds = 4ull * m.K;
+    const size_t lds = 4ull * ((m.K + 1) & ~1u) + (m.K <= HELDOUT_LDS_MAX ? 8ull * m.K : 0);
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(fold_heldout_kernel),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;

@@ -8,9 +8,13 @@
 // (its slot and pool range are freed) once it has had its initialisation and
 // `sweeps` sweeps.  In learned mode the encoder's forward pass for newly
 // admitted documents runs on the encoder's own stream, overlapped with the
-// sweep of the documents already in flight; the new documents' first launch
-// waits on it through an event.  A document's result depends only on its
-// words and request id (its random stream), not on the batch it shared.
+// sweep of the documents already in flight.  Requests at the head of the
+// queue are encoded one step ahead, into one of two stage buffers, so that
+// by their admission the proposal is usually ready and the step does not
+// wait for the encoder; a request admitted before it was encoded is encoded
+// at admission and its first launch waits on an event.  A document's result
+// depends only on its words and request id (its random stream), not on the
+// batch it shared or on when it was encoded.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -37,6 +41,8 @@ struct Pending {
     std::vector<uint32_t> words, ho;
     std::vector<uint32_t> weights;   // caller-provided learned weights (K) or empty
     double arrival;
+    int stage = -1;                  // encoded ahead into stage buffer 0/1, row stage_row
+    uint32_t stage_row = 0;
 };
 
 struct Range {
@@ -108,6 +114,15 @@ struct wlda_server_s {
     uint32_t *d_frow = nullptr, *d_fidx = nullptr;
     float *d_fval = nullptr, *d_probs = nullptr;
     uint32_t *d_cdf_stage = nullptr;
+    // encode-ahead stages (two, used alternately)
+    uint32_t *d_ah_cdf[2] = {nullptr, nullptr}, *d_ah_frow[2] = {nullptr, nullptr},
+             *d_ah_fidx[2] = {nullptr, nullptr};
+    float *d_ah_fval[2] = {nullptr, nullptr};
+    hipEvent_t ah_done[2] = {nullptr, nullptr};
+    bool ah_live[2] = {false, false};
+    int ah_next = 0;
+    std::vector<uint32_t> h_ah_rows[2], h_ah_idx[2];
+    std::vector<float> h_ah_val[2];
     // host
     std::vector<Slot> slots;
     std::vector<uint32_t> h_off, h_len, h_req, h_sweep, h_useq, h_hoff, h_hlen;
@@ -129,7 +144,8 @@ uint64_t server_bytes(const wlda_params &p, const wlda_server_params &sp, bool l
     const uint64_t n = sp.max_docs, T = sp.pool_tokens, H = sp.pool_heldout;
     uint64_t b = 8 * sa(4 * n + 4) + sa(4 * T + 4) * (2 + 2ull * p.M) + sa(4 * H + 4) + sa(8 * n + 8) +
                  sa(4 * n * p.K + 4);
-    if (learned) b += sa(4 * n + 4) + sa(4 * T + 4) + sa(4 * T + 4) + sa(4 * n * p.K) + sa(4 * n * p.K);
+    if (learned)
+        b += 3 * (sa(4 * n + 4) + sa(4 * T + 4) + sa(4 * T + 4)) + 4 * sa(4 * n * p.K);
     return b;
 }
 
@@ -194,9 +210,19 @@ wlda_status wlda_server_create(wlda_model m, wlda_encoder enc, const wlda_server
         s->d_fval = (float *)take(4 * T + 4);
         s->d_probs = (float *)take(4 * n * p.K);
         s->d_cdf_stage = (uint32_t *)take(4 * n * p.K);
+        for (int x = 0; x < 2; ++x) {
+            s->d_ah_frow[x] = (uint32_t *)take(4 * n + 4);
+            s->d_ah_fidx[x] = (uint32_t *)take(4 * T + 4);
+            s->d_ah_fval[x] = (float *)take(4 * T + 4);
+            s->d_ah_cdf[x] = (uint32_t *)take(4 * n * p.K);
+        }
         s->enc_st = (hipStream_t)wlda_encoder_get_stream(enc);
         s->buckets = wlda_encoder_get_buckets(enc);
-        if (hipEventCreateWithFlags(&s->enc_done, hipEventDisableTiming)) {
+        if (hipEventCreateWithFlags(&s->enc_done, hipEventDisableTiming) ||
+            hipEventCreateWithFlags(&s->ah_done[0], hipEventDisableTiming) ||
+            hipEventCreateWithFlags(&s->ah_done[1], hipEventDisableTiming)) {
+            for (hipEvent_t ev : {s->enc_done, s->ah_done[0], s->ah_done[1]})
+                if (ev) (void)hipEventDestroy(ev);
             delete s;
             return WLDA_E_HIP;
         }
@@ -264,6 +290,10 @@ wlda_status wlda_server_step(wlda_server s, uint32_t *n_active, uint32_t *n_pend
     };
     // ---- admission (arrival order; stop at the first request that does not fit)
     std::vector<uint32_t> fresh, fresh_enc;
+    struct Ahead {
+        uint32_t slot, stage, row;
+    };
+    std::vector<Ahead> ahead;               // admitted with a proposal encoded ahead
     std::vector<Pending> admitted;          // host copies stay alive until the sync below
     std::vector<uint32_t> f_rows(1, 0), f_idx;
     std::vector<float> f_val;
@@ -298,7 +328,9 @@ wlda_status wlda_server_step(wlda_server s, uint32_t *n_active, uint32_t *n_pend
         s->h_useq[si] = sl.learned ? 1u : 0u;
         s->h_hoff[si] = (uint32_t)hoff;
         s->h_hlen[si] = sl.n_ho;
-        if (q.weights.empty() && s->enc) {
+        if (q.weights.empty() && s->enc && q.stage >= 0) {
+            ahead.push_back({si, (uint32_t)q.stage, q.stage_row});
+        } else if (q.weights.empty() && s->enc) {
             // encoder input of this document (hashed bag of words)
             const size_t base = f_idx.size();
             f_idx.resize(base + sl.len);
@@ -314,6 +346,17 @@ wlda_status wlda_server_step(wlda_server s, uint32_t *n_active, uint32_t *n_pend
         fresh.push_back(si);
         admitted.push_back(std::move(q));
         s->pending.pop_front();
+    }
+    // proposals encoded ahead: wait for their stage on the sweep stream, copy
+    bool waited[2] = {false, false};
+    for (const Ahead &ah : ahead) {
+        if (!e && !waited[ah.stage]) {
+            e = hipStreamWaitEvent(s->st, s->ah_done[ah.stage], 0);
+            waited[ah.stage] = true;
+        }
+        if (!e)
+            e = hipMemcpyAsync(s->d_qcdf + (size_t)ah.slot * K, s->d_ah_cdf[ah.stage] + (size_t)ah.row * K, 4ull * K,
+                               hipMemcpyDeviceToDevice, s->st);
     }
     for (size_t a = 0; a < admitted.size(); ++a) {
         const uint32_t si = fresh[a];
@@ -352,6 +395,57 @@ wlda_status wlda_server_step(wlda_server s, uint32_t *n_active, uint32_t *n_pend
             e = hipMemcpyAsync(s->d_qcdf + (size_t)fresh_enc[r] * K, s->d_cdf_stage + (size_t)r * K, 4ull * K,
                                hipMemcpyDeviceToDevice, s->enc_st);
         if (!e) e = hipEventRecord(s->enc_done, s->enc_st);
+    }
+    // ---- encode ahead: the head of the queue, into the next stage buffer
+    if (!e && s->enc) {
+        const int x = s->ah_next;
+        if (s->ah_live[x]) {        // its requests not admitted by now are encoded again later
+            e = hipEventSynchronize(s->ah_done[x]);
+            for (Pending &q : s->pending)
+                if (q.stage == x) q.stage = -1;
+            s->ah_live[x] = false;
+        }
+        const uint32_t bmax = std::min<uint32_t>(wlda_encoder_get_max_batch(s->enc), (uint32_t)s->slots.size());
+        std::vector<uint32_t> &rows = s->h_ah_rows[x], &idx = s->h_ah_idx[x];
+        std::vector<float> &val = s->h_ah_val[x];
+        rows.assign(1, 0);
+        idx.clear();
+        val.clear();
+        std::vector<Pending *> picked;
+        for (Pending &q : s->pending) {
+            if (picked.size() >= bmax) break;
+            if (!q.weights.empty() || q.stage >= 0) continue;
+            if (idx.size() + q.words.size() > s->sp.pool_tokens) break;
+            const size_t base = idx.size();
+            idx.resize(base + q.words.size());
+            val.resize(base + q.words.size());
+            uint32_t nnz = 0;
+            wlda_encoder_features(s->buckets, q.words.data(), (uint32_t)q.words.size(), idx.data() + base,
+                                  val.data() + base, &nnz);
+            idx.resize(base + nnz);
+            val.resize(base + nnz);
+            rows.push_back((uint32_t)idx.size());
+            picked.push_back(&q);
+        }
+        if (!e && !picked.empty()) {
+            const uint32_t B = (uint32_t)picked.size();
+            up(s->d_ah_frow[x], rows.data(), 4ull * (B + 1), s->enc_st);
+            up(s->d_ah_fidx[x], idx.data(), 4ull * idx.size(), s->enc_st);
+            up(s->d_ah_fval[x], val.data(), 4ull * val.size(), s->enc_st);
+            if (!e && (wlda_encoder_forward(s->enc, B, s->d_ah_frow[x], s->d_ah_fidx[x], s->d_ah_fval[x],
+                                            s->d_probs) != WLDA_OK ||
+                       wlda_encoder_proposal(s->enc, B, s->d_probs, s->sp.eps, s->d_ah_cdf[x]) != WLDA_OK))
+                e = hipErrorLaunchFailure;
+            if (!e) e = hipEventRecord(s->ah_done[x], s->enc_st);
+            if (!e) {
+                for (uint32_t r = 0; r < B; ++r) {
+                    picked[r]->stage = x;
+                    picked[r]->stage_row = r;
+                }
+                s->ah_live[x] = true;
+                s->ah_next = 1 - x;
+            }
+        }
     }
     if (e) return fail(s);
     // ---- one sweep for every admitted document
@@ -454,6 +548,8 @@ wlda_status wlda_server_destroy(wlda_server s) {
     if (!s) return WLDA_E_INVALID;
     if (!s->broken) (void)hipStreamSynchronize(s->st);
     if (s->enc_done) (void)hipEventDestroy(s->enc_done);
+    for (hipEvent_t ev : s->ah_done)
+        if (ev) (void)hipEventDestroy(ev);
     delete s;
     return WLDA_OK;
 }
