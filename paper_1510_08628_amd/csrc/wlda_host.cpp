@@ -38,6 +38,7 @@ struct PhasePlan {
     std::vector<uint32_t> chunk_seg, chunk_start, tab_cap;
     std::vector<uint64_t> tab_off;          // n+1 word offsets of the per-segment tables
     uint32_t chunk_cut[9] = {};
+    uint32_t chunk = 0;                     // tokens per long-path chunk
     // device copies (inside the workspace)
     uint32_t *d_long_ids = nullptr, *d_long_prefix = nullptr,
              *d_tables = nullptr, *d_chunk_seg = nullptr, *d_chunk_start = nullptr,
@@ -95,6 +96,7 @@ void build_plan(const std::vector<uint64_t> &len, uint32_t M, uint32_t K, PhaseP
     // would be the straggler.
     const size_t n = pl.long_ids.size();
     const uint64_t huge_tokens = 1u << 20;
+    const uint32_t chunk = long_chunk(K);
     std::vector<uint32_t> order, owner(n, 8);
     uint64_t load[8] = {};
     std::vector<std::vector<std::pair<uint32_t, uint32_t>>> chunks(8);
@@ -105,9 +107,9 @@ void build_plan(const std::vector<uint64_t> &len, uint32_t M, uint32_t K, PhaseP
             order.push_back(j);
             continue;
         }
-        for (uint64_t n0 = 0; n0 < L; n0 += Tuning::LONG_CHUNK, rr = (rr + 1) & 7) {
+        for (uint64_t n0 = 0; n0 < L; n0 += chunk, rr = (rr + 1) & 7) {
             chunks[rr].push_back({j, (uint32_t)n0});
-            load[rr] += std::min<uint64_t>(Tuning::LONG_CHUNK, L - n0);
+            load[rr] += std::min<uint64_t>(chunk, L - n0);
         }
     }
     std::stable_sort(order.begin(), order.end(), [&](uint32_t x, uint32_t y) {
@@ -131,13 +133,14 @@ void build_plan(const std::vector<uint64_t> &len, uint32_t M, uint32_t K, PhaseP
         for (uint32_t j = 0; j < n; ++j) {
             if (owner[j] != (uint32_t)x) continue;
             const uint64_t L = len[pl.long_ids[j]];
-            for (uint64_t n0 = 0; n0 < L; n0 += Tuning::LONG_CHUNK) {
+            for (uint64_t n0 = 0; n0 < L; n0 += chunk) {
                 pl.chunk_seg.push_back(j);
                 pl.chunk_start.push_back((uint32_t)n0);
             }
         }
     }
     pl.chunk_cut[8] = (uint32_t)pl.chunk_seg.size();
+    pl.chunk = chunk;
     // global count tables of the long segments: dense K counts when K is
     // small or the table would reach K slots, else open addressing with the
     // smallest power of two >= 2L slots (Section 5.4's hash tables)
@@ -408,6 +411,7 @@ LongList long_list(const PhasePlan &pl) {
     ll.tab_off = pl.d_tab_off;
     ll.tab_cap = pl.d_tab_cap;
     ll.table_words = pl.tab_off.back();
+    ll.chunk = pl.chunk;
     ll.tables_new = pl.d_tables + pl.tab_off.back();
     return ll;
 }

@@ -50,6 +50,7 @@ struct LongList {
     const uint32_t *chunk_seg = nullptr;    // per chunk: index j into ids
     const uint32_t *chunk_start = nullptr;  // per chunk: first token within the segment
     uint32_t n_chunks = 0;
+    uint32_t chunk = 0;                // tokens per chunk (long_chunk(K))
     const uint32_t *chunk_cut = nullptr;    // 9 chunk-list offsets, one share per XCD
     // Per-segment counts in global memory: segment j owns the words
     // tables[tab_off[j] ..); tab_cap[j] == 0 means dense (K counts), otherwise
@@ -94,10 +95,18 @@ struct Tuning {
     static constexpr int TPT_WIDE = 16;
     static constexpr uint32_t WIDE_MAX = 256 * TPT_WIDE;     // longest segment below the long path
     static constexpr uint32_t CK_LDS_MAX = 4096;             // block c_k histogram in LDS
-    static constexpr uint32_t LONG_CHUNK = 4096;             // tokens per long-path chunk
+    // tokens per long-path chunk: LONG_CHUNK when the chunk histogram is a
+    // dense LDS array (K <= LDS_DENSE_MAX), else LONG_CHUNK_HASHED so that the
+    // LDS hash table (2 * LONG_CHUNK_HASHED slots) always has free slots
+    static constexpr uint32_t LONG_CHUNK = 8192;
+    static constexpr uint32_t LONG_CHUNK_HASHED = 4096;
     static constexpr uint32_t LDS_DENSE_MAX = 16384;         // dense LDS counts up to this K
     static constexpr uint32_t CDF_LDS_MAX = 8192;            // long-word prefix counts in LDS
 };
+
+inline uint32_t long_chunk(uint32_t K) {
+    return K <= Tuning::LDS_DENSE_MAX ? Tuning::LONG_CHUNK : Tuning::LONG_CHUNK_HASHED;
+}
 
 // Segment bins below the long path, by length: the wave kernel, the narrow
 // and the wide block kernel.

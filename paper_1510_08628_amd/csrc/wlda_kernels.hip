@@ -535,14 +535,15 @@ template <int PHASE, int NW>
 __global__ __launch_bounds__(256) void long_hist_kernel(PhaseArgs a, LongList l, uint32_t lds_dense) {
     extern __shared__ uint32_t hist[];
     const uint32_t K = a.K;
-    // LDS: dense K counts, or an open-addressed table of 2 * LONG_CHUNK slots
-    constexpr uint32_t HCAP = 2 * Tuning::LONG_CHUNK;
+    // LDS: dense K counts, or an open-addressed table of 2 * LONG_CHUNK_HASHED
+    // slots (chunks are LONG_CHUNK_HASHED tokens whenever the table is hashed)
+    constexpr uint32_t HCAP = 2 * Tuning::LONG_CHUNK_HASHED;
     uint32_t *hkey = hist, *hcnt = hist + HCAP;
     WLDA_FOR_CHUNKS(l) {
         const uint32_t j = l.chunk_seg[ci], n0 = l.chunk_start[ci];
         const uint32_t s_id = l.ids[j];
         const uint32_t beg = a.segptr[s_id], L = a.segptr[s_id + 1] - beg;
-        const uint32_t n1 = min(L, n0 + Tuning::LONG_CHUNK);
+        const uint32_t n1 = min(L, n0 + l.chunk);
         if (lds_dense) {
             for (uint32_t k = threadIdx.x; k < K; k += 256) hist[k] = 0;
         } else {
@@ -594,7 +595,7 @@ __global__ __launch_bounds__(256) void long_mh_kernel(PhaseArgs a, LongList l, u
         const uint32_t j = l.chunk_seg[ci], n0 = l.chunk_start[ci];
         const uint32_t s_id = l.ids[j];
         const uint32_t beg = a.segptr[s_id], L = a.segptr[s_id + 1] - beg;
-        const uint32_t n1 = min(L, n0 + Tuning::LONG_CHUNK);
+        const uint32_t n1 = min(L, n0 + l.chunk);
         const uint32_t zbase = l.prefix[j];
         const uint32_t *gt = l.tables + l.tab_off[j];
         const uint32_t gcap = l.tab_cap[j];
@@ -741,7 +742,7 @@ __global__ __launch_bounds__(256) void long_draw_kernel(PhaseArgs a, LongList l,
         const uint32_t j = l.chunk_seg[ci], n0 = l.chunk_start[ci];
         const uint32_t s_id = l.ids[j];
         const uint32_t beg = a.segptr[s_id], L = a.segptr[s_id + 1] - beg;
-        const uint32_t n1 = min(L, n0 + Tuning::LONG_CHUNK);
+        const uint32_t n1 = min(L, n0 + l.chunk);
         const ZT *zs = zc + l.prefix[j];
         const bool by_cdf = PHASE == PH_WORD && L > K;
         const uint32_t *cum = l.tables_new + l.tab_off[j];
@@ -1110,7 +1111,7 @@ static hipError_t long_dispatch_z(const PhaseArgs &a, const LongList &l, hipStre
     hipError_t e;
     if (ev && (e = hipEventRecord(ev[0], st)) != hipSuccess) return e;
     if (!a.draw_only) {
-        const size_t lds = lds_tab ? 4ull * a.K : 4ull * 2 * 2 * Tuning::LONG_CHUNK;
+        const size_t lds = lds_tab ? 4ull * a.K : 4ull * 2 * 2 * Tuning::LONG_CHUNK_HASHED;
         e = launch_dyn(long_hist_kernel<PHASE, NW>, dim3(1), lds, st);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL((long_hist_kernel<PHASE, NW>), dim3(blocks), dim3(256), lds, st, a, l,
@@ -1198,7 +1199,7 @@ static hipError_t ll_long_dispatch(const PhaseArgs &a, const LongList &l, double
     const bool lds_dense = a.K <= Tuning::LDS_DENSE_MAX;
     uint32_t blocks = l.n_chunks < 2048 ? l.n_chunks : 2048;
     blocks = (blocks + 7) / 8 * 8;
-    const size_t lds = lds_dense ? 4ull * a.K : 4ull * 2 * 2 * Tuning::LONG_CHUNK;
+    const size_t lds = lds_dense ? 4ull * a.K : 4ull * 2 * 2 * Tuning::LONG_CHUNK_HASHED;
     hipError_t e = launch_dyn(long_hist_kernel<PHASE, NW>, dim3(1), lds, st);
     if (e) return e;
     hipLaunchKernelGGL((long_hist_kernel<PHASE, NW>), dim3(blocks), dim3(256), lds, st, a, l,
