@@ -469,10 +469,12 @@ __global__ __launch_bounds__(256) void seg_kernel(PhaseArgs a, SegList l, uint32
 // chunks of all long segments:
 //   hist - c_w (or c_d) of each long segment from the phase-start Z, summed
 //          into a global table per segment;
-//   mh   - the table staged in LDS, M MH steps per token, z written back into
-//          the record and into a compact per-segment z array;
-//   draw - proposals by random positioning over the compact array (the
-//          segment's updated assignments), records written, c_k accumulated.
+//   mh   - the table staged in LDS, M MH steps per token, the new z written
+//          to a compact per-segment array only (records are left as they are);
+//   draw - each token's z read back from the compact array in chunk order,
+//          proposals by random positioning over that array (the segment's
+//          updated assignments) or the inverse CDF of its counts, and the
+//          whole record written, c_k accumulated.
 // Each XCD owns whole segments, so a segment's compact array is read from
 // that XCD's L2.
 // --------------------------------------------------------------------------
@@ -650,10 +652,8 @@ __global__ __launch_bounds__(256) void long_mh_kernel(PhaseArgs a, LongList l, u
                         ++acc;
                     }
                 }
-                set_fld(rec[u], 0, s);
-                st_rec<NW>(a.recs, pos[u], rec[u]);
                 zk[bt * LONG_BATCH + u] = s;
-                if (!by_cdf) zc[zbase + n] = (ZT)s;
+                zc[zbase + n] = (ZT)s;
             }
         }
         if (by_cdf) {
@@ -754,8 +754,14 @@ __global__ __launch_bounds__(256) void long_draw_kernel(PhaseArgs a, LongList l,
             uint32_t pos[LONG_BATCH];
             Rec<NW> rec[LONG_BATCH];
             load_positions<LONG_BATCH>(a.idx, beg, nb, n1, pos);
+            // the record is rebuilt from the updated z alone (compact array,
+            // read in chunk order): nothing of the old record survives
 #pragma unroll
-            for (int u = 0; u < LONG_BATCH; ++u) rec[u] = ld_rec<NW>(a.recs, pos[u]);
+            for (int u = 0; u < LONG_BATCH; ++u) {
+#pragma unroll
+                for (int w = 0; w < (NW > 0 ? NW : 1); ++w) rec[u].w[w] = 0;
+                set_fld(rec[u], 0, (uint32_t)zs[min(nb + u * 256, n1 - 1)]);
+            }
             // all random-positioning reads (or CDF lookups) of the batch are
             // issued before any record is written back
             uint32_t jj[LONG_BATCH * M] = {};
