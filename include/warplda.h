@@ -92,7 +92,10 @@ wlda_status wlda_init(wlda_sampler s);
  * document proposals with the acceptance rate pi_doc of Eq. (7) (counts held
  * fixed for the whole phase), and then draws M word proposals from the
  * updated column (random positioning, Section 4.3, mixing weight
- * L_w / (L_w + K beta)).  Requires init; must alternate with doc_phase. */
+ * L_w / (L_w + K beta)); columns longer than both K and 4096 tokens, the
+ * intra-word-parallel words of Section 5.4, take the count part from the
+ * inverse CDF of the updated c_w instead (the same law).  Requires init;
+ * must alternate with doc_phase. */
 wlda_status wlda_word_phase(wlda_sampler s);
 
 /* Document phase = VisitByRow: c_d rebuilt per document, M MH steps over the

@@ -71,6 +71,7 @@ def lib():
         L.oracle_accepted.argtypes = [vp, C.c_int]
         L.oracle_accepted.restype = u64
         L.oracle_set_visit_reversed.argtypes = [vp, C.c_int]
+        L.oracle_set_cdf_min_len.argtypes = [vp, u64]
         L.oracle_copy_assignments.argtypes = [vp, vp, vp]
         L.oracle_copy_csc.argtypes = [vp, vp, vp]
         L.oracle_copy_layout.argtypes = [vp, vp, vp, vp, vp]
@@ -204,6 +205,11 @@ class Oracle:
 
     def accepted(self, phase: int) -> int:
         return lib().oracle_accepted(self.h, phase)
+
+    def set_cdf_min_len(self, n: int):
+        """Test hook: inverse-CDF word proposals for every column longer than
+        both K and n tokens (the sampler's own threshold is 4096)."""
+        lib().oracle_set_cdf_min_len(self.h, int(n))
 
     def set_visit_reversed(self, rev: bool):
         lib().oracle_set_visit_reversed(self.h, int(rev))

@@ -32,11 +32,11 @@
  *   - counts include the token's own assignment (Eq. 5 has no "not dn");
  *   - proposals are drawn from the counts *after* this phase's updates;
  *   - both proposals use random positioning (Section 4.3) over the canonical
- *     row/column order, except that words with L_w > K (Section 5.4's
- *     intra-word-parallel words, whose proposal the paper draws from a table
- *     over c_w) take the inverse CDF of the updated c_w; the word-proposal
- *     mixing weight is L_w / (L_w + K beta) (the prior mass of C_wk + beta
- *     over K topics);
+ *     row/column order, except that words with L_w > K and L_w > 4096
+ *     (Section 5.4's intra-word-parallel words, whose proposal the paper
+ *     draws from a table over c_w) take the inverse CDF of the updated c_w;
+ *     the word-proposal mixing weight is L_w / (L_w + K beta) (the prior
+ *     mass of C_wk + beta over K topics);
  *   - all acceptance and coin arithmetic is IEEE binary32 with the exact
  *     expressions below, no fused multiply-add, strict "<";
  *   - randomness is Philox4x32-10 (Salmon et al., SC'11) with the counter
@@ -160,6 +160,10 @@ static int32_t cdf_topic(const int64_t *cum, uint32_t K, uint32_t j)
 /* ------------------------------------------------------------------------ */
 /* Sampler state                                                            */
 /* ------------------------------------------------------------------------ */
+/* Word proposals take the inverse CDF of c_w only in columns longer than
+ * both K and this many tokens (reading of the word-proposal table, below). */
+#define CDF_MIN_LEN 4096u
+
 typedef struct {
     uint32_t V, D, K, M;
     double alpha, beta;
@@ -180,6 +184,7 @@ typedef struct {
     int next_phase;     /* 0 = not initialised, PH_WORD or PH_DOC */
     uint64_t accepted_word, accepted_doc;   /* last phase of each kind */
     int visit_reversed; /* visit rows/columns in reverse order (tests) */
+    uint64_t cdf_min_len; /* inverse-CDF word proposals need L_w above this */
     /* binary32 constants */
     float a, b, alpha_bar, beta_k, beta_bar;
 } oracle_t;
@@ -261,6 +266,7 @@ oracle_t *oracle_create(const oracle_params *p, const uint32_t *word_ids,
     o->V = p->V; o->D = p->D; o->K = p->K; o->M = p->M;
     o->alpha = p->alpha; o->beta = p->beta; o->seed = p->seed;
     o->T = n_tokens;
+    o->cdf_min_len = CDF_MIN_LEN;
     set_constants(o);
     size_t T = (size_t)n_tokens;
     o->colptr = malloc((o->V + 1) * sizeof(uint64_t));
@@ -355,14 +361,14 @@ static void word_column(oracle_t *o, uint32_t w, uint32_t iter, int64_t *ck_next
     }
     for (uint64_t n = 0; n < L; ++n) cw[o->z[beg + n]] = 0;
     for (uint64_t n = 0; n < L; ++n) o->z[beg + n] = znew[beg + n];
-    /* Words with L_w > K are the intra-word-parallel words of Section 5.4,
-     * whose word proposal the paper draws from a table built over the
-     * column's counts c_w rather than from a token position.  For them the
-     * count part is the inverse CDF of the updated c_w: j = Dice(r, L_w),
-     * and the proposal is the smallest topic k whose inclusive prefix count
-     * C(k) exceeds j.  Each token's topic occupies one unit of [0, L_w), so
-     * the law is that of random positioning. */
-    int by_cdf = L > o->K;
+    /* Long words (L_w > K and L_w > CDF_MIN_LEN) are the intra-word-parallel
+     * words of Section 5.4, whose word proposal the paper draws from a table
+     * built over the column's counts c_w rather than from a token position.
+     * For them the count part is the inverse CDF of the updated c_w:
+     * j = Dice(r, L_w), and the proposal is the smallest topic k whose
+     * inclusive prefix count C(k) exceeds j.  Each token's topic occupies one
+     * unit of [0, L_w), so the law is that of random positioning. */
+    int by_cdf = L > o->K && L > o->cdf_min_len;
     if (by_cdf) {
         for (uint64_t n = 0; n < L; ++n) cw[o->z[beg + n]]++;
         for (uint32_t k = 1; k < o->K; ++k) cw[k] += cw[k - 1];
@@ -589,6 +595,9 @@ uint64_t oracle_accepted(const oracle_t *o, int phase)
     return phase == PH_WORD ? o->accepted_word : o->accepted_doc;
 }
 void oracle_set_visit_reversed(oracle_t *o, int rev) { o->visit_reversed = rev; }
+/* Test hook: lowers the inverse-CDF length threshold (0 = every L_w > K) so
+ * that tiny enumerable corpora reach that proposal rule. */
+void oracle_set_cdf_min_len(oracle_t *o, uint64_t n) { o->cdf_min_len = n; }
 
 /* z (and the M proposals, proposal-major) in input order. */
 void oracle_copy_assignments(const oracle_t *o, int32_t *z_input,

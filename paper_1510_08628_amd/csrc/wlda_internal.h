@@ -104,6 +104,15 @@ struct Tuning {
     static constexpr uint32_t CDF_LDS_MAX = 8192;            // long-word prefix counts in LDS
 };
 
+// Word proposals (count part): columns longer than both K and CDF_MIN_LEN
+// tokens take the inverse CDF of their updated counts, all others a token of
+// the updated column (random positioning); both sample the same law.  Part of
+// the sampler's definition, not a tuning knob: the segment kernels hold
+// columns of at most WIDE_MAX tokens and use random positioning only.
+constexpr uint32_t CDF_MIN_LEN = 4096;
+static_assert(Tuning::WIDE_MAX <= CDF_MIN_LEN, "segment kernels have no inverse-CDF draw");
+__host__ __device__ inline bool word_cdf(uint32_t L, uint32_t K) { return L > K && L > CDF_MIN_LEN; }
+
 inline uint32_t long_chunk(uint32_t K) {
     return K <= Tuning::LDS_DENSE_MAX ? Tuning::LONG_CHUNK : Tuning::LONG_CHUNK_HASHED;
 }

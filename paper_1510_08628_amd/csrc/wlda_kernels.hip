@@ -171,53 +171,10 @@ __device__ __forceinline__ void group_sync() {
     }
 }
 
-// Inclusive prefix sums of a[0..K) in place by the GROUP threads of a group
-// (each thread a contiguous run of entries); ends with a group barrier.
-template <int GROUP>
-__device__ void group_inclusive_scan(uint32_t *a, uint32_t K, uint32_t lane) {
-    const uint32_t per = (K + GROUP - 1) / GROUP;
-    const uint32_t k0 = min(K, lane * per), k1 = min(K, k0 + per);
-    uint32_t sum = 0;
-    for (uint32_t k = k0; k < k1; ++k) sum += a[k];
-    uint32_t x = sum;
-    const uint32_t wl = lane & 63;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const uint32_t y = __shfl_up(x, off, 64);
-        if (wl >= (uint32_t)off) x += y;
-    }
-    if constexpr (GROUP > 64) {
-        __shared__ uint32_t wsum[GROUP / 64];
-        if (wl == 63) wsum[lane >> 6] = x;
-        __syncthreads();
-        for (uint32_t w = 0; w < (lane >> 6); ++w) x += wsum[w];
-        __syncthreads();
-    }
-    uint32_t run = x - sum;
-    for (uint32_t k = k0; k < k1; ++k) {
-        run += a[k];
-        a[k] = run;
-    }
-    group_sync<GROUP>();
-}
-
-// Inverse CDF: the smallest topic k with cum[k] > j (cum inclusive prefix
-// counts over topics 0..K-1, j < cum[K-1]).
-__device__ __forceinline__ uint32_t cdf_find(const uint32_t *cum, uint32_t K, uint32_t j) {
-    uint32_t lo = 0, hi = K - 1;
-    while (lo < hi) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if (cum[mid] > j)
-            hi = mid;
-        else
-            lo = mid + 1;
-    }
-    return lo;
-}
-
-// N independent inverse-CDF lookups at once, j[d] replaced by its topic: a
-// branch-free binary search whose trip count depends on K only, so the N
-// loads of each step are in flight together.
+// Inverse CDF, N lookups at once: each j[d] (< cum[K-1]) is replaced by the
+// smallest topic k with cum[k] > j[d], cum holding inclusive prefix counts
+// over topics 0..K-1.  A branch-free binary search whose trip count depends
+// on K only, so the N loads of each step are in flight together.
 template <int N>
 __device__ __forceinline__ void cdf_find_n(const uint32_t *cum, uint32_t K, uint32_t (&j)[N]) {
     uint32_t base[N];
@@ -233,6 +190,28 @@ __device__ __forceinline__ void cdf_find_n(const uint32_t *cum, uint32_t K, uint
     for (int d = 0; d < N; ++d) j[d] = base[d] + (cum[base[d]] <= j[d] ? 1u : 0u);
 }
 
+// The same search over prefix counts in LDS, stepping 32-bit LDS pointers:
+// one add, one LDS load, one compare and one select per lookup and step.
+typedef __attribute__((address_space(3))) const uint32_t lds_cu32;
+template <int N>
+__device__ __forceinline__ void cdf_find_lds(const uint32_t *cum_generic, uint32_t K, uint32_t (&j)[N]) {
+    lds_cu32 *cum = (lds_cu32 *)cum_generic;
+    lds_cu32 *b[N];
+#pragma unroll
+    for (int d = 0; d < N; ++d) b[d] = cum;
+    for (uint32_t n = K; n > 1;) {
+        const uint32_t half = n >> 1;
+#pragma unroll
+        for (int d = 0; d < N; ++d) {
+            lds_cu32 *p = b[d] + half;
+            b[d] = *p <= j[d] ? p : b[d];
+        }
+        n -= half;
+    }
+#pragma unroll
+    for (int d = 0; d < N; ++d) j[d] = (uint32_t)(b[d] - cum) + (*b[d] <= j[d] ? 1u : 0u);
+}
+
 __device__ __forceinline__ void add_accepted(unsigned long long *dst, unsigned long long v) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
@@ -245,7 +224,7 @@ __device__ __forceinline__ void add_accepted(unsigned long long *dst, unsigned l
 // list are taken in ascending order so that the rows visited at the same time
 // are neighbours (their tokens share cache lines of each column, Section 5.2).
 // --------------------------------------------------------------------------
-template <int PHASE, int M, int NW, int GROUP, int TPT, bool CDF>
+template <int PHASE, int M, int NW, int GROUP, int TPT>
 __global__ __launch_bounds__(256) void seg_kernel(PhaseArgs a, SegList l, uint32_t cap_max,
                                                   uint32_t dense_u, uint32_t ck_lds_u) {
     extern __shared__ uint32_t lds[];
@@ -303,9 +282,6 @@ __global__ __launch_bounds__(256) void seg_kernel(PhaseArgs a, SegList l, uint32
     Rec<NW> rec[TPT];
     if (li < hi) fetch(li, beg, L, pos, rec);
     for (; li < hi; li += ngx) {
-        // word proposals of a column with L > K: inverse CDF of its updated
-        // counts (the table is dense whenever L > K: K < L <= GROUP * TPT)
-        const bool by_cdf = CDF && PHASE == PH_WORD && !a.draw_only && dense && L > K;
         uint32_t znew[TPT];
         if (!a.draw_only) {
             uint32_t mask = 0;
@@ -349,23 +325,13 @@ __global__ __launch_bounds__(256) void seg_kernel(PhaseArgs a, SegList l, uint32
                 for (int r = 0; r < TPT; ++r)
                     if (r * GROUP + lane < L) tcnt[fld(rec[r], 0)] = 0;
             }
-            if (by_cdf) {       // counts of the updated column, then prefix sums
-                group_sync<GROUP>();
-#pragma unroll
-                for (int r = 0; r < TPT; ++r)
-                    if (r * GROUP + lane < L) atomicAdd(&tcnt[znew[r]], 1u);
-                group_sync<GROUP>();
-                group_inclusive_scan<GROUP>(tcnt, K, lane);
-            }
         } else {
 #pragma unroll
             for (int r = 0; r < TPT; ++r) znew[r] = fld(rec[r], 0);
         }
-        if (!by_cdf) {
 #pragma unroll
-            for (int r = 0; r < TPT; ++r)
-                if (r * GROUP + lane < L) zarr[r * GROUP + lane] = znew[r];
-        }
+        for (int r = 0; r < TPT; ++r)
+            if (r * GROUP + lane < L) zarr[r * GROUP + lane] = znew[r];
         group_sync<GROUP>();
         // Word phase: the next segment's loads go out before this one's stores
         // (loads and stores share one in-order counter, so loads issued after
@@ -377,13 +343,11 @@ __global__ __launch_bounds__(256) void seg_kernel(PhaseArgs a, SegList l, uint32
         Rec<NW> nrec[TPT];
         if (PREFETCH && li + ngx < hi) fetch(li + ngx, nbeg, nL, npos, nrec);
         // Draws, DB tokens at a time: the count part is a token of the updated
-        // segment (random positioning) or, for columns with L > K, the
-        // inverse CDF of their counts, resolved for the whole batch at once.
+        // segment (random positioning over its new z in LDS).
         constexpr int DB = TPT < 4 ? TPT : 4;
 #pragma unroll
         for (int r0 = 0; r0 < TPT; r0 += DB) {
             uint32_t pw[DB * M];
-            uint32_t pend = 0;          // bit q*M + i - 1: pw holds an index for the CDF
 #pragma unroll
             for (int q = 0; q < DB; ++q) {
                 const uint32_t n = (r0 + q) * GROUP + lane;
@@ -398,26 +362,12 @@ __global__ __launch_bounds__(256) void seg_kernel(PhaseArgs a, SegList l, uint32
                             const int i = 2 * j - 1 + h;
                             if (i > M) continue;
                             const uint32_t w = word4(RB, 2 * h + 1);
-                            if (!take_count_part(unif24(word4(RB, 2 * h)), L, mass)) {
-                                pw[q * M + i - 1] = dice(w, K);
-                            } else if (by_cdf) {
-                                pw[q * M + i - 1] = dice(w, L);
-                                pend |= 1u << (q * M + i - 1);
-                            } else {
-                                pw[q * M + i - 1] = zarr[dice(w, L)];
-                            }
+                            pw[q * M + i - 1] = take_count_part(unif24(word4(RB, 2 * h)), L, mass)
+                                                    ? zarr[dice(w, L)]
+                                                    : dice(w, K);
                         }
                     }
                 }
-            }
-            if (by_cdf) {
-                uint32_t jj[DB * M];
-#pragma unroll
-                for (int d = 0; d < DB * M; ++d) jj[d] = (pend >> d) & 1u ? pw[d] : 0u;
-                cdf_find_n<DB * M>(tcnt, K, jj);
-#pragma unroll
-                for (int d = 0; d < DB * M; ++d)
-                    if ((pend >> d) & 1u) pw[d] = jj[d];
             }
 #pragma unroll
             for (int q = 0; q < DB; ++q) {
@@ -438,10 +388,6 @@ __global__ __launch_bounds__(256) void seg_kernel(PhaseArgs a, SegList l, uint32
             }
         }
         group_sync<GROUP>();
-        if (by_cdf) {           // prefix sums fill the table: clear all of it
-            for (uint32_t k = lane; k < K; k += GROUP) tcnt[k] = 0;
-            group_sync<GROUP>();
-        }
         if constexpr (PREFETCH) {
             beg = nbeg;
             L = nL;
@@ -612,9 +558,9 @@ __global__ __launch_bounds__(256) void long_mh_kernel(PhaseArgs a, LongList l, u
             for (uint32_t k = threadIdx.x; k < K; k += 256) tab[k] = gt[k];
             __syncthreads();
         }
-        // L > K: the word proposals take the inverse CDF of the updated
-        // counts, gathered here instead of the compact z array
-        const bool by_cdf = PHASE == PH_WORD && L > K;
+        // columns past the inverse-CDF threshold also gather the counts of
+        // their updated z for the word proposals' inverse CDF
+        const bool by_cdf = PHASE == PH_WORD && word_cdf(L, K);
         constexpr int PER_THREAD = Tuning::LONG_CHUNK / 256;
         uint32_t zk[PER_THREAD];
 #pragma unroll
@@ -688,7 +634,7 @@ __global__ __launch_bounds__(256) void long_cdf_kernel(LongList l, const uint32_
     constexpr int PER = 16;
     for (uint32_t j = blockIdx.x; j < l.n; j += gridDim.x) {
         const uint32_t s = l.ids[j];
-        if (segptr[s + 1] - segptr[s] <= K) continue;
+        if (!word_cdf(segptr[s + 1] - segptr[s], K)) continue;
         uint32_t *cnt = l.tables_new + l.tab_off[j];
         uint32_t carry = 0;
         for (uint32_t t0 = 0; t0 < K; t0 += 256 * PER) {
@@ -744,7 +690,7 @@ __global__ __launch_bounds__(256) void long_draw_kernel(PhaseArgs a, LongList l,
         const uint32_t beg = a.segptr[s_id], L = a.segptr[s_id + 1] - beg;
         const uint32_t n1 = min(L, n0 + l.chunk);
         const ZT *zs = zc + l.prefix[j];
-        const bool by_cdf = PHASE == PH_WORD && L > K;
+        const bool by_cdf = PHASE == PH_WORD && word_cdf(L, K);
         const uint32_t *cum = l.tables_new + l.tab_off[j];
         if (by_cdf && cdf_lds) {
             for (uint32_t k = threadIdx.x; k < K; k += 256) cdfl[k] = cum[k];
@@ -790,7 +736,7 @@ __global__ __launch_bounds__(256) void long_draw_kernel(PhaseArgs a, LongList l,
             }
             if (by_cdf) {
                 if (cdf_lds)
-                    cdf_find_n<LONG_BATCH * M>(cdfl, K, jj);
+                    cdf_find_lds<LONG_BATCH * M>(cdfl, K, jj);
                 else
                     cdf_find_n<LONG_BATCH * M>(cum, K, jj);
 #pragma unroll
@@ -1014,15 +960,16 @@ static hipError_t launch_dyn(Kern k, dim3 grid, size_t lds, hipStream_t st) {
     return hipSuccess;
 }
 
-template <int PHASE, int M, int NW, int GROUP, int TPT, bool CDF>
-static hipError_t run_seg_k(const PhaseArgs &a, const SegList &l, uint32_t cap_bound, hipStream_t st) {
+template <int PHASE, int M, int NW, int GROUP, int TPT>
+static hipError_t run_seg(const PhaseArgs &a, const SegList &l, uint32_t cap_bound, hipStream_t st) {
+    if (l.n == 0) return hipSuccess;
     const bool dense = a.K <= cap_bound;
     const bool ck_lds = a.K <= Tuning::CK_LDS_MAX;
     const uint32_t cap_max = dense ? 0 : cap_bound;
     const uint32_t tab_words = dense ? a.K : 2 * cap_max;
     constexpr int GPB = 256 / GROUP;
     const size_t lds = 4ull * ((ck_lds ? 2 * a.K : 0) + GPB * (tab_words + GROUP * TPT));
-    auto kern = seg_kernel<PHASE, M, NW, GROUP, TPT, CDF>;
+    auto kern = seg_kernel<PHASE, M, NW, GROUP, TPT>;
     hipError_t e = launch_dyn(kern, dim3(1), lds, st);
     if (e != hipSuccess) return e;
     // Blocks are assigned to XCDs round robin; use a multiple of 8 and
@@ -1034,19 +981,6 @@ static hipError_t run_seg_k(const PhaseArgs &a, const SegList &l, uint32_t cap_b
     hipLaunchKernelGGL(kern, dim3(blocks), dim3(256), lds, st, a, l, cap_max, (uint32_t)dense,
                        (uint32_t)ck_lds);
     return hipGetLastError();
-}
-
-// The inverse-CDF word proposals (columns with L > K) are compiled in only
-// where the bin can hold such a column, so the other variants keep their
-// register budget.
-template <int PHASE, int M, int NW, int GROUP, int TPT>
-static hipError_t run_seg(const PhaseArgs &a, const SegList &l, uint32_t cap_bound, hipStream_t st) {
-    if (l.n == 0) return hipSuccess;
-    if constexpr (PHASE == PH_WORD) {
-        if (!a.draw_only && a.K < (uint32_t)(GROUP * TPT))
-            return run_seg_k<PHASE, M, NW, GROUP, TPT, true>(a, l, cap_bound, st);
-    }
-    return run_seg_k<PHASE, M, NW, GROUP, TPT, false>(a, l, cap_bound, st);
 }
 
 // Calls f(std::integral_constant<int, RF>) with the record format of M topics

@@ -187,8 +187,14 @@ def _chi2_ok(counts, probs, n, min_expected=5.0):
     dict(words=[0, 1, 0], docs=[0, 0, 1], V=2, K=3, M=2, alpha=0.7, beta=0.4, n_iter=2),
     dict(words=[0, 0, 1, 1], docs=[0, 1, 0, 1], V=2, K=2, M=1, alpha=0.3, beta=0.9, n_iter=3),
     dict(words=[0, 1, 2, 1], docs=[0, 0, 0, 1], V=3, K=3, M=1, alpha=0.5, beta=0.2, n_iter=2),
-    # L_w > K: word 0's proposals come from the inverse CDF of its counts
-    dict(words=[0, 0, 0, 1], docs=[0, 1, 0, 1], V=2, K=2, M=1, alpha=0.6, beta=0.3, n_iter=2),
+    # L_w > K with the length threshold lowered to 0: word 0's proposals come
+    # from the inverse CDF of its counts (long columns of the real threshold
+    # are far beyond enumeration)
+    dict(words=[0, 0, 0, 1], docs=[0, 1, 0, 1], V=2, K=2, M=1, alpha=0.6, beta=0.3, n_iter=2,
+         cdf_min_len=0),
+    dict(words=[0, 0, 0, 1, 0], docs=[0, 1, 0, 1, 1], V=2, K=2, M=2, alpha=0.4, beta=0.7, n_iter=2,
+         cdf_min_len=0),
+    # the same corpus under the real threshold: random positioning
     dict(words=[0, 0, 0, 1, 0], docs=[0, 1, 0, 1, 1], V=2, K=2, M=2, alpha=0.4, beta=0.7, n_iter=2),
 ])
 def test_chain_law_matches_enumeration(case):
@@ -205,6 +211,8 @@ def test_chain_law_matches_enumeration(case):
     counts = np.zeros(len(states))
     for seed in range(n):
         o = oracle.Oracle(w, d, V, D, K, M, case["alpha"], case["beta"], seed=1000 + seed)
+        if "cdf_min_len" in case:
+            o.set_cdf_min_len(case["cdf_min_len"])
         o.init()
         o.iterate(case["n_iter"])
         z, _ = o.assignments()
