@@ -33,7 +33,10 @@
 //     num = (cnt[c] + prior) * (ck[s] + beta_bar),
 //     den = (cnt[s] + prior) * (ck[c] + beta_bar)            (Eq. 7)
 //   count part iff U * (L + mass) < L, then the topic of a uniformly chosen
-//   token of the (updated) segment, else a uniform topic       (Eq. 6, Sec. 4.3)
+//   token of the (updated) segment, else a uniform topic       (Eq. 6, Sec. 4.3);
+//   word-phase columns longer than both K and CDF_MIN_LEN take the count
+//   part as the inverse CDF of their updated counts at Dice(r, L) instead
+//   (same law; the long path's tables of Section 5.4)
 //   U(r) = (r >> 8) * 2^-24,  Dice(r, n) = (r * n) >> 32.
 // Random words per (token, iteration, phase): Philox call 0 gives the M
 // acceptance uniforms; call j >= 1 the (coin, index) words of proposals 2j-1
