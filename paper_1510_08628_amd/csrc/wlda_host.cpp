@@ -30,6 +30,7 @@ struct BinList {
     std::vector<uint32_t> ids;
     uint32_t cut[9] = {};
     uint32_t *d_ids = nullptr, *d_cut = nullptr;   // device copies
+    uint2 *d_span = nullptr;                       // [segptr[id], segptr[id + 1]) per listed id
 };
 
 struct PhasePlan {
@@ -219,7 +220,7 @@ struct Sizes {
 
 uint64_t plan_bytes(const PhasePlan &pl, uint32_t K) {
     uint64_t b = 0;
-    for (const BinList &bl : pl.bins) b += align_up(4ull * bl.ids.size() + 4) + align_up(9 * 4);
+    for (const BinList &bl : pl.bins) b += align_up(4ull * bl.ids.size() + 4) + align_up(9 * 4) + align_up(8ull * bl.ids.size() + 8);
     return b + align_up(4ull * pl.long_ids.size() + 4) + align_up(4ull * pl.long_prefix.size()) +
            align_up(8ull * pl.tab_off.back() + 4) + align_up(8ull * pl.tab_off.size()) +
            align_up(4ull * pl.tab_cap.size() + 4) + 2 * align_up(4ull * pl.chunk_seg.size() + 4) +
@@ -340,10 +341,11 @@ hipError_t upload(void *dst, const void *src, uint64_t bytes, hipStream_t st) {
     return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st);
 }
 
-hipError_t place_plan(PhasePlan &pl, uint8_t *&cur, uint32_t K, hipStream_t st) {
+hipError_t place_plan(PhasePlan &pl, const std::vector<uint32_t> &segptr, uint8_t *&cur, uint32_t K, hipStream_t st) {
     for (BinList &b : pl.bins) {
         b.d_ids = (uint32_t *)carve(cur, 4ull * b.ids.size() + 4);
         b.d_cut = (uint32_t *)carve(cur, 9 * 4);
+        b.d_span = (uint2 *)carve(cur, 8ull * b.ids.size() + 8);
     }
     pl.d_long_ids = (uint32_t *)carve(cur, 4ull * pl.long_ids.size() + 4);
     pl.d_long_prefix = (uint32_t *)carve(cur, 4ull * pl.long_prefix.size());
@@ -363,6 +365,11 @@ hipError_t place_plan(PhasePlan &pl, uint8_t *&cur, uint32_t K, hipStream_t st) 
     for (BinList &b : pl.bins) {
         if ((e = upload(b.d_ids, b.ids.data(), 4ull * b.ids.size(), st))) return e;
         if ((e = upload(b.d_cut, b.cut, 9 * 4, st))) return e;
+        std::vector<uint2> span(b.ids.size());
+        for (size_t i = 0; i < b.ids.size(); ++i) span[i] = make_uint2(segptr[b.ids[i]], segptr[b.ids[i] + 1]);
+        if ((e = upload(b.d_span, span.data(), 8ull * span.size(), st))) return e;
+        // the copy is enqueued; keep the host buffer alive until it is done
+        if ((e = hipStreamSynchronize(st))) return e;
     }
     if ((e = upload(pl.d_long_ids, pl.long_ids.data(), 4ull * pl.long_ids.size(), st))) return e;
     if ((e = upload(pl.d_long_prefix, pl.long_prefix.data(), 4ull * pl.long_prefix.size(), st)))
@@ -444,7 +451,7 @@ wlda_status run_phase(wlda_sampler s, uint32_t phase, uint32_t iter, bool draw_o
     const bool prof = s->prof && !draw_only;
     for (int bin = 0; bin < NBINS; ++bin) {
         const BinList &b = pl.bins[bin];
-        const SegList l{b.d_ids, (uint32_t)b.ids.size(), b.d_cut};
+        const SegList l{b.d_ids, (uint32_t)b.ids.size(), b.d_cut, b.d_span};
         a.max_blocks = s->seg_blocks[kb + bin];
         auto launch = [&] {
             return bin == BIN_WAVE ? launch_wave_segments(a, phase, s->p.M, l, s->st)
@@ -676,8 +683,8 @@ wlda_status wlda_create(const wlda_params *p, const uint32_t *word_ids, const ui
     if (!e && s->blocked) e = upload(s->colidx, s->mem.data(), 4ull * T, s->st);
     if (!s->blocked) s->colidx = nullptr;   // identity: kernels use the CSC position
     if (!e) e = upload(s->rowidx, rowidx.data(), 4ull * T, s->st);
-    if (!e) e = place_plan(s->word, cur, p->K, s->st);
-    if (!e) e = place_plan(s->doc, cur, p->K, s->st);
+    if (!e) e = place_plan(s->word, colptr, cur, p->K, s->st);
+    if (!e) e = place_plan(s->doc, rowptr, cur, p->K, s->st);
     if (!e) e = launch_fill_u32(s->ck[0], 0, 2ull * align_up(4ull * p->K) / 4, s->st);
     if (!e) e = hipStreamSynchronize(s->st);
     if (e) {

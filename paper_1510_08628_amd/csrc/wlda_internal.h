@@ -32,11 +32,14 @@ inline uint32_t record_bytes(uint32_t M, uint32_t K) {
 // of segment s has the canonical position segptr[s] + n of its phase (CSC in
 // the word phase, CSR in the doc phase; the RNG counter uses it) and its
 // record at recs[idx[segptr[s] + n]] (idx = colidx or rowidx: the record
-// layout is blocked by documents, see the host runtime).
+// layout is blocked by documents, see the host runtime).  A list also holds
+// each segment's span, so a kernel reaches its tokens' record positions in
+// one dependent load fewer.
 struct SegList {
     const uint32_t *ids = nullptr;   // segment ids, ascending
     uint32_t n = 0;
     const uint32_t *xcd_cut = nullptr;   // 9 list offsets: XCD x owns [cut[x], cut[x+1])
+    const uint2 *span = nullptr;     // per listed segment: segptr[id], segptr[id + 1]
 };
 
 // Segments longer than one workgroup's share ("long") are cut into chunks of

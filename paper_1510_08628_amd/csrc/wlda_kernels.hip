@@ -266,9 +266,9 @@ __global__ __launch_bounds__(256) void seg_kernel(PhaseArgs a, SegList l, uint32
     // with no branch around any load (slots past the segment's end re-read its
     // last token), so each batch is in flight at once.
     auto fetch = [&](uint32_t lj, uint32_t &fbeg, uint32_t &fL, uint32_t(&fpos)[TPT], Rec<NW>(&frec)[TPT]) {
-        const uint32_t s_id = l.ids[lj];
-        fbeg = a.segptr[s_id];
-        fL = a.segptr[s_id + 1] - fbeg;
+        const uint2 sp = l.span[lj];
+        fbeg = sp.x;
+        fL = sp.y - sp.x;
         if (a.idx) {
 #pragma unroll
             for (int r = 0; r < TPT; ++r) fpos[r] = a.idx[fbeg + min(r * GROUP + lane, fL - 1)];
