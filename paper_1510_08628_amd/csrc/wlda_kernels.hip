@@ -459,8 +459,13 @@ __device__ __forceinline__ uint32_t gtab_get(const uint32_t *base, uint32_t cap,
     }
 }
 
-// tokens per thread whose loads are issued together in the long kernels
-constexpr int LONG_BATCH = 8;
+// Tokens per thread whose loads are issued together in the long kernels.  The
+// histogram and MH passes wait on their gathers and want many in flight; the
+// draw pass is bound by its arithmetic (Philox, the CDF search), and a
+// larger batch only costs it registers.
+constexpr int HIST_BATCH = 16;
+constexpr int MH_BATCH = 16;
+constexpr int DRAW_BATCH = 4;
 
 // Record positions of tokens nb, nb + 256, ... of a segment starting at
 // canonical position beg, clamped to the chunk's last token n1 - 1 so that
@@ -501,14 +506,14 @@ __global__ __launch_bounds__(256) void long_hist_kernel(PhaseArgs a, LongList l,
             for (uint32_t k = threadIdx.x; k < HCAP; k += 256) hkey[k] = EMPTY_KEY, hcnt[k] = 0;
         }
         __syncthreads();
-        // LONG_BATCH tokens per thread in flight: all loads, then the inserts
-        for (uint32_t nb = n0 + threadIdx.x; nb < n1; nb += 256 * LONG_BATCH) {
-            uint32_t pos[LONG_BATCH], z[LONG_BATCH];
-            load_positions<LONG_BATCH>(a.idx, beg, nb, n1, pos);
+        // HIST_BATCH tokens per thread in flight: all loads, then the inserts
+        for (uint32_t nb = n0 + threadIdx.x; nb < n1; nb += 256 * HIST_BATCH) {
+            uint32_t pos[HIST_BATCH], z[HIST_BATCH];
+            load_positions<HIST_BATCH>(a.idx, beg, nb, n1, pos);
 #pragma unroll
-            for (int u = 0; u < LONG_BATCH; ++u) z[u] = fld(ld_rec<NW>(a.recs, pos[u]), 0);
+            for (int u = 0; u < HIST_BATCH; ++u) z[u] = fld(ld_rec<NW>(a.recs, pos[u]), 0);
 #pragma unroll
-            for (int u = 0; u < LONG_BATCH; ++u)
+            for (int u = 0; u < HIST_BATCH; ++u)
                 if (nb + u * 256 < n1) tab_insert(hkey, lds_dense ? hist : hcnt, HCAP - 1, lds_dense != 0, z[u]);
         }
         __syncthreads();
@@ -567,15 +572,15 @@ __global__ __launch_bounds__(256) void long_mh_kernel(PhaseArgs a, LongList l, u
         constexpr int PER_THREAD = Tuning::LONG_CHUNK / 256;
         uint32_t zk[PER_THREAD];
 #pragma unroll
-        for (int bt = 0; bt < PER_THREAD / LONG_BATCH; ++bt) {
-            const uint32_t nb = n0 + threadIdx.x + bt * 256 * LONG_BATCH;
-            uint32_t pos[LONG_BATCH];
-            Rec<NW> rec[LONG_BATCH];
-            load_positions<LONG_BATCH>(a.idx, beg, nb, n1, pos);
+        for (int bt = 0; bt < PER_THREAD / MH_BATCH; ++bt) {
+            const uint32_t nb = n0 + threadIdx.x + bt * 256 * MH_BATCH;
+            uint32_t pos[MH_BATCH];
+            Rec<NW> rec[MH_BATCH];
+            load_positions<MH_BATCH>(a.idx, beg, nb, n1, pos);
 #pragma unroll
-            for (int u = 0; u < LONG_BATCH; ++u) rec[u] = ld_rec<NW>(a.recs, pos[u]);
+            for (int u = 0; u < MH_BATCH; ++u) rec[u] = ld_rec<NW>(a.recs, pos[u]);
 #pragma unroll
-            for (int u = 0; u < LONG_BATCH; ++u) {
+            for (int u = 0; u < MH_BATCH; ++u) {
                 const uint32_t n = nb + u * 256;
                 if (n >= n1) continue;
                 uint32_t s = fld(rec[u], 0);
@@ -601,7 +606,7 @@ __global__ __launch_bounds__(256) void long_mh_kernel(PhaseArgs a, LongList l, u
                         ++acc;
                     }
                 }
-                zk[bt * LONG_BATCH + u] = s;
+                zk[bt * MH_BATCH + u] = s;
                 zc[zbase + n] = (ZT)s;
             }
         }
@@ -699,24 +704,24 @@ __global__ __launch_bounds__(256) void long_draw_kernel(PhaseArgs a, LongList l,
             for (uint32_t k = threadIdx.x; k < K; k += 256) cdfl[k] = cum[k];
             __syncthreads();
         }
-        for (uint32_t nb = n0 + threadIdx.x; nb < n1; nb += 256 * LONG_BATCH) {
-            uint32_t pos[LONG_BATCH];
-            Rec<NW> rec[LONG_BATCH];
-            load_positions<LONG_BATCH>(a.idx, beg, nb, n1, pos);
+        for (uint32_t nb = n0 + threadIdx.x; nb < n1; nb += 256 * DRAW_BATCH) {
+            uint32_t pos[DRAW_BATCH];
+            Rec<NW> rec[DRAW_BATCH];
+            load_positions<DRAW_BATCH>(a.idx, beg, nb, n1, pos);
             // the record is rebuilt from the updated z alone (compact array,
             // read in chunk order): nothing of the old record survives
 #pragma unroll
-            for (int u = 0; u < LONG_BATCH; ++u) {
+            for (int u = 0; u < DRAW_BATCH; ++u) {
 #pragma unroll
                 for (int w = 0; w < (NW > 0 ? NW : 1); ++w) rec[u].w[w] = 0;
                 set_fld(rec[u], 0, (uint32_t)zs[min(nb + u * 256, n1 - 1)]);
             }
             // all random-positioning reads (or CDF lookups) of the batch are
             // issued before any record is written back
-            uint32_t jj[LONG_BATCH * M] = {};
+            uint32_t jj[DRAW_BATCH * M] = {};
             uint32_t coin = 0;
 #pragma unroll
-            for (int u = 0; u < LONG_BATCH; ++u) {
+            for (int u = 0; u < DRAW_BATCH; ++u) {
                 const uint32_t n = nb + u * 256;
                 if (n >= n1) continue;
 #pragma unroll
@@ -739,15 +744,15 @@ __global__ __launch_bounds__(256) void long_draw_kernel(PhaseArgs a, LongList l,
             }
             if (by_cdf) {
                 if (cdf_lds)
-                    cdf_find_lds<LONG_BATCH * M>(cdfl, K, jj);
+                    cdf_find_lds<DRAW_BATCH * M>(cdfl, K, jj);
                 else
-                    cdf_find_n<LONG_BATCH * M>(cum, K, jj);
+                    cdf_find_n<DRAW_BATCH * M>(cum, K, jj);
 #pragma unroll
-                for (int d = 0; d < LONG_BATCH * M; ++d)
+                for (int d = 0; d < DRAW_BATCH * M; ++d)
                     if ((coin >> d) & 1u) set_fld(rec[d / M], d % M + 1, jj[d]);
             }
 #pragma unroll
-            for (int u = 0; u < LONG_BATCH; ++u) {
+            for (int u = 0; u < DRAW_BATCH; ++u) {
                 if (nb + u * 256 >= n1) continue;
                 st_rec<NW>(a.recs, pos[u], rec[u]);
                 const uint32_t z = fld(rec[u], 0);
