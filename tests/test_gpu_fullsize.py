@@ -3,7 +3,8 @@ times: the NYTimes-shaped corpus (~99M tokens, K=1000, M=2) through init and
 one full iteration, every token compared bit for bit after each phase; and a
 PubMed-shaped corpus (K=1e4, M=4; 200k documents of the 8M-document shape) for
 two iterations.  The oracle computes its own state from the same seeded
-inputs (it takes ~4M tokens/s on one core)."""
+inputs (it takes ~4M tokens/s on one core).  The PubMed-shaped workload at its
+full 8M-document size is checked by properties that hold at any size."""
 import numpy as np
 import pytest
 
@@ -93,3 +94,51 @@ def test_clueweb_shape_k1e6(W):
         compare_csc(s, o, f"doc phase {it + 1}")
     ll_s, ll_o = s.log_likelihood(), o.log_likelihood()
     assert abs(ll_s - ll_o) <= 1e-6 * abs(ll_o), (ll_s, ll_o)
+
+
+@pytest.mark.timeout(900)
+def test_pubmed_shape_full_size_properties(W):
+    """The PubMed-shaped workload at its full size (8M documents, ~720M
+    tokens, K = 1e4, M = 4), in the launch configuration the benchmark uses,
+    where the oracle would take hours: checked by properties that hold at any
+    size.  Every topic and pending proposal lies in [0, K); the sampler's c_k
+    is the exact histogram of its Z and sums to T; acceptance counts are in
+    range; the log likelihood is finite and rises over the first iterations;
+    and an iteration replayed from a saved state reproduces every token (no
+    race or order dependence at full occupancy)."""
+    import sys
+    wl = synth.WORKLOADS["pubmed-shape-k1e4"]
+    log = lambda m: print(f"[pubmed full size] {m}", file=sys.__stderr__, flush=True)
+    c = wl.make()
+    T, K, M = c.T, wl.K, wl.M
+    log(f"corpus T={T}")
+    s = W.Sampler(c.word_ids, c.doc_ids, c.V, c.D, K, M, wl.alpha, wl.beta, seed=3)
+    del c
+    s.init()
+    ll0 = s.log_likelihood()
+    s.iterate(1)
+    blob = s.save_state()
+    s.iterate(1)
+    acc_w, acc_d = s.accepted(1), s.accepted(2)
+    z, p = s.assignments()
+    ck = s.topic_counts()
+    ll2 = s.log_likelihood()
+    log(f"two iterations, LL {ll0:.6e} -> {ll2:.6e}")
+    assert z.min() >= 0 and z.max() < K
+    assert p.min() >= 0 and p.max() < K
+    assert ck.sum() == T
+    assert np.array_equal(ck, np.bincount(z, minlength=K))
+    assert 0 < acc_w <= M * T and 0 < acc_d <= M * T
+    assert np.isfinite(ll0) and np.isfinite(ll2) and ll2 > ll0
+    p_sample = p[:, ::101].copy()
+    del p
+    s.load_state(blob)
+    del blob
+    s.iterate(1)
+    z2, p2 = s.assignments()
+    assert np.array_equal(z, z2)
+    assert np.array_equal(p_sample, p2[:, ::101])
+    assert np.array_equal(ck, s.topic_counts())
+    assert (s.accepted(1), s.accepted(2)) == (acc_w, acc_d)
+    log("replay from the saved state matches")
+    s.close()
