@@ -65,8 +65,9 @@ struct LongList {
     const uint32_t *tab_cap = nullptr;
     uint64_t table_words = 0;
     void *zc = nullptr;                // total compact topics (u16 if K <= 65535, else u32)
-    // Dense counts of the updated z of every word with L > K (same offsets as
-    // `tables`, which are dense for those words), turned into inclusive
+    // Dense counts of the updated z of every word past the inverse-CDF
+    // threshold (word_cdf; same offsets as `tables`, which are dense for
+    // those words since 2L > K), turned into inclusive
     // prefix counts for the inverse-CDF word proposals; zeroed before use.
     uint32_t *tables_new = nullptr;
 };

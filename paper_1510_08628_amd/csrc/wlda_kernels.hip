@@ -636,7 +636,8 @@ __global__ __launch_bounds__(256) void long_mh_kernel(PhaseArgs a, LongList l, u
 }
 
 // Inclusive prefix sums, in place, of the updated counts of every long word
-// with L > K: one workgroup per word, tiles of 4096 topics.
+// past the inverse-CDF threshold (word_cdf): one workgroup per word, tiles of
+// 4096 topics.
 __global__ __launch_bounds__(256) void long_cdf_kernel(LongList l, const uint32_t *segptr, uint32_t K) {
     __shared__ uint32_t wsum[4];
     constexpr int PER = 16;
@@ -681,7 +682,7 @@ template <int PHASE, int M, int NW, typename ZT>
 __global__ __launch_bounds__(256) void long_draw_kernel(PhaseArgs a, LongList l, uint32_t ck_lds_u,
                                                         uint32_t zero_tables, uint32_t cdf_lds_u) {
     // LDS: [c_k histogram of the new Z (ck_lds) | prefix counts of the
-    // current word (cdf_lds, words with L > K)]
+    // current word (cdf_lds, words past the inverse-CDF threshold)]
     extern __shared__ uint32_t ckh[];
     const bool ck_lds = ck_lds_u != 0, cdf_lds = cdf_lds_u != 0;
     const uint32_t K = a.K;
