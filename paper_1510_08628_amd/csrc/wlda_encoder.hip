@@ -184,9 +184,126 @@ __global__ void colsum_kernel(int rows, int cols, const float *g, float *db) {
     }
 }
 
-// dW1[idx_n] += val_n * g1[b]
+// Embedding-bag backward, dW1[u] = sum over the batch's nonzeros (b, u, val)
+// of val * g1[b].  The batch (CSR by document) is transposed into lists per
+// bucket u (count, exclusive scan, scatter), and one workgroup sums each
+// touched bucket's list into its gradient row: no atomics on the H-wide rows.
+// A batch with more nonzeros than the list holds (rowptr[B] > cap, known only
+// on the device) takes the atomic kernel instead; every kernel below reads
+// rowptr[B] and returns at once when it is not the one in charge.
+__global__ __launch_bounds__(256) void embag_count_kernel(const uint32_t *rowptr, const uint32_t *idx, uint32_t B,
+                                                          uint32_t cap, uint32_t *cnt) {
+    if (rowptr[B] > cap) return;
+    const uint32_t b = blockIdx.x;
+    for (uint32_t n = rowptr[b] + threadIdx.x; n < rowptr[b + 1]; n += 256) atomicAdd(&cnt[idx[n]], 1u);
+}
+
+// Exclusive scan of cnt[0..nb) into off[0..nb] (off[nb] = total), copied to
+// cur; one workgroup of 1024 threads walks tiles of 4096 counts, each thread
+// four consecutive ones (coalesced), carrying the running total.
+__global__ __launch_bounds__(1024) void embag_scan_kernel(const uint32_t *rowptr, uint32_t B, uint32_t cap,
+                                                          uint32_t nb, const uint32_t *cnt, uint32_t *off,
+                                                          uint32_t *cur) {
+    if (rowptr[B] > cap) return;
+    __shared__ uint32_t wsum[16];
+    const uint32_t wl = threadIdx.x & 63;
+    uint32_t carry = 0;
+    for (uint32_t t0 = 0; t0 < nb; t0 += 4096) {
+        const uint32_t k0 = t0 + threadIdx.x * 4;
+        uint32_t v[4], sum = 0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            v[i] = k0 + i < nb ? cnt[k0 + i] : 0u;
+            sum += v[i];
+        }
+        uint32_t x = sum;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t y = __shfl_up(x, o, 64);
+            if (wl >= (uint32_t)o) x += y;
+        }
+        if (wl == 63) wsum[threadIdx.x >> 6] = x;
+        __syncthreads();
+        uint32_t base = carry, tile = 0;
+        for (uint32_t w = 0; w < 16; ++w) {
+            if (w < (threadIdx.x >> 6)) base += wsum[w];
+            tile += wsum[w];
+        }
+        uint32_t run = base + x - sum;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            if (k0 + i < nb) {
+                off[k0 + i] = run;
+                cur[k0 + i] = run;
+            }
+            run += v[i];
+        }
+        carry += tile;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) off[nb] = carry;
+}
+
+__global__ __launch_bounds__(256) void embag_scatter_kernel(const uint32_t *rowptr, const uint32_t *idx,
+                                                            const float *val, uint32_t B, uint32_t cap,
+                                                            uint32_t *cur, uint2 *list) {
+    if (rowptr[B] > cap) return;
+    const uint32_t b = blockIdx.x;
+    for (uint32_t n = rowptr[b] + threadIdx.x; n < rowptr[b + 1]; n += 256) {
+        const uint32_t q = atomicAdd(&cur[idx[n]], 1u);
+        list[q] = make_uint2(b, __float_as_uint(val[n]));
+    }
+}
+
+// One workgroup per touched bucket: its list goes through LDS 256 entries at
+// a time, and each thread sums its columns with eight g1 rows in flight.
+__global__ __launch_bounds__(256) void embag_wgrad_kernel(const uint32_t *rowptr, uint32_t B, uint32_t cap,
+                                                          uint32_t nb, int H, const uint32_t *off,
+                                                          const uint2 *list, const float *g1, float *dW1) {
+    if (rowptr[B] > cap) return;
+    __shared__ uint2 ent[256];
+    for (uint32_t u = blockIdx.x; u < nb; u += gridDim.x) {
+        const uint32_t q0 = off[u], q1 = off[u + 1];
+        if (q0 == q1) continue;
+        // columns of this thread: j = threadIdx.x + 256 c, c < CMAX (H <= 4096)
+        constexpr int CMAX = 16;
+        float acc[CMAX];
+#pragma unroll
+        for (int c = 0; c < CMAX; ++c) acc[c] = 0.f;
+        for (uint32_t e0 = q0; e0 < q1; e0 += 256) {
+            const uint32_t ne = min(256u, q1 - e0);
+            __syncthreads();
+            if (threadIdx.x < ne) ent[threadIdx.x] = list[e0 + threadIdx.x];
+            __syncthreads();
+#pragma unroll
+            for (int c = 0; c < CMAX; ++c) {
+                const int j = threadIdx.x + 256 * c;
+                if (j >= H) break;
+                uint32_t q = 0;
+                for (; q + 8 <= ne; q += 8) {
+                    float g[8];
+#pragma unroll
+                    for (int r = 0; r < 8; ++r) g[r] = g1[(size_t)ent[q + r].x * H + j];
+#pragma unroll
+                    for (int r = 0; r < 8; ++r) acc[c] += __uint_as_float(ent[q + r].y) * g[r];
+                }
+                for (; q < ne; ++q) acc[c] += __uint_as_float(ent[q].y) * g1[(size_t)ent[q].x * H + j];
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < CMAX; ++c) {
+            const int j = threadIdx.x + 256 * c;
+            if (j < H) dW1[(size_t)u * H + j] = acc[c];
+        }
+    }
+}
+
+// dW1[idx_n] += val_n * g1[b], one workgroup per document (batches too large
+// for the transpose lists only).
 __global__ __launch_bounds__(256) void embag_bwd_kernel(int H, const uint32_t *rowptr, const uint32_t *idx,
-                                                        const float *val, const float *g1, float *dW1) {
+                                                        const float *val, const float *g1, float *dW1,
+                                                        uint32_t B, uint32_t cap) {
+    if (rowptr[B] <= cap) return;
     const int b = blockIdx.x;
     for (uint32_t n = rowptr[b]; n < rowptr[b + 1]; ++n)
         for (int j = threadIdx.x; j < H; j += 256)
@@ -266,6 +383,10 @@ struct wlda_encoder_s {
     float *a1 = nullptr, *a2 = nullptr, *c2 = nullptr, *c3 = nullptr, *probs = nullptr, *g3 = nullptr,
           *d2 = nullptr, *g2 = nullptr, *d1 = nullptr, *g1 = nullptr, *loss_rows = nullptr;
     uint16_t *h1b = nullptr, *h2b = nullptr, *g3b = nullptr, *g2b = nullptr;
+    // embedding-bag backward: per-bucket counts, offsets, cursors and lists
+    uint32_t *tcnt = nullptr, *toff = nullptr, *tcur = nullptr;
+    uint2 *tlist = nullptr;
+    uint32_t tcap = 0;
     uint64_t steps = 0;
 };
 
@@ -289,6 +410,13 @@ void param_sizes(const wlda_encoder_params &p, long n[6]) {
     n[5] = p.K;                          // b3
 }
 
+// Nonzeros the embedding-bag backward's transpose lists hold: 4096 per
+// document of a full batch, at most 2^22 (a larger batch takes the atomic
+// kernel).
+uint32_t transpose_cap(const wlda_encoder_params &p) {
+    return (uint32_t)std::min<uint64_t>(4096ull * p.max_batch, 1ull << 22);
+}
+
 uint64_t enc_bytes(const wlda_encoder_params &p) {
     long n[6];
     param_sizes(p, n);
@@ -297,6 +425,7 @@ uint64_t enc_bytes(const wlda_encoder_params &p) {
     t += ea(2ull * n[0]) + ea(2ull * n[2]) + ea(2ull * n[4]);
     const uint64_t B = p.max_batch, Hd = p.hidden, K = p.K;
     t += 7 * ea(4 * B * Hd) + 3 * ea(4 * B * K) + ea(4 * B) + 3 * ea(2 * B * Hd) + ea(2 * B * K);
+    t += 3 * ea(4ull * (p.buckets + 1)) + ea(8ull * transpose_cap(p));
     return t;
 }
 
@@ -354,7 +483,15 @@ hipError_t backward(wlda_encoder e, uint32_t B, const uint32_t *rowptr, const ui
     // layer 1 (embedding bag)
     hipLaunchKernelGGL(colsum_kernel, dim3(grid(Hd)), dim3(256), 0, st, (int)B, Hd, e->g1, e->g[1]);
     hipLaunchKernelGGL(zero_f32_kernel, dim3(grid(e->n[0])), dim3(256), 0, st, e->n[0], e->g[0]);
-    hipLaunchKernelGGL(embag_bwd_kernel, dim3(B), dim3(256), 0, st, Hd, rowptr, idx, val, e->g1, e->g[0]);
+    const uint32_t nb = e->p.buckets, cap = e->tcap;
+    hipLaunchKernelGGL(zero_f32_kernel, dim3(grid(nb)), dim3(256), 0, st, (long)nb, (float *)e->tcnt);
+    hipLaunchKernelGGL(embag_count_kernel, dim3(B), dim3(256), 0, st, rowptr, idx, B, cap, e->tcnt);
+    hipLaunchKernelGGL(embag_scan_kernel, dim3(1), dim3(1024), 0, st, rowptr, B, cap, nb, e->tcnt, e->toff, e->tcur);
+    hipLaunchKernelGGL(embag_scatter_kernel, dim3(B), dim3(256), 0, st, rowptr, idx, val, B, cap, e->tcur,
+                       e->tlist);
+    hipLaunchKernelGGL(embag_wgrad_kernel, dim3(std::min<uint32_t>(nb, 8192)), dim3(256), 0, st, rowptr, B, cap,
+                       nb, Hd, e->toff, e->tlist, e->g1, e->g[0]);
+    hipLaunchKernelGGL(embag_bwd_kernel, dim3(B), dim3(256), 0, st, Hd, rowptr, idx, val, e->g1, e->g[0], B, cap);
     return hipGetLastError();
 }
 
@@ -413,6 +550,11 @@ wlda_status wlda_encoder_create(const wlda_encoder_params *p, void *ws, uint64_t
     e->h2b = (uint16_t *)take(2 * B * Hd);
     e->g2b = (uint16_t *)take(2 * B * Hd);
     e->g3b = (uint16_t *)take(2 * B * K);
+    e->tcnt = (uint32_t *)take(4ull * (p->buckets + 1));
+    e->toff = (uint32_t *)take(4ull * (p->buckets + 1));
+    e->tcur = (uint32_t *)take(4ull * (p->buckets + 1));
+    e->tcap = transpose_cap(*p);
+    e->tlist = (uint2 *)take(8ull * e->tcap);
     hipError_t r = hipSuccess;
     for (int i = 0; i < 6 && !r; ++i) {
         hipLaunchKernelGGL(zero_f32_kernel, dim3(grid(e->n[i])), dim3(256), 0, e->st, e->n[i], e->w[i]);
