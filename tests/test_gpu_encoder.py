@@ -64,6 +64,28 @@ def test_gradients_match_oracle(W, buckets, hidden, K, B):
     assert np.all(g_g[0][untouched] == 0)
 
 
+def test_gradients_past_transpose_capacity(W):
+    """The first layer's gradient goes through per-bucket lists that hold 4096
+    nonzeros per document of a full batch; a batch with more takes the atomic
+    kernel.  One document with ~6000 distinct buckets at max_batch = 1 checks
+    that path against the oracle too."""
+    buckets, hidden, K = 20000, 128, 40
+    enc = W.Encoder(buckets, hidden, K, max_batch=1)
+    ws = synth.encoder_init_weights(buckets, hidden, K, 5)
+    enc.set_weights(ws)
+    rng = np.random.default_rng(9)
+    docs = [rng.integers(0, 200000, 9000)]
+    theta = rng.dirichlet(np.full(K, 0.2), size=1)
+    rowptr, idx, val = E.batch_features(buckets, docs)
+    assert rowptr[-1] > 4096
+    _, _, g_o = E.forward_backward(ws, rowptr, idx, val, theta, round=True)
+    d_rp, d_idx, d_val, d_th = to_dev(rowptr, idx, val, theta.astype(np.float32))
+    _, g_g = enc.gradients(d_rp, d_idx, d_val, d_th)
+    for name, gg, go in zip(W.Encoder.NAMES, g_g, g_o):
+        err = np.linalg.norm(gg - go) / max(np.linalg.norm(go), 1e-30)
+        assert err < 5e-3, (name, err)
+
+
 def test_training_lowers_loss(W):
     buckets, hidden, K, B = 4000, 256, 50, 128
     enc = W.Encoder(buckets, hidden, K, max_batch=B, lr=3e-3)
