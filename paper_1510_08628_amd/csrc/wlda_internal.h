@@ -99,13 +99,14 @@ struct Tuning {
     static constexpr int TPT_WIDE = 16;
     static constexpr uint32_t WIDE_MAX = 256 * TPT_WIDE;     // longest segment below the long path
     static constexpr uint32_t CK_LDS_MAX = 4096;             // block c_k histogram in LDS
+    static constexpr uint32_t CKB_LDS_MAX = 16384;           // segment kernels: c_k + beta_bar in LDS
     // tokens per long-path chunk: LONG_CHUNK when the chunk histogram is a
     // dense LDS array (K <= LDS_DENSE_MAX), else LONG_CHUNK_HASHED so that the
     // LDS hash table (2 * LONG_CHUNK_HASHED slots) always has free slots
     static constexpr uint32_t LONG_CHUNK = 8192;
     static constexpr uint32_t LONG_CHUNK_HASHED = 4096;
     static constexpr uint32_t LDS_DENSE_MAX = 16384;         // dense LDS counts up to this K
-    static constexpr uint32_t CDF_LDS_MAX = 8192;            // long-word prefix counts in LDS
+    static constexpr uint32_t CDF_LDS_MAX = 16384;           // long-word prefix counts in LDS
 };
 
 // Word proposals (count part): columns longer than both K and CDF_MIN_LEN

@@ -232,24 +232,26 @@ __global__ __launch_bounds__(256) void seg_kernel(PhaseArgs a, SegList l, uint32
                                                   uint32_t dense_u, uint32_t ck_lds_u) {
     extern __shared__ uint32_t lds[];
     constexpr int GPB = 256 / GROUP;
-    const bool dense = dense_u != 0, ck_lds = ck_lds_u != 0;
+    // ck_lds_u: bit 0 = the c_k histogram of the new Z in LDS (K <= CK_LDS_MAX),
+    // bit 1 = c_k + beta_bar staged in LDS (K <= CKB_LDS_MAX)
+    const bool dense = dense_u != 0, ckh_lds = (ck_lds_u & 1u) != 0, ckb_lds = (ck_lds_u & 2u) != 0;
     const uint32_t g = threadIdx.x / GROUP, lane = threadIdx.x % GROUP;
     const uint32_t K = a.K;
-    // LDS: [c_k histogram of the new Z | c_k + beta_bar as binary32] when
-    // K <= CK_LDS_MAX, then per group [count table | new z of the segment]
-    const uint32_t ck_words = ck_lds ? 2 * K : 0;
+    // LDS: [c_k + beta_bar as binary32 (ckb_lds)] [c_k histogram of the new
+    // Z (ckh_lds)], then per group [count table | new z of the segment]
+    const uint32_t ck_words = (ckb_lds ? K : 0) + (ckh_lds ? K : 0);
     const uint32_t tab_words = dense ? K : 2 * cap_max;
-    uint32_t *ckh = lds;
-    float *ckb = reinterpret_cast<float *>(lds + K);
+    float *ckb = reinterpret_cast<float *>(lds);
+    uint32_t *ckh = lds + (ckb_lds ? K : 0);
     uint32_t *gbase = lds + ck_words + g * (tab_words + GROUP * TPT);
     uint32_t *tkey = gbase;
     uint32_t *tcnt = dense ? gbase : gbase + cap_max;
     uint32_t *zarr = gbase + tab_words;
 
-    if (ck_lds)
+    if (ckh_lds || ckb_lds)
         for (uint32_t i = threadIdx.x; i < K; i += 256) {
-            ckh[i] = 0;
-            ckb[i] = (float)a.ck[i] + a.beta_bar;
+            if (ckh_lds) ckh[i] = 0;
+            if (ckb_lds) ckb[i] = (float)a.ck[i] + a.beta_bar;
         }
     if (dense)
         for (uint32_t i = lane; i < K; i += GROUP) tcnt[i] = 0;
@@ -312,7 +314,7 @@ __global__ __launch_bounds__(256) void seg_kernel(PhaseArgs a, SegList l, uint32
                         const uint32_t cc = tab_get(tkey, tcnt, mask, dense, c);
                         const uint32_t cs = tab_get(tkey, tcnt, mask, dense, s);
                         const float u = unif24(word4(RA, i - 1));
-                        const bool ok = ck_lds ? mh_accept_b(u, cc, cs, prior, ckb[s], ckb[c])
+                        const bool ok = ckb_lds ? mh_accept_b(u, cc, cs, prior, ckb[s], ckb[c])
                                                : mh_accept(u, cc, cs, prior, a.ck[s], a.ck[c], beta_bar);
                         if (ok) {
                             s = c;
@@ -383,7 +385,7 @@ __global__ __launch_bounds__(256) void seg_kernel(PhaseArgs a, SegList l, uint32
 #pragma unroll
                     for (int i = 1; i <= M; ++i) set_fld(out, i, pw[q * M + i - 1]);
                     st_rec<NW>(a.recs, pos[r], out);
-                    if (ck_lds)
+                    if (ckh_lds)
                         atomicAdd(&ckh[znew[r]], 1u);
                     else
                         atomicAdd(&a.ck_next[znew[r]], 1u);
@@ -405,7 +407,7 @@ __global__ __launch_bounds__(256) void seg_kernel(PhaseArgs a, SegList l, uint32
     }
     add_accepted(a.accepted, acc);
     __syncthreads();
-    if (ck_lds) {
+    if (ckh_lds) {
         for (uint32_t k = threadIdx.x; k < K; k += 256) {
             const uint32_t v = ckh[k];
             if (v) atomicAdd(&a.ck_next[k], v);
@@ -973,11 +975,11 @@ template <int PHASE, int M, int NW, int GROUP, int TPT>
 static hipError_t run_seg(const PhaseArgs &a, const SegList &l, uint32_t cap_bound, hipStream_t st) {
     if (l.n == 0) return hipSuccess;
     const bool dense = a.K <= cap_bound;
-    const bool ck_lds = a.K <= Tuning::CK_LDS_MAX;
+    const bool ckh_lds = a.K <= Tuning::CK_LDS_MAX, ckb_lds = a.K <= Tuning::CKB_LDS_MAX;
     const uint32_t cap_max = dense ? 0 : cap_bound;
     const uint32_t tab_words = dense ? a.K : 2 * cap_max;
     constexpr int GPB = 256 / GROUP;
-    const size_t lds = 4ull * ((ck_lds ? 2 * a.K : 0) + GPB * (tab_words + GROUP * TPT));
+    const size_t lds = 4ull * ((ckh_lds ? a.K : 0) + (ckb_lds ? a.K : 0) + GPB * (tab_words + GROUP * TPT));
     auto kern = seg_kernel<PHASE, M, NW, GROUP, TPT>;
     hipError_t e = launch_dyn(kern, dim3(1), lds, st);
     if (e != hipSuccess) return e;
@@ -988,7 +990,7 @@ static hipError_t run_seg(const PhaseArgs &a, const SegList &l, uint32_t cap_bou
     blocks = blocks < cap_blocks ? blocks : cap_blocks;
     blocks = (blocks + 7) / 8 * 8;
     hipLaunchKernelGGL(kern, dim3(blocks), dim3(256), lds, st, a, l, cap_max, (uint32_t)dense,
-                       (uint32_t)ck_lds);
+                       (uint32_t)ckh_lds | (uint32_t)ckb_lds << 1);
     return hipGetLastError();
 }
 
