@@ -100,6 +100,10 @@ struct Tuning {
     static constexpr uint32_t WIDE_MAX = 256 * TPT_WIDE;     // longest segment below the long path
     static constexpr uint32_t CK_LDS_MAX = 4096;             // block c_k histogram in LDS
     static constexpr uint32_t CKB_LDS_MAX = 16384;           // segment kernels: c_k + beta_bar in LDS
+    // long kernels: c_k + beta_bar (MH pass) and the c_k histogram (draw pass)
+    // in LDS; they run few workgroups per CU anyway, where the segment kernels
+    // would lose half their occupancy to a K-word histogram
+    static constexpr uint32_t LONG_CK_LDS_MAX = 16384;
     // tokens per long-path chunk: LONG_CHUNK when the chunk histogram is a
     // dense LDS array (K <= LDS_DENSE_MAX), else LONG_CHUNK_HASHED so that the
     // LDS hash table (2 * LONG_CHUNK_HASHED slots) always has free slots

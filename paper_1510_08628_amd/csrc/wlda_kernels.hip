@@ -1055,7 +1055,7 @@ static hipError_t long_dispatch_z(const PhaseArgs &a, const LongList &l, hipStre
     return with_rf_m<M>(a.rf, [&](auto rfc) -> hipError_t {
     constexpr int NW = decltype(rfc)::value;
     const bool lds_tab = a.K <= Tuning::LDS_DENSE_MAX;
-    const bool ck_lds = a.K <= Tuning::CK_LDS_MAX;
+    const bool ck_lds = a.K <= Tuning::LONG_CK_LDS_MAX;
     const uint32_t cap_blocks = a.max_blocks >= 8 ? a.max_blocks : 8;
     uint32_t blocks = l.n_chunks < cap_blocks ? l.n_chunks : cap_blocks;
     blocks = (blocks + 7) / 8 * 8;
