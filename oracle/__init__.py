@@ -6,8 +6,8 @@ its Python binding) never imports it.
 
 ``warplda_oracle.c`` is a plain, single-threaded C implementation written from
 the paper (Algorithm 2, Eq. (5)-(7), the log joint likelihood of Section 6.1);
-this module loads it with ctypes.  ``enumerate.py`` holds the exact (binary64)
-enumerators used to pin it.
+this module loads it with ctypes.  The exact (binary64) enumerators that pin it
+live with the tests (``tests/enum_chain.py``).
 """
 from __future__ import annotations
 
@@ -71,7 +71,6 @@ def lib():
         L.oracle_accepted.argtypes = [vp, C.c_int]
         L.oracle_accepted.restype = u64
         L.oracle_set_visit_reversed.argtypes = [vp, C.c_int]
-        L.oracle_set_cdf_min_len.argtypes = [vp, u64]
         L.oracle_copy_assignments.argtypes = [vp, vp, vp]
         L.oracle_copy_csc.argtypes = [vp, vp, vp]
         L.oracle_copy_layout.argtypes = [vp, vp, vp, vp, vp]
@@ -86,8 +85,12 @@ def lib():
         L.oracle_frozen_chain.argtypes = [vp, u32, u32, C.c_int, vp]
         L.oracle_frozen_chain.restype = C.c_int
         L.oracle_philox4x32_10.argtypes = [vp, vp, vp]
-        L.oracle_phase_subset.argtypes = [vp, C.c_int, u32, vp, u64]
-        L.oracle_phase_subset.restype = C.c_int
+        L.oracle_theta.argtypes = [vp, u32, u32, vp]
+        L.oracle_theta.restype = C.c_int
+        L.oracle_phi.argtypes = [vp, u32, u32, vp]
+        L.oracle_phi.restype = C.c_int
+        L.oracle_instant_iterate.argtypes = [vp, u32]
+        L.oracle_instant_iterate.restype = C.c_int
         L.oracle_foldin.argtypes = [u32, u32, u32, C.c_double, C.c_double, u64, vp, vp, vp,
                                     u32, vp, vp, vp, u32, u32, vp, u32, vp, vp]
         L.oracle_foldin.restype = C.c_int
@@ -206,11 +209,6 @@ class Oracle:
     def accepted(self, phase: int) -> int:
         return lib().oracle_accepted(self.h, phase)
 
-    def set_cdf_min_len(self, n: int):
-        """Test hook: inverse-CDF word proposals for every column longer than
-        both K and n tokens (the sampler's own threshold is 4096)."""
-        lib().oracle_set_cdf_min_len(self.h, int(n))
-
     def set_visit_reversed(self, rev: bool):
         lib().oracle_set_visit_reversed(self.h, int(rev))
 
@@ -257,9 +255,23 @@ class Oracle:
         else:
             lib().oracle_set_csc_state(self.h, _ptr(z), None)
 
-    def phase_subset(self, phase: int, iteration: int, segments):
-        segs = np.ascontiguousarray(segments, dtype=np.uint32)
-        self._check(lib().oracle_phase_subset(self.h, phase, iteration, _ptr(segs), len(segs)))
+    def theta(self, d0: int = 0, nd: int | None = None) -> np.ndarray:
+        """theta_hat of Eq. (4) for documents d0 .. d0+nd-1 (nd x K, binary64)."""
+        nd = self.D - d0 if nd is None else nd
+        out = np.empty((nd, self.K), dtype=np.float64)
+        self._check(lib().oracle_theta(self.h, d0, nd, _ptr(out)))
+        return out
+
+    def phi(self, w0: int = 0, nw: int | None = None) -> np.ndarray:
+        """phi_hat of Eq. (4) for words w0 .. w0+nw-1 (nw x K, binary64)."""
+        nw = self.V - w0 if nw is None else nw
+        out = np.empty((nw, self.K), dtype=np.float64)
+        self._check(lib().oracle_phi(self.h, w0, nw, _ptr(out)))
+        return out
+
+    def instant_iterate(self, n: int = 1):
+        """n iterations of the instant-update (collapsed Gibbs-MH) variant."""
+        self._check(lib().oracle_instant_iterate(self.h, n))
 
     def frozen_chain(self, t: int, rounds: int, mode: int) -> np.ndarray:
         hist = np.zeros(self.K, dtype=np.uint64)

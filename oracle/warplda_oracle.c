@@ -32,9 +32,9 @@
  *   - counts include the token's own assignment (Eq. 5 has no "not dn");
  *   - proposals are drawn from the counts *after* this phase's updates;
  *   - both proposals use random positioning (Section 4.3) over the canonical
- *     row/column order, except that words with L_w > K and L_w > 4096
- *     (Section 5.4's intra-word-parallel words, whose proposal the paper
- *     draws from a table over c_w) take the inverse CDF of the updated c_w;
+ *     row/column order, except that words with L_w > K (Section 5.4's
+ *     intra-word-parallel words, whose proposal the paper draws from a table
+ *     over c_w) take the inverse CDF of the updated c_w;
  *     the word-proposal mixing weight is L_w / (L_w + K beta) (the prior
  *     mass of C_wk + beta over K topics);
  *   - all acceptance and coin arithmetic is IEEE binary32 with the exact
@@ -160,10 +160,6 @@ static int32_t cdf_topic(const int64_t *cum, uint32_t K, uint32_t j)
 /* ------------------------------------------------------------------------ */
 /* Sampler state                                                            */
 /* ------------------------------------------------------------------------ */
-/* Word proposals take the inverse CDF of c_w only in columns longer than
- * both K and this many tokens (reading of the word-proposal table, below). */
-#define CDF_MIN_LEN 4096u
-
 typedef struct {
     uint32_t V, D, K, M;
     double alpha, beta;
@@ -184,7 +180,6 @@ typedef struct {
     int next_phase;     /* 0 = not initialised, PH_WORD or PH_DOC */
     uint64_t accepted_word, accepted_doc;   /* last phase of each kind */
     int visit_reversed; /* visit rows/columns in reverse order (tests) */
-    uint64_t cdf_min_len; /* inverse-CDF word proposals need L_w above this */
     /* binary32 constants */
     float a, b, alpha_bar, beta_k, beta_bar;
 } oracle_t;
@@ -266,7 +261,6 @@ oracle_t *oracle_create(const oracle_params *p, const uint32_t *word_ids,
     o->V = p->V; o->D = p->D; o->K = p->K; o->M = p->M;
     o->alpha = p->alpha; o->beta = p->beta; o->seed = p->seed;
     o->T = n_tokens;
-    o->cdf_min_len = CDF_MIN_LEN;
     set_constants(o);
     size_t T = (size_t)n_tokens;
     o->colptr = malloc((o->V + 1) * sizeof(uint64_t));
@@ -361,14 +355,14 @@ static void word_column(oracle_t *o, uint32_t w, uint32_t iter, int64_t *ck_next
     }
     for (uint64_t n = 0; n < L; ++n) cw[o->z[beg + n]] = 0;
     for (uint64_t n = 0; n < L; ++n) o->z[beg + n] = znew[beg + n];
-    /* Long words (L_w > K and L_w > CDF_MIN_LEN) are the intra-word-parallel
-     * words of Section 5.4, whose word proposal the paper draws from a table
-     * built over the column's counts c_w rather than from a token position.
-     * For them the count part is the inverse CDF of the updated c_w:
-     * j = Dice(r, L_w), and the proposal is the smallest topic k whose
-     * inclusive prefix count C(k) exceeds j.  Each token's topic occupies one
-     * unit of [0, L_w), so the law is that of random positioning. */
-    int by_cdf = L > o->K && L > o->cdf_min_len;
+    /* Words with L_w > K are the intra-word-parallel words of Section 5.4,
+     * whose word proposal the paper draws from a table built over the
+     * column's counts c_w rather than from a token position.  For them the
+     * count part is the inverse CDF of the updated c_w: j = Dice(r, L_w), and
+     * the proposal is the smallest topic k whose inclusive prefix count C(k)
+     * exceeds j.  Each token's topic occupies one unit of [0, L_w), so the
+     * law is that of random positioning. */
+    int by_cdf = L > o->K;
     if (by_cdf) {
         for (uint64_t n = 0; n < L; ++n) cw[o->z[beg + n]]++;
         for (uint32_t k = 1; k < o->K; ++k) cw[k] += cw[k - 1];
@@ -467,28 +461,6 @@ int oracle_doc_phase(oracle_t *o)
     o->accepted_doc = accepted;
     o->iter = iter;
     o->next_phase = PH_WORD;
-    return 0;
-}
-
-/* The phase restricted to the listed columns (phase 1) or rows (phase 2),
- * with the current c_k and the given iteration number; other segments, c_k
- * and the phase bookkeeping are left untouched.  Segments are independent
- * within a phase, so the listed segments get exactly their full-phase
- * result.  Used to check large runs on a sample of segments. */
-int oracle_phase_subset(oracle_t *o, int phase, uint32_t iter,
-                        const uint32_t *segs, uint64_t n)
-{
-    int64_t *cnt = calloc(o->K, sizeof(int64_t));
-    int32_t *znew = malloc(o->T * sizeof(int32_t) + 1);
-    if (!cnt || !znew) { free(cnt); free(znew); return -1; }
-    uint64_t accepted = 0;
-    for (uint64_t k = 0; k < n; ++k) {
-        if (phase == PH_WORD && segs[k] < o->V)
-            word_column(o, segs[k], iter, NULL, &accepted, cnt, znew);
-        else if (phase == PH_DOC && segs[k] < o->D)
-            doc_row(o, segs[k], iter, NULL, &accepted, cnt, znew);
-    }
-    free(cnt); free(znew);
     return 0;
 }
 
@@ -595,9 +567,6 @@ uint64_t oracle_accepted(const oracle_t *o, int phase)
     return phase == PH_WORD ? o->accepted_word : o->accepted_doc;
 }
 void oracle_set_visit_reversed(oracle_t *o, int rev) { o->visit_reversed = rev; }
-/* Test hook: lowers the inverse-CDF length threshold (0 = every L_w > K) so
- * that tiny enumerable corpora reach that proposal rule. */
-void oracle_set_cdf_min_len(oracle_t *o, uint64_t n) { o->cdf_min_len = n; }
 
 /* z (and the M proposals, proposal-major) in input order. */
 void oracle_copy_assignments(const oracle_t *o, int32_t *z_input,
@@ -673,6 +642,137 @@ void oracle_set_csc_state(oracle_t *o, const int32_t *z_csc,
     memcpy(o->z, z_csc, o->T * sizeof(int32_t));
     if (props_csc) memcpy(o->prop, props_csc, (size_t)o->M * o->T * sizeof(int32_t));
     recount_ck(o);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Point estimates of Eq. (4) from the current Z, binary64:                 */
+/*   theta_dk = (C_dk + alpha) / (L_d + K alpha)                            */
+/*   phi_wk   = (C_wk + beta)  / (C_k + V beta)                             */
+/* (the M-step of Section 4.2 with alpha' = alpha + 1, beta' = beta + 1).    */
+/* theta: nd x K for documents d0 .. d0+nd-1; phi: nw x K for words         */
+/* w0 .. w0+nw-1, row-major.                                                */
+/* ------------------------------------------------------------------------ */
+int oracle_theta(const oracle_t *o, uint32_t d0, uint32_t nd, double *out)
+{
+    if ((uint64_t)d0 + nd > o->D) return -1;
+    for (uint32_t e = 0; e < nd; ++e) {
+        uint32_t d = d0 + e;
+        uint64_t beg = o->rowptr[d], L = o->rowptr[d + 1] - beg;
+        double *row = out + (size_t)e * o->K;
+        for (uint32_t k = 0; k < o->K; ++k) row[k] = 0.0;
+        for (uint64_t n = 0; n < L; ++n) row[o->z[o->row[beg + n]]] += 1.0;
+        double den = (double)L + (double)o->K * o->alpha;
+        for (uint32_t k = 0; k < o->K; ++k) row[k] = (row[k] + o->alpha) / den;
+    }
+    return 0;
+}
+
+int oracle_phi(const oracle_t *o, uint32_t w0, uint32_t nw, double *out)
+{
+    if ((uint64_t)w0 + nw > o->V) return -1;
+    double beta_bar = (double)o->V * o->beta;
+    for (uint32_t e = 0; e < nw; ++e) {
+        uint32_t w = w0 + e;
+        uint64_t beg = o->colptr[w], L = o->colptr[w + 1] - beg;
+        double *row = out + (size_t)e * o->K;
+        for (uint32_t k = 0; k < o->K; ++k) row[k] = 0.0;
+        for (uint64_t n = 0; n < L; ++n) row[o->z[beg + n]] += 1.0;
+        for (uint32_t k = 0; k < o->K; ++k)
+            row[k] = (row[k] + o->beta) / ((double)o->ck[k] + beta_bar);
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Instant-update variant (quality study of Section 6.3, not the sampler).  */
+/* The counts C_d, C_w and C_k change as soon as a token moves, as in       */
+/* LightLDA's collapsed Gibbs-MH, instead of once per phase.  Tokens are    */
+/* visited document by document in canonical row order.  For each token:   */
+/* its own assignment is taken out of the counts ("not dn", Eq. (1)); M     */
+/* steps with the document proposal q_doc ~ C_dk + alpha (random            */
+/* positioning over the document's other tokens, coin                       */
+/* (L_d - 1) / (L_d - 1 + K alpha)) judged with the word-side ratio of      */
+/* Eq. (7); M steps with the word proposal q_word ~ C_wk + beta (the        */
+/* column's other tokens, coin (L_w - 1) / (L_w - 1 + K beta)) judged with  */
+/* the document-side ratio; the assignment is put back.  Each step leaves   */
+/* p(z_dn = k | rest) ~ (C_dk+alpha)(C_wk+beta)/(C_k+V beta) invariant, so  */
+/* the scan targets the collapsed posterior p(Z | W) of Eq. (1), which the  */
+/* delayed-update sampler does not do exactly.  Binary32 decisions as in    */
+/* mh_accept(); random words: counter (t, iteration, PH_INSTANT << 16 |     */
+/* step, 0) with t the canonical CSR position and step 1..2M (doc steps     */
+/* first); words 0, 1, 2 = acceptance uniform, coin, index/topic.           */
+/* c_k, the acceptance count (reported as the doc phase's) and the          */
+/* iteration count are kept; pending proposals are left untouched.         */
+/* ------------------------------------------------------------------------ */
+enum { PH_INSTANT = 10 };
+
+/* The other tokens of a row (or column) in order, skipping position `self`:
+ * index u in [0, L-1) -> position u or u+1. */
+static uint64_t skip_self(uint64_t u, uint64_t self) { return u < self ? u : u + 1; }
+
+int oracle_instant_iterate(oracle_t *o, uint32_t n_iter)
+{
+    if (o->next_phase != PH_WORD) return -4;
+    int64_t *cd = calloc(o->K, sizeof(int64_t));
+    int64_t *cwk = calloc((size_t)o->V * o->K, sizeof(int64_t));
+    uint64_t *pos_in_col = malloc(o->T * sizeof(uint64_t) + 1);
+    if (!cd || !cwk || !pos_in_col) { free(cd); free(cwk); free(pos_in_col); return -1; }
+    for (uint32_t w = 0; w < o->V; ++w)
+        for (uint64_t t = o->colptr[w]; t < o->colptr[w + 1]; ++t) {
+            cwk[(size_t)w * o->K + o->z[t]]++;
+            pos_in_col[t] = t - o->colptr[w];
+        }
+    recount_ck(o);
+    for (uint32_t it = 0; it < n_iter; ++it) {
+        uint32_t iter = o->iter + 1;
+        uint64_t accepted = 0;
+        for (uint32_t d = 0; d < o->D; ++d) {
+            uint64_t beg = o->rowptr[d], Ld = o->rowptr[d + 1] - beg;
+            if (Ld == 0) continue;
+            for (uint64_t n = 0; n < Ld; ++n) cd[o->z[o->row[beg + n]]]++;
+            for (uint64_t n = 0; n < Ld; ++n) {
+                uint32_t t = o->row[beg + n];
+                uint32_t w = o->word_of[t];
+                int64_t *cw = cwk + (size_t)w * o->K;
+                uint64_t cbeg = o->colptr[w], Lw = o->colptr[w + 1] - cbeg;
+                int32_t s = o->z[t];
+                cd[s]--; cw[s]--; o->ck[s]--;           /* not dn */
+                for (uint32_t step = 1; step <= 2 * o->M; ++step) {
+                    uint32_t r[4];
+                    rng_call(o->seed, (uint32_t)(beg + n), iter, PH_INSTANT, step, 0, r);
+                    int32_t c;
+                    if (step <= o->M) {   /* doc proposal, word-side ratio */
+                        c = Ld > 1 && take_count_part(unif24(r[1]), Ld - 1, o->alpha_bar)
+                                ? o->z[o->row[beg + skip_self(dice(r[2], (uint32_t)(Ld - 1)), n)]]
+                                : (int32_t)dice(r[2], o->K);
+                        if (mh_accept(unif24(r[0]), cw[c], cw[s], o->b, o->ck[s], o->ck[c],
+                                      o->beta_bar)) {
+                            s = c;
+                            accepted++;
+                        }
+                    } else {              /* word proposal, doc-side ratio */
+                        c = Lw > 1 && take_count_part(unif24(r[1]), Lw - 1, o->beta_k)
+                                ? o->z[cbeg + skip_self(dice(r[2], (uint32_t)(Lw - 1)),
+                                                        pos_in_col[t])]
+                                : (int32_t)dice(r[2], o->K);
+                        if (mh_accept(unif24(r[0]), cd[c], cd[s], o->a, o->ck[s], o->ck[c],
+                                      o->beta_bar)) {
+                            s = c;
+                            accepted++;
+                        }
+                    }
+                }
+                o->z[t] = s;
+                cd[s]++; cw[s]++; o->ck[s]++;
+            }
+            for (uint64_t n = 0; n < Ld; ++n) cd[o->z[o->row[beg + n]]] = 0;
+        }
+        o->iter = iter;
+        o->accepted_word = 0;
+        o->accepted_doc = accepted;
+    }
+    free(cd); free(cwk); free(pos_in_col);
+    return 0;
 }
 
 /* ------------------------------------------------------------------------ */

@@ -202,3 +202,87 @@ def fold_distribution(words, K, M, alpha, beta, V, cwk, ck, sweeps, learned=None
     for _ in range(sweeps):
         pi = pi @ P
     return states, pi
+
+
+# --------------------------------------------------------------------------
+# Instant-update (collapsed Gibbs-MH) variant: tokens visited one at a time,
+# counts updated as soon as a token moves (Section 6.3's comparison of
+# delayed and instant count updates).
+# --------------------------------------------------------------------------
+def row_order(word_ids, doc_ids):
+    """Input indices in the order the scan visits them: documents ascending,
+    inside a document by (word, input index) -- ascending canonical column
+    position."""
+    T = len(word_ids)
+    return sorted(range(T), key=lambda i: (doc_ids[i], word_ids[i], i))
+
+
+def instant_iteration_matrix(word_ids, doc_ids, K, M, alpha, beta, V):
+    """K^T x K^T matrix of one instant-update iteration.  For each token in
+    scan order, with its own assignment taken out of the counts: M steps with
+    q_doc ~ C_dk + alpha judged by the word-side ratio of Eq. (7), then M
+    steps with q_word ~ C_wk + beta judged by the document-side ratio."""
+    T = len(word_ids)
+    states = list(itertools.product(range(K), repeat=T))
+    index = {s: i for i, s in enumerate(states)}
+    bbar = V * beta
+    P = np.eye(len(states))
+    for t in row_order(word_ids, doc_ids):
+        w, d = word_ids[t], doc_ids[t]
+        Pt = np.zeros((len(states), len(states)))
+        for si, z in enumerate(states):
+            others = [i for i in range(T) if i != t]
+            ck = np.bincount([z[i] for i in others], minlength=K).astype(np.float64)
+            cd = np.bincount([z[i] for i in others if doc_ids[i] == d], minlength=K).astype(np.float64)
+            cw = np.bincount([z[i] for i in others if word_ids[i] == w], minlength=K).astype(np.float64)
+            qd = (cd + alpha) / (cd.sum() + K * alpha)
+            qw = (cw + beta) / (cw.sum() + K * beta)
+
+            def acc_d(s, c):
+                return min(1.0, (cw[c] + beta) * (ck[s] + bbar) / ((cw[s] + beta) * (ck[c] + bbar)))
+
+            def acc_w(s, c):
+                return min(1.0, (cd[c] + alpha) * (ck[s] + bbar) / ((cd[s] + alpha) * (ck[c] + bbar)))
+            dist = _mh_outcome(z[t], qd, acc_d, K, M)
+            nd = np.zeros(K)
+            for s0 in range(K):
+                if dist[s0]:
+                    nd += dist[s0] * _mh_outcome(s0, qw, acc_w, K, M)
+            for k in range(K):
+                z2 = list(z)
+                z2[t] = k
+                Pt[si, index[tuple(z2)]] += nd[k]
+        P = P @ Pt
+    return states, P
+
+
+def instant_distribution_after(word_ids, doc_ids, K, M, alpha, beta, V, n_iter):
+    """Exact law of Z after n_iter instant-update iterations from z ~ iid Uniform(K)."""
+    states, P = instant_iteration_matrix(word_ids, doc_ids, K, M, alpha, beta, V)
+    pi = np.full(len(states), 1.0 / len(states))
+    for _ in range(n_iter):
+        pi = pi @ P
+    return states, pi
+
+
+def collapsed_posterior(word_ids, doc_ids, K, alpha, beta, V):
+    """p(Z | W) of Eq. (1), by enumeration: proportional to the product over
+    documents of prod_k Gamma(alpha + C_dk) and over topics of
+    prod_w Gamma(beta + C_wk) / Gamma(V beta + C_k)."""
+    from math import lgamma
+    T = len(word_ids)
+    states = list(itertools.product(range(K), repeat=T))
+    logp = np.zeros(len(states))
+    for si, z in enumerate(states):
+        lp = 0.0
+        for d in set(doc_ids):
+            c = np.bincount([z[i] for i in range(T) if doc_ids[i] == d], minlength=K)
+            lp += sum(lgamma(alpha + x) for x in c)
+        for w in set(word_ids):
+            c = np.bincount([z[i] for i in range(T) if word_ids[i] == w], minlength=K)
+            lp += sum(lgamma(beta + x) for x in c)
+        ck = np.bincount(list(z), minlength=K)
+        lp -= sum(lgamma(V * beta + x) for x in ck)
+        logp[si] = lp
+    p = np.exp(logp - logp.max())
+    return states, p / p.sum()

@@ -187,15 +187,14 @@ def _chi2_ok(counts, probs, n, min_expected=5.0):
     dict(words=[0, 1, 0], docs=[0, 0, 1], V=2, K=3, M=2, alpha=0.7, beta=0.4, n_iter=2),
     dict(words=[0, 0, 1, 1], docs=[0, 1, 0, 1], V=2, K=2, M=1, alpha=0.3, beta=0.9, n_iter=3),
     dict(words=[0, 1, 2, 1], docs=[0, 0, 0, 1], V=3, K=3, M=1, alpha=0.5, beta=0.2, n_iter=2),
-    # L_w > K with the length threshold lowered to 0: word 0's proposals come
-    # from the inverse CDF of its counts (long columns of the real threshold
-    # are far beyond enumeration)
-    dict(words=[0, 0, 0, 1], docs=[0, 1, 0, 1], V=2, K=2, M=1, alpha=0.6, beta=0.3, n_iter=2,
-         cdf_min_len=0),
-    dict(words=[0, 0, 0, 1, 0], docs=[0, 1, 0, 1, 1], V=2, K=2, M=2, alpha=0.4, beta=0.7, n_iter=2,
-         cdf_min_len=0),
-    # the same corpus under the real threshold: random positioning
+    # L_w > K: word 0's proposals come from the inverse CDF of its updated
+    # counts (Section 5.4's words, whose proposal is drawn from a table over
+    # c_w); the law is that of random positioning
+    dict(words=[0, 0, 0, 1], docs=[0, 1, 0, 1], V=2, K=2, M=1, alpha=0.6, beta=0.3, n_iter=2),
     dict(words=[0, 0, 0, 1, 0], docs=[0, 1, 0, 1, 1], V=2, K=2, M=2, alpha=0.4, beta=0.7, n_iter=2),
+    # the boundary: L_w = K (random positioning) and L_w = K + 1 (inverse CDF)
+    dict(words=[0, 0, 0, 1], docs=[0, 1, 0, 1], V=2, K=3, M=1, alpha=0.5, beta=0.25, n_iter=2),
+    dict(words=[0, 0, 0, 0, 1], docs=[0, 1, 0, 1, 1], V=2, K=3, M=1, alpha=0.5, beta=0.25, n_iter=2),
 ])
 def test_chain_law_matches_enumeration(case):
     """The law of Z after n iterations from the oracle's init equals the exact
@@ -211,8 +210,6 @@ def test_chain_law_matches_enumeration(case):
     counts = np.zeros(len(states))
     for seed in range(n):
         o = oracle.Oracle(w, d, V, D, K, M, case["alpha"], case["beta"], seed=1000 + seed)
-        if "cdf_min_len" in case:
-            o.set_cdf_min_len(case["cdf_min_len"])
         o.init()
         o.iterate(case["n_iter"])
         z, _ = o.assignments()
