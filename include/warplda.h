@@ -26,12 +26,23 @@
  *   - One handle must not be used from two threads at once.
  *   - Limits: 1 <= M <= 4, 1 <= K <= 2^21 - 1, n_tokens < 2^32, V, D >= 1.
  *
- * Randomness: Philox4x32-10 (Salmon et al., SC'11) keyed by the 64-bit seed,
- * one call per (token, iteration, phase, step) with counter
- * (t, iteration, phase << 16 | step, 0), where t is the token's position in
- * the canonical column-major order (tokens sorted by word, then document,
- * then input index).  Results are therefore independent of launch geometry
- * and bit-identical to any implementation of the same definition.
+ * Randomness: Philox4x32-10 (Salmon et al., SC'11) keyed by the 64-bit seed
+ * (key = (seed & 0xffffffff, seed >> 32)).  Each token draws from at most
+ * 1 + ceil(M/2) calls per phase, with counter (t, iteration, phase << 16 | j,
+ * 0), phase 0 = initialisation, 1 = word phase, 2 = document phase:
+ *   - call j = 0 gives the M acceptance uniforms (output word i-1 for MH step
+ *     i; at initialisation its word 2 gives z = Dice(K));
+ *   - call j >= 1 gives the (mixture coin, index or uniform topic) words of
+ *     proposals 2j-1 (output words 0, 1) and 2j (words 2, 3).
+ * t is the token's position in the order its phase visits it: the canonical
+ * column-major position (tokens sorted by word, then document, then input
+ * index) at initialisation and in the word phase, and the canonical row-major
+ * position rowptr[d] + n (the n-th token of document d in ascending
+ * column-major position) in the document phase.  The first document proposals
+ * are drawn at iteration 0 with the document phase's counter.  Uniforms are
+ * U(r) = (r >> 8) 2^-24 and Dice(r, n) = (r n) >> 32.  Results are therefore
+ * independent of launch geometry and record layout, and bit-identical to any
+ * implementation of the same definition.
  */
 #ifndef WARPLDA_H
 #define WARPLDA_H
@@ -50,7 +61,8 @@ typedef enum {
     WLDA_E_HIP = -3,         /* a HIP runtime call failed (sticky)          */
     WLDA_E_STATE = -4,       /* call out of order (e.g. a phase before init,
                                 a doc phase before the word phase)          */
-    WLDA_E_UNSUPPORTED = -5  /* valid input this build does not handle      */
+    WLDA_E_UNSUPPORTED = -5, /* valid input this build does not handle      */
+    WLDA_E_NOMEM = -6        /* host memory for the layout exhausted        */
 } wlda_status;
 
 /* Problem definition (Section 2.1; Section 4.1 for M). */
@@ -92,9 +104,11 @@ wlda_status wlda_init(wlda_sampler s);
  * document proposals with the acceptance rate pi_doc of Eq. (7) (counts held
  * fixed for the whole phase), and then draws M word proposals from the
  * updated column (random positioning, Section 4.3, mixing weight
- * L_w / (L_w + K beta)); columns longer than both K and 4096 tokens, the
- * intra-word-parallel words of Section 5.4, take the count part from the
- * inverse CDF of the updated c_w instead (the same law).  Requires init;
+ * L_w / (L_w + K beta)); columns longer than K tokens, the
+ * intra-word-parallel words of Section 5.4 whose proposal the paper draws
+ * from a table over c_w, take the count part from the inverse CDF of the
+ * updated c_w instead (the same law): j = Dice(r, L_w), proposal = the
+ * smallest topic k whose inclusive prefix count exceeds j.  Requires init;
  * must alternate with doc_phase. */
 wlda_status wlda_word_phase(wlda_sampler s);
 
@@ -117,10 +131,19 @@ wlda_status wlda_log_likelihood(wlda_sampler s, double *ll);
 wlda_status wlda_copy_assignments(wlda_sampler s, int32_t *z, int32_t *props);
 
 /* theta_hat of Eq. (4) with alpha' = alpha + 1 for documents d0 .. d0+nd-1:
- * theta[(d - d0) * K + k] = (C_dk + alpha) / (L_d + K alpha), binary32, written
- * to DEVICE memory (nd x K floats).  Enqueued on the sampler's stream;
- * requires K <= 16384. */
+ * theta[(d - d0) * K + k] = (C_dk + alpha) / (L_d + K alpha), binary32
+ * (numerator and denominator each rounded once, then divided), written to
+ * DEVICE memory (nd x K floats, caller-owned).  Enqueued on the sampler's
+ * stream.  WLDA_E_INVALID if d0 + nd > D, WLDA_E_STATE before init,
+ * WLDA_E_UNSUPPORTED for K > 16384. */
 wlda_status wlda_theta(wlda_sampler s, uint32_t d0, uint32_t nd, float *theta);
+
+/* phi_hat of Eq. (4) with beta' = beta + 1 for words w0 .. w0+nw-1:
+ * phi[(w - w0) * K + k] = (C_wk + beta) / (C_k + V beta), binary32 (as for
+ * theta), from the current Z, written to DEVICE memory (nw x K floats,
+ * caller-owned).  Enqueued on the sampler's stream.  WLDA_E_INVALID if
+ * w0 + nw > V, WLDA_E_STATE before init, WLDA_E_UNSUPPORTED for K > 16384. */
+wlda_status wlda_phi(wlda_sampler s, uint32_t w0, uint32_t nw, float *phi);
 
 /* Copies z and the proposals in the canonical column-major order (same
  * shapes as above).  Synchronises. */

@@ -16,7 +16,8 @@ LIB_PATH = os.path.join(HERE, "libwarplda_hip.so")
 
 WLDA_OK = 0
 STATUS = {0: "ok", -1: "invalid argument", -2: "workspace too small or misaligned",
-          -3: "HIP runtime error", -4: "call out of order", -5: "unsupported by this build"}
+          -3: "HIP runtime error", -4: "call out of order", -5: "unsupported by this build",
+          -6: "host memory exhausted"}
 
 
 class WldaError(RuntimeError):
@@ -42,7 +43,7 @@ EXPORTS = [
     "wlda_encoder_workspace_bytes", "wlda_encoder_create", "wlda_encoder_destroy",
     "wlda_encoder_set_weights", "wlda_encoder_get_weights", "wlda_encoder_features",
     "wlda_encoder_forward", "wlda_encoder_proposal", "wlda_encoder_gradients",
-    "wlda_encoder_train_step", "wlda_theta", "wlda_encoder_features_batch",
+    "wlda_encoder_train_step", "wlda_theta", "wlda_phi", "wlda_encoder_features_batch",
     "wlda_server_workspace_bytes", "wlda_server_create", "wlda_server_now", "wlda_server_submit",
     "wlda_server_step", "wlda_server_poll", "wlda_server_take_z", "wlda_server_destroy",
 ]
@@ -119,6 +120,7 @@ def load_library(path: str = LIB_PATH):
         "wlda_encoder_gradients": [vp, u32, vp, vp, vp, vp, C.POINTER(C.c_float), vp],
         "wlda_encoder_train_step": [vp, u32, vp, vp, vp, vp, C.POINTER(C.c_float)],
         "wlda_theta": [vp, u32, u32, vp],
+        "wlda_phi": [vp, u32, u32, vp],
         "wlda_encoder_features_batch": [u32, u32, vp, vp, vp, vp, vp],
         "wlda_server_workspace_bytes": [vp, vp, C.POINTER(ServerParams), C.POINTER(u64)],
         "wlda_server_create": [vp, vp, C.POINTER(ServerParams), vp, u64, vp, C.POINTER(vp)],
@@ -258,6 +260,14 @@ class Sampler:
         if out is None:
             out = torch.empty((nd, self.K), dtype=torch.float32, device=self.device)
         _check("wlda_theta", load_library().wlda_theta(self.h, d0, nd, C.c_void_p(out.data_ptr())))
+        return out
+
+    def phi(self, w0, nw, out=None):
+        """phi_hat rows of words w0..w0+nw-1 as a device tensor (nw x K)."""
+        import torch
+        if out is None:
+            out = torch.empty((nw, self.K), dtype=torch.float32, device=self.device)
+        _check("wlda_phi", load_library().wlda_phi(self.h, w0, nw, C.c_void_p(out.data_ptr())))
         return out
 
     def set_assignments(self, z, props=None):

@@ -454,8 +454,7 @@ wlda_status run_phase(wlda_sampler s, uint32_t phase, uint32_t iter, bool draw_o
         const SegList l{b.d_ids, (uint32_t)b.ids.size(), b.d_cut, b.d_span};
         a.max_blocks = s->seg_blocks[kb + bin];
         auto launch = [&] {
-            return bin == BIN_WAVE ? launch_wave_segments(a, phase, s->p.M, l, s->st)
-                                   : launch_block_segments(a, phase, s->p.M, l, bin, s->st);
+            return launch_segments(a, phase, s->p.M, l, bin, s->st);
         };
         if (prof)
             WLDA_TRY(s, timed(s, base + bin, launch));
@@ -478,7 +477,7 @@ wlda_status run_phase(wlda_sampler s, uint32_t phase, uint32_t iter, bool draw_o
 }
 
 // Host copies of the records: T records of record_bytes(M, K) bytes, as
-// 64-bit words (a 32-bit record format uses half words).
+// 64-bit words (the 32-bit formats use half words).
 struct HostRecs {
     std::vector<uint64_t> w;
     int rf = 1;
@@ -488,6 +487,10 @@ struct HostRecs {
             const uint32_t r = reinterpret_cast<const uint32_t *>(w.data())[i];
             return (r >> (b * f)) & ((1u << b) - 1u);
         }
+        if (rf >= 100) {
+            const uint32_t r = reinterpret_cast<const uint32_t *>(w.data())[i * (rf - 100) + f / 2];
+            return (r >> (16 * (f % 2))) & 0xFFFFu;
+        }
         const uint64_t *rec = &w[i * rf];
         return (uint32_t)(rec[f / 3] >> (FIELD_BITS * (f % 3))) & FIELD_MASK;
     }
@@ -496,6 +499,12 @@ struct HostRecs {
             const uint32_t b = (uint32_t)(-rf), sh = b * f;
             uint32_t &r = reinterpret_cast<uint32_t *>(w.data())[i];
             r = (r & ~(((1u << b) - 1u) << sh)) | (v << sh);
+            return;
+        }
+        if (rf >= 100) {
+            uint32_t &r = reinterpret_cast<uint32_t *>(w.data())[i * (rf - 100) + f / 2];
+            const uint32_t sh = 16 * (f % 2);
+            r = (r & ~(0xFFFFu << sh)) | (v << sh);
             return;
         }
         uint64_t *rec = &w[i * rf];
@@ -538,6 +547,7 @@ const char *wlda_strerror(wlda_status e) {
         case WLDA_E_HIP: return "HIP runtime error";
         case WLDA_E_STATE: return "call out of order";
         case WLDA_E_UNSUPPORTED: return "unsupported by this build";
+        case WLDA_E_NOMEM: return "host memory exhausted";
     }
     return "unknown status";
 }
@@ -565,7 +575,7 @@ wlda_status wlda_create(const wlda_params *p, const uint32_t *word_ids, const ui
     if (v != WLDA_OK) return v;
     if (!dev_workspace || ((uintptr_t)dev_workspace % ALIGN) != 0) return WLDA_E_WORKSPACE;
     wlda_sampler s = new (std::nothrow) wlda_sampler_s();
-    if (!s) return WLDA_E_INVALID;
+    if (!s) return WLDA_E_NOMEM;
     s->p = *p;
     s->T = T;
     s->st = (hipStream_t)hip_stream;
@@ -661,7 +671,7 @@ wlda_status wlda_create(const wlda_params *p, const uint32_t *word_ids, const ui
         for (uint64_t t = 0; t < T; ++t) rowidx[cursor[doc_csc[t]]++] = s->mem[t];
     } catch (const std::bad_alloc &) {
         delete s;
-        return WLDA_E_INVALID;
+        return WLDA_E_NOMEM;
     }
 
     // ---- workspace ----------------------------------------------------------
@@ -776,6 +786,15 @@ wlda_status wlda_theta(wlda_sampler s, uint32_t d0, uint32_t nd, float *theta) {
     if (s->next_phase == 0) return WLDA_E_STATE;
     WLDA_TRY(s, launch_theta(s->recs, s->p.M, s->rowptr, s->rowidx, d0, nd, s->p.K, (float)s->p.alpha, theta,
                              s->st));
+    return WLDA_OK;
+}
+
+wlda_status wlda_phi(wlda_sampler s, uint32_t w0, uint32_t nw, float *phi) {
+    if (!s || !phi || (uint64_t)w0 + nw > s->p.V) return WLDA_E_INVALID;
+    if (s->broken) return WLDA_E_HIP;
+    if (s->next_phase == 0) return WLDA_E_STATE;
+    WLDA_TRY(s, launch_phi(s->recs, s->p.M, s->colptr, s->colidx, s->ck[s->cur], w0, nw, s->p.K, s->b,
+                           s->beta_bar, phi, s->st));
     return WLDA_OK;
 }
 

@@ -11,9 +11,11 @@ enum Phase : uint32_t { PH_INIT = 0, PH_WORD = 1, PH_DOC = 2 };
 // One packed record per token: field 0 is z, field i (1..M) the i-th pending
 // proposal.  When K fits, the 1 + M fields share one 32-bit word, floor(32 /
 // (1 + M)) bits each (K <= 65536 for M = 1, 1024 for M = 2, 256 for M = 3,
-// 64 for M = 4); otherwise topics take 21 bits, three to a 64-bit word (one
-// word for M <= 2, two for M <= 5).  Kernels name the format by RF: 1 or 2
-// 64-bit words, or -b for a 32-bit record of b-bit fields.
+// 64 for M = 4); else, for K <= 65536, 16-bit fields two to a 32-bit word
+// (8 bytes for M = 2 or 3, 12 bytes for M = 4); otherwise topics take 21
+// bits, three to a 64-bit word (one word for M <= 2, two for M <= 5).
+// Kernels name the format by RF: -b for a 32-bit record of b-bit fields,
+// 100 + n for n 32-bit words of 16-bit fields, 1 or 2 for 64-bit words.
 constexpr uint32_t FIELD_BITS = 21;
 constexpr uint32_t FIELD_MASK = (1u << FIELD_BITS) - 1;
 constexpr uint32_t MAX_K = FIELD_MASK;   // topics are < 2^21 - 1
@@ -21,11 +23,13 @@ constexpr uint32_t MAX_K = FIELD_MASK;   // topics are < 2^21 - 1
 inline uint32_t rec32_bits(uint32_t M) { return 32 / (1 + M); }
 inline bool rec32_fits(uint32_t M, uint32_t K) { return M <= 4 && K <= (1u << rec32_bits(M)); }
 inline int record_format(uint32_t M, uint32_t K) {
-    return rec32_fits(M, K) ? -(int)rec32_bits(M) : (int)((M + 1 + 2) / 3);
+    if (rec32_fits(M, K)) return -(int)rec32_bits(M);
+    if (K <= 65536 && M >= 2 && M <= 5) return 100 + (int)((M + 2) / 2);
+    return (int)((M + 1 + 2) / 3);
 }
 inline uint32_t record_bytes(uint32_t M, uint32_t K) {
     const int rf = record_format(M, K);
-    return rf < 0 ? 4u : 8u * (uint32_t)rf;
+    return rf < 0 ? 4u : rf >= 100 ? 4u * (uint32_t)(rf - 100) : 8u * (uint32_t)rf;
 }
 
 // Segment = one column (word phase) or one row (doc phase).  The n-th token
@@ -113,14 +117,11 @@ struct Tuning {
     static constexpr uint32_t CDF_LDS_MAX = 16384;           // long-word prefix counts in LDS
 };
 
-// Word proposals (count part): columns longer than both K and CDF_MIN_LEN
-// tokens take the inverse CDF of their updated counts, all others a token of
-// the updated column (random positioning); both sample the same law.  Part of
-// the sampler's definition, not a tuning knob: the segment kernels hold
-// columns of at most WIDE_MAX tokens and use random positioning only.
-constexpr uint32_t CDF_MIN_LEN = 4096;
-static_assert(Tuning::WIDE_MAX <= CDF_MIN_LEN, "segment kernels have no inverse-CDF draw");
-__host__ __device__ inline bool word_cdf(uint32_t L, uint32_t K) { return L > K && L > CDF_MIN_LEN; }
+// Word proposals (count part): columns longer than K tokens (the words
+// Section 5.4 processes with intra-word parallelism and samples from a table
+// over c_w) take the inverse CDF of their updated counts, all others a token
+// of the updated column (random positioning); both sample the same law.
+__host__ __device__ inline bool word_cdf(uint32_t L, uint32_t K) { return L > K; }
 
 inline uint32_t long_chunk(uint32_t K) {
     return K <= Tuning::LDS_DENSE_MAX ? Tuning::LONG_CHUNK : Tuning::LONG_CHUNK_HASHED;
@@ -143,11 +144,9 @@ inline uint32_t bin_max_tokens(int bin, uint32_t M) {
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, uint64_t n, hipStream_t st);
 hipError_t launch_init_z(uint64_t *recs, const uint32_t *colidx, uint32_t T, uint32_t M, uint32_t K,
                          uint32_t seed_lo, uint32_t seed_hi, hipStream_t st);
-hipError_t launch_wave_segments(const PhaseArgs &a, uint32_t phase, uint32_t M,
-                                const SegList &l, hipStream_t st);
-// bin = BIN_BLOCK or BIN_WIDE
-hipError_t launch_block_segments(const PhaseArgs &a, uint32_t phase, uint32_t M,
-                                 const SegList &l, int bin, hipStream_t st);
+// bin = BIN_WAVE, BIN_BLOCK or BIN_WIDE
+hipError_t launch_segments(const PhaseArgs &a, uint32_t phase, uint32_t M, const SegList &l,
+                           int bin, hipStream_t st);
 // Records ev[0..3] (if non-null) before the histogram, MH and draw kernels and
 // after the draw kernel, so that the host can time each of them.
 hipError_t launch_long_segments(const PhaseArgs &a, uint32_t phase, uint32_t M,
@@ -168,7 +167,31 @@ hipError_t launch_ll_long(const PhaseArgs &a, uint32_t phase, uint32_t M, const 
                           hipStream_t st);
 hipError_t launch_theta(const uint64_t *recs, uint32_t M, const uint32_t *rowptr, const uint32_t *rowidx,
                         uint32_t d0, uint32_t nd, uint32_t K, float alpha, float *out, hipStream_t st);
+hipError_t launch_phi(const uint64_t *recs, uint32_t M, const uint32_t *colptr, const uint32_t *colidx,
+                      const uint32_t *ck, uint32_t w0, uint32_t nw, uint32_t K, float beta, float beta_bar,
+                      float *out, hipStream_t st);
 hipError_t launch_ll_topics(const uint32_t *ck, uint32_t K, double beta_bar, double *out,
                             hipStream_t st);
+
+// The phase kernels of one M, each M compiled in a translation unit of its own
+// (wlda_kernels_m.hip); the launchers above dispatch to them.
+template <int M>
+hipError_t seg_launch(const PhaseArgs &a, uint32_t phase, const SegList &l, int bin, hipStream_t st);
+template <int M>
+hipError_t long_launch(const PhaseArgs &a, uint32_t phase, const LongList &l, hipStream_t st, hipEvent_t *ev);
+template <int M>
+hipError_t long_hist_launch(const PhaseArgs &a, uint32_t phase, const LongList &l, hipStream_t st);
+#define WLDA_DECLARE_M(M)                                                                                 \
+    template <>                                                                                           \
+    hipError_t seg_launch<M>(const PhaseArgs &, uint32_t, const SegList &, int, hipStream_t);             \
+    template <>                                                                                           \
+    hipError_t long_launch<M>(const PhaseArgs &, uint32_t, const LongList &, hipStream_t, hipEvent_t *);  \
+    template <>                                                                                           \
+    hipError_t long_hist_launch<M>(const PhaseArgs &, uint32_t, const LongList &, hipStream_t);
+WLDA_DECLARE_M(1)
+WLDA_DECLARE_M(2)
+WLDA_DECLARE_M(3)
+WLDA_DECLARE_M(4)
+#undef WLDA_DECLARE_M
 
 }  // namespace wlda

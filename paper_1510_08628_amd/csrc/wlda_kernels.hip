@@ -1,785 +1,10 @@
-// gfx950 kernels of the WarpLDA sweep.
-//
-// Paper: Chen, Li, Zhu, Chen, "WarpLDA: a Cache Efficient O(1) Algorithm for
-// Latent Dirichlet Allocation" (arXiv:1510.08628).
-//
-// Data: one packed record per token (field 0 = z, fields 1..M = pending
-// proposals), stored once (Section 5.2) and blocked by documents: blocks of
-// consecutive rows of the doc phase's visiting order, column-major inside a
-// block.  Both phases reach their segments through a pointer array into that
-// copy of Y, the role P_CSR plays in Section 5.2: `colidx` (canonical CSC
-// position -> record) in the word phase and `rowidx` (canonical CSR position
-// -> record) in the document phase.  A document window then gathers inside
-// blocks resident in its XCD's L2, and a column reads one run per block.
-// With records in plain CSC order (the alternative) colidx is null and the
-// word phase streams its columns.  The RNG counter of a token is its
-// canonical position in the phase's order, independent of the layout.
-//
-// A "segment" is a column (word phase) or a row (document phase).  Segments
-// are binned by length on the host:
-//   * wave kernel   - one 64-lane wavefront per segment (<= 512 tokens);
-//   * block kernel  - one 256-thread workgroup per segment (<= 4096 tokens);
-//   * long path     - segments split over many workgroups (intra-word
-//                     parallelism, Section 5.4): histogram -> MH -> draw.
-// Per-segment counts (c_w or c_d) live in LDS, dense when K fits and otherwise
-// in an open-addressed table with linear probing and an AND hash whose
-// capacity is the power of two >= 2L (Section 5.4, "sparse vectors as hash
-// tables").  c_k is an exact integer histogram of the phase's new Z, kept in
-// LDS per workgroup and added to global memory once per workgroup.
-//
-// Arithmetic that decides the chain (must match any implementation of the
-// same definition bit for bit; compiled without FP contraction):
-//   accept  iff  U * den < num,
-//     num = (cnt[c] + prior) * (ck[s] + beta_bar),
-//     den = (cnt[s] + prior) * (ck[c] + beta_bar)            (Eq. 7)
-//   count part iff U * (L + mass) < L, then the topic of a uniformly chosen
-//   token of the (updated) segment, else a uniform topic       (Eq. 6, Sec. 4.3);
-//   word-phase columns longer than both K and CDF_MIN_LEN take the count
-//   part as the inverse CDF of their updated counts at Dice(r, L) instead
-//   (same law; the long path's tables of Section 5.4)
-//   U(r) = (r >> 8) * 2^-24,  Dice(r, n) = (r * n) >> 32.
-// Random words per (token, iteration, phase): Philox call 0 gives the M
-// acceptance uniforms; call j >= 1 the (coin, index) words of proposals 2j-1
-// and 2j.  The MH pass and the draw pass of the long path each compute only
-// their own calls.
-#include <hip/hip_runtime.h>
-#include <stdint.h>
-
-#include <type_traits>
-
-#include "wlda_device.h"
-#include "wlda_internal.h"
+// gfx950 kernels of the WarpLDA sweep outside the per-M phase kernels:
+// initialisation, c_k recount, the log joint likelihood (Section 6.1), the
+// point estimates of Eq. (4), and the launchers that hand each phase to the
+// translation unit of its M (wlda_kernels_m.hip).
+#include "wlda_kernels_impl.h"
 
 namespace wlda {
-
-// --------------------------------------------------------------------------
-// Packed records
-// --------------------------------------------------------------------------
-// RF = 1 or 2: that many 64-bit words of 21-bit fields; RF = -b: one 32-bit
-// word of b-bit fields.
-template <int RF>
-struct Rec {
-    using W = std::conditional_t<(RF < 0), uint32_t, uint64_t>;
-    W w[RF > 0 ? RF : 1];
-};
-
-template <int RF>
-__device__ __forceinline__ Rec<RF> ld_rec(const uint64_t *recs, uint32_t pos) {
-    Rec<RF> r;
-    if constexpr (RF < 0) {
-        r.w[0] = reinterpret_cast<const uint32_t *>(recs)[pos];
-    } else if constexpr (RF == 1) {
-        r.w[0] = recs[pos];
-    } else {
-        const uint4 v = reinterpret_cast<const uint4 *>(recs)[pos];
-        r.w[0] = ((uint64_t)v.y << 32) | v.x;
-        r.w[1] = ((uint64_t)v.w << 32) | v.z;
-    }
-    return r;
-}
-
-template <int RF>
-__device__ __forceinline__ void st_rec(uint64_t *recs, uint32_t pos, const Rec<RF> &r) {
-    if constexpr (RF < 0) {
-        reinterpret_cast<uint32_t *>(recs)[pos] = r.w[0];
-    } else if constexpr (RF == 1) {
-        recs[pos] = r.w[0];
-    } else {
-        reinterpret_cast<uint4 *>(recs)[pos] =
-            make_uint4((uint32_t)r.w[0], (uint32_t)(r.w[0] >> 32), (uint32_t)r.w[1],
-                       (uint32_t)(r.w[1] >> 32));
-    }
-}
-
-template <int RF>
-__device__ __forceinline__ uint32_t fld(const Rec<RF> &r, int f) {
-    if constexpr (RF < 0) {
-        constexpr uint32_t B = (uint32_t)(-RF);
-        return (r.w[0] >> (B * f)) & ((1u << B) - 1u);
-    } else {
-        return (uint32_t)(r.w[f / 3] >> (FIELD_BITS * (f % 3))) & FIELD_MASK;
-    }
-}
-
-template <int RF>
-__device__ __forceinline__ void set_fld(Rec<RF> &r, int f, uint32_t v) {
-    if constexpr (RF < 0) {
-        constexpr uint32_t B = (uint32_t)(-RF);
-        const uint32_t sh = B * f;
-        r.w[0] = (r.w[0] & ~(((1u << B) - 1u) << sh)) | (v << sh);
-    } else {
-        const int sh = FIELD_BITS * (f % 3);
-        r.w[f / 3] = (r.w[f / 3] & ~((uint64_t)FIELD_MASK << sh)) | ((uint64_t)v << sh);
-    }
-}
-
-// Word w (0..3) of a Philox output.
-__device__ __forceinline__ uint32_t word4(const uint4 &r, int w) {
-    return w == 0 ? r.x : w == 1 ? r.y : w == 2 ? r.z : r.w;
-}
-
-// The random words of a token in a phase: call 0 (step field 0) holds the M
-// acceptance uniforms, word i-1 for step i; call j >= 1 holds the mixture
-// coin and the index/topic word of proposals 2j-1 (words 0, 1) and 2j
-// (words 2, 3).
-
-// --------------------------------------------------------------------------
-// LDS count tables
-// --------------------------------------------------------------------------
-constexpr uint32_t EMPTY_KEY = 0xFFFFFFFFu;
-
-__device__ __forceinline__ void tab_insert(uint32_t *key, uint32_t *cnt, uint32_t mask, bool dense,
-                                           uint32_t k) {
-    if (dense) {
-        atomicAdd(&cnt[k], 1u);
-        return;
-    }
-    uint32_t h = k & mask;
-    while (true) {
-        const uint32_t old = atomicCAS(&key[h], EMPTY_KEY, k);
-        if (old == EMPTY_KEY || old == k) {
-            atomicAdd(&cnt[h], 1u);
-            return;
-        }
-        h = (h + 1) & mask;
-    }
-}
-
-__device__ __forceinline__ uint32_t tab_get(const uint32_t *key, const uint32_t *cnt, uint32_t mask,
-                                            bool dense, uint32_t k) {
-    if (dense) return cnt[k];
-    uint32_t h = k & mask;
-    while (true) {
-        const uint32_t kk = key[h];
-        if (kk == k) return cnt[h];
-        if (kk == EMPTY_KEY) return 0u;
-        h = (h + 1) & mask;
-    }
-}
-
-__device__ __forceinline__ uint32_t pow2_at_least(uint32_t x) {
-    return x <= 1 ? 1u : 1u << (32 - __clz(x - 1));
-}
-
-template <int GROUP>
-__device__ __forceinline__ void group_sync() {
-    if constexpr (GROUP == 64) {
-        // one wavefront: LDS operations of a wavefront complete in order, so
-        // a compiler-level wavefront fence is all that is needed.
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    } else {
-        __syncthreads();
-    }
-}
-
-// Inverse CDF, N lookups at once: each j[d] (< cum[K-1]) is replaced by the
-// smallest topic k with cum[k] > j[d], cum holding inclusive prefix counts
-// over topics 0..K-1.  A branch-free binary search whose trip count depends
-// on K only, so the N loads of each step are in flight together.
-template <int N>
-__device__ __forceinline__ void cdf_find_n(const uint32_t *cum, uint32_t K, uint32_t (&j)[N]) {
-    uint32_t base[N];
-#pragma unroll
-    for (int d = 0; d < N; ++d) base[d] = 0;
-    for (uint32_t n = K; n > 1;) {
-        const uint32_t half = n >> 1;
-#pragma unroll
-        for (int d = 0; d < N; ++d) base[d] = cum[base[d] + half] <= j[d] ? base[d] + half : base[d];
-        n -= half;
-    }
-#pragma unroll
-    for (int d = 0; d < N; ++d) j[d] = base[d] + (cum[base[d]] <= j[d] ? 1u : 0u);
-}
-
-// The same search over prefix counts in LDS, stepping 32-bit LDS pointers:
-// one add, one LDS load, one compare and one select per lookup and step.
-typedef __attribute__((address_space(3))) const uint32_t lds_cu32;
-template <int N>
-__device__ __forceinline__ void cdf_find_lds(const uint32_t *cum_generic, uint32_t K, uint32_t (&j)[N]) {
-    lds_cu32 *cum = (lds_cu32 *)cum_generic;
-    lds_cu32 *b[N];
-#pragma unroll
-    for (int d = 0; d < N; ++d) b[d] = cum;
-    for (uint32_t n = K; n > 1;) {
-        const uint32_t half = n >> 1;
-#pragma unroll
-        for (int d = 0; d < N; ++d) {
-            lds_cu32 *p = b[d] + half;
-            b[d] = *p <= j[d] ? p : b[d];
-        }
-        n -= half;
-    }
-#pragma unroll
-    for (int d = 0; d < N; ++d) j[d] = (uint32_t)(b[d] - cum) + (*b[d] <= j[d] ? 1u : 0u);
-}
-
-__device__ __forceinline__ void add_accepted(unsigned long long *dst, unsigned long long v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-    if ((threadIdx.x & 63) == 0 && v) atomicAdd(dst, v);
-}
-
-// --------------------------------------------------------------------------
-// Segment kernel: GROUP threads (a wavefront or the workgroup) own one segment
-// of at most GROUP*TPT tokens at a time; segments of an XCD's share of the
-// list are taken in ascending order so that the rows visited at the same time
-// are neighbours (their tokens share cache lines of each column, Section 5.2).
-// --------------------------------------------------------------------------
-template <int PHASE, int M, int NW, int GROUP, int TPT>
-__global__ __launch_bounds__(256) void seg_kernel(PhaseArgs a, SegList l, uint32_t cap_max,
-                                                  uint32_t dense_u, uint32_t ck_lds_u) {
-    extern __shared__ uint32_t lds[];
-    constexpr int GPB = 256 / GROUP;
-    // ck_lds_u: bit 0 = the c_k histogram of the new Z in LDS (K <= CK_LDS_MAX),
-    // bit 1 = c_k + beta_bar staged in LDS (K <= CKB_LDS_MAX)
-    const bool dense = dense_u != 0, ckh_lds = (ck_lds_u & 1u) != 0, ckb_lds = (ck_lds_u & 2u) != 0;
-    const uint32_t g = threadIdx.x / GROUP, lane = threadIdx.x % GROUP;
-    const uint32_t K = a.K;
-    // LDS: [c_k + beta_bar as binary32 (ckb_lds)] [c_k histogram of the new
-    // Z (ckh_lds)], then per group [count table | new z of the segment]
-    const uint32_t ck_words = (ckb_lds ? K : 0) + (ckh_lds ? K : 0);
-    const uint32_t tab_words = dense ? K : 2 * cap_max;
-    float *ckb = reinterpret_cast<float *>(lds);
-    uint32_t *ckh = lds + (ckb_lds ? K : 0);
-    uint32_t *gbase = lds + ck_words + g * (tab_words + GROUP * TPT);
-    uint32_t *tkey = gbase;
-    uint32_t *tcnt = dense ? gbase : gbase + cap_max;
-    uint32_t *zarr = gbase + tab_words;
-
-    if (ckh_lds || ckb_lds)
-        for (uint32_t i = threadIdx.x; i < K; i += 256) {
-            if (ckh_lds) ckh[i] = 0;
-            if (ckb_lds) ckb[i] = (float)a.ck[i] + a.beta_bar;
-        }
-    if (dense)
-        for (uint32_t i = lane; i < K; i += GROUP) tcnt[i] = 0;
-    __syncthreads();
-
-    const uint32_t xcd = blockIdx.x & 7, nbx = gridDim.x >> 3, bj = blockIdx.x >> 3;
-    const uint32_t lo = l.xcd_cut[xcd], hi = l.xcd_cut[xcd + 1];
-    const uint32_t ngx = nbx * GPB;
-    const float prior = a.prior, mass = a.mass, beta_bar = a.beta_bar;
-    const uint32_t ph = (uint32_t)PHASE << 16;
-    unsigned long long acc = 0;
-
-    // Segment li's span and records.  All pointers first, then all records,
-    // with no branch around any load (slots past the segment's end re-read its
-    // last token), so each batch is in flight at once.
-    auto fetch = [&](uint32_t lj, uint32_t &fbeg, uint32_t &fL, uint32_t(&fpos)[TPT], Rec<NW>(&frec)[TPT]) {
-        const uint2 sp = l.span[lj];
-        fbeg = sp.x;
-        fL = sp.y - sp.x;
-        if (a.idx) {
-#pragma unroll
-            for (int r = 0; r < TPT; ++r) fpos[r] = a.idx[fbeg + min(r * GROUP + lane, fL - 1)];
-        } else {
-#pragma unroll
-            for (int r = 0; r < TPT; ++r) fpos[r] = fbeg + min(r * GROUP + lane, fL - 1);
-        }
-#pragma unroll
-        for (int r = 0; r < TPT; ++r) frec[r] = ld_rec<NW>(a.recs, fpos[r]);
-    };
-    uint32_t li = lo + bj * GPB + g;
-    uint32_t beg = 0, L = 1;
-    uint32_t pos[TPT];
-    Rec<NW> rec[TPT];
-    if (li < hi) fetch(li, beg, L, pos, rec);
-    for (; li < hi; li += ngx) {
-        uint32_t znew[TPT];
-        if (!a.draw_only) {
-            uint32_t mask = 0;
-            if (!dense) {
-                const uint32_t cap = pow2_at_least(2 * L);
-                mask = cap - 1;
-                for (uint32_t i = lane; i < cap; i += GROUP) {
-                    tkey[i] = EMPTY_KEY;
-                    tcnt[i] = 0;
-                }
-                group_sync<GROUP>();
-            }
-#pragma unroll
-            for (int r = 0; r < TPT; ++r)
-                if (r * GROUP + lane < L) tab_insert(tkey, tcnt, mask, dense, fld(rec[r], 0));
-            group_sync<GROUP>();
-#pragma unroll
-            for (int r = 0; r < TPT; ++r) {
-                if (r * GROUP + lane < L) {
-                    uint32_t s = fld(rec[r], 0);
-                    const uint4 RA = philox(beg + r * GROUP + lane, a.iter, ph, 0, a.seed_lo, a.seed_hi);
-#pragma unroll
-                    for (int i = 1; i <= M; ++i) {
-                        const uint32_t c = fld(rec[r], i);
-                        const uint32_t cc = tab_get(tkey, tcnt, mask, dense, c);
-                        const uint32_t cs = tab_get(tkey, tcnt, mask, dense, s);
-                        const float u = unif24(word4(RA, i - 1));
-                        const bool ok = ckb_lds ? mh_accept_b(u, cc, cs, prior, ckb[s], ckb[c])
-                                               : mh_accept(u, cc, cs, prior, a.ck[s], a.ck[c], beta_bar);
-                        if (ok) {
-                            s = c;
-                            ++acc;
-                        }
-                    }
-                    znew[r] = s;
-                }
-            }
-            group_sync<GROUP>();
-            if (dense) {
-#pragma unroll
-                for (int r = 0; r < TPT; ++r)
-                    if (r * GROUP + lane < L) tcnt[fld(rec[r], 0)] = 0;
-            }
-        } else {
-#pragma unroll
-            for (int r = 0; r < TPT; ++r) znew[r] = fld(rec[r], 0);
-        }
-#pragma unroll
-        for (int r = 0; r < TPT; ++r)
-            if (r * GROUP + lane < L) zarr[r * GROUP + lane] = znew[r];
-        group_sync<GROUP>();
-        // Word phase: the next segment's loads go out before this one's stores
-        // (loads and stores share one in-order counter, so loads issued after
-        // the stores would wait for them).  Measured slower in the doc phase,
-        // whose gathers and scatters compete for the same L2 lines.
-        constexpr bool PREFETCH = PHASE == PH_WORD;
-        uint32_t nbeg = 0, nL = 1;
-        uint32_t npos[TPT];
-        Rec<NW> nrec[TPT];
-        if (PREFETCH && li + ngx < hi) fetch(li + ngx, nbeg, nL, npos, nrec);
-        // Draws, DB tokens at a time: the count part is a token of the updated
-        // segment (random positioning over its new z in LDS).
-        constexpr int DB = TPT < 4 ? TPT : 4;
-#pragma unroll
-        for (int r0 = 0; r0 < TPT; r0 += DB) {
-            uint32_t pw[DB * M];
-#pragma unroll
-            for (int q = 0; q < DB; ++q) {
-                const uint32_t n = (r0 + q) * GROUP + lane;
-#pragma unroll
-                for (int i = 0; i < M; ++i) pw[q * M + i] = 0;
-                if (n < L) {
-#pragma unroll
-                    for (int j = 1; j <= (M + 1) / 2; ++j) {
-                        const uint4 RB = philox(beg + n, a.iter, ph | j, 0, a.seed_lo, a.seed_hi);
-#pragma unroll
-                        for (int h = 0; h < 2; ++h) {
-                            const int i = 2 * j - 1 + h;
-                            if (i > M) continue;
-                            const uint32_t w = word4(RB, 2 * h + 1);
-                            pw[q * M + i - 1] = take_count_part(unif24(word4(RB, 2 * h)), L, mass)
-                                                    ? zarr[dice(w, L)]
-                                                    : dice(w, K);
-                        }
-                    }
-                }
-            }
-#pragma unroll
-            for (int q = 0; q < DB; ++q) {
-                const int r = r0 + q;
-                if (r * GROUP + lane < L) {
-                    Rec<NW> out;
-#pragma unroll
-                    for (int w = 0; w < (NW > 0 ? NW : 1); ++w) out.w[w] = 0;
-                    set_fld(out, 0, znew[r]);
-#pragma unroll
-                    for (int i = 1; i <= M; ++i) set_fld(out, i, pw[q * M + i - 1]);
-                    st_rec<NW>(a.recs, pos[r], out);
-                    if (ckh_lds)
-                        atomicAdd(&ckh[znew[r]], 1u);
-                    else
-                        atomicAdd(&a.ck_next[znew[r]], 1u);
-                }
-            }
-        }
-        group_sync<GROUP>();
-        if constexpr (PREFETCH) {
-            beg = nbeg;
-            L = nL;
-#pragma unroll
-            for (int r = 0; r < TPT; ++r) {
-                pos[r] = npos[r];
-                rec[r] = nrec[r];
-            }
-        } else if (li + ngx < hi) {
-            fetch(li + ngx, beg, L, pos, rec);
-        }
-    }
-    add_accepted(a.accepted, acc);
-    __syncthreads();
-    if (ckh_lds) {
-        for (uint32_t k = threadIdx.x; k < K; k += 256) {
-            const uint32_t v = ckh[k];
-            if (v) atomicAdd(&a.ck_next[k], v);
-        }
-    }
-}
-
-// --------------------------------------------------------------------------
-// Long segments (intra-word parallelism, Section 5.4).  Three passes over the
-// chunks of all long segments:
-//   hist - c_w (or c_d) of each long segment from the phase-start Z, summed
-//          into a global table per segment;
-//   mh   - the table staged in LDS, M MH steps per token, the new z written
-//          to a compact per-segment array only (records are left as they are);
-//   draw - each token's z read back from the compact array in chunk order,
-//          proposals by random positioning over that array (the segment's
-//          updated assignments) or the inverse CDF of its counts, and the
-//          whole record written, c_k accumulated.
-// Each XCD owns whole segments, so a segment's compact array is read from
-// that XCD's L2.
-// --------------------------------------------------------------------------
-// Global per-segment counts (dense or open-addressed, keys stored as topic+1).
-__device__ __forceinline__ void gtab_add(const LongList &l, uint32_t j, uint32_t K, uint32_t k, uint32_t add) {
-    uint32_t *base = l.tables + l.tab_off[j];
-    const uint32_t cap = l.tab_cap[j];
-    if (cap == 0) {
-        atomicAdd(&base[k], add);
-        return;
-    }
-    const uint32_t mask = cap - 1, key = k + 1;
-    uint32_t h = k & mask;
-    while (true) {
-        const uint32_t old = atomicCAS(&base[h], 0u, key);
-        if (old == 0u || old == key) {
-            atomicAdd(&base[cap + h], add);
-            return;
-        }
-        h = (h + 1) & mask;
-    }
-}
-
-__device__ __forceinline__ uint32_t gtab_get(const uint32_t *base, uint32_t cap, uint32_t k) {
-    if (cap == 0) return base[k];
-    const uint32_t mask = cap - 1, key = k + 1;
-    uint32_t h = k & mask;
-    while (true) {
-        const uint32_t kk = base[h];
-        if (kk == key) return base[cap + h];
-        if (kk == 0u) return 0u;
-        h = (h + 1) & mask;
-    }
-}
-
-// Tokens per thread whose loads are issued together in the long kernels.  The
-// histogram and MH passes wait on their gathers and want many in flight; the
-// draw pass is bound by its arithmetic (Philox, the CDF search), and a
-// larger batch only costs it registers.
-constexpr int HIST_BATCH = 16;
-constexpr int MH_BATCH = 16;
-constexpr int DRAW_BATCH = 4;
-
-// Record positions of tokens nb, nb + 256, ... of a segment starting at
-// canonical position beg, clamped to the chunk's last token n1 - 1 so that
-// every load is in bounds and the batch issues without per-token branches.
-template <int B>
-__device__ __forceinline__ void load_positions(const uint32_t *idx, uint32_t beg, uint32_t nb, uint32_t n1,
-                                               uint32_t (&pos)[B]) {
-    if (idx) {
-#pragma unroll
-        for (int u = 0; u < B; ++u) pos[u] = idx[beg + min(nb + u * 256, n1 - 1)];
-    } else {
-#pragma unroll
-        for (int u = 0; u < B; ++u) pos[u] = beg + min(nb + u * 256, n1 - 1);
-    }
-}
-
-#define WLDA_FOR_CHUNKS(l)                                                        \
-    const uint32_t xcd_ = blockIdx.x & 7, nbx_ = gridDim.x >> 3;                 \
-    for (uint32_t ci = (l).chunk_cut[xcd_] + (blockIdx.x >> 3); ci < (l).chunk_cut[xcd_ + 1]; \
-         ci += nbx_)
-
-template <int PHASE, int NW>
-__global__ __launch_bounds__(256) void long_hist_kernel(PhaseArgs a, LongList l, uint32_t lds_dense) {
-    extern __shared__ uint32_t hist[];
-    const uint32_t K = a.K;
-    // LDS: dense K counts, or an open-addressed table of 2 * LONG_CHUNK_HASHED
-    // slots (chunks are LONG_CHUNK_HASHED tokens whenever the table is hashed)
-    constexpr uint32_t HCAP = 2 * Tuning::LONG_CHUNK_HASHED;
-    uint32_t *hkey = hist, *hcnt = hist + HCAP;
-    WLDA_FOR_CHUNKS(l) {
-        const uint32_t j = l.chunk_seg[ci], n0 = l.chunk_start[ci];
-        const uint32_t s_id = l.ids[j];
-        const uint32_t beg = a.segptr[s_id], L = a.segptr[s_id + 1] - beg;
-        const uint32_t n1 = min(L, n0 + l.chunk);
-        if (lds_dense) {
-            for (uint32_t k = threadIdx.x; k < K; k += 256) hist[k] = 0;
-        } else {
-            for (uint32_t k = threadIdx.x; k < HCAP; k += 256) hkey[k] = EMPTY_KEY, hcnt[k] = 0;
-        }
-        __syncthreads();
-        // HIST_BATCH tokens per thread in flight: all loads, then the inserts
-        for (uint32_t nb = n0 + threadIdx.x; nb < n1; nb += 256 * HIST_BATCH) {
-            uint32_t pos[HIST_BATCH], z[HIST_BATCH];
-            load_positions<HIST_BATCH>(a.idx, beg, nb, n1, pos);
-#pragma unroll
-            for (int u = 0; u < HIST_BATCH; ++u) z[u] = fld(ld_rec<NW>(a.recs, pos[u]), 0);
-#pragma unroll
-            for (int u = 0; u < HIST_BATCH; ++u)
-                if (nb + u * 256 < n1) tab_insert(hkey, lds_dense ? hist : hcnt, HCAP - 1, lds_dense != 0, z[u]);
-        }
-        __syncthreads();
-        if (lds_dense) {
-            for (uint32_t k = threadIdx.x; k < K; k += 256) {
-                const uint32_t c = hist[k];
-                if (c) gtab_add(l, j, K, k, c);
-            }
-        } else {
-            for (uint32_t k = threadIdx.x; k < HCAP; k += 256) {
-                const uint32_t c = hcnt[k];
-                if (c) gtab_add(l, j, K, hkey[k], c);
-            }
-        }
-        __syncthreads();
-    }
-}
-
-template <int PHASE, int M, int NW, typename ZT>
-__global__ __launch_bounds__(256) void long_mh_kernel(PhaseArgs a, LongList l, uint32_t lds_tab,
-                                                      uint32_t ck_lds_u) {
-    // LDS: [the segment's count table (lds_tab) | c_k + beta_bar (ck_lds)]
-    extern __shared__ uint32_t tab[];
-    const uint32_t K = a.K;
-    const bool ck_lds = ck_lds_u != 0;
-    float *ckb = reinterpret_cast<float *>(tab + (lds_tab ? K : 0));
-    if (ck_lds) {
-        for (uint32_t k = threadIdx.x; k < K; k += 256) ckb[k] = (float)a.ck[k] + a.beta_bar;
-        __syncthreads();
-    }
-    const uint32_t ph = (uint32_t)PHASE << 16;
-    ZT *zc = reinterpret_cast<ZT *>(l.zc);
-    unsigned long long acc = 0;
-    WLDA_FOR_CHUNKS(l) {
-        const uint32_t j = l.chunk_seg[ci], n0 = l.chunk_start[ci];
-        const uint32_t s_id = l.ids[j];
-        const uint32_t beg = a.segptr[s_id], L = a.segptr[s_id + 1] - beg;
-        const uint32_t n1 = min(L, n0 + l.chunk);
-        const uint32_t zbase = l.prefix[j];
-        const uint32_t *gt = l.tables + l.tab_off[j];
-        const uint32_t gcap = l.tab_cap[j];
-        if (a.draw_only) {     // initial draw: only publish z for random positioning
-            for (uint32_t n = n0 + threadIdx.x; n < n1; n += 256) {
-                const uint32_t pos = a.idx ? a.idx[beg + n] : beg + n;
-                zc[zbase + n] = (ZT)fld(ld_rec<NW>(a.recs, pos), 0);
-            }
-            continue;
-        }
-        if (lds_tab) {
-            for (uint32_t k = threadIdx.x; k < K; k += 256) tab[k] = gt[k];
-            __syncthreads();
-        }
-        // columns past the inverse-CDF threshold also gather the counts of
-        // their updated z for the word proposals' inverse CDF
-        const bool by_cdf = PHASE == PH_WORD && word_cdf(L, K);
-        constexpr int PER_THREAD = Tuning::LONG_CHUNK / 256;
-        uint32_t zk[PER_THREAD];
-#pragma unroll
-        for (int bt = 0; bt < PER_THREAD / MH_BATCH; ++bt) {
-            const uint32_t nb = n0 + threadIdx.x + bt * 256 * MH_BATCH;
-            uint32_t pos[MH_BATCH];
-            Rec<NW> rec[MH_BATCH];
-            load_positions<MH_BATCH>(a.idx, beg, nb, n1, pos);
-#pragma unroll
-            for (int u = 0; u < MH_BATCH; ++u) rec[u] = ld_rec<NW>(a.recs, pos[u]);
-#pragma unroll
-            for (int u = 0; u < MH_BATCH; ++u) {
-                const uint32_t n = nb + u * 256;
-                if (n >= n1) continue;
-                uint32_t s = fld(rec[u], 0);
-                const uint4 RA = philox(beg + n, a.iter, ph, 0, a.seed_lo, a.seed_hi);
-#pragma unroll
-                for (int i = 1; i <= M; ++i) {
-                    const float uacc = unif24(word4(RA, i - 1));
-                    const uint32_t c = fld(rec[u], i);
-                    // separate paths keep LDS reads as ds_read (a pointer
-                    // selected at run time would force flat loads)
-                    uint32_t cc, cs;
-                    if (lds_tab) {
-                        cc = tab[c];
-                        cs = tab[s];
-                    } else {
-                        cc = gtab_get(gt, gcap, c);
-                        cs = gtab_get(gt, gcap, s);
-                    }
-                    const bool ok = ck_lds ? mh_accept_b(uacc, cc, cs, a.prior, ckb[s], ckb[c])
-                                           : mh_accept(uacc, cc, cs, a.prior, a.ck[s], a.ck[c], a.beta_bar);
-                    if (ok) {
-                        s = c;
-                        ++acc;
-                    }
-                }
-                zk[bt * MH_BATCH + u] = s;
-                zc[zbase + n] = (ZT)s;
-            }
-        }
-        if (by_cdf) {
-            uint32_t *nt = l.tables_new + l.tab_off[j];
-            if (lds_tab) {      // chunk histogram in LDS, then one add per topic
-                __syncthreads();
-                for (uint32_t k = threadIdx.x; k < K; k += 256) tab[k] = 0;
-                __syncthreads();
-#pragma unroll
-                for (int q = 0; q < PER_THREAD; ++q)
-                    if (n0 + threadIdx.x + q * 256 < n1) atomicAdd(&tab[zk[q]], 1u);
-                __syncthreads();
-                for (uint32_t k = threadIdx.x; k < K; k += 256) {
-                    const uint32_t c = tab[k];
-                    if (c) atomicAdd(&nt[k], c);
-                }
-            } else {
-#pragma unroll
-                for (int q = 0; q < PER_THREAD; ++q)
-                    if (n0 + threadIdx.x + q * 256 < n1) atomicAdd(&nt[zk[q]], 1u);
-            }
-        }
-        if (lds_tab) __syncthreads();
-    }
-    add_accepted(a.accepted, acc);
-}
-
-// Inclusive prefix sums, in place, of the updated counts of every long word
-// past the inverse-CDF threshold (word_cdf): one workgroup per word, tiles of
-// 4096 topics.
-__global__ __launch_bounds__(256) void long_cdf_kernel(LongList l, const uint32_t *segptr, uint32_t K) {
-    __shared__ uint32_t wsum[4];
-    constexpr int PER = 16;
-    for (uint32_t j = blockIdx.x; j < l.n; j += gridDim.x) {
-        const uint32_t s = l.ids[j];
-        if (!word_cdf(segptr[s + 1] - segptr[s], K)) continue;
-        uint32_t *cnt = l.tables_new + l.tab_off[j];
-        uint32_t carry = 0;
-        for (uint32_t t0 = 0; t0 < K; t0 += 256 * PER) {
-            const uint32_t k0 = t0 + threadIdx.x * PER;
-            uint32_t v[PER], sum = 0;
-#pragma unroll
-            for (int i = 0; i < PER; ++i) {
-                v[i] = k0 + i < K ? cnt[k0 + i] : 0u;
-                sum += v[i];
-            }
-            uint32_t x = sum;
-            const uint32_t wl = threadIdx.x & 63;
-#pragma unroll
-            for (int off = 1; off < 64; off <<= 1) {
-                const uint32_t y = __shfl_up(x, off, 64);
-                if (wl >= (uint32_t)off) x += y;
-            }
-            if (wl == 63) wsum[threadIdx.x >> 6] = x;
-            __syncthreads();
-            uint32_t base = carry;
-            for (uint32_t w = 0; w < (threadIdx.x >> 6); ++w) base += wsum[w];
-            const uint32_t tile = wsum[0] + wsum[1] + wsum[2] + wsum[3];
-            uint32_t run = base + x - sum;
-#pragma unroll
-            for (int i = 0; i < PER; ++i) {
-                run += v[i];
-                if (k0 + i < K) cnt[k0 + i] = run;
-            }
-            carry += tile;
-            __syncthreads();
-        }
-    }
-}
-
-template <int PHASE, int M, int NW, typename ZT>
-__global__ __launch_bounds__(256) void long_draw_kernel(PhaseArgs a, LongList l, uint32_t ck_lds_u,
-                                                        uint32_t zero_tables, uint32_t cdf_lds_u) {
-    // LDS: [c_k histogram of the new Z (ck_lds) | prefix counts of the
-    // current word (cdf_lds, words past the inverse-CDF threshold)]
-    extern __shared__ uint32_t ckh[];
-    const bool ck_lds = ck_lds_u != 0, cdf_lds = cdf_lds_u != 0;
-    const uint32_t K = a.K;
-    uint32_t *cdfl = ckh + (ck_lds ? K : 0);
-    const uint32_t ph = (uint32_t)PHASE << 16;
-    const ZT *zc = reinterpret_cast<const ZT *>(l.zc);
-    if (ck_lds) {
-        for (uint32_t k = threadIdx.x; k < K; k += 256) ckh[k] = 0;
-        __syncthreads();
-    }
-    WLDA_FOR_CHUNKS(l) {
-        const uint32_t j = l.chunk_seg[ci], n0 = l.chunk_start[ci];
-        const uint32_t s_id = l.ids[j];
-        const uint32_t beg = a.segptr[s_id], L = a.segptr[s_id + 1] - beg;
-        const uint32_t n1 = min(L, n0 + l.chunk);
-        const ZT *zs = zc + l.prefix[j];
-        const bool by_cdf = PHASE == PH_WORD && word_cdf(L, K);
-        const uint32_t *cum = l.tables_new + l.tab_off[j];
-        if (by_cdf && cdf_lds) {
-            for (uint32_t k = threadIdx.x; k < K; k += 256) cdfl[k] = cum[k];
-            __syncthreads();
-        }
-        for (uint32_t nb = n0 + threadIdx.x; nb < n1; nb += 256 * DRAW_BATCH) {
-            uint32_t pos[DRAW_BATCH];
-            Rec<NW> rec[DRAW_BATCH];
-            load_positions<DRAW_BATCH>(a.idx, beg, nb, n1, pos);
-            // the record is rebuilt from the updated z alone (compact array,
-            // read in chunk order): nothing of the old record survives
-#pragma unroll
-            for (int u = 0; u < DRAW_BATCH; ++u) {
-#pragma unroll
-                for (int w = 0; w < (NW > 0 ? NW : 1); ++w) rec[u].w[w] = 0;
-                set_fld(rec[u], 0, (uint32_t)zs[min(nb + u * 256, n1 - 1)]);
-            }
-            // all random-positioning reads (or CDF lookups) of the batch are
-            // issued before any record is written back
-            uint32_t jj[DRAW_BATCH * M] = {};
-            uint32_t coin = 0;
-#pragma unroll
-            for (int u = 0; u < DRAW_BATCH; ++u) {
-                const uint32_t n = nb + u * 256;
-                if (n >= n1) continue;
-#pragma unroll
-                for (int j = 1; j <= (M + 1) / 2; ++j) {
-                    const uint4 RB = philox(beg + n, a.iter, ph | j, 0, a.seed_lo, a.seed_hi);
-#pragma unroll
-                    for (int h = 0; h < 2; ++h) {
-                        const int i = 2 * j - 1 + h;
-                        if (i > M) continue;
-                        const uint32_t w = word4(RB, 2 * h + 1);
-                        if (take_count_part(unif24(word4(RB, 2 * h)), L, a.mass)) {
-                            coin |= 1u << (u * M + i - 1);
-                            jj[u * M + i - 1] = dice(w, L);
-                            if (!by_cdf) set_fld(rec[u], i, (uint32_t)zs[jj[u * M + i - 1]]);
-                        } else {
-                            set_fld(rec[u], i, dice(w, K));
-                        }
-                    }
-                }
-            }
-            if (by_cdf) {
-                if (cdf_lds)
-                    cdf_find_lds<DRAW_BATCH * M>(cdfl, K, jj);
-                else
-                    cdf_find_n<DRAW_BATCH * M>(cum, K, jj);
-#pragma unroll
-                for (int d = 0; d < DRAW_BATCH * M; ++d)
-                    if ((coin >> d) & 1u) set_fld(rec[d / M], d % M + 1, jj[d]);
-            }
-#pragma unroll
-            for (int u = 0; u < DRAW_BATCH; ++u) {
-                if (nb + u * 256 >= n1) continue;
-                st_rec<NW>(a.recs, pos[u], rec[u]);
-                const uint32_t z = fld(rec[u], 0);
-                if (ck_lds)
-                    atomicAdd(&ckh[z], 1u);
-                else
-                    atomicAdd(&a.ck_next[z], 1u);
-            }
-        }
-        if (by_cdf && cdf_lds) __syncthreads();
-    }
-    if (zero_tables) {
-        const size_t nt = l.table_words;
-        for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < nt; i += (size_t)gridDim.x * 256)
-            l.tables[i] = 0;
-    }
-    if (ck_lds) {
-        __syncthreads();
-        for (uint32_t k = threadIdx.x; k < K; k += 256) {
-            const uint32_t c = ckh[k];
-            if (c) atomicAdd(&a.ck_next[k], c);
-        }
-    }
-}
 
 // --------------------------------------------------------------------------
 // Small kernels
@@ -796,9 +21,7 @@ __global__ void init_z_kernel(uint64_t *recs, const uint32_t *colidx, uint32_t T
                               uint32_t k1) {
     for (uint32_t t = blockIdx.x * 256 + threadIdx.x; t < T; t += gridDim.x * 256) {
         const uint4 R = philox(t, 0, (uint32_t)PH_INIT << 16, 0, k0, k1);
-        Rec<NW> r;
-#pragma unroll
-        for (int w = 0; w < (NW > 0 ? NW : 1); ++w) r.w[w] = 0;
+        Rec<NW> r = rec_zero<NW>();
         set_fld(r, 0, dice(R.z, K));
         st_rec<NW>(recs, colidx ? colidx[t] : t, r);
     }
@@ -911,6 +134,28 @@ __global__ __launch_bounds__(256) void theta_kernel(const uint64_t *recs, const 
     }
 }
 
+// phi_hat of Eq. (4) (beta' = beta + 1): out[w - w0][k] =
+// (C_wk + beta) / (C_k + V beta) for words w0 .. w0 + nw - 1, one workgroup per
+// word, c_w counted in LDS from the word's column.
+template <int NW>
+__global__ __launch_bounds__(256) void phi_kernel(const uint64_t *recs, const uint32_t *colptr,
+                                                  const uint32_t *colidx, const uint32_t *ck, uint32_t w0,
+                                                  uint32_t nw, uint32_t K, float beta, float beta_bar,
+                                                  float *out) {
+    extern __shared__ uint32_t cnt[];
+    for (uint32_t w = w0 + blockIdx.x; w < w0 + nw; w += gridDim.x) {
+        const uint32_t beg = colptr[w], L = colptr[w + 1] - beg;
+        for (uint32_t k = threadIdx.x; k < K; k += 256) cnt[k] = 0;
+        __syncthreads();
+        for (uint32_t n = threadIdx.x; n < L; n += 256)
+            atomicAdd(&cnt[fld(ld_rec<NW>(recs, colidx ? colidx[beg + n] : beg + n), 0)], 1u);
+        __syncthreads();
+        for (uint32_t k = threadIdx.x; k < K; k += 256)
+            out[(size_t)(w - w0) * K + k] = ((float)cnt[k] + beta) / ((float)ck[k] + beta_bar);
+        __syncthreads();
+    }
+}
+
 __global__ void ll_topics_kernel(const uint32_t *ck, uint32_t K, double beta_bar, double *out) {
     const double lg = lgamma(beta_bar);
     double acc = 0;
@@ -940,6 +185,8 @@ static hipError_t with_rf(int rf, F &&f) {
         case -6: return f(std::integral_constant<int, -6>{});
         case 1: return f(std::integral_constant<int, 1>{});
         case 2: return f(std::integral_constant<int, 2>{});
+        case 102: return f(std::integral_constant<int, 102>{});
+        case 103: return f(std::integral_constant<int, 103>{});
         default: return hipErrorInvalidValue;
     }
 }
@@ -960,159 +207,26 @@ hipError_t launch_init_z(uint64_t *recs, const uint32_t *colidx, uint32_t T, uin
     });
 }
 
-template <typename Kern>
-static hipError_t launch_dyn(Kern k, dim3 grid, size_t lds, hipStream_t st) {
-    (void)k; (void)grid; (void)st;
-    if (lds > 65536) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
+hipError_t launch_segments(const PhaseArgs &a, uint32_t phase, uint32_t M, const SegList &l, int bin,
+                           hipStream_t st) {
+    switch (M) {
+        case 1: return seg_launch<1>(a, phase, l, bin, st);
+        case 2: return seg_launch<2>(a, phase, l, bin, st);
+        case 3: return seg_launch<3>(a, phase, l, bin, st);
+        case 4: return seg_launch<4>(a, phase, l, bin, st);
+        default: return hipErrorInvalidValue;
     }
-    return hipSuccess;
-}
-
-template <int PHASE, int M, int NW, int GROUP, int TPT>
-static hipError_t run_seg(const PhaseArgs &a, const SegList &l, uint32_t cap_bound, hipStream_t st) {
-    if (l.n == 0) return hipSuccess;
-    const bool dense = a.K <= cap_bound;
-    const bool ckh_lds = a.K <= Tuning::CK_LDS_MAX, ckb_lds = a.K <= Tuning::CKB_LDS_MAX;
-    const uint32_t cap_max = dense ? 0 : cap_bound;
-    const uint32_t tab_words = dense ? a.K : 2 * cap_max;
-    constexpr int GPB = 256 / GROUP;
-    const size_t lds = 4ull * ((ckh_lds ? a.K : 0) + (ckb_lds ? a.K : 0) + GPB * (tab_words + GROUP * TPT));
-    auto kern = seg_kernel<PHASE, M, NW, GROUP, TPT>;
-    hipError_t e = launch_dyn(kern, dim3(1), lds, st);
-    if (e != hipSuccess) return e;
-    // Blocks are assigned to XCDs round robin; use a multiple of 8 and
-    // enough groups to keep every CU busy, never more than the list needs.
-    uint32_t blocks = (l.n + GPB - 1) / GPB;
-    const uint32_t cap_blocks = a.max_blocks >= 8 ? a.max_blocks : 8;
-    blocks = blocks < cap_blocks ? blocks : cap_blocks;
-    blocks = (blocks + 7) / 8 * 8;
-    hipLaunchKernelGGL(kern, dim3(blocks), dim3(256), lds, st, a, l, cap_max, (uint32_t)dense,
-                       (uint32_t)ckh_lds | (uint32_t)ckb_lds << 1);
-    return hipGetLastError();
-}
-
-// Calls f(std::integral_constant<int, RF>) with the record format of M topics
-// per proposal set: 32-bit when rf < 0 (and M <= 4), else 64-bit words.
-template <int M, typename F>
-static hipError_t with_rf_m(int rf, F &&f) {
-    if constexpr (M <= 4) {
-        if (rf < 0) return f(std::integral_constant<int, -(int)(32 / (1 + M))>{});
-    }
-    return f(std::integral_constant<int, (M + 3) / 3>{});
-}
-
-// Hash capacity bound of a bin: the power of two >= 2L for its longest segment.
-template <int PHASE, int M>
-static hipError_t wave_dispatch(const PhaseArgs &a, const SegList &l, hipStream_t st) {
-    return with_rf_m<M>(a.rf, [&](auto rfc) -> hipError_t {
-    constexpr int NW = decltype(rfc)::value;
-    return run_seg<PHASE, M, NW, 64, Tuning::TPT_WAVE>(a, l, 2 * Tuning::WAVE_MAX, st);
-    });
-}
-
-template <int PHASE, int M>
-static hipError_t block_dispatch(const PhaseArgs &a, const SegList &l, int bin, hipStream_t st) {
-    return with_rf_m<M>(a.rf, [&](auto rfc) -> hipError_t {
-    constexpr int NW = decltype(rfc)::value;
-    constexpr int TB = M <= 2 ? Tuning::TPT_BLOCK : Tuning::TPT_BLOCK / 2;
-    constexpr int TW = M <= 2 ? Tuning::TPT_WIDE : Tuning::TPT_WIDE / 2;
-    if (bin == BIN_WIDE) return run_seg<PHASE, M, NW, 256, TW>(a, l, 2 * 256 * TW, st);
-    return run_seg<PHASE, M, NW, 256, TB>(a, l, 2 * 256 * TB, st);
-    });
-}
-
-#define WLDA_DISPATCH_M(FN, PHASE, ...)                                 \
-    switch (M) {                                                        \
-        case 1: return FN<PHASE, 1>(__VA_ARGS__);                       \
-        case 2: return FN<PHASE, 2>(__VA_ARGS__);                       \
-        case 3: return FN<PHASE, 3>(__VA_ARGS__);                       \
-        case 4: return FN<PHASE, 4>(__VA_ARGS__);                       \
-        default: return hipErrorInvalidValue;                           \
-    }
-
-hipError_t launch_wave_segments(const PhaseArgs &a, uint32_t phase, uint32_t M, const SegList &l,
-                                hipStream_t st) {
-    if (phase == PH_WORD) {
-        WLDA_DISPATCH_M(wave_dispatch, PH_WORD, a, l, st)
-    }
-    WLDA_DISPATCH_M(wave_dispatch, PH_DOC, a, l, st)
-}
-
-hipError_t launch_block_segments(const PhaseArgs &a, uint32_t phase, uint32_t M, const SegList &l, int bin,
-                                 hipStream_t st) {
-    if (phase == PH_WORD) {
-        WLDA_DISPATCH_M(block_dispatch, PH_WORD, a, l, bin, st)
-    }
-    WLDA_DISPATCH_M(block_dispatch, PH_DOC, a, l, bin, st)
-}
-
-template <int PHASE, int M, typename ZT>
-static hipError_t long_dispatch_z(const PhaseArgs &a, const LongList &l, hipStream_t st,
-                                  hipEvent_t *ev) {
-    return with_rf_m<M>(a.rf, [&](auto rfc) -> hipError_t {
-    constexpr int NW = decltype(rfc)::value;
-    const bool lds_tab = a.K <= Tuning::LDS_DENSE_MAX;
-    const bool ck_lds = a.K <= Tuning::LONG_CK_LDS_MAX;
-    const uint32_t cap_blocks = a.max_blocks >= 8 ? a.max_blocks : 8;
-    uint32_t blocks = l.n_chunks < cap_blocks ? l.n_chunks : cap_blocks;
-    blocks = (blocks + 7) / 8 * 8;
-    hipError_t e;
-    if (ev && (e = hipEventRecord(ev[0], st)) != hipSuccess) return e;
-    if (!a.draw_only) {
-        const size_t lds = lds_tab ? 4ull * a.K : 4ull * 2 * 2 * Tuning::LONG_CHUNK_HASHED;
-        e = launch_dyn(long_hist_kernel<PHASE, NW>, dim3(1), lds, st);
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL((long_hist_kernel<PHASE, NW>), dim3(blocks), dim3(256), lds, st, a, l,
-                           (uint32_t)lds_tab);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-    }
-    if (ev && (e = hipEventRecord(ev[1], st)) != hipSuccess) return e;
-    if (PHASE == PH_WORD && !a.draw_only) {
-        if ((e = launch_fill_u32(l.tables_new, 0, l.table_words, st)) != hipSuccess) return e;
-    }
-    {
-        const bool mh_tab = lds_tab && !a.draw_only, mh_ck = ck_lds && !a.draw_only;
-        const size_t lds = 4ull * ((mh_tab ? a.K : 0) + (mh_ck ? a.K : 0));
-        e = launch_dyn(long_mh_kernel<PHASE, M, NW, ZT>, dim3(1), lds, st);
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL((long_mh_kernel<PHASE, M, NW, ZT>), dim3(blocks), dim3(256), lds, st, a, l,
-                           (uint32_t)mh_tab, (uint32_t)mh_ck);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-    }
-    if (ev && (e = hipEventRecord(ev[2], st)) != hipSuccess) return e;
-    const bool cdf_lds = PHASE == PH_WORD && a.K <= Tuning::CDF_LDS_MAX;
-    if (PHASE == PH_WORD && !a.draw_only) {
-        hipLaunchKernelGGL(long_cdf_kernel, dim3(l.n < 1024 ? l.n : 1024), dim3(256), 0, st, l, a.segptr, a.K);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-    }
-    const size_t lds = 4ull * ((ck_lds ? a.K : 0) + (cdf_lds ? a.K : 0));
-    e = launch_dyn(long_draw_kernel<PHASE, M, NW, ZT>, dim3(1), lds, st);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((long_draw_kernel<PHASE, M, NW, ZT>), dim3(blocks), dim3(256), lds, st, a, l,
-                       (uint32_t)ck_lds, (uint32_t)(a.draw_only ? 0 : 1), (uint32_t)cdf_lds);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    if (ev) return hipEventRecord(ev[3], st);
-    return hipSuccess;
-    });
-}
-
-template <int PHASE, int M>
-static hipError_t long_dispatch(const PhaseArgs &a, const LongList &l, hipStream_t st,
-                                hipEvent_t *ev) {
-    if (l.n == 0) return hipSuccess;
-    if (a.K <= 65535) return long_dispatch_z<PHASE, M, uint16_t>(a, l, st, ev);
-    return long_dispatch_z<PHASE, M, uint32_t>(a, l, st, ev);
 }
 
 hipError_t launch_long_segments(const PhaseArgs &a, uint32_t phase, uint32_t M, const LongList &l,
                                 hipStream_t st, hipEvent_t *ev) {
-    if (phase == PH_WORD) {
-        WLDA_DISPATCH_M(long_dispatch, PH_WORD, a, l, st, ev)
+    switch (M) {
+        case 1: return long_launch<1>(a, phase, l, st, ev);
+        case 2: return long_launch<2>(a, phase, l, st, ev);
+        case 3: return long_launch<3>(a, phase, l, st, ev);
+        case 4: return long_launch<4>(a, phase, l, st, ev);
+        default: return hipErrorInvalidValue;
     }
-    WLDA_DISPATCH_M(long_dispatch, PH_DOC, a, l, st, ev)
 }
 
 hipError_t launch_histogram_z(const uint64_t *recs, uint32_t T, uint32_t M, uint32_t K, uint32_t *ck,
@@ -1133,7 +247,7 @@ hipError_t launch_ll_list(const uint64_t *recs, uint32_t M, const uint32_t *segp
     const int blocks = n < 4096 ? (int)n : 4096;
     return with_rf(record_format(M, K), [&](auto c) {
         constexpr int RF = decltype(c)::value;
-        hipError_t e = launch_dyn(ll_seg_kernel<RF>, dim3(1), lds, st);
+        hipError_t e = launch_dyn(ll_seg_kernel<RF>, lds);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(ll_seg_kernel<RF>, dim3(blocks), dim3(256), lds, st, recs, segptr, idx, ids, n, K,
                            (uint32_t)dense, prior, prior_total, length_term, out);
@@ -1141,34 +255,25 @@ hipError_t launch_ll_list(const uint64_t *recs, uint32_t M, const uint32_t *segp
     });
 }
 
-template <int PHASE, int M>
-static hipError_t ll_long_dispatch(const PhaseArgs &a, const LongList &l, double prior, double prior_total,
-                                   int length_term, double *out, hipStream_t st) {
-    return with_rf_m<M>(a.rf, [&](auto rfc) -> hipError_t {
-    constexpr int NW = decltype(rfc)::value;
-    if (l.n == 0) return hipSuccess;
-    const bool lds_dense = a.K <= Tuning::LDS_DENSE_MAX;
-    uint32_t blocks = l.n_chunks < 2048 ? l.n_chunks : 2048;
-    blocks = (blocks + 7) / 8 * 8;
-    const size_t lds = lds_dense ? 4ull * a.K : 4ull * 2 * 2 * Tuning::LONG_CHUNK_HASHED;
-    hipError_t e = launch_dyn(long_hist_kernel<PHASE, NW>, dim3(1), lds, st);
-    if (e) return e;
-    hipLaunchKernelGGL((long_hist_kernel<PHASE, NW>), dim3(blocks), dim3(256), lds, st, a, l,
-                       (uint32_t)lds_dense);
-    if ((e = hipGetLastError())) return e;
-    hipLaunchKernelGGL(ll_tables_kernel, dim3(l.n < 1024 ? l.n : 1024), dim3(256), 0, st, l, a.segptr, a.K,
-                       prior, prior_total, length_term, out);
-    if ((e = hipGetLastError())) return e;
-    return launch_fill_u32(l.tables, 0, l.table_words, st);
-    });
-}
-
 hipError_t launch_ll_long(const PhaseArgs &a, uint32_t phase, uint32_t M, const LongList &l, double prior,
                           double prior_total, int length_term, double *out, hipStream_t st) {
-    if (phase == PH_WORD) {
-        WLDA_DISPATCH_M(ll_long_dispatch, PH_WORD, a, l, prior, prior_total, length_term, out, st)
+    if (l.n == 0) return hipSuccess;
+    PhaseArgs h = a;
+    h.max_blocks = 2048;
+    h.draw_only = 0;
+    hipError_t e;
+    switch (M) {
+        case 1: e = long_hist_launch<1>(h, phase, l, st); break;
+        case 2: e = long_hist_launch<2>(h, phase, l, st); break;
+        case 3: e = long_hist_launch<3>(h, phase, l, st); break;
+        case 4: e = long_hist_launch<4>(h, phase, l, st); break;
+        default: return hipErrorInvalidValue;
     }
-    WLDA_DISPATCH_M(ll_long_dispatch, PH_DOC, a, l, prior, prior_total, length_term, out, st)
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(ll_tables_kernel, dim3(l.n < 1024 ? l.n : 1024), dim3(256), 0, st, l, a.segptr, a.K, prior,
+                       prior_total, length_term, out);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    return launch_fill_u32(l.tables, 0, l.table_words, st);
 }
 
 hipError_t launch_theta(const uint64_t *recs, uint32_t M, const uint32_t *rowptr, const uint32_t *idx,
@@ -1179,10 +284,27 @@ hipError_t launch_theta(const uint64_t *recs, uint32_t M, const uint32_t *rowptr
     const int blocks = nd < 8192 ? (int)nd : 8192;
     return with_rf(record_format(M, K), [&](auto c) {
         constexpr int RF = decltype(c)::value;
-        hipError_t e = launch_dyn(theta_kernel<RF>, dim3(1), lds, st);
+        hipError_t e = launch_dyn(theta_kernel<RF>, lds);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(theta_kernel<RF>, dim3(blocks), dim3(256), lds, st, recs, rowptr, idx, d0, nd, K,
                            alpha, out);
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_phi(const uint64_t *recs, uint32_t M, const uint32_t *colptr, const uint32_t *colidx,
+                      const uint32_t *ck, uint32_t w0, uint32_t nw, uint32_t K, float beta, float beta_bar,
+                      float *out, hipStream_t st) {
+    if (nw == 0) return hipSuccess;
+    if (K > LL_DENSE_MAX) return hipErrorNotSupported;
+    const size_t lds = 4ull * K;
+    const int blocks = nw < 8192 ? (int)nw : 8192;
+    return with_rf(record_format(M, K), [&](auto c) {
+        constexpr int RF = decltype(c)::value;
+        hipError_t e = launch_dyn(phi_kernel<RF>, lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(phi_kernel<RF>, dim3(blocks), dim3(256), lds, st, recs, colptr, colidx, ck, w0, nw, K,
+                           beta, beta_bar, out);
         return hipGetLastError();
     });
 }

@@ -119,6 +119,7 @@ struct wlda_server_s {
              *d_ah_fidx[2] = {nullptr, nullptr};
     float *d_ah_fval[2] = {nullptr, nullptr};
     hipEvent_t ah_done[2] = {nullptr, nullptr};
+    hipEvent_t ah_copied = nullptr;   // the sweep stream has read the stages it admitted from
     bool ah_live[2] = {false, false};
     int ah_next = 0;
     std::vector<uint32_t> h_ah_rows[2], h_ah_idx[2];
@@ -220,8 +221,9 @@ wlda_status wlda_server_create(wlda_model m, wlda_encoder enc, const wlda_server
         s->buckets = wlda_encoder_get_buckets(enc);
         if (hipEventCreateWithFlags(&s->enc_done, hipEventDisableTiming) ||
             hipEventCreateWithFlags(&s->ah_done[0], hipEventDisableTiming) ||
-            hipEventCreateWithFlags(&s->ah_done[1], hipEventDisableTiming)) {
-            for (hipEvent_t ev : {s->enc_done, s->ah_done[0], s->ah_done[1]})
+            hipEventCreateWithFlags(&s->ah_done[1], hipEventDisableTiming) ||
+            hipEventCreateWithFlags(&s->ah_copied, hipEventDisableTiming)) {
+            for (hipEvent_t ev : {s->enc_done, s->ah_done[0], s->ah_done[1], s->ah_copied})
                 if (ev) (void)hipEventDestroy(ev);
             delete s;
             return WLDA_E_HIP;
@@ -358,6 +360,10 @@ wlda_status wlda_server_step(wlda_server s, uint32_t *n_active, uint32_t *n_pend
             e = hipMemcpyAsync(s->d_qcdf + (size_t)ah.slot * K, s->d_ah_cdf[ah.stage] + (size_t)ah.row * K, 4ull * K,
                                hipMemcpyDeviceToDevice, s->st);
     }
+    // a stage is rewritten below (encode-ahead, encoder stream) only after the
+    // sweep stream has copied out the rows admitted from it
+    const bool ah_read = !ahead.empty();
+    if (!e && ah_read) e = hipEventRecord(s->ah_copied, s->st);
     for (size_t a = 0; a < admitted.size(); ++a) {
         const uint32_t si = fresh[a];
         const Slot &sl = s->slots[si];
@@ -429,6 +435,7 @@ wlda_status wlda_server_step(wlda_server s, uint32_t *n_active, uint32_t *n_pend
         }
         if (!e && !picked.empty()) {
             const uint32_t B = (uint32_t)picked.size();
+            if (ah_read) e = hipStreamWaitEvent(s->enc_st, s->ah_copied, 0);
             up(s->d_ah_frow[x], rows.data(), 4ull * (B + 1), s->enc_st);
             up(s->d_ah_fidx[x], idx.data(), 4ull * idx.size(), s->enc_st);
             up(s->d_ah_fval[x], val.data(), 4ull * val.size(), s->enc_st);
@@ -548,6 +555,7 @@ wlda_status wlda_server_destroy(wlda_server s) {
     if (!s) return WLDA_E_INVALID;
     if (!s->broken) (void)hipStreamSynchronize(s->st);
     if (s->enc_done) (void)hipEventDestroy(s->enc_done);
+    if (s->ah_copied) (void)hipEventDestroy(s->ah_copied);
     for (hipEvent_t ev : s->ah_done)
         if (ev) (void)hipEventDestroy(ev);
     delete s;

@@ -26,6 +26,28 @@ def batch(buckets, K, B, seed, vocab=20000):
     return docs, theta
 
 
+def assert_grads_close(names, g_g, g_o, idx=None, rtol=2e-2, atol_frac=2e-3):
+    """Element by element: |g - g_o| <= atol + rtol |g_o|, atol a fraction of
+    the tensor's largest entry (bf16 operands are rounded at the same points
+    on both sides; fp32 against binary64 accumulation can move a rounding by
+    one bf16 ulp); the relative Frobenius error is kept as a summary.  For W1
+    also the norm of every touched row."""
+    for name, gg, go in zip(names, g_g, g_o):
+        err = np.linalg.norm(gg - go) / max(np.linalg.norm(go), 1e-30)
+        assert err < 5e-3, (name, err)
+        atol = atol_frac * float(np.abs(go).max())
+        excess = np.abs(gg - go) - (atol + rtol * np.abs(go))
+        i = np.unravel_index(int(np.argmax(excess)), go.shape)
+        assert excess[i] <= 0, f"{name}: worst entry {i}: gpu {gg[i]!r}, oracle {go[i]!r}, atol {atol:.3g}"
+    if idx is not None:
+        rows = np.unique(idx)
+        rg = np.linalg.norm(g_g[0][rows], axis=1)
+        ro = np.linalg.norm(g_o[0][rows], axis=1)
+        bad = np.abs(rg - ro) - (1e-2 * ro + 1e-3 * ro.max())
+        j = int(np.argmax(bad))
+        assert bad[j] <= 0, f"W1 row {rows[j]}: norm gpu {rg[j]!r}, oracle {ro[j]!r}"
+
+
 def to_dev(*arrs):
     import torch
     return [torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0") for a in arrs]
@@ -56,9 +78,7 @@ def test_gradients_match_oracle(W, buckets, hidden, K, B):
     assert abs(loss_g - loss_o) <= 1e-4 * abs(loss_o), (loss_g, loss_o)
     q_g = enc.forward(d_rp, d_idx, d_val).cpu().numpy()
     assert np.abs(q_g - q_o).max() <= 1e-4
-    for name, gg, go in zip(W.Encoder.NAMES, g_g, g_o):
-        err = np.linalg.norm(gg - go) / max(np.linalg.norm(go), 1e-30)
-        assert err < 5e-3, (name, err)
+    assert_grads_close(W.Encoder.NAMES, g_g, g_o, idx)
     # sparse first layer: rows no document touches get no gradient
     untouched = np.setdiff1d(np.arange(buckets), idx)
     assert np.all(g_g[0][untouched] == 0)
@@ -81,9 +101,7 @@ def test_gradients_past_transpose_capacity(W):
     _, _, g_o = E.forward_backward(ws, rowptr, idx, val, theta, round=True)
     d_rp, d_idx, d_val, d_th = to_dev(rowptr, idx, val, theta.astype(np.float32))
     _, g_g = enc.gradients(d_rp, d_idx, d_val, d_th)
-    for name, gg, go in zip(W.Encoder.NAMES, g_g, g_o):
-        err = np.linalg.norm(gg - go) / max(np.linalg.norm(go), 1e-30)
-        assert err < 5e-3, (name, err)
+    assert_grads_close(W.Encoder.NAMES, g_g, g_o, idx)
 
 
 def test_training_lowers_loss(W):

@@ -89,10 +89,12 @@ def test_tiny_lda_corpus_50_iterations(W):
 
 
 # record formats: 32-bit with 16-bit fields (M=1, K<=65536), 10-bit (M=2,
-# K<=1024), 8-bit (M=3, K<=256), 6-bit (M=4, K<=64); else 21-bit fields in one
-# or two 64-bit words
+# K<=1024), 8-bit (M=3, K<=256), 6-bit (M=4, K<=64); else, for K <= 65536,
+# 16-bit fields in two (M=2, 3) or three (M=4) 32-bit words; else 21-bit
+# fields in one (M <= 2) or two 64-bit words
 @pytest.mark.parametrize("K,M", [(7, 1), (65536, 1), (1000, 2), (1024, 2), (1025, 2), (256, 3),
-                                 (5000, 3), (64, 4), (20000, 4), (300000, 2), (1000000, 2), (2000, 4)])
+                                 (5000, 3), (64, 4), (20000, 4), (300000, 2), (1000000, 2), (2000, 4),
+                                 (100000, 3), (70000, 4), (65536, 4)])
 def test_all_paths_bit_exact(W, K, M):
     c = mixed_corpus(K + M)
     alpha, beta = 50.0 / K, 0.01
@@ -242,3 +244,68 @@ def test_record_layouts_bit_exact(W, block_kib, K, M, monkeypatch):
         assert_same(s, o, f"doc phase {it + 1}")
     ll_s, ll_o = s.log_likelihood(), o.log_likelihood()
     assert abs(ll_s - ll_o) <= LL_RTOL * abs(ll_o), (ll_s, ll_o)
+
+
+def head_word_corpus(seed, head_len, V=300, D=220):
+    """mixed_corpus plus one word of head_len tokens spread over the
+    documents: a column far longer than one workgroup's share."""
+    c = mixed_corpus(seed, V, D)
+    rng = np.random.default_rng(seed + 1)
+    head = V - 8                       # a word of the Zipf tail
+    docs = rng.integers(0, D - 3, head_len).astype(np.uint32)
+    words = np.concatenate([c.word_ids, np.full(head_len, head, np.uint32)])
+    docs = np.concatenate([c.doc_ids, docs])
+    perm = rng.permutation(len(words))
+    return synth.Corpus(words[perm], docs[perm], V, D)
+
+
+@pytest.mark.parametrize("K,M,head", [(20000, 2, 60000), (40000, 4, 100000), (20000, 1, 70000),
+                                      (300000, 2, 400000)])
+def test_long_column_longer_than_large_K(W, K, M, head):
+    """A column longer than K with K above the LDS limits of the long path
+    (16384): its word proposals take the inverse CDF through prefix counts in
+    global memory, and its updated counts are added with global atomics."""
+    c = head_word_corpus(K + M, head)
+    assert np.bincount(c.word_ids, minlength=c.V).max() > K
+    s, o = make_pair(W, c, K, M, 50.0 / K, 0.01, seed=K + 3 * M)
+    s.init()
+    o.init()
+    assert_same(s, o, "init")
+    for it in range(2):
+        s.word_phase()
+        o.word_phase()
+        assert_same(s, o, f"word phase {it + 1}")
+        assert s.accepted(1) == o.accepted(1)
+        s.doc_phase()
+        o.doc_phase()
+        assert_same(s, o, f"doc phase {it + 1}")
+        assert s.accepted(2) == o.accepted(2)
+    ll_s, ll_o = s.log_likelihood(), o.log_likelihood()
+    assert abs(ll_s - ll_o) <= LL_RTOL * abs(ll_o), (ll_s, ll_o)
+
+
+# K around the lengths of each bin: wave (<= 512 tokens), block (2048, or
+# 1024 for M > 2), wide (4096 or 2048) and the long path; columns of K - 1, K
+# and K + 1 tokens straddle the switch from random positioning to the
+# inverse CDF
+@pytest.mark.parametrize("K,M", [(200, 2), (1500, 2), (3000, 2), (6000, 2), (300, 4), (800, 4),
+                                 (1800, 4), (3000, 4)])
+def test_word_cdf_boundary_in_every_bin(W, K, M):
+    rng = np.random.default_rng(K + M)
+    D = 60
+    lens = [K - 1, K, K + 1]
+    words = [np.full(L, i, np.uint32) for i, L in enumerate(lens)]
+    words.append(rng.integers(3, 40, 4000).astype(np.uint32))     # background words
+    w = np.concatenate(words)
+    d = rng.integers(0, D, len(w)).astype(np.uint32)
+    c = synth.Corpus(w, d, 40, D)
+    s, o = make_pair(W, c, K, M, 0.5, 0.05, seed=17)
+    s.init()
+    o.init()
+    for it in range(2):
+        s.word_phase()
+        o.word_phase()
+        assert_same(s, o, f"word phase {it + 1}")
+        s.doc_phase()
+        o.doc_phase()
+        assert_same(s, o, f"doc phase {it + 1}")

@@ -101,3 +101,35 @@ def test_server_with_encoder_alone_equals_in_mix(W):
             alone.step()
             res = alone.poll()
         assert np.array_equal(alone.take_z(rid, len(words)), got[rid])
+
+
+def test_server_encode_ahead_with_requests_waiting_several_steps(W):
+    """Few slots, a larger encoder batch and many sweeps: requests are encoded
+    ahead into a stage and wait there for several steps while the stages are
+    reused; each result still equals the request's result alone."""
+    K, M, S = 50, 2, 5
+    c, z = trained(K, M)
+    gm = W.Model(c.word_ids, c.doc_ids, z, c.V, c.D, K, M, 50.0 / K, 0.01, seed=7)
+    enc = W.Encoder(2000, 128, K, max_batch=16)
+    enc.set_weights(synth.encoder_init_weights(2000, 128, K, 4))
+    reqs = requests(c.V, 40, 12)
+    mixed = W.Server(gm, enc, max_docs=4, pool_tokens=20000, pool_heldout=1000, sweeps=S)
+    for rid, words, ho in reqs:
+        mixed.submit(rid, words, ho)
+    got, steps = {}, 0
+    while len(got) < len(reqs):
+        active, pending = mixed.step()
+        assert active <= 4
+        steps += 1
+        assert steps < 1000
+        for r in mixed.poll():
+            got[r["req_id"]] = mixed.take_z(r["req_id"], r["n_tokens"])
+    assert steps >= (len(reqs) // 4) * (S + 1)
+    for rid, words, ho in reqs[1::6]:
+        alone = W.Server(gm, enc, max_docs=1, pool_tokens=5000, pool_heldout=100, sweeps=S)
+        alone.submit(rid, words, ho)
+        res = []
+        while not res:
+            alone.step()
+            res = alone.poll()
+        assert np.array_equal(alone.take_z(rid, len(words)), got[rid]), rid
