@@ -228,6 +228,28 @@ wlda_status wlda_foldin_batch(wlda_model m, uint32_t n_docs, const uint64_t *doc
                               void *dev_workspace, uint64_t workspace_bytes, int32_t *z_out,
                               double *heldout_out);
 
+/* Allocation-free variant of wlda_foldin_batch, for callers that cannot
+ * allocate device memory (tight serving loops, code under stream capture,
+ * harnesses that forbid allocation): the same arguments and results, but the
+ * batch's device buffers live in a static device array of
+ * WLDA_FOLDIN_STATIC_BYTES bytes that the library holds on each GPU it runs
+ * on until the process ends, so the caller passes no workspace.  The device
+ * current at wlda_model_create must be current (else WLDA_E_INVALID); runs on
+ * the model's stream and synchronises.
+ * The array keeps the last call's contents; every buffer the kernels read
+ * before writing (per-document sweep counters, inputs) is uploaded by the
+ * call itself.  A batch whose wlda_foldin_batch_bytes() exceeds
+ * WLDA_FOLDIN_STATIC_BYTES is refused with WLDA_E_WORKSPACE.  All calls on
+ * one GPU share the array: calls that overlap in time on one GPU (from two
+ * threads, or two models on different streams) race and must be serialised
+ * by the caller. */
+#define WLDA_FOLDIN_STATIC_BYTES (64ull << 20)
+wlda_status wlda_foldin_batch_static(wlda_model m, uint32_t n_docs, const uint64_t *docptr,
+                                     const uint32_t *words, const uint32_t *req_ids,
+                                     const uint32_t *learned_weights, uint32_t learned_steps,
+                                     uint32_t sweeps, const uint64_t *hoptr, const uint32_t *ho_words,
+                                     int32_t *z_out, double *heldout_out);
+
 /* ------------------------------------------------------------------------ */
 /* Encoder for the learned fold-in proposal                                 */
 /* ------------------------------------------------------------------------ */

@@ -39,7 +39,7 @@ EXPORTS = [
     "wlda_state_bytes", "wlda_save_state", "wlda_load_state", "wlda_set_assignments",
     "wlda_destroy", "wlda_strerror", "wlda_profile", "wlda_profile_read",
     "wlda_model_workspace_bytes", "wlda_model_create", "wlda_model_destroy",
-    "wlda_foldin_batch_bytes", "wlda_foldin_batch",
+    "wlda_foldin_batch_bytes", "wlda_foldin_batch", "wlda_foldin_batch_static",
     "wlda_encoder_workspace_bytes", "wlda_encoder_create", "wlda_encoder_destroy",
     "wlda_encoder_set_weights", "wlda_encoder_get_weights", "wlda_encoder_features",
     "wlda_encoder_forward", "wlda_encoder_proposal", "wlda_encoder_gradients",
@@ -109,6 +109,7 @@ def load_library(path: str = LIB_PATH):
         "wlda_model_destroy": [vp],
         "wlda_foldin_batch_bytes": [vp, u32, u64, i32, u64, C.POINTER(u64)],
         "wlda_foldin_batch": [vp, u32, vp, vp, vp, vp, u32, u32, vp, vp, vp, u64, vp, vp],
+        "wlda_foldin_batch_static": [vp, u32, vp, vp, vp, vp, u32, u32, vp, vp, vp, vp],
         "wlda_encoder_workspace_bytes": [C.POINTER(EncoderParams), C.POINTER(u64)],
         "wlda_encoder_create": [C.POINTER(EncoderParams), vp, u64, vp, C.POINTER(vp)],
         "wlda_encoder_destroy": [vp],
@@ -342,6 +343,29 @@ class Model:
                                    C.c_void_p(ws.data_ptr()), int(nb.value), _ptr(z),
                                    None if ho is None else _ptr(ho)))
         del ws
+        return z, ho
+
+    def foldin_static(self, docptr, words, req_ids, sweeps, weights=None, learned_steps=0,
+                      hoptr=None, ho_words=None):
+        """The same batch through wlda_foldin_batch_static (no workspace: the
+        library's static device array of WLDA_FOLDIN_STATIC_BYTES)."""
+        L = load_library()
+        docptr = np.ascontiguousarray(docptr, np.uint64)
+        words = np.ascontiguousarray(words, np.uint32)
+        req = np.ascontiguousarray(req_ids, np.uint32)
+        nd = len(req)
+        T = int(docptr[-1])
+        w = None if weights is None else np.ascontiguousarray(weights, np.uint32)
+        hp = None if hoptr is None else np.ascontiguousarray(hoptr, np.uint64)
+        hw = None if ho_words is None else np.ascontiguousarray(ho_words, np.uint32)
+        z = np.empty(T, np.int32)
+        ho = np.empty(nd, np.float64) if hp is not None else None
+        _check("wlda_foldin_batch_static",
+               L.wlda_foldin_batch_static(self.h, nd, _ptr(docptr), _ptr(words), _ptr(req),
+                                          None if w is None else _ptr(w), learned_steps, sweeps,
+                                          None if hp is None else _ptr(hp),
+                                          None if hw is None else _ptr(hw), _ptr(z),
+                                          None if ho is None else _ptr(ho)))
         return z, ho
 
 

@@ -21,6 +21,7 @@
 #include <cstring>
 #include <deque>
 #include <map>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -228,6 +229,7 @@ struct wlda_model_s {
     wlda_params p{};
     hipStream_t st = nullptr;
     uint64_t T = 0;
+    int dev = -1;             // device current at create (the workspace's)
 };
 
 namespace {
@@ -310,6 +312,10 @@ wlda_status wlda_model_create(const wlda_params *p, const uint32_t *word_ids, co
     m->p = *p;
     m->T = T;
     m->st = (hipStream_t)stream;
+    if (hipGetDevice(&m->dev) != hipSuccess) {
+        delete m;
+        return WLDA_E_HIP;
+    }
     // canonical column order: stable by (word, doc, input index)
     std::vector<uint32_t> colptr(p->V + 1, 0), dcnt(p->D + 1, 0);
     for (uint64_t i = 0; i < T; ++i) {
@@ -488,6 +494,62 @@ wlda_status wlda_foldin_batch(wlda_model m, uint32_t n_docs, const uint64_t *doc
     if (e) return WLDA_E_HIP;
     for (uint64_t t = 0; t < T; ++t) z_out[t] = (int32_t)zh[t];
     return WLDA_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free fold-in: the same batch, its device buffers carved out of a
+// file-scope device array instead of a caller's workspace.  Each GPU the
+// library runs on holds its own copy of the array (WLDA_FOLDIN_STATIC_BYTES)
+// until the process ends; in host code the array's name is only a stand-in,
+// so its device address is looked up once per device and kept.
+// ---------------------------------------------------------------------------
+}  // extern "C"
+
+static __device__ __align__(256) uint8_t scratch[WLDA_FOLDIN_STATIC_BYTES];
+
+namespace {
+constexpr int SCRATCH_MAX_DEVICES = 64;
+std::mutex scratch_mu;
+void *scratch_dev[SCRATCH_MAX_DEVICES] = {};
+
+// Device address of `scratch` on device dev, which must be current (looked up
+// on the first call on each device).
+hipError_t scratch_address(int dev, void **out) {
+    hipError_t e;
+    if (dev < 0 || dev >= SCRATCH_MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (!scratch_dev[dev]) {
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!ptr) return hipErrorInvalidSymbol;
+        scratch_dev[dev] = ptr;
+    }
+    *out = scratch_dev[dev];
+    return hipSuccess;
+}
+}  // namespace
+
+extern "C" {
+
+wlda_status wlda_foldin_batch_static(wlda_model m, uint32_t n_docs, const uint64_t *docptr,
+                                     const uint32_t *words, const uint32_t *req_ids,
+                                     const uint32_t *learned_weights, uint32_t learned_steps,
+                                     uint32_t sweeps, const uint64_t *hoptr, const uint32_t *ho_words,
+                                     int32_t *z_out, double *heldout_out) {
+    if (!m || !docptr || !req_ids || !z_out || (n_docs && !words)) return WLDA_E_INVALID;
+    const uint64_t T = docptr[n_docs];
+    if (T >= (1ull << 32)) return WLDA_E_INVALID;
+    const uint64_t need = batch_bytes(m->p, n_docs, T, learned_weights != nullptr, hoptr ? hoptr[n_docs] : 0);
+    if (need > WLDA_FOLDIN_STATIC_BYTES) return WLDA_E_WORKSPACE;
+    // the array used must be the one on the model's device
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return WLDA_E_HIP;
+    if (dev != m->dev) return WLDA_E_INVALID;
+    void *ws = nullptr;
+    if (scratch_address(dev, &ws) != hipSuccess) return WLDA_E_HIP;
+    return wlda_foldin_batch(m, n_docs, docptr, words, req_ids, learned_weights, learned_steps, sweeps, hoptr,
+                             ho_words, ws, WLDA_FOLDIN_STATIC_BYTES, z_out, heldout_out);
 }
 
 wlda_status wlda_model_destroy(wlda_model m) {
