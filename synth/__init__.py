@@ -23,6 +23,9 @@ downstream relies on that order.
 from __future__ import annotations
 
 import dataclasses
+import os
+from concurrent.futures import ThreadPoolExecutor
+
 import numpy as np
 
 CORPUS_SEED_BASE = 20151028
@@ -63,12 +66,23 @@ def zipf_corpus(D: int, V: int, s: float, mean_len: float, sigma: float,
     cdf /= cdf[-1]
     rank_to_word = rng.permutation(V).astype(np.uint32)
     word_ids = np.empty(T, dtype=np.uint32)
-    for lo in range(0, T, chunk):
-        hi = min(T, lo + chunk)
-        u = rng.random(hi - lo)
+
+    def fill(lo, u):   # inverse CDF of one chunk (numpy releases the GIL here)
         r = np.searchsorted(cdf, u, side="right")
         np.minimum(r, V - 1, out=r)
-        word_ids[lo:hi] = rank_to_word[r]
+        word_ids[lo:lo + len(u)] = rank_to_word[r]
+
+    # the uniforms are drawn in order from the one generator, so the corpus
+    # does not depend on how many threads convert them
+    workers = max(1, min(16, os.cpu_count() or 1))
+    with ThreadPoolExecutor(workers) as ex:
+        pending = []
+        for lo in range(0, T, chunk):
+            pending.append(ex.submit(fill, lo, rng.random(min(T, lo + chunk) - lo)))
+            if len(pending) >= 2 * workers:
+                pending.pop(0).result()
+        for f in pending:
+            f.result()
     doc_ids = np.repeat(np.arange(D, dtype=np.uint32), lengths)
     return Corpus(word_ids, doc_ids, V, D)
 
