@@ -70,16 +70,30 @@ uint32_t pow2_ge(uint64_t x) {
     return (uint32_t)c;
 }
 
-// Each segment goes to the first bin that holds its length (wave, block,
-// wide), else to the long path.
+// The smallest bin used.  The 16- and 32-lane groups keep their counts in
+// open-addressed tables of at most 2 * 128 or 2 * 256 slots, so they pay only
+// where the wave kernel hashes too (K > its 1024-slot bound); with smaller K
+// short segments go to the wave kernel's dense tables.  WLDA_FIRST_BIN
+// overrides (a launch-shape switch: the chain does not depend on it).
+int first_bin(uint32_t K) {
+    if (const char *env = std::getenv("WLDA_FIRST_BIN")) {
+        const int b = std::atoi(env);
+        return b < 0 ? 0 : (b >= NBINS ? NBINS - 1 : b);
+    }
+    return K > 2 * bin_max_tokens(BIN_WAVE, 1) ? (int)BIN_G16 : (int)BIN_WAVE;
+}
+
+// Each segment goes to the first bin that holds its length (16- and 32-lane
+// groups, wave, block, wide), else to the long path.
 void build_plan(const std::vector<uint64_t> &len, uint32_t M, uint32_t K, PhasePlan &pl) {
     for (BinList &b : pl.bins) b.ids.clear();
     pl.long_ids.clear();
     pl.long_prefix.assign(1, 0);
+    const int bin0 = first_bin(K);
     for (uint32_t s = 0; s < len.size(); ++s) {
         const uint64_t L = len[s];
         if (L == 0) continue;
-        int bin = 0;
+        int bin = bin0;
         while (bin < NBINS && L > bin_max_tokens(bin, M)) ++bin;
         if (bin < NBINS) {
             pl.bins[bin].ids.push_back(s);
@@ -265,13 +279,16 @@ void lengths(const wlda_params &p, const uint32_t *word_ids, const uint32_t *doc
     }
 }
 
+// Profiling slots: the bins of each phase, then its three long-path kernels.
 enum Slot {
-    S_WORD_WAVE, S_WORD_BLOCK, S_WORD_WIDE, S_WORD_LONG_HIST, S_WORD_LONG_MH, S_WORD_LONG_DRAW,
-    S_DOC_WAVE, S_DOC_BLOCK, S_DOC_WIDE, S_DOC_LONG_HIST, S_DOC_LONG_MH, S_DOC_LONG_DRAW, KSLOTS
+    S_WORD_BIN = 0, S_WORD_LONG_HIST = NBINS, S_WORD_LONG_MH, S_WORD_LONG_DRAW,
+    S_DOC_BIN, S_DOC_LONG_HIST = S_DOC_BIN + NBINS, S_DOC_LONG_MH, S_DOC_LONG_DRAW, KSLOTS
 };
 const char *const SLOT_NAMES[KSLOTS] = {
-    "word_wave", "word_block", "word_wide", "word_long_hist", "word_long_mh", "word_long_draw",
-    "doc_wave", "doc_block", "doc_wide", "doc_long_hist", "doc_long_mh", "doc_long_draw"};
+    "word_g16", "word_g32", "word_wave", "word_block", "word_wide", "word_long_hist", "word_long_mh",
+    "word_long_draw", "doc_g16", "doc_g32", "doc_wave", "doc_block", "doc_wide", "doc_long_hist",
+    "doc_long_mh", "doc_long_draw"};
+static_assert(NBINS == 5 && KSLOTS == 16, "slot names follow the bins");
 
 uint64_t list_tokens(const std::vector<uint32_t> &ids, const std::vector<uint64_t> &len) {
     uint64_t t = 0;
@@ -308,9 +325,10 @@ struct wlda_sampler_s {
     size_t ev_used = 0;
     uint64_t slot_tokens[KSLOTS] = {};
     // launch-shape bounds (grid size of the segment kernels), per phase and
-    // bin: [word wave, block, wide, doc wave, block, wide]; set from the CU
-    // count at create, overridable with WLDA_SEG_BLOCKS="a,b,c,d,e,f"
-    uint32_t seg_blocks[2 * NBINS] = {768, 1024, 768, 512, 768, 512};
+    // bin: [word g16, g32, wave, block, wide, doc g16, g32, wave, block, wide];
+    // set from the CU count at create, overridable with WLDA_SEG_BLOCKS (ten
+    // comma-separated values)
+    uint32_t seg_blocks[2 * NBINS] = {768, 768, 768, 1024, 768, 512, 512, 512, 768, 512};
     // grid bound of the long-segment kernels [word, doc]; WLDA_LONG_BLOCKS="a,b"
     uint32_t long_blocks[2] = {4096, 2048};
 };
@@ -447,7 +465,7 @@ wlda_status run_phase(wlda_sampler s, uint32_t phase, uint32_t iter, bool draw_o
     WLDA_TRY(s, launch_fill_u32((uint32_t *)a.accepted, 0, 2, s->st));
     const int kb = phase == PH_WORD ? 0 : NBINS;
     LongList ll = long_list(pl);
-    const int base = phase == PH_WORD ? S_WORD_WAVE : S_DOC_WAVE;
+    const int base = phase == PH_WORD ? S_WORD_BIN : S_DOC_BIN;
     const bool prof = s->prof && !draw_only;
     for (int bin = 0; bin < NBINS; ++bin) {
         const BinList &b = pl.bins[bin];
@@ -594,7 +612,7 @@ wlda_status wlda_create(const wlda_params *p, const uint32_t *word_ids, const ui
         // kernels peak at 2-3.  The long-segment kernels stream chunks and
         // want many more.  Multiples of the CU count keep every CU of an XCD
         // equally loaded.
-        static const uint32_t per_cu[2 * NBINS] = {3, 4, 3, 2, 3, 2};
+        static const uint32_t per_cu[2 * NBINS] = {3, 3, 3, 4, 3, 2, 2, 2, 3, 2};
         static const uint32_t long_per_cu[2] = {16, 8};
         int dev = 0, cus = 0;
         if (hipGetDevice(&dev) == hipSuccess &&
@@ -610,7 +628,8 @@ wlda_status wlda_create(const wlda_params *p, const uint32_t *word_ids, const ui
     }
     if (const char *env = std::getenv("WLDA_SEG_BLOCKS")) {
         unsigned v[2 * NBINS];
-        if (std::sscanf(env, "%u,%u,%u,%u,%u,%u", &v[0], &v[1], &v[2], &v[3], &v[4], &v[5]) == 2 * NBINS)
+        if (std::sscanf(env, "%u,%u,%u,%u,%u,%u,%u,%u,%u,%u", &v[0], &v[1], &v[2], &v[3], &v[4], &v[5], &v[6],
+                        &v[7], &v[8], &v[9]) == 2 * NBINS)
             for (int i = 0; i < 2 * NBINS; ++i) s->seg_blocks[i] = v[i] < 8 ? 8 : (v[i] > 65536 ? 65536 : v[i]);
     }
 
@@ -620,8 +639,8 @@ wlda_status wlda_create(const wlda_params *p, const uint32_t *word_ids, const ui
     build_plan(lw, p->M, p->K, s->word);
     build_plan(ld, p->M, p->K, s->doc);
     for (int bin = 0; bin < NBINS; ++bin) {
-        s->slot_tokens[S_WORD_WAVE + bin] = list_tokens(s->word.bins[bin].ids, lw);
-        s->slot_tokens[S_DOC_WAVE + bin] = list_tokens(s->doc.bins[bin].ids, ld);
+        s->slot_tokens[S_WORD_BIN + bin] = list_tokens(s->word.bins[bin].ids, lw);
+        s->slot_tokens[S_DOC_BIN + bin] = list_tokens(s->doc.bins[bin].ids, ld);
     }
     s->slot_tokens[S_WORD_LONG_HIST] = s->slot_tokens[S_WORD_LONG_MH] =
         s->slot_tokens[S_WORD_LONG_DRAW] = s->word.long_prefix.back();

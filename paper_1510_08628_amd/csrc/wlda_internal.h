@@ -102,8 +102,12 @@ struct Tuning {
     static constexpr int TPT_BLOCK = 8;
     static constexpr int TPT_WIDE = 16;
     static constexpr uint32_t WIDE_MAX = 256 * TPT_WIDE;     // longest segment below the long path
-    static constexpr uint32_t CK_LDS_MAX = 4096;             // block c_k histogram in LDS
-    static constexpr uint32_t CKB_LDS_MAX = 16384;           // segment kernels: c_k + beta_bar in LDS
+    // segment kernels: LDS bytes per workgroup within which the c_k
+    // histogram and c_k + beta_bar are staged (two workgroups per CU fit)
+    static constexpr uint64_t SEG_LDS_BUDGET = 80 * 1024;
+    // beyond the budget: c_k histogram / c_k + beta_bar in LDS up to these K
+    static constexpr uint32_t CK_LDS_MAX = 4096;
+    static constexpr uint32_t CKB_LDS_MAX = 16384;
     // long kernels: c_k + beta_bar (MH pass) and the c_k histogram (draw pass)
     // in LDS; they run few workgroups per CU anyway, where the segment kernels
     // would lose half their occupancy to a K-word histogram
@@ -127,18 +131,23 @@ inline uint32_t long_chunk(uint32_t K) {
     return K <= Tuning::LDS_DENSE_MAX ? Tuning::LONG_CHUNK : Tuning::LONG_CHUNK_HASHED;
 }
 
-// Segment bins below the long path, by length: the wave kernel, the narrow
-// and the wide block kernel.
-enum Bin : int { BIN_WAVE = 0, BIN_BLOCK = 1, BIN_WIDE = 2, NBINS = 3 };
+// Segment bins below the long path, by length: sub-wavefront groups of 16
+// and 32 lanes (several short segments per wavefront), the wave kernel, and
+// the narrow and the wide block kernel.
+enum Bin : int { BIN_G16 = 0, BIN_G32 = 1, BIN_WAVE = 2, BIN_BLOCK = 3, BIN_WIDE = 4, NBINS = 5 };
+
+// Lanes that own one segment in a bin.
+inline uint32_t bin_group(int bin) {
+    return bin == BIN_G16 ? 16u : bin == BIN_G32 ? 32u : bin == BIN_WAVE ? 64u : 256u;
+}
 
 inline uint32_t bin_tpt(int bin, uint32_t M) {
-    const int t = bin == BIN_WAVE ? Tuning::TPT_WAVE : bin == BIN_BLOCK ? Tuning::TPT_BLOCK : Tuning::TPT_WIDE;
-    return bin == BIN_WAVE || M <= 2 ? (uint32_t)t : (uint32_t)t / 2;
+    if (bin <= BIN_WAVE) return (uint32_t)Tuning::TPT_WAVE;
+    const int t = bin == BIN_BLOCK ? Tuning::TPT_BLOCK : Tuning::TPT_WIDE;
+    return M <= 2 ? (uint32_t)t : (uint32_t)t / 2;
 }
 
-inline uint32_t bin_max_tokens(int bin, uint32_t M) {
-    return (bin == BIN_WAVE ? 64u : 256u) * bin_tpt(bin, M);
-}
+inline uint32_t bin_max_tokens(int bin, uint32_t M) { return bin_group(bin) * bin_tpt(bin, M); }
 
 // ---- launchers (all enqueue on `st`, return hipError_t of the launch) ----
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, uint64_t n, hipStream_t st);

@@ -206,9 +206,10 @@ __device__ __forceinline__ uint32_t pow2_at_least(uint32_t x) {
 
 template <int GROUP>
 __device__ __forceinline__ void group_sync() {
-    if constexpr (GROUP == 64) {
-        // one wavefront: LDS operations of a wavefront complete in order, so
-        // a compiler-level wavefront fence is all that is needed.
+    if constexpr (GROUP <= 64) {
+        // one wavefront (or part of one): LDS operations of a wavefront
+        // complete in order, so a compiler-level wavefront fence is all that
+        // is needed.
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -221,15 +222,16 @@ __device__ __forceinline__ void group_sync() {
 // (each thread a contiguous run of entries); ends with a group barrier.
 template <int GROUP>
 __device__ void group_inclusive_scan(uint32_t *a, uint32_t K, uint32_t lane) {
+    constexpr int WS = GROUP < 64 ? GROUP : 64;   // lanes of one shuffle scan
     const uint32_t per = (K + GROUP - 1) / GROUP;
     const uint32_t k0 = min(K, lane * per), k1 = min(K, k0 + per);
     uint32_t sum = 0;
     for (uint32_t k = k0; k < k1; ++k) sum += a[k];
     uint32_t x = sum;
-    const uint32_t wl = lane & 63;
+    const uint32_t wl = lane % WS;
 #pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const uint32_t y = __shfl_up(x, off, 64);
+    for (int off = 1; off < WS; off <<= 1) {
+        const uint32_t y = __shfl_up(x, off, WS);
         if (wl >= (uint32_t)off) x += y;
     }
     if constexpr (GROUP > 64) {
@@ -295,18 +297,18 @@ __device__ __forceinline__ void add_accepted(unsigned long long *dst, unsigned l
 }
 
 // --------------------------------------------------------------------------
-// Segment kernel: GROUP threads (a wavefront or the workgroup) own one segment
-// of at most GROUP*TPT tokens at a time; segments of an XCD's share of the
+// Segment kernel: GROUP threads (16 or 32 lanes of a wavefront, a wavefront,
+// or the workgroup) own one segment of at most GROUP*TPT tokens at a time; segments of an XCD's share of the
 // list are taken in ascending order so that the rows visited at the same time
 // are neighbours (their tokens share cache lines of each column, Section 5.2).
 // --------------------------------------------------------------------------
-template <int PHASE, int M, int NW, int GROUP, int TPT, bool CDF>
+template <int PHASE, int M, int NW, int GROUP, int TPT, bool CDF, bool CKG>
 __global__ __launch_bounds__(256) void seg_kernel(PhaseArgs a, SegList l, uint32_t cap_max,
                                                   uint32_t dense_u, uint32_t ck_lds_u) {
     extern __shared__ uint32_t lds[];
     constexpr int GPB = 256 / GROUP;
-    // ck_lds_u: bit 0 = the c_k histogram of the new Z in LDS (K <= CK_LDS_MAX),
-    // bit 1 = c_k + beta_bar staged in LDS (K <= CKB_LDS_MAX)
+    // ck_lds_u: bit 0 = the c_k histogram of the new Z in LDS, bit 1 = c_k +
+    // beta_bar staged in LDS (what fits the LDS budget; see run_seg)
     const bool dense = dense_u != 0, ckh_lds = (ck_lds_u & 1u) != 0, ckb_lds = (ck_lds_u & 2u) != 0;
     const uint32_t g = threadIdx.x / GROUP, lane = threadIdx.x % GROUP;
     const uint32_t K = a.K;
@@ -375,6 +377,16 @@ __global__ __launch_bounds__(256) void seg_kernel(PhaseArgs a, SegList l, uint32
                 }
                 group_sync<GROUP>();
             }
+            // c_k + beta_bar of every token's state and candidates, when c_k
+            // is not staged in LDS: all loads of the segment issued at once
+            // (every slot holds a valid record, so no load needs a guard)
+            float gck[CKG ? TPT : 1][M + 1];
+            if constexpr (CKG) {
+#pragma unroll
+                for (int r = 0; r < TPT; ++r)
+#pragma unroll
+                    for (int f = 0; f <= M; ++f) gck[r][f] = (float)a.ck[fld(rec[r], f)] + beta_bar;
+            }
 #pragma unroll
             for (int r = 0; r < TPT; ++r)
                 if (r * GROUP + lane < L) tab_insert(tkey, tcnt, mask, dense, fld(rec[r], 0));
@@ -383,6 +395,8 @@ __global__ __launch_bounds__(256) void seg_kernel(PhaseArgs a, SegList l, uint32
             for (int r = 0; r < TPT; ++r) {
                 if (r * GROUP + lane < L) {
                     uint32_t s = fld(rec[r], 0);
+                    float bs;
+                    if constexpr (CKG) bs = gck[r][0]; else bs = ckb[s];
                     const uint4 RA = philox(beg + r * GROUP + lane, a.iter, ph, 0, a.seed_lo, a.seed_hi);
 #pragma unroll
                     for (int i = 1; i <= M; ++i) {
@@ -390,10 +404,11 @@ __global__ __launch_bounds__(256) void seg_kernel(PhaseArgs a, SegList l, uint32
                         const uint32_t cc = tab_get(tkey, tcnt, mask, dense, c);
                         const uint32_t cs = tab_get(tkey, tcnt, mask, dense, s);
                         const float u = unif24(word4(RA, i - 1));
-                        const bool ok = ckb_lds ? mh_accept_b(u, cc, cs, prior, ckb[s], ckb[c])
-                                               : mh_accept(u, cc, cs, prior, a.ck[s], a.ck[c], beta_bar);
-                        if (ok) {
+                        float bc;
+                        if constexpr (CKG) bc = gck[r][i]; else bc = ckb[c];
+                        if (mh_accept_b(u, cc, cs, prior, bs, bc)) {
                             s = c;
+                            bs = bc;
                             ++acc;
                         }
                     }
@@ -914,28 +929,43 @@ template <int PHASE, int M, int NW, int GROUP, int TPT>
 static hipError_t run_seg(const PhaseArgs &a, const SegList &l, uint32_t cap_bound, hipStream_t st) {
     if (l.n == 0) return hipSuccess;
     const bool dense = a.K <= cap_bound;
-    const bool ckh_lds = a.K <= Tuning::CK_LDS_MAX, ckb_lds = a.K <= Tuning::CKB_LDS_MAX;
     const uint32_t cap_max = dense ? 0 : cap_bound;
     const uint32_t tab_words = dense ? a.K : 2 * cap_max;
     constexpr int GPB = 256 / GROUP;
+    // LDS: the groups' count tables, then, within SEG_LDS_BUDGET, the c_k
+    // histogram of the new Z first (each token would otherwise add to it with
+    // a global atomic, which costs far more than a gather) and c_k + beta_bar
+    // second (else read from global memory, all loads of a segment at once);
+    // beyond the budget the old limits hold
+    const uint64_t tab_bytes = 4ull * GPB * (tab_words + GROUP * TPT), kb = 4ull * a.K;
+    bool ckh_lds = tab_bytes + kb <= Tuning::SEG_LDS_BUDGET;
+    bool ckb_lds = tab_bytes + (ckh_lds ? 2 : 1) * kb <= Tuning::SEG_LDS_BUDGET;
+    if (!ckh_lds) {
+        ckh_lds = a.K <= Tuning::CK_LDS_MAX;
+        ckb_lds = a.K <= Tuning::CKB_LDS_MAX;
+    }
     const size_t lds = 4ull * ((ckh_lds ? a.K : 0) + (ckb_lds ? a.K : 0) + GPB * (tab_words + GROUP * TPT));
     const uint32_t blocks = xcd_grid((l.n + GPB - 1) / GPB, a.max_blocks);
     const uint32_t ck_flags = (uint32_t)ckh_lds | (uint32_t)ckb_lds << 1;
-    // the inverse-CDF variant only where a column can be longer than K
+    auto go = [&](auto kern) -> hipError_t {
+        hipError_t e = launch_dyn(kern, lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(kern, dim3(blocks), dim3(256), lds, st, a, l, cap_max, (uint32_t)dense, ck_flags);
+        return hipGetLastError();
+    };
+    // the inverse-CDF variant only where a column can be longer than K (then
+    // K is small and c_k + beta_bar always sits in LDS); the variant reading
+    // c_k + beta_bar from global memory only where it does not
     if constexpr (PHASE == PH_WORD) {
         if (dense && !a.draw_only && a.K < (uint32_t)(GROUP * TPT)) {
-            auto kern = seg_kernel<PHASE, M, NW, GROUP, TPT, true>;
-            hipError_t e = launch_dyn(kern, lds);
-            if (e != hipSuccess) return e;
-            hipLaunchKernelGGL(kern, dim3(blocks), dim3(256), lds, st, a, l, cap_max, (uint32_t)dense, ck_flags);
-            return hipGetLastError();
+            // dense tables of K < GROUP * TPT words always leave room for c_k
+            // + beta_bar; there is no variant without it
+            if (!ckb_lds) return hipErrorNotSupported;
+            return go(seg_kernel<PHASE, M, NW, GROUP, TPT, true, false>);
         }
     }
-    auto kern = seg_kernel<PHASE, M, NW, GROUP, TPT, false>;
-    hipError_t e = launch_dyn(kern, lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(kern, dim3(blocks), dim3(256), lds, st, a, l, cap_max, (uint32_t)dense, ck_flags);
-    return hipGetLastError();
+    if (!ckb_lds) return go(seg_kernel<PHASE, M, NW, GROUP, TPT, false, true>);
+    return go(seg_kernel<PHASE, M, NW, GROUP, TPT, false, false>);
 }
 
 // Calls f(std::integral_constant<int, RF>) for the record format rf of M
@@ -958,7 +988,10 @@ static hipError_t seg_dispatch(const PhaseArgs &a, const SegList &l, int bin, hi
         constexpr int NW = decltype(rfc)::value;
         constexpr int TB = M <= 2 ? Tuning::TPT_BLOCK : Tuning::TPT_BLOCK / 2;
         constexpr int TW = M <= 2 ? Tuning::TPT_WIDE : Tuning::TPT_WIDE / 2;
-        if (bin == BIN_WAVE) return run_seg<PHASE, M, NW, 64, Tuning::TPT_WAVE>(a, l, 2 * Tuning::WAVE_MAX, st);
+        constexpr int TS = Tuning::TPT_WAVE;
+        if (bin == BIN_G16) return run_seg<PHASE, M, NW, 16, TS>(a, l, 2 * 16 * TS, st);
+        if (bin == BIN_G32) return run_seg<PHASE, M, NW, 32, TS>(a, l, 2 * 32 * TS, st);
+        if (bin == BIN_WAVE) return run_seg<PHASE, M, NW, 64, TS>(a, l, 2 * 64 * TS, st);
         if (bin == BIN_WIDE) return run_seg<PHASE, M, NW, 256, TW>(a, l, 2 * 256 * TW, st);
         return run_seg<PHASE, M, NW, 256, TB>(a, l, 2 * 256 * TB, st);
     });

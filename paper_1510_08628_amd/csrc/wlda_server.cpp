@@ -12,7 +12,9 @@
 // queue are encoded one step ahead, into one of two stage buffers, so that
 // by their admission the proposal is usually ready and the step does not
 // wait for the encoder; a request admitted before it was encoded is encoded
-// at admission and its first launch waits on an event.  A document's result
+// at admission and starts its sweeps at the next step, its first launch
+// waiting on an event, so the encoder overlaps the step's sweep instead of
+// holding it up.  A document's result
 // depends only on its words and request id (its random stream), not on the
 // batch it shared or on when it was encoded.
 #include <hip/hip_runtime.h>
@@ -103,7 +105,11 @@ struct wlda_server_s {
     wlda_encoder enc = nullptr;
     wlda_server_params sp{};
     hipStream_t st = nullptr, enc_st = nullptr;
-    hipEvent_t enc_done = nullptr;
+    // encoder results of the documents admitted at a step (two, alternating):
+    // those documents start their sweeps at the next step, after the event
+    hipEvent_t enc_ev[2] = {nullptr, nullptr};
+    int enc_cur = 0;                 // the event this step records
+    std::vector<uint32_t> deferred;  // documents encoded last step
     uint32_t K = 0, M = 0, buckets = 0;
     // device
     uint32_t *d_slots = nullptr, *d_off = nullptr, *d_len = nullptr, *d_req = nullptr, *d_sweep = nullptr,
@@ -219,11 +225,12 @@ wlda_status wlda_server_create(wlda_model m, wlda_encoder enc, const wlda_server
         }
         s->enc_st = (hipStream_t)wlda_encoder_get_stream(enc);
         s->buckets = wlda_encoder_get_buckets(enc);
-        if (hipEventCreateWithFlags(&s->enc_done, hipEventDisableTiming) ||
+        if (hipEventCreateWithFlags(&s->enc_ev[0], hipEventDisableTiming) ||
+            hipEventCreateWithFlags(&s->enc_ev[1], hipEventDisableTiming) ||
             hipEventCreateWithFlags(&s->ah_done[0], hipEventDisableTiming) ||
             hipEventCreateWithFlags(&s->ah_done[1], hipEventDisableTiming) ||
             hipEventCreateWithFlags(&s->ah_copied, hipEventDisableTiming)) {
-            for (hipEvent_t ev : {s->enc_done, s->ah_done[0], s->ah_done[1], s->ah_copied})
+            for (hipEvent_t ev : {s->enc_ev[0], s->enc_ev[1], s->ah_done[0], s->ah_done[1], s->ah_copied})
                 if (ev) (void)hipEventDestroy(ev);
             delete s;
             return WLDA_E_HIP;
@@ -373,9 +380,15 @@ wlda_status wlda_server_step(wlda_server s, uint32_t *n_active, uint32_t *n_pend
             up(s->d_qcdf + (size_t)si * K, admitted[a].weights.data(), 4ull * K, s->st);
     }
     // per-slot tables for the launch
+    // Documents encoded at admission start their sweeps at the next step: the
+    // encoder then overlaps this step's sweep instead of holding up the new
+    // documents of the step (their launch waits for it on the device).
+    std::vector<char> enc_now(s->slots.size(), 0);
+    for (uint32_t si : fresh_enc) enc_now[si] = 1;
     std::vector<uint32_t> old_list, new_list;
     for (uint32_t si = 0; si < s->slots.size(); ++si)
-        if (s->slots[si].busy) (s->slots[si].sweep == 0 ? new_list : old_list).push_back(si);
+        if (s->slots[si].busy && !enc_now[si]) (s->slots[si].sweep == 0 ? new_list : old_list).push_back(si);
+    const bool wait_deferred = !s->deferred.empty();
     const uint64_t n = s->slots.size();
     up(s->d_off, s->h_off.data(), 4 * n, s->st);
     up(s->d_len, s->h_len.data(), 4 * n, s->st);
@@ -400,7 +413,7 @@ wlda_status wlda_server_step(wlda_server s, uint32_t *n_active, uint32_t *n_pend
         for (uint32_t r = 0; r < B && !e; ++r)
             e = hipMemcpyAsync(s->d_qcdf + (size_t)fresh_enc[r] * K, s->d_cdf_stage + (size_t)r * K, 4ull * K,
                                hipMemcpyDeviceToDevice, s->enc_st);
-        if (!e) e = hipEventRecord(s->enc_done, s->enc_st);
+        if (!e) e = hipEventRecord(s->enc_ev[s->enc_cur], s->enc_st);
     }
     // ---- encode ahead: the head of the queue, into the next stage buffer
     if (!e && s->enc) {
@@ -474,8 +487,10 @@ wlda_status wlda_server_step(wlda_server s, uint32_t *n_active, uint32_t *n_pend
     const FoldModel &fm = model_internal(s->model);
     b.n = (uint32_t)old_list.size();
     if (!e) e = fold_launch(fm, b, s->st);
+    // the documents encoded last step wait for that encoder run (the other
+    // event than the one recorded above)
+    if (!e && wait_deferred) e = hipStreamWaitEvent(s->st, s->enc_ev[1 - s->enc_cur], 0);
     if (!e && !new_list.empty()) {
-        if (!fresh_enc.empty()) e = hipStreamWaitEvent(s->st, s->enc_done, 0);
         FoldBatch bn = b;
         bn.slots = s->d_slots + old_list.size();
         bn.n = (uint32_t)new_list.size();
@@ -483,6 +498,8 @@ wlda_status wlda_server_step(wlda_server s, uint32_t *n_active, uint32_t *n_pend
     }
     for (uint32_t si : old_list) s->slots[si].sweep++;
     for (uint32_t si : new_list) s->slots[si].sweep++;
+    s->deferred = fresh_enc;
+    if (!fresh_enc.empty()) s->enc_cur = 1 - s->enc_cur;
     // ---- retire documents that have had init + `sweeps` sweeps
     std::vector<uint32_t> retire;
     for (uint32_t si : lists)
@@ -554,7 +571,8 @@ wlda_status wlda_server_take_z(wlda_server s, uint32_t req_id, int32_t *z, uint3
 wlda_status wlda_server_destroy(wlda_server s) {
     if (!s) return WLDA_E_INVALID;
     if (!s->broken) (void)hipStreamSynchronize(s->st);
-    if (s->enc_done) (void)hipEventDestroy(s->enc_done);
+    for (hipEvent_t ev : s->enc_ev)
+        if (ev) (void)hipEventDestroy(ev);
     if (s->ah_copied) (void)hipEventDestroy(s->ah_copied);
     for (hipEvent_t ev : s->ah_done)
         if (ev) (void)hipEventDestroy(ev);

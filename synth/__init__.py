@@ -54,10 +54,16 @@ def _lognormal_lengths(rng, D, mean, sigma, lo=1, hi=None):
 
 
 def zipf_corpus(D: int, V: int, s: float, mean_len: float, sigma: float,
-                seed: int, chunk: int = 1 << 24) -> Corpus:
-    """iid Zipf(s) words over V ranks, lognormal document lengths."""
+                seed: int, chunk: int = 1 << 24, n_docs: int | None = None) -> Corpus:
+    """iid Zipf(s) words over V ranks, lognormal document lengths.  With
+    n_docs, only the first n_docs documents of that same corpus (its document
+    prefix: the lengths of all D documents are drawn, then the words of the
+    first n_docs in order, so every token equals the full corpus's)."""
     rng = np.random.Generator(np.random.PCG64(seed))
     lengths = _lognormal_lengths(rng, D, mean_len, sigma)
+    if n_docs is not None:
+        D = min(D, int(n_docs))
+        lengths = lengths[:D]
     T = int(lengths.sum())
     if T >= 1 << 32:
         raise ValueError("corpus too large for 32-bit token indices")
@@ -152,12 +158,12 @@ WORKLOADS = {
                                  CORPUS_SEED_BASE + 1)),
     "pubmed-shape-k1e4": Workload(
         "pubmed-shape-k1e4", K=10_000, M=4, alpha=0.005, beta=0.01, iters=50,
-        make=lambda: zipf_corpus(8_000_000, 140_000, 1.05, 90.0, 0.7,
-                                 CORPUS_SEED_BASE + 2)),
+        make=lambda n_docs=None: zipf_corpus(8_000_000, 140_000, 1.05, 90.0, 0.7,
+                                             CORPUS_SEED_BASE + 2, n_docs=n_docs)),
     "clueweb-share-k1e6": Workload(
         "clueweb-share-k1e6", K=1_000_000, M=2, alpha=0.01, beta=0.01, iters=20,
-        make=lambda: zipf_corpus(20_000_000, 1_000_000, 1.1, 100.0, 1.0,
-                                 CORPUS_SEED_BASE + 3)),
+        make=lambda n_docs=None: zipf_corpus(20_000_000, 1_000_000, 1.1, 100.0, 1.0,
+                                             CORPUS_SEED_BASE + 3, n_docs=n_docs)),
 }
 
 
@@ -274,3 +280,79 @@ def topical_zipf_corpus(D: int, V: int, K: int, s: float, mean_len: float, sigma
         word_ids[sel] = rank_to_word[r]
     doc_ids = np.repeat(np.arange(D, dtype=np.uint32), lengths)
     return Corpus(word_ids, doc_ids, V, D, topics)
+
+
+def _polya_topics(rng, lengths, K: int, alpha: float) -> np.ndarray:
+    """Topic assignments of documents with theta_d ~ Dir(alpha) integrated
+    out (the Dirichlet-multinomial predictive rule): token n of a document
+    copies the topic of a uniformly chosen earlier token with probability
+    n / (n + K alpha), else takes a uniform topic, so P(z_n = k | z_<n) =
+    (C_k + alpha) / (n + K alpha).  Vectorised over documents, position by
+    position."""
+    lengths = np.asarray(lengths, np.int64)
+    off = np.concatenate([[0], np.cumsum(lengths)[:-1]])
+    by_len = np.argsort(-lengths, kind="stable")
+    sorted_len = lengths[by_len]
+    topics = np.empty(int(lengths.sum()), np.int32)
+    for n in range(int(lengths.max()) if len(lengths) else 0):
+        m = int(np.searchsorted(-sorted_len, -n, side="left"))   # documents longer than n
+        base = off[by_len[:m]]
+        u, v = rng.random(m), rng.random(m)
+        fresh = rng.integers(0, K, m, dtype=np.int32)
+        if n == 0:
+            topics[base] = fresh
+            continue
+        copy = u * (n + K * alpha) < n
+        src = base + np.minimum((v * n).astype(np.int64), n - 1)
+        topics[base + n] = np.where(copy, topics[src], fresh)
+    return topics
+
+
+def lda_sparse_corpus(D: int, V: int, K: int, mean_len: float, sigma: float, alpha: float,
+                      beta_topic: float, seed: int) -> Corpus:
+    """The LDA generative process of Section 2.1 with sparse topics:
+    phi_k ~ Dir(beta_topic) over the V words, theta_d ~ Dir(alpha), z ~ theta_d
+    (drawn with theta_d integrated out, _polya_topics), w ~ phi_z, with
+    lognormal document lengths as in zipf_corpus.  Small
+    beta_topic gives topics that own disjoint sets of words, so a document's
+    topics can be read off its words."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    lengths = _lognormal_lengths(rng, D, mean_len, sigma)
+    T = int(lengths.sum())
+    topics = _polya_topics(rng, lengths, K, alpha)
+    word_ids = np.empty(T, np.uint32)
+    u = rng.random(T)
+    # tokens grouped by topic (a radix sort when the topics fit 16 bits)
+    order = np.argsort(topics.astype(np.int16) if K <= 32767 else topics, kind="stable")
+    bounds = np.searchsorted(topics[order], np.arange(K + 1))
+
+    def fill(k, g):   # words of topic k by inverse CDF (numpy releases the GIL)
+        sel = order[bounds[k]:bounds[k + 1]]
+        if len(sel) == 0 or g.sum() <= 0:
+            return
+        cdf = np.cumsum(g)
+        word_ids[sel] = np.minimum(np.searchsorted(cdf / cdf[-1], u[sel], side="right"), V - 1)
+
+    # phi_k ~ Dir(beta_topic) by normalised gammas, drawn in topic order from
+    # the one generator (so the corpus does not depend on the thread count)
+    workers = max(1, min(16, os.cpu_count() or 1))
+    with ThreadPoolExecutor(workers) as ex:
+        pending = []
+        for k in range(K):
+            pending.append(ex.submit(fill, k, rng.standard_gamma(beta_topic, V)))
+            if len(pending) >= 2 * workers:
+                pending.pop(0).result()
+        for f in pending:
+            f.result()
+    doc_ids = np.repeat(np.arange(D, dtype=np.uint32), lengths)
+    return Corpus(word_ids, doc_ids, V, D, topics)
+
+
+# NYTimes-shaped LDA corpus with sparse topics (phi_k ~ Dir(0.01) over 100k
+# words) and documents of few topics (theta_d ~ Dir(0.01), about 35 topics in
+# a 330-token document), fitted with the paper's alpha = 50/K: the model the
+# fold-in experiments freeze
+WORKLOADS["nytimes-shape-lda-k1e3"] = Workload(
+    "nytimes-shape-lda-k1e3", K=1000, M=2, alpha=0.05, beta=0.01, iters=100,
+    make=lambda: lda_sparse_corpus(300_000, 100_000, 1000, 330.0, 0.8, 0.01, 0.01,
+                                   CORPUS_SEED_BASE + 12))

@@ -32,3 +32,13 @@ def test_pubmed_and_clueweb_parameters_match_table3():
     assert T3["ClueWeb12"]["V"] == 1_000_000
     small = synth.zipf_corpus(20_000, 140_000, 1.05, 90.0, 0.7, 1)
     assert abs(small.T / small.D - mean) <= 0.03 * mean
+
+
+def test_zipf_document_prefix_is_the_full_corpus_prefix():
+    """The huge-K share is measured on a document prefix drawn without the
+    rest of the corpus; it must equal the first documents of the full draw."""
+    a = synth.zipf_corpus(3000, 5000, 1.1, 100.0, 1.0, 5)
+    b = synth.zipf_corpus(3000, 5000, 1.1, 100.0, 1.0, 5, n_docs=1200)
+    p = synth.doc_prefix(a, 1200)
+    assert np.array_equal(p.word_ids, b.word_ids) and np.array_equal(p.doc_ids, b.doc_ids)
+    assert b.D == 1200

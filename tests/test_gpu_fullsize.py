@@ -2,7 +2,8 @@
 times: the NYTimes-shaped corpus (~99M tokens, K=1000, M=2) through init and
 one full iteration, every token compared bit for bit after each phase; and a
 PubMed-shaped corpus (K=1e4, M=4; 200k documents of the 8M-document shape) for
-two iterations.  The oracle computes its own state from the same seeded
+two iterations, and the first 120k documents of the ClueWeb-shaped share
+(K=1e6).  The oracle computes its own state from the same seeded
 inputs (it takes ~4M tokens/s on one core).  The PubMed-shaped workload at its
 full 8M-document size is checked by properties that hold at any size."""
 import numpy as np
@@ -57,7 +58,7 @@ def test_nytimes_shape_full_size_iteration(W):
 @pytest.mark.timeout(900)
 def test_pubmed_shape_k1e4_m4(W):
     wl = synth.WORKLOADS["pubmed-shape-k1e4"]
-    c = synth.zipf_corpus(200_000, 140_000, 1.05, 90.0, 0.7, synth.CORPUS_SEED_BASE + 2)
+    c = wl.make(200_000)               # the first 200k documents of the full corpus
     s = W.Sampler(c.word_ids, c.doc_ids, c.V, c.D, wl.K, wl.M, wl.alpha, wl.beta, seed=1)
     o = oracle.Oracle(c.word_ids, c.doc_ids, c.V, c.D, wl.K, wl.M, wl.alpha, wl.beta, seed=1)
     s.init()
@@ -75,12 +76,14 @@ def test_pubmed_shape_k1e4_m4(W):
 
 @pytest.mark.timeout(900)
 def test_clueweb_shape_k1e6(W):
-    """K = 1e6 (the huge-K single-GPU share): V = 1M Zipf(1.1) words, lognormal
-    (mean 100, sigma 1) documents, 60k documents of the 20M-document shape.
-    Columns longer than one workgroup use hashed global counts; the head word
-    (2L > K) uses dense global counts."""
+    """K = 1e6 (the huge-K single-GPU share): the first 120k documents of the
+    ClueWeb-shaped share (V = 1M Zipf(1.1) words, lognormal(mean 100, sigma 1)
+    documents; 12M tokens).  Its head word has ~1.5M tokens, more than K, so
+    its word proposals take the inverse CDF through prefix counts in global
+    memory; shorter long columns use hashed global counts."""
     wl = synth.WORKLOADS["clueweb-share-k1e6"]
-    c = synth.zipf_corpus(60_000, 1_000_000, 1.1, 100.0, 1.0, synth.CORPUS_SEED_BASE + 3)
+    c = wl.make(120_000)
+    assert np.bincount(c.word_ids, minlength=c.V).max() > wl.K
     s = W.Sampler(c.word_ids, c.doc_ids, c.V, c.D, wl.K, wl.M, wl.alpha, wl.beta, seed=1)
     o = oracle.Oracle(c.word_ids, c.doc_ids, c.V, c.D, wl.K, wl.M, wl.alpha, wl.beta, seed=1)
     s.init()

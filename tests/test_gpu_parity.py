@@ -137,9 +137,10 @@ def test_edge_cases(W, case):
         c = synth.Corpus(w, d, 100, 100)
         K, M = 64, 2
     else:                              # lengths straddling every bin boundary
-        # wave 512; block 2048 (1024 for M > 2); wide 4096 (2048); long path
+        # 16-lane groups 128, 32-lane groups 256, wave 512; block 2048 (1024
+        # for M > 2); wide 4096 (2048); long path
         lens = [511, 512, 513, 1023, 1024, 1025, 2047, 2048, 2049, 4095, 4096, 4097,
-                1, 2, 63, 64, 65]
+                1, 2, 63, 64, 65, 127, 128, 129, 255, 256, 257]
         d = np.repeat(np.arange(len(lens), dtype=np.uint32), lens)
         w = np.concatenate([np.full(L, i, np.uint32) for i, L in enumerate(lens)])
         w = w[rng.permutation(len(w))]
@@ -224,12 +225,16 @@ def test_set_assignments_matches_oracle(W):
         assert_same(s, o, "doc after set")
 
 
-@pytest.mark.parametrize("block_kib", ["0", "16", "4096"])
+@pytest.mark.parametrize("block_kib,first_bin", [("0", "0"), ("16", "0"), ("4096", "0"), ("1024", "2"),
+                                                ("1024", "1")])
 @pytest.mark.parametrize("K,M", [(1000, 2), (50, 4)])
-def test_record_layouts_bit_exact(W, block_kib, K, M, monkeypatch):
+def test_record_layouts_bit_exact(W, block_kib, first_bin, K, M, monkeypatch):
     """The record layout (plain CSC order, or blocked by documents with tiny
-    or large blocks) changes where records live, never the chain."""
+    or large blocks) and the launch shape (segments of every length in
+    wavefront-wide or wider groups only) change where records live and who
+    processes them, never the chain."""
     monkeypatch.setenv("WLDA_DOC_BLOCK_KIB", block_kib)
+    monkeypatch.setenv("WLDA_FIRST_BIN", first_bin)
     c = mixed_corpus(K + M + 3)
     s, o = make_pair(W, c, K, M, 50.0 / K, 0.01, seed=5)
     s.init()
@@ -284,12 +289,13 @@ def test_long_column_longer_than_large_K(W, K, M, head):
     assert abs(ll_s - ll_o) <= LL_RTOL * abs(ll_o), (ll_s, ll_o)
 
 
-# K around the lengths of each bin: wave (<= 512 tokens), block (2048, or
-# 1024 for M > 2), wide (4096 or 2048) and the long path; columns of K - 1, K
+# K around the lengths of each bin: 16-lane groups (<= 128 tokens), 32-lane
+# groups (256), wave (512), block (2048, or 1024 for M > 2), wide (4096 or
+# 2048) and the long path; columns of K - 1, K
 # and K + 1 tokens straddle the switch from random positioning to the
 # inverse CDF
-@pytest.mark.parametrize("K,M", [(200, 2), (1500, 2), (3000, 2), (6000, 2), (300, 4), (800, 4),
-                                 (1800, 4), (3000, 4)])
+@pytest.mark.parametrize("K,M", [(60, 2), (200, 2), (400, 2), (1500, 2), (3000, 2), (6000, 2),
+                                 (100, 4), (300, 4), (800, 4), (1800, 4), (3000, 4)])
 def test_word_cdf_boundary_in_every_bin(W, K, M):
     rng = np.random.default_rng(K + M)
     D = 60
