@@ -195,7 +195,7 @@ def measure(W, c, wl, M, steps, warmup, dev, tag):
 # --------------------------------------------------------------------------
 # Learned proposal + serving (fold-in of new documents against the fit)
 # --------------------------------------------------------------------------
-SWEEP_GRID = [1, 2, 3, 4, 5, 6, 8, 10, 12, 16, 24, 32, 48, 64, 96, 128, 200]
+SWEEP_GRID = [1, 2, 3, 4, 5, 6, 8, 10, 12, 14, 16, 20, 24, 28, 32, 36, 40, 48, 56, 64, 80, 96, 128, 160, 200]
 
 
 def corpus_features(W, c, buckets, dev):
@@ -211,14 +211,20 @@ def corpus_features(W, c, buckets, dev):
 
 
 def train_encoder(W, s, c, wl, dev, epochs, batch, hidden=512, buckets=100_000, lr=2e-3,
-                  w1_std=1.0, n_val=8192):
-    """Adam on the sampler's own (document, theta_hat_d) pairs; the last n_val
-    documents are held out to report the KL gap to their targets."""
+                  w1_std=1.0, n_val=8192, avg_iters=20):
+    """Adam on the sampler's own (document, theta_hat_d) pairs, theta_hat_d
+    averaged over the sampler's next avg_iters iterations (one state of the
+    chain is a noisy target); the last n_val documents are held out to report
+    the KL gap to their targets."""
     import torch
     import synth
     t0 = time.perf_counter()
     d_rp, d_idx, d_val = corpus_features(W, c, buckets, dev)
-    theta = s.theta(0, c.D)
+    theta = torch.zeros((c.D, wl.K), dtype=torch.float32, device=dev)
+    for _ in range(avg_iters):
+        s.iterate(1)
+        theta += s.theta(0, c.D)
+    theta /= avg_iters
     enc = W.Encoder(buckets, hidden, wl.K, max_batch=batch, lr=lr, device=dev)
     enc.set_weights(synth.encoder_init_weights(buckets, hidden, wl.K, 11, w1_std))
     n_train = c.D - n_val
@@ -250,7 +256,7 @@ def train_encoder(W, s, c, wl, dev, epochs, batch, hidden=512, buckets=100_000, 
         f"loss {v0:.4f} -> {v1:.4f}, target entropy {ent:.4f}: KL {v0 - ent:.4f} -> {v1 - ent:.4f}")
     del theta, d_rp, d_idx, d_val
     return enc, dict(steps=steps, train_s=t_train, epochs=epochs, batch=batch, hidden=hidden,
-                     buckets=buckets, lr=lr, heldout_docs=n_val, heldout_loss_first=v0,
+                     buckets=buckets, lr=lr, target_average_iterations=avg_iters, heldout_docs=n_val, heldout_loss_first=v0,
                      heldout_loss_last=v1, target_entropy=ent, heldout_kl_first=v0 - ent,
                      heldout_kl_last=v1 - ent, kl_gap_closed=1.0 - (v1 - ent) / (v0 - ent),
                      heldout_loss_by_epoch=curve)
@@ -356,7 +362,7 @@ def serving_experiment(W, dev, args, workload="nytimes-shape-lda-k1e3"):
     rq = synth.docs_from_model(c.word_ids, z, c.V, wl.K, 0.01, wl.beta, args.serve_requests, 32)
     del z
     req = np.arange(args.serve_eval, dtype=np.uint32)
-    ls = 2
+    ls = args.learned_steps
     c_plain = foldin_curve(gm, ev[0], ev[1], req, ev[2], ev[3])
     ref = c_plain[200]
     w_ev = encoder_weights(W, enc, ev[0], ev[1], dev)
@@ -425,7 +431,9 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=2000.0)
     ap.add_argument("--fit-iters", type=int, default=1000,
                     help="iterations of the fit that the fold-in model is frozen from")
-    ap.add_argument("--enc-epochs", type=int, default=12)
+    ap.add_argument("--enc-epochs", type=int, default=8)
+    ap.add_argument("--learned-steps", type=int, default=1,
+                    help="MH steps per token and sweep with the learned proposal")
     ap.add_argument("--enc-batch", type=int, default=512)
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="first run a plain device copy of this many MiB (counter calibration)")

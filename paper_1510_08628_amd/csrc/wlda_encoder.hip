@@ -91,25 +91,61 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(int M, int N, int Kd, co
 __global__ __launch_bounds__(256) void embag_fwd_kernel(int H, const uint32_t *rowptr, const uint32_t *idx,
                                                         const float *val, const uint16_t *W1b,
                                                         const float *b1, float *a1, uint16_t *h1b) {
-    constexpr int U = 8;
+    // The document's nonzeros are split into four contiguous quarters, one
+    // per wavefront; for each block of 64 * JPL hidden units every lane
+    // accumulates JPL of them (lane, lane + 64, ...) over R rows at a time, so
+    // R * JPL row loads are in flight; the four partial sums are then added
+    // in a fixed order.
+    constexpr int JPL = 8, R = 4, JB = 64 * JPL;
+    __shared__ float part[4][JB];
     const int b = blockIdx.x;
     const uint32_t n0 = rowptr[b], n1 = rowptr[b + 1];
-    for (int j = threadIdx.x; j < H; j += 256) {
-        float acc[U];
+    const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const uint32_t q = (n1 - n0 + 3) / 4;
+    const uint32_t r0 = min(n1, n0 + wave * q), r1 = min(n1, r0 + q);
+    for (int jb = 0; jb < H; jb += JB) {
+        float acc[JPL];
 #pragma unroll
-        for (int u = 0; u < U; ++u) acc[u] = 0.f;
-        uint32_t n = n0;
-        for (; n + U <= n1; n += U) {
-            float w[U];
+        for (int u = 0; u < JPL; ++u) acc[u] = 0.f;
+        // hidden units past H read unit H - 1 (in bounds, never stored), so
+        // every load of a batch is issued without a branch
+        int jc[JPL];
 #pragma unroll
-            for (int u = 0; u < U; ++u) w[u] = from_bf16(W1b[(size_t)idx[n + u] * H + j]);
+        for (int u = 0; u < JPL; ++u) jc[u] = min(jb + (int)lane + 64 * u, H - 1);
+        uint32_t n = r0;
+        for (; n + R <= r1; n += R) {
+            uint32_t row[R];
+            float v[R], w[R][JPL];
 #pragma unroll
-            for (int u = 0; u < U; ++u) acc[u] += val[n + u] * w[u];
+            for (int r = 0; r < R; ++r) {
+                row[r] = idx[n + r];
+                v[r] = val[n + r];
+            }
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+#pragma unroll
+                for (int u = 0; u < JPL; ++u) w[r][u] = from_bf16(W1b[(size_t)row[r] * H + jc[u]]);
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+#pragma unroll
+                for (int u = 0; u < JPL; ++u) acc[u] += v[r] * w[r][u];
         }
-        for (int u = 0; n < n1; ++n, ++u) acc[u] += val[n] * from_bf16(W1b[(size_t)idx[n] * H + j]);
-        const float sum = b1[j] + (((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7])));
-        a1[(size_t)b * H + j] = sum;
-        h1b[(size_t)b * H + j] = to_bf16(sum > 0.f ? sum : 0.f);
+        for (; n < r1; ++n) {
+            const uint32_t row = idx[n];
+            const float v = val[n];
+#pragma unroll
+            for (int u = 0; u < JPL; ++u) acc[u] += v * from_bf16(W1b[(size_t)row * H + jc[u]]);
+        }
+#pragma unroll
+        for (int u = 0; u < JPL; ++u) part[wave][lane + 64 * u] = acc[u];
+        __syncthreads();
+        for (int jj = threadIdx.x; jj < JB && jb + jj < H; jj += 256) {
+            const int j = jb + jj;
+            const float sum = b1[j] + ((part[0][jj] + part[1][jj]) + (part[2][jj] + part[3][jj]));
+            a1[(size_t)b * H + j] = sum;
+            h1b[(size_t)b * H + j] = to_bf16(sum > 0.f ? sum : 0.f);
+        }
+        __syncthreads();
     }
 }
 

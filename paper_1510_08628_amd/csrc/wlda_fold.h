@@ -46,8 +46,13 @@ uint32_t wlda_encoder_get_buckets(wlda_encoder e);
 uint32_t wlda_encoder_get_max_batch(wlda_encoder e);
 void *wlda_encoder_get_stream(wlda_encoder e);
 hipError_t fold_launch(const FoldModel &m, const FoldBatch &b, hipStream_t st);
+// Held-out log likelihood of the documents of b: hchunk (b.n + 1 entries)
+// holds the prefix sums of heldout_chunks(ho_len) over the listed documents,
+// n_chunks its last entry; ho_log is scratch indexed like ho_words.
 hipError_t fold_heldout(const FoldModel &m, const FoldBatch &b, const uint32_t *ho_off,
-                        const uint32_t *ho_len, const uint32_t *ho_words, double alpha, double beta,
-                        double *out, hipStream_t st);
+                        const uint32_t *ho_len, const uint32_t *ho_words, const uint32_t *hchunk,
+                        uint32_t n_chunks, double *ho_log, double alpha, double beta, double *out,
+                        hipStream_t st);
+uint32_t heldout_chunks(uint32_t n_heldout);
 
 }  // namespace wlda

@@ -143,19 +143,34 @@ __global__ __launch_bounds__(256) void fold_sweep_kernel(FoldModel m, FoldBatch 
 // Held-out log likelihood by document completion (binary64): theta from the
 // document's assignments, phi from the frozen counts (Eq. 4, alpha' = alpha+1,
 // beta' = beta+1); out[d] = sum over held-out tokens of log sum_k theta phi.
-// theta_k / (c_k + beta_bar) of one document is staged in LDS (binary64) up to
-// this K; each held-out word then costs one dot product with its row of C_w.
+// Two kernels: heldout_word_kernel takes blocks of HO_CHUNK held-out words of
+// one document (hchunk: prefix sums of the documents' block counts) and
+// writes log p(w | d) of each word to ho_log (indexed like ho_words);
+// heldout_sum_kernel adds each document's words in a fixed order.  So a
+// document's result does not depend on which others share the launch, and
+// many blocks keep the row loads of C_w in flight at once.
+// theta_k / (c_k + beta_bar) of the document is staged in LDS (binary64) up
+// to this K; each held-out word then costs one dot product with its row of C_w.
 constexpr uint32_t HELDOUT_LDS_MAX = 8192;
+constexpr uint32_t HO_CHUNK = 16;
 
-__global__ __launch_bounds__(256) void fold_heldout_kernel(FoldModel m, FoldBatch b,
-                                                           const uint32_t *ho_off,
-                                                           const uint32_t *ho_len,
-                                                           const uint32_t *ho_words, double a,
-                                                           double beta, double *out) {
+__global__ __launch_bounds__(256) void heldout_word_kernel(FoldModel m, FoldBatch b, const uint32_t *ho_off,
+                                                           const uint32_t *ho_len, const uint32_t *ho_words,
+                                                           const uint32_t *hchunk, double a, double beta,
+                                                           double *ho_log) {
     extern __shared__ uint32_t cnt[];   // K counts, then (K <= HELDOUT_LDS_MAX) K doubles
-    __shared__ double part[4];
     const uint32_t K = m.K;
-    const uint32_t slot = b.slots[blockIdx.x];
+    // the document of this block: the last i with hchunk[i] <= blockIdx.x
+    uint32_t lo = 0, hi = b.n;
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (hchunk[mid] <= blockIdx.x)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    const uint32_t slot = b.slots[lo];
+    const uint32_t h0 = (blockIdx.x - hchunk[lo]) * HO_CHUNK, h1 = min(ho_len[slot], h0 + HO_CHUNK);
     const uint32_t off = b.off[slot], L = b.len[slot];
     for (uint32_t k = threadIdx.x; k < K; k += 256) cnt[k] = 0;
     __syncthreads();
@@ -170,23 +185,42 @@ __global__ __launch_bounds__(256) void fold_heldout_kernel(FoldModel m, FoldBatc
         __syncthreads();
     }
     // one wavefront per held-out word: p_h = sum_k theta_k phi_k(w) (Eq. 4),
-    // a wavefront-wide sum, log p_h added by lane 0 in word order
+    // four row loads per lane in flight, then a wavefront-wide sum
     const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    double total = 0;
-    for (uint32_t h = wave; h < ho_len[slot]; h += 4) {
+    for (uint32_t h = h0 + wave; h < h1; h += 4) {
         const uint32_t w = ho_words[ho_off[slot] + h];
         const uint32_t *cw = m.cwk + (size_t)w * K;
-        double p = 0;
+        double p[4] = {0, 0, 0, 0};
+        uint32_t k = lane;
         if (staged) {
-            for (uint32_t k = lane; k < K; k += 64) p += tk[k] * ((double)cw[k] + beta);
+            for (; k + 192 < K; k += 256) {
+                const uint32_t c0 = cw[k], c1 = cw[k + 64], c2 = cw[k + 128], c3 = cw[k + 192];
+                p[0] += tk[k] * ((double)c0 + beta);
+                p[1] += tk[k + 64] * ((double)c1 + beta);
+                p[2] += tk[k + 128] * ((double)c2 + beta);
+                p[3] += tk[k + 192] * ((double)c3 + beta);
+            }
+            for (; k < K; k += 64) p[0] += tk[k] * ((double)cw[k] + beta);
         } else {
-            for (uint32_t k = lane; k < K; k += 64)
-                p += ((double)cnt[k] + a) / denom_d * (((double)cw[k] + beta) / ((double)m.ck[k] + bbar));
+            for (; k < K; k += 64)
+                p[0] += ((double)cnt[k] + a) / denom_d * (((double)cw[k] + beta) / ((double)m.ck[k] + bbar));
         }
-        for (int o = 32; o > 0; o >>= 1) p += __shfl_down(p, o, 64);
-        if (lane == 0) total += log(p);
+        double q = (p[0] + p[1]) + (p[2] + p[3]);
+        for (int o = 32; o > 0; o >>= 1) q += __shfl_down(q, o, 64);
+        if (lane == 0) ho_log[ho_off[slot] + h] = log(q);
     }
-    if (lane == 0) part[wave] = total;
+}
+
+__global__ __launch_bounds__(256) void heldout_sum_kernel(FoldBatch b, const uint32_t *ho_off,
+                                                          const uint32_t *ho_len, const double *ho_log,
+                                                          double *out) {
+    __shared__ double part[4];
+    const uint32_t slot = b.slots[blockIdx.x];
+    const double *x = ho_log + ho_off[slot];
+    double t = 0;
+    for (uint32_t h = threadIdx.x; h < ho_len[slot]; h += 256) t += x[h];
+    for (int o = 32; o > 0; o >>= 1) t += __shfl_down(t, o, 64);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = t;
     __syncthreads();
     if (threadIdx.x == 0) out[slot] = (part[0] + part[1]) + (part[2] + part[3]);
 }
@@ -257,15 +291,20 @@ hipError_t launch_fold(const FoldModel &m, const FoldBatch &b, hipStream_t st) {
 }
 
 hipError_t launch_heldout(const FoldModel &m, const FoldBatch &b, const uint32_t *ho_off,
-                          const uint32_t *ho_len, const uint32_t *ho_words, double alpha, double beta,
-                          double *out, hipStream_t st) {
+                          const uint32_t *ho_len, const uint32_t *ho_words, const uint32_t *hchunk,
+                          uint32_t n_chunks, double *ho_log, double alpha, double beta, double *out,
+                          hipStream_t st) {
     if (b.n == 0) return hipSuccess;
-    const size_t lds = 4ull * ((m.K + 1) & ~1u) + (m.K <= HELDOUT_LDS_MAX ? 8ull * m.K : 0);
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(fold_heldout_kernel),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(fold_heldout_kernel, dim3(b.n), dim3(256), lds, st, m, b, ho_off, ho_len, ho_words,
-                       alpha, beta, out);
+    if (n_chunks) {
+        const size_t lds = 4ull * ((m.K + 1) & ~1u) + (m.K <= HELDOUT_LDS_MAX ? 8ull * m.K : 0);
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(heldout_word_kernel),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(heldout_word_kernel, dim3(n_chunks), dim3(256), lds, st, m, b, ho_off, ho_len, ho_words,
+                           hchunk, alpha, beta, ho_log);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(heldout_sum_kernel, dim3(b.n), dim3(256), 0, st, b, ho_off, ho_len, ho_log, out);
     return hipGetLastError();
 }
 
@@ -277,10 +316,13 @@ const FoldModel &model_internal(wlda_model m) { return m->m; }
 const wlda_params &model_params(wlda_model m) { return m->p; }
 hipError_t fold_launch(const FoldModel &m, const FoldBatch &b, hipStream_t st) { return launch_fold(m, b, st); }
 hipError_t fold_heldout(const FoldModel &m, const FoldBatch &b, const uint32_t *ho_off,
-                        const uint32_t *ho_len, const uint32_t *ho_words, double alpha, double beta,
-                        double *out, hipStream_t st) {
-    return launch_heldout(m, b, ho_off, ho_len, ho_words, alpha, beta, out, st);
+                        const uint32_t *ho_len, const uint32_t *ho_words, const uint32_t *hchunk,
+                        uint32_t n_chunks, double *ho_log, double alpha, double beta, double *out,
+                        hipStream_t st) {
+    return launch_heldout(m, b, ho_off, ho_len, ho_words, hchunk, n_chunks, ho_log, alpha, beta, out, st);
 }
+
+uint32_t heldout_chunks(uint32_t n_heldout) { return (n_heldout + HO_CHUNK - 1) / HO_CHUNK; }
 }  // namespace wlda
 
 extern "C" {
@@ -383,7 +425,8 @@ wlda_status wlda_model_create(const wlda_params *p, const uint32_t *word_ids, co
 
 static uint64_t batch_bytes(const wlda_params &p, uint32_t n, uint64_t T, bool learned, uint64_t n_ho) {
     return 5 * fa(4ull * n + 4) + 2 * fa(4ull * n + 4) + fa(4ull * T + 4) * (2 + 2ull * p.M) +
-           (learned ? fa(4ull * n * p.K) : 0) + fa(4ull * n_ho + 4) + fa(8ull * n + 8);
+           (learned ? fa(4ull * n * p.K) : 0) + fa(4ull * n_ho + 4) + fa(8ull * n + 8) + fa(4ull * n + 8) +
+           fa(8ull * n_ho + 8);
 }
 
 wlda_status wlda_foldin_batch_bytes(wlda_model m, uint32_t n_docs, uint64_t n_tokens, int learned,
@@ -453,6 +496,10 @@ wlda_status wlda_foldin_batch(wlda_model m, uint32_t n_docs, const uint64_t *doc
     uint32_t *d_cdf = learned_weights ? (uint32_t *)fcarve(c, 4ull * n_docs * K) : nullptr;
     uint32_t *d_how = (uint32_t *)fcarve(c, 4ull * n_ho + 4);
     double *d_out = (double *)fcarve(c, 8ull * n_docs + 8);
+    uint32_t *d_hchunk = (uint32_t *)fcarve(c, 4ull * n_docs + 8);
+    double *d_holog = (double *)fcarve(c, 8ull * n_ho + 8);
+    std::vector<uint32_t> hchunk(n_docs + 1, 0);
+    for (uint32_t d = 0; d < n_docs; ++d) hchunk[d + 1] = hchunk[d] + heldout_chunks(ho_len[d]);
     hipStream_t st = m->st;
     hipError_t e = hipSuccess;
     auto up = [&](void *dst, const void *src, uint64_t bytes) {
@@ -467,6 +514,7 @@ wlda_status wlda_foldin_batch(wlda_model m, uint32_t n_docs, const uint64_t *doc
     up(d_hlen, ho_len.data(), 4ull * n_docs);
     up(d_words, words, 4ull * T);
     if (learned_weights) up(d_cdf, cdf.data(), 4ull * n_docs * K);
+    if (hoptr) up(d_hchunk, hchunk.data(), 4ull * (n_docs + 1));
     if (n_ho) up(d_how, ho_words, 4ull * n_ho);
     FoldBatch b{};
     b.n = n_docs;
@@ -485,7 +533,8 @@ wlda_status wlda_foldin_batch(wlda_model m, uint32_t n_docs, const uint64_t *doc
     b.max_sweep = 0xFFFFFFFFu;
     for (uint32_t s = 0; s <= sweeps && !e; ++s) e = launch_fold(m->m, b, st);
     if (!e && heldout_out && hoptr)
-        e = launch_heldout(m->m, b, d_hoff, d_hlen, d_how, p.alpha, p.beta, d_out, st);
+        e = launch_heldout(m->m, b, d_hoff, d_hlen, d_how, d_hchunk, hchunk[n_docs], d_holog, p.alpha, p.beta,
+                           d_out, st);
     std::vector<uint32_t> zh(T);
     if (!e && T) e = hipMemcpyAsync(zh.data(), d_z, 4ull * T, hipMemcpyDeviceToHost, st);
     if (!e && heldout_out && hoptr)

@@ -117,6 +117,8 @@ struct wlda_server_s {
     uint32_t *d_words = nullptr, *d_z = nullptr, *d_pd = nullptr, *d_pw = nullptr, *d_how = nullptr;
     uint32_t *d_qcdf = nullptr;
     double *d_out = nullptr;
+    uint32_t *d_hchunk = nullptr;    // held-out blocks of the retiring documents (prefix sums)
+    double *d_holog = nullptr;       // log p of every held-out token (held-out pool order)
     uint32_t *d_frow = nullptr, *d_fidx = nullptr;
     float *d_fval = nullptr, *d_probs = nullptr;
     uint32_t *d_cdf_stage = nullptr;
@@ -150,7 +152,7 @@ double now_s(const wlda_server_s *s) {
 uint64_t server_bytes(const wlda_params &p, const wlda_server_params &sp, bool learned) {
     const uint64_t n = sp.max_docs, T = sp.pool_tokens, H = sp.pool_heldout;
     uint64_t b = 8 * sa(4 * n + 4) + sa(4 * T + 4) * (2 + 2ull * p.M) + sa(4 * H + 4) + sa(8 * n + 8) +
-                 sa(4 * n * p.K + 4);
+                 sa(4 * n * p.K + 4) + sa(4 * n + 8) + sa(8 * H + 8);
     if (learned)
         b += 3 * (sa(4 * n + 4) + sa(4 * T + 4) + sa(4 * T + 4)) + 4 * sa(4 * n * p.K);
     return b;
@@ -211,6 +213,8 @@ wlda_status wlda_server_create(wlda_model m, wlda_encoder enc, const wlda_server
     s->d_how = (uint32_t *)take(4 * H + 4);
     s->d_out = (double *)take(8 * n + 8);
     s->d_qcdf = (uint32_t *)take(4 * n * p.K + 4);
+    s->d_hchunk = (uint32_t *)take(4 * n + 8);
+    s->d_holog = (double *)take(8 * H + 8);
     if (enc) {
         s->d_frow = (uint32_t *)take(4 * n + 4);
         s->d_fidx = (uint32_t *)take(4 * T + 4);
@@ -510,7 +514,13 @@ wlda_status wlda_server_step(wlda_server s, uint32_t *n_active, uint32_t *n_pend
         FoldBatch br = b;
         up(s->d_slots, retire.data(), 4ull * retire.size(), s->st);
         br.n = (uint32_t)retire.size();
-        if (!e) e = fold_heldout(fm, br, s->d_hoff, s->d_hlen, s->d_how, p.alpha, p.beta, s->d_out, s->st);
+        std::vector<uint32_t> hchunk(retire.size() + 1, 0);
+        for (size_t r = 0; r < retire.size(); ++r)
+            hchunk[r + 1] = hchunk[r] + heldout_chunks(s->slots[retire[r]].n_ho);
+        up(s->d_hchunk, hchunk.data(), 4ull * hchunk.size(), s->st);
+        if (!e)
+            e = fold_heldout(fm, br, s->d_hoff, s->d_hlen, s->d_how, s->d_hchunk, hchunk.back(), s->d_holog,
+                             p.alpha, p.beta, s->d_out, s->st);
         for (size_t r = 0; r < retire.size() && !e; ++r) {
             const Slot &sl = s->slots[retire[r]];
             zs[r].resize(sl.len);
