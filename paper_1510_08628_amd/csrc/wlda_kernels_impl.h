@@ -200,6 +200,37 @@ __device__ __forceinline__ uint32_t tab_get(const uint32_t *key, const uint32_t 
     }
 }
 
+// Packed open-addressed counts for K <= 65535: one 32-bit word per slot,
+// (topic + 1) in the high half and the count in the low half, 0 = empty, so a
+// probe is one LDS access and the table half the size.  Counts stay below
+// 2^16 (segments hold at most 4096 tokens).
+constexpr uint32_t PACKED_MAX_K = 65535;
+
+__device__ __forceinline__ void ptab_insert(uint32_t *tab, uint32_t mask, uint32_t k) {
+    const uint32_t key = (k + 1) << 16;
+    uint32_t h = k & mask;
+    while (true) {
+        const uint32_t old = atomicCAS(&tab[h], 0u, key | 1u);
+        if (old == 0u) return;
+        if ((old & 0xFFFF0000u) == key) {
+            atomicAdd(&tab[h], 1u);
+            return;
+        }
+        h = (h + 1) & mask;
+    }
+}
+
+__device__ __forceinline__ uint32_t ptab_get(const uint32_t *tab, uint32_t mask, uint32_t k) {
+    const uint32_t key = (k + 1) << 16;
+    uint32_t h = k & mask;
+    while (true) {
+        const uint32_t v = tab[h];
+        if ((v & 0xFFFF0000u) == key) return v & 0xFFFFu;
+        if (v == 0u) return 0u;
+        h = (h + 1) & mask;
+    }
+}
+
 __device__ __forceinline__ uint32_t pow2_at_least(uint32_t x) {
     return x <= 1 ? 1u : 1u << (32 - __clz(x - 1));
 }
@@ -302,11 +333,12 @@ __device__ __forceinline__ void add_accepted(unsigned long long *dst, unsigned l
 // list are taken in ascending order so that the rows visited at the same time
 // are neighbours (their tokens share cache lines of each column, Section 5.2).
 // --------------------------------------------------------------------------
-template <int PHASE, int M, int NW, int GROUP, int TPT, bool CDF, bool CKG>
+template <int PHASE, int M, int NW, int GROUP, int TPT, bool CDF, bool CKG, bool PK>
 __global__ __launch_bounds__(256) void seg_kernel(PhaseArgs a, SegList l, uint32_t cap_max,
                                                   uint32_t dense_u, uint32_t ck_lds_u) {
     extern __shared__ uint32_t lds[];
     constexpr int GPB = 256 / GROUP;
+    static_assert(TPT * (M + 1) <= 64, "one bit per lookup of a lane's tokens");
     // ck_lds_u: bit 0 = the c_k histogram of the new Z in LDS, bit 1 = c_k +
     // beta_bar staged in LDS (what fits the LDS budget; see run_seg)
     const bool dense = dense_u != 0, ckh_lds = (ck_lds_u & 1u) != 0, ckb_lds = (ck_lds_u & 2u) != 0;
@@ -315,7 +347,9 @@ __global__ __launch_bounds__(256) void seg_kernel(PhaseArgs a, SegList l, uint32
     // LDS: [c_k + beta_bar as binary32 (ckb_lds)] [c_k histogram of the new
     // Z (ckh_lds)], then per group [count table | new z of the segment]
     const uint32_t ck_words = (ckb_lds ? K : 0) + (ckh_lds ? K : 0);
-    const uint32_t tab_words = dense ? K : 2 * cap_max;
+    // count table: dense K words, or cap_max packed words (PK), or cap_max
+    // keys followed by cap_max counts
+    const uint32_t tab_words = dense ? K : (PK ? cap_max : 2 * cap_max);
     float *ckb = reinterpret_cast<float *>(lds);
     uint32_t *ckh = lds + (ckb_lds ? K : 0);
     uint32_t *gbase = lds + ck_words + g * (tab_words + GROUP * TPT);
@@ -372,8 +406,12 @@ __global__ __launch_bounds__(256) void seg_kernel(PhaseArgs a, SegList l, uint32
                 const uint32_t cap = pow2_at_least(2 * L);
                 mask = cap - 1;
                 for (uint32_t i = lane; i < cap; i += GROUP) {
-                    tkey[i] = EMPTY_KEY;
-                    tcnt[i] = 0;
+                    if constexpr (PK) {
+                        tkey[i] = 0;
+                    } else {
+                        tkey[i] = EMPTY_KEY;
+                        tcnt[i] = 0;
+                    }
                 }
                 group_sync<GROUP>();
             }
@@ -389,25 +427,66 @@ __global__ __launch_bounds__(256) void seg_kernel(PhaseArgs a, SegList l, uint32
             }
 #pragma unroll
             for (int r = 0; r < TPT; ++r)
-                if (r * GROUP + lane < L) tab_insert(tkey, tcnt, mask, dense, fld(rec[r], 0));
+                if (r * GROUP + lane < L) {
+                    if constexpr (PK)
+                        ptab_insert(tkey, mask, fld(rec[r], 0));
+                    else
+                        tab_insert(tkey, tcnt, mask, dense, fld(rec[r], 0));
+                }
             group_sync<GROUP>();
+            // The counts each token needs: its state s0 and its M candidates
+            // (the chain's state is always one of them).  All first probes of
+            // the segment's tokens are issued together; the rare lookups that
+            // hit a slot of another topic finish with a probing loop.
+            uint32_t cnt[TPT][M + 1];
+            uint64_t pend = 0;   // bit r * (M + 1) + f: lookup still open
+#pragma unroll
+            for (int r = 0; r < TPT; ++r)
+#pragma unroll
+                for (int f = 0; f <= M; ++f) {
+                    const uint32_t k = fld(rec[r], f);
+                    if (dense) {
+                        cnt[r][f] = tcnt[k];
+                    } else if constexpr (PK) {
+                        const uint32_t v = tkey[k & mask];
+                        cnt[r][f] = (v & 0xFFFF0000u) == (k + 1) << 16 ? v & 0xFFFFu : 0u;
+                        if (v != 0u && (v & 0xFFFF0000u) != (k + 1) << 16) pend |= 1ull << (r * (M + 1) + f);
+                    } else {
+                        const uint32_t kk = tkey[k & mask];
+                        cnt[r][f] = 0;
+                        if (kk == k) cnt[r][f] = tcnt[k & mask];
+                        else if (kk != EMPTY_KEY) pend |= 1ull << (r * (M + 1) + f);
+                    }
+                }
+            if (pend) {
+#pragma unroll
+                for (int r = 0; r < TPT; ++r)
+#pragma unroll
+                    for (int f = 0; f <= M; ++f)
+                        if ((pend >> (r * (M + 1) + f)) & 1ull) {
+                            const uint32_t k = fld(rec[r], f);
+                            if constexpr (PK)
+                                cnt[r][f] = ptab_get(tkey, mask, k);
+                            else
+                                cnt[r][f] = tab_get(tkey, tcnt, mask, false, k);
+                        }
+            }
 #pragma unroll
             for (int r = 0; r < TPT; ++r) {
                 if (r * GROUP + lane < L) {
-                    uint32_t s = fld(rec[r], 0);
+                    uint32_t s = fld(rec[r], 0), cs = cnt[r][0];
                     float bs;
                     if constexpr (CKG) bs = gck[r][0]; else bs = ckb[s];
                     const uint4 RA = philox(beg + r * GROUP + lane, a.iter, ph, 0, a.seed_lo, a.seed_hi);
 #pragma unroll
                     for (int i = 1; i <= M; ++i) {
-                        const uint32_t c = fld(rec[r], i);
-                        const uint32_t cc = tab_get(tkey, tcnt, mask, dense, c);
-                        const uint32_t cs = tab_get(tkey, tcnt, mask, dense, s);
+                        const uint32_t c = fld(rec[r], i), cc = cnt[r][i];
                         const float u = unif24(word4(RA, i - 1));
                         float bc;
                         if constexpr (CKG) bc = gck[r][i]; else bc = ckb[c];
                         if (mh_accept_b(u, cc, cs, prior, bs, bc)) {
                             s = c;
+                            cs = cc;
                             bs = bc;
                             ++acc;
                         }
@@ -930,7 +1009,8 @@ static hipError_t run_seg(const PhaseArgs &a, const SegList &l, uint32_t cap_bou
     if (l.n == 0) return hipSuccess;
     const bool dense = a.K <= cap_bound;
     const uint32_t cap_max = dense ? 0 : cap_bound;
-    const uint32_t tab_words = dense ? a.K : 2 * cap_max;
+    const bool packed = !dense && a.K <= PACKED_MAX_K;
+    const uint32_t tab_words = dense ? a.K : (packed ? cap_max : 2 * cap_max);
     constexpr int GPB = 256 / GROUP;
     // LDS: the groups' count tables, then, within SEG_LDS_BUDGET, the c_k
     // histogram of the new Z first (each token would otherwise add to it with
@@ -961,11 +1041,15 @@ static hipError_t run_seg(const PhaseArgs &a, const SegList &l, uint32_t cap_bou
             // dense tables of K < GROUP * TPT words always leave room for c_k
             // + beta_bar; there is no variant without it
             if (!ckb_lds) return hipErrorNotSupported;
-            return go(seg_kernel<PHASE, M, NW, GROUP, TPT, true, false>);
+            return go(seg_kernel<PHASE, M, NW, GROUP, TPT, true, false, false>);
         }
     }
-    if (!ckb_lds) return go(seg_kernel<PHASE, M, NW, GROUP, TPT, false, true>);
-    return go(seg_kernel<PHASE, M, NW, GROUP, TPT, false, false>);
+    if (packed) {
+        if (!ckb_lds) return go(seg_kernel<PHASE, M, NW, GROUP, TPT, false, true, true>);
+        return go(seg_kernel<PHASE, M, NW, GROUP, TPT, false, false, true>);
+    }
+    if (!ckb_lds) return go(seg_kernel<PHASE, M, NW, GROUP, TPT, false, true, false>);
+    return go(seg_kernel<PHASE, M, NW, GROUP, TPT, false, false, false>);
 }
 
 // Calls f(std::integral_constant<int, RF>) for the record format rf of M
