@@ -514,9 +514,21 @@ __global__ __launch_bounds__(256) void seg_kernel(PhaseArgs a, SegList l, uint32
 #pragma unroll
             for (int r = 0; r < TPT; ++r) znew[r] = fld(rec[r], 0);
         }
+        // The segment's new z in LDS, in segment order for random positioning.
+        // For a column with L > K the count part of a word proposal is the
+        // inverse CDF of its updated counts at an index j < L, which is entry j
+        // of the column's new topics sorted by topic: a counting sort through
+        // the prefix sums writes them in that order (entries of one topic are
+        // equal, so the order in which the atomics land does not matter), and
+        // the draw reads one entry in both cases.
+        bool sorted = false;
+        if constexpr (CDF) sorted = by_cdf;
 #pragma unroll
         for (int r = 0; r < TPT; ++r)
-            if (r * GROUP + lane < L) zarr[r * GROUP + lane] = znew[r];
+            if (r * GROUP + lane < L) {
+                const uint32_t at = sorted ? atomicSub(&tcnt[znew[r]], 1u) - 1u : r * GROUP + lane;
+                zarr[at] = znew[r];
+            }
         group_sync<GROUP>();
         // Word phase: the next segment's loads go out before this one's stores
         // (loads and stores share one in-order counter, so loads issued after
@@ -527,19 +539,17 @@ __global__ __launch_bounds__(256) void seg_kernel(PhaseArgs a, SegList l, uint32
         uint32_t npos[TPT];
         Rec<NW> nrec[TPT];
         if (PREFETCH && li + ngx < hi) fetch(li + ngx, nbeg, nL, npos, nrec);
-        // Draws, DB tokens at a time: the count part is a token of the updated
-        // segment (random positioning over its new z in LDS) or, for a column
-        // with L > K, the inverse CDF of its updated counts at the same index.
+        // Draws, DB tokens at a time: the count part is entry j of the
+        // segment's new z array in LDS (see above).
         constexpr int DB = TPT < 4 ? TPT : 4;
 #pragma unroll
         for (int r0 = 0; r0 < TPT; r0 += DB) {
-            uint32_t pw[DB * M], jj[DB * M];
-            uint32_t coin = 0;
+            uint32_t pw[DB * M];
 #pragma unroll
             for (int q = 0; q < DB; ++q) {
                 const uint32_t n = (r0 + q) * GROUP + lane;
 #pragma unroll
-                for (int i = 0; i < M; ++i) pw[q * M + i] = jj[q * M + i] = 0;
+                for (int i = 0; i < M; ++i) pw[q * M + i] = 0;
                 if (n < L) {
 #pragma unroll
                     for (int j = 1; j <= (M + 1) / 2; ++j) {
@@ -549,28 +559,12 @@ __global__ __launch_bounds__(256) void seg_kernel(PhaseArgs a, SegList l, uint32
                             const int i = 2 * j - 1 + h;
                             if (i > M) continue;
                             const uint32_t w = word4(RB, 2 * h + 1);
-                            if (take_count_part(unif24(word4(RB, 2 * h)), L, mass)) {
-                                const uint32_t u = dice(w, L);
-                                if constexpr (CDF) {
-                                    jj[q * M + i - 1] = u;
-                                    coin |= 1u << (q * M + i - 1);
-                                    pw[q * M + i - 1] = by_cdf ? 0u : zarr[u];
-                                } else {
-                                    pw[q * M + i - 1] = zarr[u];
-                                }
-                            } else {
+                            if (take_count_part(unif24(word4(RB, 2 * h)), L, mass))
+                                pw[q * M + i - 1] = zarr[dice(w, L)];
+                            else
                                 pw[q * M + i - 1] = dice(w, K);
-                            }
                         }
                     }
-                }
-            }
-            if constexpr (CDF) {
-                if (by_cdf) {
-                    cdf_find_lds<DB * M>(tcnt, K, jj);
-#pragma unroll
-                    for (int d = 0; d < DB * M; ++d)
-                        if ((coin >> d) & 1u) pw[d] = jj[d];
                 }
             }
 #pragma unroll
@@ -591,7 +585,7 @@ __global__ __launch_bounds__(256) void seg_kernel(PhaseArgs a, SegList l, uint32
         }
         group_sync<GROUP>();
         if constexpr (CDF) {
-            if (by_cdf) {       // prefix sums fill the table: clear all of it
+            if (by_cdf) {       // what the sort left of the prefix sums: clear all of it
                 for (uint32_t k = lane; k < K; k += GROUP) tcnt[k] = 0;
                 group_sync<GROUP>();
             }
