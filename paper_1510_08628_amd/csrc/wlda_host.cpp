@@ -611,13 +611,18 @@ wlda_status wlda_create(const wlda_params *p, const uint32_t *word_ids, const ui
         // fill (4 per CU costs the row kernel 20%); the word phase's column
         // kernels peak at 2-3.  The long-segment kernels stream chunks and
         // want many more.  Multiples of the CU count keep every CU of an XCD
-        // equally loaded.
+        // equally loaded.  For M > 2 the sub-workgroup bins hold half as many
+        // tokens per lane, and the doc phase's run best at three per CU
+        // (measured on the PubMed-shaped corpus, K = 1e4, M = 4).
         static const uint32_t per_cu[2 * NBINS] = {3, 3, 3, 4, 3, 2, 2, 2, 3, 2};
         static const uint32_t long_per_cu[2] = {16, 8};
         int dev = 0, cus = 0;
         if (hipGetDevice(&dev) == hipSuccess &&
             hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0) {
-            for (int i = 0; i < 2 * NBINS; ++i) s->seg_blocks[i] = per_cu[i] * (uint32_t)cus;
+            for (int i = 0; i < 2 * NBINS; ++i) {
+                const bool doc_narrow = i >= NBINS && i < NBINS + BIN_BLOCK;
+                s->seg_blocks[i] = (p->M > 2 && doc_narrow ? 3u : per_cu[i]) * (uint32_t)cus;
+            }
             for (int i = 0; i < 2; ++i) s->long_blocks[i] = long_per_cu[i] * (uint32_t)cus;
         }
     }

@@ -93,9 +93,9 @@ struct PhaseArgs {
 };
 
 struct Tuning {
-    // wave kernel: segments of at most 64 * TPT_WAVE tokens
+    // wave kernel (and the 16- and 32-lane groups): TPT_WAVE tokens per lane,
+    // half as many for M > 2, whose counts and records take twice the registers
     static constexpr int TPT_WAVE = 8;
-    static constexpr uint32_t WAVE_MAX = 64 * TPT_WAVE;
     // block kernels (one 256-thread workgroup per segment): the narrow one
     // keeps TPT_BLOCK tokens per thread in registers (high occupancy), the
     // wide one twice as many; M > 2 halves both (two-word records)
@@ -142,7 +142,7 @@ inline uint32_t bin_group(int bin) {
 }
 
 inline uint32_t bin_tpt(int bin, uint32_t M) {
-    if (bin <= BIN_WAVE) return (uint32_t)Tuning::TPT_WAVE;
+    if (bin <= BIN_WAVE) return M <= 2 ? (uint32_t)Tuning::TPT_WAVE : (uint32_t)Tuning::TPT_WAVE / 2;
     const int t = bin == BIN_BLOCK ? Tuning::TPT_BLOCK : Tuning::TPT_WIDE;
     return M <= 2 ? (uint32_t)t : (uint32_t)t / 2;
 }

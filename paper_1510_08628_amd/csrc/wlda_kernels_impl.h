@@ -1066,7 +1066,7 @@ static hipError_t seg_dispatch(const PhaseArgs &a, const SegList &l, int bin, hi
         constexpr int NW = decltype(rfc)::value;
         constexpr int TB = M <= 2 ? Tuning::TPT_BLOCK : Tuning::TPT_BLOCK / 2;
         constexpr int TW = M <= 2 ? Tuning::TPT_WIDE : Tuning::TPT_WIDE / 2;
-        constexpr int TS = Tuning::TPT_WAVE;
+        constexpr int TS = M <= 2 ? Tuning::TPT_WAVE : Tuning::TPT_WAVE / 2;
         if (bin == BIN_G16) return run_seg<PHASE, M, NW, 16, TS>(a, l, 2 * 16 * TS, st);
         if (bin == BIN_G32) return run_seg<PHASE, M, NW, 32, TS>(a, l, 2 * 32 * TS, st);
         if (bin == BIN_WAVE) return run_seg<PHASE, M, NW, 64, TS>(a, l, 2 * 64 * TS, st);
