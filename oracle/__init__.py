@@ -89,6 +89,8 @@ def lib():
         L.oracle_theta.restype = C.c_int
         L.oracle_phi.argtypes = [vp, u32, u32, vp]
         L.oracle_phi.restype = C.c_int
+        L.oracle_set_alpha.argtypes = [vp, vp]
+        L.oracle_set_alpha.restype = C.c_int
         L.oracle_instant_iterate.argtypes = [vp, u32]
         L.oracle_instant_iterate.restype = C.c_int
         L.oracle_foldin.argtypes = [u32, u32, u32, C.c_double, C.c_double, u64, vp, vp, vp,
@@ -268,6 +270,19 @@ class Oracle:
         out = np.empty((nw, self.K), dtype=np.float64)
         self._check(lib().oracle_phi(self.h, w0, nw, _ptr(out)))
         return out
+
+    def set_alpha(self, alpha):
+        """Asymmetric document-topic prior alpha_k (K positive values, taken
+        as binary32), or None for the symmetric alpha; before init()."""
+        if alpha is None:
+            self._check(lib().oracle_set_alpha(self.h, None))
+            self.alpha_k = None
+            return
+        a = np.ascontiguousarray(alpha, dtype=np.float32)
+        if a.shape != (self.K,):
+            raise ValueError("alpha must hold K values")
+        self._check(lib().oracle_set_alpha(self.h, _ptr(a)))
+        self.alpha_k = a
 
     def instant_iterate(self, n: int = 1):
         """n iterations of the instant-update (collapsed Gibbs-MH) variant."""

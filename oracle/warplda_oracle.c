@@ -22,6 +22,10 @@
  *   - c_k, the exact histogram of Z at the start of every phase (Section 4.4,
  *     "M-step": counts computed on the fly from Z);
  *   - the log joint likelihood of Section 6.1, in double precision;
+ *   - optionally an asymmetric document-topic prior alpha_k (the general
+ *     form of Eq. (6)-(7)): doc proposals q_doc(k) ~ C_dk + alpha_k, the
+ *     word-proposal acceptance rate with alpha_c, alpha_s, the LL and theta
+ *     with alpha_k (oracle_set_alpha);
  *   - fold-in of new documents against frozen word-topic counts (MCEM E-step
  *     of Eq. (5) with C_w and c_k held fixed), used by the serving path.
  *
@@ -129,12 +133,18 @@ static uint32_t dice(uint32_t r, uint32_t n)
  * phase, c_d in the doc phase) of the candidate c and the current state s,
  * prior is beta (word phase) or alpha (doc phase); ck_* are the global topic
  * counts.  Accept iff u * den < num, i.e. with probability min(1, num/den). */
+static int mh_accept2(float u, int64_t cnt_c, int64_t cnt_s, float prior_c, float prior_s,
+                      int64_t ck_s, int64_t ck_c, float beta_bar)
+{
+    float num = ((float)cnt_c + prior_c) * ((float)ck_s + beta_bar);
+    float den = ((float)cnt_s + prior_s) * ((float)ck_c + beta_bar);
+    return u * den < num;
+}
+
 static int mh_accept(float u, int64_t cnt_c, int64_t cnt_s, float prior,
                      int64_t ck_s, int64_t ck_c, float beta_bar)
 {
-    float num = ((float)cnt_c + prior) * ((float)ck_s + beta_bar);
-    float den = ((float)cnt_s + prior) * ((float)ck_c + beta_bar);
-    return u * den < num;
+    return mh_accept2(u, cnt_c, cnt_s, prior, prior, ck_s, ck_c, beta_bar);
 }
 
 /* Mixture coin of Section 2.2 / Section 4.3: pick the count part (random
@@ -182,6 +192,10 @@ typedef struct {
     int visit_reversed; /* visit rows/columns in reverse order (tests) */
     /* binary32 constants */
     float a, b, alpha_bar, beta_k, beta_bar;
+    /* asymmetric alpha (NULL: symmetric): alpha_k as binary32, and its
+     * running sums in topic order, binary64 */
+    float *alpha_k;
+    double *alpha_cum;
 } oracle_t;
 
 typedef struct {
@@ -197,6 +211,29 @@ static void set_constants(oracle_t *o)
     o->alpha_bar = (float)o->K * o->a;   /* alpha_bar = K alpha */
     o->beta_k = (float)o->K * o->b;      /* prior mass of C_wk + beta */
     o->beta_bar = (float)o->V * o->b;    /* beta_bar = V beta */
+}
+
+/* alpha of topic k (Eq. 6-7): alpha_k, or the symmetric alpha. */
+static float alpha_of(const oracle_t *o, int32_t k)
+{
+    return o->alpha_k ? o->alpha_k[k] : o->a;
+}
+
+/* The prior part of a doc proposal: topic k with probability alpha_k /
+ * alpha_bar.  Symmetric alpha: Dice(K).  Asymmetric: x = r 2^-32 A_{K-1} in
+ * binary64, with A_k the running sums of alpha_k in topic order, and the
+ * smallest k with A_k > x (x < A_{K-1} always). */
+static int32_t prior_topic(const oracle_t *o, uint32_t r)
+{
+    if (!o->alpha_k) return (int32_t)dice(r, o->K);
+    double x = (double)r * 0x1p-32 * o->alpha_cum[o->K - 1];
+    uint32_t lo = 0, hi = o->K - 1;
+    while (lo < hi) {
+        uint32_t mid = (lo + hi) / 2;
+        if (o->alpha_cum[mid] > x) hi = mid;
+        else lo = mid + 1;
+    }
+    return (int32_t)lo;
 }
 
 /* Layout of Section 5.2: Y in CSC form with every column sorted by row id,
@@ -242,6 +279,7 @@ void oracle_destroy(oracle_t *o)
     if (!o) return;
     free(o->colptr); free(o->rowptr); free(o->row); free(o->inv);
     free(o->word_of); free(o->doc_of); free(o->z); free(o->prop); free(o->ck);
+    free(o->alpha_k); free(o->alpha_cum);
     free(o);
 }
 
@@ -302,7 +340,7 @@ static void draw_doc_proposals(oracle_t *o, uint32_t d, uint32_t iter)
             if (take_count_part(unif24(cw_), L, o->alpha_bar))
                 prop = o->z[o->row[beg + dice(iw, (uint32_t)L)]];
             else
-                prop = (int32_t)dice(iw, o->K);
+                prop = prior_topic(o, iw);
             o->prop[(uint64_t)(i - 1) * o->T + t] = prop;
         }
     }
@@ -322,6 +360,35 @@ int oracle_init(oracle_t *o)
     o->iter = 0;
     o->next_phase = PH_WORD;
     o->accepted_word = o->accepted_doc = 0;
+    return 0;
+}
+
+/* Asymmetric document-topic prior: alpha[k] > 0 (finite, binary32) for every
+ * topic, or NULL to return to the symmetric alpha.  Only before oracle_init.
+ * alpha_bar becomes the binary64 sum of the alpha_k, rounded to binary32. */
+int oracle_set_alpha(oracle_t *o, const float *alpha)
+{
+    if (o->next_phase != 0) return -4;
+    free(o->alpha_k); free(o->alpha_cum);
+    o->alpha_k = NULL; o->alpha_cum = NULL;
+    set_constants(o);
+    if (!alpha) return 0;
+    for (uint32_t k = 0; k < o->K; ++k)
+        if (!(alpha[k] > 0.0f) || !isfinite(alpha[k])) return -1;
+    o->alpha_k = malloc(o->K * sizeof(float));
+    o->alpha_cum = malloc(o->K * sizeof(double));
+    if (!o->alpha_k || !o->alpha_cum) {
+        free(o->alpha_k); free(o->alpha_cum);
+        o->alpha_k = NULL; o->alpha_cum = NULL;
+        return -1;
+    }
+    double run = 0.0;
+    for (uint32_t k = 0; k < o->K; ++k) {
+        o->alpha_k[k] = alpha[k];
+        run += (double)alpha[k];
+        o->alpha_cum[k] = run;
+    }
+    o->alpha_bar = (float)run;
     return 0;
 }
 
@@ -424,8 +491,8 @@ static void doc_row(oracle_t *o, uint32_t d, uint32_t iter, int64_t *ck_next,
         accept_words(o->seed, (uint32_t)(beg + n), iter, PH_DOC, ra);
         for (uint32_t i = 1; i <= o->M; ++i) {
             int32_t c = o->prop[(uint64_t)(i - 1) * o->T + t];
-            if (mh_accept(unif24(ra[i - 1]), cd[c], cd[s], o->a, o->ck[s],
-                          o->ck[c], o->beta_bar)) {
+            if (mh_accept2(unif24(ra[i - 1]), cd[c], cd[s], alpha_of(o, c), alpha_of(o, s),
+                           o->ck[s], o->ck[c], o->beta_bar)) {
                 s = c;
                 (*accepted)++;
             }
@@ -523,7 +590,8 @@ double oracle_log_joint(uint64_t T, uint32_t V, uint32_t D, uint32_t K,
 /* LL of the sampler's current Z (same formula, counts from the layout). */
 double oracle_log_likelihood(const oracle_t *o)
 {
-    double alpha_bar = o->K * o->alpha, beta_bar = o->V * o->beta;
+    double alpha_bar = o->alpha_k ? o->alpha_cum[o->K - 1] : o->K * o->alpha;
+    double beta_bar = o->V * o->beta;
     int64_t *cnt = calloc(o->K, sizeof(int64_t));
     if (!cnt) return NAN;
     double ll = 0.0;
@@ -535,7 +603,8 @@ double oracle_log_likelihood(const oracle_t *o)
         /* each distinct topic of the row once: add, then clear */
         for (uint64_t n = 0; n < L; ++n) {
             int32_t k = o->z[o->row[beg + n]];
-            if (cnt[k]) ll += lgamma(o->alpha + (double)cnt[k]) - lgamma(o->alpha);
+            double ak = o->alpha_k ? (double)o->alpha_k[k] : o->alpha;
+            if (cnt[k]) ll += lgamma(ak + (double)cnt[k]) - lgamma(ak);
             cnt[k] = 0;
         }
     }
@@ -646,7 +715,7 @@ void oracle_set_csc_state(oracle_t *o, const int32_t *z_csc,
 
 /* ------------------------------------------------------------------------ */
 /* Point estimates of Eq. (4) from the current Z, binary64:                 */
-/*   theta_dk = (C_dk + alpha) / (L_d + K alpha)                            */
+/*   theta_dk = (C_dk + alpha_k) / (L_d + alpha_bar)                        */
 /*   phi_wk   = (C_wk + beta)  / (C_k + V beta)                             */
 /* (the M-step of Section 4.2 with alpha' = alpha + 1, beta' = beta + 1).    */
 /* theta: nd x K for documents d0 .. d0+nd-1; phi: nw x K for words         */
@@ -661,8 +730,9 @@ int oracle_theta(const oracle_t *o, uint32_t d0, uint32_t nd, double *out)
         double *row = out + (size_t)e * o->K;
         for (uint32_t k = 0; k < o->K; ++k) row[k] = 0.0;
         for (uint64_t n = 0; n < L; ++n) row[o->z[o->row[beg + n]]] += 1.0;
-        double den = (double)L + (double)o->K * o->alpha;
-        for (uint32_t k = 0; k < o->K; ++k) row[k] = (row[k] + o->alpha) / den;
+        double den = (double)L + (o->alpha_k ? o->alpha_cum[o->K - 1] : (double)o->K * o->alpha);
+        for (uint32_t k = 0; k < o->K; ++k)
+            row[k] = (row[k] + (o->alpha_k ? (double)o->alpha_k[k] : o->alpha)) / den;
     }
     return 0;
 }
@@ -744,7 +814,7 @@ int oracle_instant_iterate(oracle_t *o, uint32_t n_iter)
                     if (step <= o->M) {   /* doc proposal, word-side ratio */
                         c = Ld > 1 && take_count_part(unif24(r[1]), Ld - 1, o->alpha_bar)
                                 ? o->z[o->row[beg + skip_self(dice(r[2], (uint32_t)(Ld - 1)), n)]]
-                                : (int32_t)dice(r[2], o->K);
+                                : prior_topic(o, r[2]);
                         if (mh_accept(unif24(r[0]), cw[c], cw[s], o->b, o->ck[s], o->ck[c],
                                       o->beta_bar)) {
                             s = c;
@@ -755,8 +825,8 @@ int oracle_instant_iterate(oracle_t *o, uint32_t n_iter)
                                 ? o->z[cbeg + skip_self(dice(r[2], (uint32_t)(Lw - 1)),
                                                         pos_in_col[t])]
                                 : (int32_t)dice(r[2], o->K);
-                        if (mh_accept(unif24(r[0]), cd[c], cd[s], o->a, o->ck[s], o->ck[c],
-                                      o->beta_bar)) {
+                        if (mh_accept2(unif24(r[0]), cd[c], cd[s], alpha_of(o, c), alpha_of(o, s),
+                                       o->ck[s], o->ck[c], o->beta_bar)) {
                             s = c;
                             accepted++;
                         }
@@ -804,7 +874,7 @@ int oracle_frozen_chain(const oracle_t *o, uint32_t t, uint32_t rounds,
                 rng_call(o->seed, rd, i, PH_FROZEN, 1, t, r);
                 int32_t c = take_count_part(unif24(r[1]), Ld, o->alpha_bar)
                                 ? o->z[o->row[rbeg + dice(r[2], (uint32_t)Ld)]]
-                                : (int32_t)dice(r[2], o->K);
+                                : prior_topic(o, r[2]);
                 if (mh_accept(unif24(r[0]), cw[c], cw[x], o->b, o->ck[x],
                               o->ck[c], o->beta_bar))
                     x = c;
@@ -814,8 +884,8 @@ int oracle_frozen_chain(const oracle_t *o, uint32_t t, uint32_t rounds,
                 int32_t c = take_count_part(unif24(r[1]), Lw, o->beta_k)
                                 ? o->z[cbeg + dice(r[2], (uint32_t)Lw)]
                                 : (int32_t)dice(r[2], o->K);
-                if (mh_accept(unif24(r[0]), cd[c], cd[x], o->a, o->ck[x],
-                              o->ck[c], o->beta_bar))
+                if (mh_accept2(unif24(r[0]), cd[c], cd[x], alpha_of(o, c), alpha_of(o, x),
+                               o->ck[x], o->ck[c], o->beta_bar))
                     x = c;
             }
         }

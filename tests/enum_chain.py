@@ -3,14 +3,16 @@
 Written from the paper's definitions, independently of the C oracle, to pin it:
 
 * Proposals (Eq. 6), drawn as the two-part mixture of Section 2.2:
-    q_doc(k)  = (C_dk + alpha) / (L_d + K alpha)
+    q_doc(k)  = (C_dk + alpha_k) / (L_d + alpha_bar)
     q_word(k) = (C_wk + beta)  / (L_w + K beta)
   (random positioning over a row/column returns topic k with probability
   C_k / L, which gives exactly these laws).
 * Acceptance (Eq. 7), with counts frozen for the whole phase (delayed update,
   Section 4.2):
     doc proposal,  judged in the word phase: (C_wc+beta)(C_s+bbar) / ((C_ws+beta)(C_c+bbar))
-    word proposal, judged in the doc phase:  (C_dc+alpha)(C_s+bbar) / ((C_ds+alpha)(C_c+bbar))
+    word proposal, judged in the doc phase:  (C_dc+alpha_c)(C_s+bbar) / ((C_ds+alpha_s)(C_c+bbar))
+  alpha may be a scalar (symmetric prior, alpha_bar = K alpha) or a vector of
+  K values alpha_k (asymmetric, alpha_bar = sum_k alpha_k).
 * Order (Section 4.4): word phase = judge the pending doc proposals, then draw
   word proposals from the updated column; doc phase = judge the word
   proposals, then draw doc proposals from the updated row.  The first doc
@@ -24,6 +26,11 @@ from __future__ import annotations
 
 import itertools
 import numpy as np
+
+
+def _alpha(alpha, K):
+    """alpha as K values (a scalar is the symmetric prior)."""
+    return np.broadcast_to(np.asarray(alpha, dtype=np.float64), (K,))
 
 
 def _counts(z, groups, K):
@@ -62,6 +69,8 @@ def phase_matrix(word_ids, doc_ids, K, M, alpha, beta, V, phase, drop_ck=False):
     T = len(word_ids)
     states = list(itertools.product(range(K), repeat=T))
     bbar = V * beta
+    av = _alpha(alpha, K)
+    abar = av.sum()
     P = np.zeros((len(states), len(states)))
     for si, z in enumerate(states):
         ck = np.bincount(z, minlength=K).astype(np.float64)
@@ -75,7 +84,7 @@ def phase_matrix(word_ids, doc_ids, K, M, alpha, beta, V, phase, drop_ck=False):
             if phase == "word":
                 # pending doc proposals, drawn from c_d of this Z
                 Ld = cd[d].sum()
-                q = (cd[d] + alpha) / (Ld + K * alpha)
+                q = (cd[d] + av) / (Ld + abar)
                 c_row = cw[w]
 
                 def acc(s, c, c_row=c_row):
@@ -87,8 +96,8 @@ def phase_matrix(word_ids, doc_ids, K, M, alpha, beta, V, phase, drop_ck=False):
                 c_row = cd[d]
 
                 def acc(s, c, c_row=c_row):
-                    return min(1.0, (c_row[c] + alpha) * (ck[s] + bbar) /
-                               ((c_row[s] + alpha) * (ck[c] + bbar)))
+                    return min(1.0, (c_row[c] + av[c]) * (ck[s] + bbar) /
+                               ((c_row[s] + av[s]) * (ck[c] + bbar)))
             per_token.append(_mh_outcome(z[t], q, acc, K, M))
         for sj, z2 in enumerate(states):
             pr = 1.0
@@ -226,6 +235,7 @@ def instant_iteration_matrix(word_ids, doc_ids, K, M, alpha, beta, V):
     states = list(itertools.product(range(K), repeat=T))
     index = {s: i for i, s in enumerate(states)}
     bbar = V * beta
+    av = _alpha(alpha, K)
     P = np.eye(len(states))
     for t in row_order(word_ids, doc_ids):
         w, d = word_ids[t], doc_ids[t]
@@ -235,14 +245,14 @@ def instant_iteration_matrix(word_ids, doc_ids, K, M, alpha, beta, V):
             ck = np.bincount([z[i] for i in others], minlength=K).astype(np.float64)
             cd = np.bincount([z[i] for i in others if doc_ids[i] == d], minlength=K).astype(np.float64)
             cw = np.bincount([z[i] for i in others if word_ids[i] == w], minlength=K).astype(np.float64)
-            qd = (cd + alpha) / (cd.sum() + K * alpha)
+            qd = (cd + av) / (cd.sum() + av.sum())
             qw = (cw + beta) / (cw.sum() + K * beta)
 
             def acc_d(s, c):
                 return min(1.0, (cw[c] + beta) * (ck[s] + bbar) / ((cw[s] + beta) * (ck[c] + bbar)))
 
             def acc_w(s, c):
-                return min(1.0, (cd[c] + alpha) * (ck[s] + bbar) / ((cd[s] + alpha) * (ck[c] + bbar)))
+                return min(1.0, (cd[c] + av[c]) * (ck[s] + bbar) / ((cd[s] + av[s]) * (ck[c] + bbar)))
             dist = _mh_outcome(z[t], qd, acc_d, K, M)
             nd = np.zeros(K)
             for s0 in range(K):
@@ -267,17 +277,18 @@ def instant_distribution_after(word_ids, doc_ids, K, M, alpha, beta, V, n_iter):
 
 def collapsed_posterior(word_ids, doc_ids, K, alpha, beta, V):
     """p(Z | W) of Eq. (1), by enumeration: proportional to the product over
-    documents of prod_k Gamma(alpha + C_dk) and over topics of
+    documents of prod_k Gamma(alpha_k + C_dk) and over topics of
     prod_w Gamma(beta + C_wk) / Gamma(V beta + C_k)."""
     from math import lgamma
     T = len(word_ids)
     states = list(itertools.product(range(K), repeat=T))
+    av = _alpha(alpha, K)
     logp = np.zeros(len(states))
     for si, z in enumerate(states):
         lp = 0.0
         for d in set(doc_ids):
             c = np.bincount([z[i] for i in range(T) if doc_ids[i] == d], minlength=K)
-            lp += sum(lgamma(alpha + x) for x in c)
+            lp += sum(lgamma(av[k] + x) for k, x in enumerate(c))
         for w in set(word_ids):
             c = np.bincount([z[i] for i in range(T) if word_ids[i] == w], minlength=K)
             lp += sum(lgamma(beta + x) for x in c)
