@@ -94,6 +94,26 @@ wlda_status wlda_create(const wlda_params *p, const uint32_t *word_ids,
                         void *dev_workspace, uint64_t workspace_bytes,
                         void *hip_stream, wlda_sampler *out);
 
+/* Asymmetric document-topic prior (the alpha_k of Eq. (6)-(7) in their
+ * general form), replacing the symmetric alpha of wlda_params.  alpha is a
+ * host array of K binary32 values, each > 0 and finite (else
+ * WLDA_E_INVALID); it is copied into the workspace.  Only before the first
+ * wlda_init (else WLDA_E_STATE).  NULL returns to the symmetric alpha.
+ * With alpha_k:
+ *   - alpha_bar = sum_k alpha_k (binary64, in topic order), rounded to
+ *     binary32 for the doc proposals' coin u (L_d + alpha_bar) < L_d;
+ *   - the prior part of a doc proposal is topic k with probability
+ *     alpha_k / alpha_bar: with A_k the binary64 running sums of alpha_k and
+ *     r the proposal's index word, x = r 2^-32 A_{K-1} and the proposal is
+ *     the smallest k with A_k > x;
+ *   - the word proposals' acceptance rate pi_word of Eq. (7) reads
+ *     num = (C_dc + alpha_c)(C_s + beta_bar), den = (C_ds + alpha_s)(C_c + beta_bar)
+ *     (pi_doc does not involve alpha);
+ *   - wlda_log_likelihood's document part and wlda_theta use alpha_k.
+ * Saved states do not carry alpha_k: set it again before loading one into a
+ * new sampler.  Synchronises. */
+wlda_status wlda_set_alpha(wlda_sampler s, const float *alpha);
+
 /* Initialisation (Algorithm 2): z = Dice(K) for every token, then the first
  * M document proposals per token drawn from that Z by the document phase's
  * proposal rule, then c_k = histogram(Z).  May be called again to restart. */

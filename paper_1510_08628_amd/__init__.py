@@ -33,7 +33,8 @@ class Params(C.Structure):
 
 # Every symbol declared in include/warplda.h (checked by the CPU tests).
 EXPORTS = [
-    "wlda_workspace_bytes", "wlda_create", "wlda_init", "wlda_word_phase", "wlda_doc_phase",
+    "wlda_workspace_bytes", "wlda_create", "wlda_set_alpha", "wlda_init", "wlda_word_phase",
+    "wlda_doc_phase",
     "wlda_iterate", "wlda_log_likelihood", "wlda_copy_assignments",
     "wlda_copy_assignments_csc", "wlda_copy_topic_counts", "wlda_accepted", "wlda_iteration",
     "wlda_state_bytes", "wlda_save_state", "wlda_load_state", "wlda_set_assignments",
@@ -92,6 +93,7 @@ def load_library(path: str = LIB_PATH):
         "wlda_workspace_bytes": [P, vp, vp, u64, C.POINTER(u64)],
         "wlda_create": [P, vp, vp, u64, vp, u64, vp, C.POINTER(vp)],
         "wlda_init": [vp], "wlda_word_phase": [vp], "wlda_doc_phase": [vp],
+        "wlda_set_alpha": [vp, vp],
         "wlda_iterate": [vp, u32],
         "wlda_log_likelihood": [vp, C.POINTER(C.c_double)],
         "wlda_copy_assignments": [vp, vp, vp],
@@ -192,6 +194,17 @@ class Sampler:
             self.close()
         except Exception:
             pass
+
+    def set_alpha(self, alpha):
+        """Asymmetric document-topic prior alpha_k (K positive values, taken as
+        binary32), or None for the symmetric alpha; before the first init()."""
+        if alpha is None:
+            _check("wlda_set_alpha", load_library().wlda_set_alpha(self.h, None))
+            return
+        a = np.ascontiguousarray(alpha, dtype=np.float32)
+        if a.shape != (self.K,):
+            raise ValueError("alpha must hold K values")
+        _check("wlda_set_alpha", load_library().wlda_set_alpha(self.h, a.ctypes.data))
 
     def init(self):
         _check("wlda_init", load_library().wlda_init(self.h))

@@ -51,6 +51,32 @@ __device__ __forceinline__ bool mh_accept(float u, uint32_t cnt_c, uint32_t cnt_
     return mh_accept_b(u, cnt_c, cnt_s, prior, (float)ck_s + beta_bar, (float)ck_c + beta_bar);
 }
 
+// The same with a prior per topic (asymmetric alpha in the doc phase):
+// prior_c for the candidate, prior_s for the current state.  With
+// prior_c == prior_s == prior the result is that of mh_accept_b.
+__device__ __forceinline__ bool mh_accept_b2(float u, uint32_t cnt_c, uint32_t cnt_s, float prior_c,
+                                             float prior_s, float ckb_s, float ckb_c) {
+    const float num = ((float)cnt_c + prior_c) * ckb_s;
+    const float den = ((float)cnt_s + prior_s) * ckb_c;
+    return u * den < num;
+}
+
+// Prior part of a doc proposal under an asymmetric alpha: topic k with
+// probability alpha_k / alpha_bar, given the running sums cum[k] = alpha_0 +
+// ... + alpha_k in binary64: x = r 2^-32 cum[K-1] and the smallest k with
+// cum[k] > x (one exists, since x < cum[K-1]).  A search whose trip count
+// depends on K only.
+__device__ __forceinline__ uint32_t alpha_prior_topic(const double *cum, uint32_t K, uint32_t r) {
+    const double x = (double)r * 0x1p-32 * cum[K - 1];
+    uint32_t base = 0;
+    for (uint32_t n = K; n > 1;) {
+        const uint32_t half = n >> 1;
+        if (cum[base + half - 1] <= x) base += half;
+        n -= half;
+    }
+    return base;
+}
+
 // Mixture coin of the proposals (Section 4.3): the count part with
 // probability L / (L + mass).
 __device__ __forceinline__ bool take_count_part(float u, uint32_t L, float mass) {

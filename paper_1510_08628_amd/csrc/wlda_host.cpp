@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdint>
 #include <cstdio>
 #include <cstdlib>
@@ -227,7 +228,7 @@ inline uint64_t zc_bytes(const PhasePlan &pl, uint32_t K) {
 }
 
 struct Sizes {
-    uint64_t recs, colptr, rowptr, colidx, rowidx, ck, misc;
+    uint64_t recs, colptr, rowptr, colidx, rowidx, ck, alpha, misc;
     uint64_t plan_word, plan_doc;
     uint64_t total;
 };
@@ -249,10 +250,12 @@ Sizes compute_sizes(const wlda_params &p, uint64_t T, const PhasePlan &w, const 
     s.colidx = align_up(4ull * T + 4);
     s.rowidx = align_up(4ull * T + 4);
     s.ck = 2 * align_up(4ull * p.K);
+    s.alpha = align_up(4ull * p.K) + align_up(8ull * p.K);   // asymmetric alpha and its running sums
     s.misc = ALIGN;
     s.plan_word = plan_bytes(w, p.K);
     s.plan_doc = plan_bytes(d, p.K);
-    s.total = s.recs + s.colptr + s.rowptr + s.colidx + s.rowidx + s.ck + s.misc + s.plan_word + s.plan_doc;
+    s.total = s.recs + s.colptr + s.rowptr + s.colidx + s.rowidx + s.ck + s.alpha + s.misc + s.plan_word +
+              s.plan_doc;
     return s;
 }
 
@@ -318,6 +321,12 @@ struct wlda_sampler_s {
     int next_phase = 0;                  // 0: not initialised, 1: word, 2: doc
     bool broken = false;
     float a = 0, b = 0, alpha_bar = 0, beta_k = 0, beta_bar = 0;
+    // asymmetric alpha (wlda_set_alpha): alpha_k and its binary64 running
+    // sums on the device, and their total
+    bool asym = false;
+    float *d_alpha = nullptr;
+    double *d_alpha_cum = nullptr;
+    double alpha_total = 0;
     // profiling: event pairs per kernel kind
     bool prof = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pairs[KSLOTS];
@@ -458,6 +467,10 @@ wlda_status run_phase(wlda_sampler s, uint32_t phase, uint32_t iter, bool draw_o
     a.ck_next = s->ck[1 - s->cur];
     a.prior = phase == PH_WORD ? s->b : s->a;
     a.mass = phase == PH_WORD ? s->beta_k : s->alpha_bar;
+    if (phase == PH_DOC && s->asym) {
+        a.alpha_k = s->d_alpha;
+        a.alpha_cum = s->d_alpha_cum;
+    }
     a.beta_bar = s->beta_bar;
     a.accepted = s->acc + (phase == PH_WORD ? 0 : 1);
     a.draw_only = draw_only ? 1 : 0;
@@ -707,6 +720,8 @@ wlda_status wlda_create(const wlda_params *p, const uint32_t *word_ids, const ui
     s->rowidx = (uint32_t *)carve(cur, 4ull * T + 4);
     s->ck[0] = (uint32_t *)carve(cur, 4ull * p->K);
     s->ck[1] = (uint32_t *)carve(cur, 4ull * p->K);
+    s->d_alpha = (float *)carve(cur, 4ull * p->K);
+    s->d_alpha_cum = (double *)carve(cur, 8ull * p->K);
     uint8_t *misc = carve(cur, ALIGN);
     s->acc = (unsigned long long *)misc;
     s->ll = (double *)(misc + 16);
@@ -727,6 +742,37 @@ wlda_status wlda_create(const wlda_params *p, const uint32_t *word_ids, const ui
         return st;
     }
     *out = s;
+    return WLDA_OK;
+}
+
+wlda_status wlda_set_alpha(wlda_sampler s, const float *alpha) {
+    if (!s) return WLDA_E_INVALID;
+    if (s->broken) return WLDA_E_HIP;
+    if (s->next_phase != 0) return WLDA_E_STATE;
+    const uint32_t K = s->p.K;
+    if (!alpha) {
+        s->asym = false;
+        s->alpha_bar = (float)K * s->a;
+        return WLDA_OK;
+    }
+    std::vector<double> cum;
+    try {
+        cum.resize(K);
+    } catch (const std::bad_alloc &) {
+        return WLDA_E_NOMEM;
+    }
+    double run = 0.0;
+    for (uint32_t k = 0; k < K; ++k) {
+        if (!(alpha[k] > 0.0f) || !std::isfinite(alpha[k])) return WLDA_E_INVALID;
+        run += (double)alpha[k];
+        cum[k] = run;
+    }
+    WLDA_TRY(s, upload(s->d_alpha, alpha, 4ull * K, s->st));
+    WLDA_TRY(s, upload(s->d_alpha_cum, cum.data(), 8ull * K, s->st));
+    WLDA_TRY(s, hipStreamSynchronize(s->st));
+    s->asym = true;
+    s->alpha_total = run;
+    s->alpha_bar = (float)run;
     return WLDA_OK;
 }
 
@@ -785,17 +831,19 @@ wlda_status wlda_log_likelihood(wlda_sampler s, double *ll) {
         const uint32_t *segptr = ph == PH_WORD ? s->colptr : s->rowptr;
         const uint32_t *idx = ph == PH_WORD ? s->colidx : s->rowidx;
         const double prior = ph == PH_WORD ? s->p.beta : s->p.alpha;
-        const double total = ph == PH_WORD ? 0.0 : (double)K * s->p.alpha;
+        const bool asym = ph == PH_DOC && s->asym;
+        const double total = ph == PH_WORD ? 0.0 : (asym ? s->alpha_total : (double)K * s->p.alpha);
         const int lt = ph == PH_DOC;
         for (const BinList &b : pl.bins)
             WLDA_TRY(s, launch_ll_list(s->recs, s->p.M, segptr, idx, b.d_ids, (uint32_t)b.ids.size(), K,
-                                       prior, total, lt, s->ll, s->st));
+                                       prior, total, lt, s->ll, s->st, asym ? s->d_alpha : nullptr));
         PhaseArgs a;
         a.recs = s->recs;
         a.rf = record_format(s->p.M, s->p.K);
         a.segptr = segptr;
         a.idx = idx;
         a.K = K;
+        a.alpha_k = asym ? s->d_alpha : nullptr;
         WLDA_TRY(s, launch_ll_long(a, ph, s->p.M, long_list(pl), prior, total, lt, s->ll, s->st));
     }
     WLDA_TRY(s, launch_ll_topics(s->ck[s->cur], K, (double)s->p.V * s->p.beta, s->ll, s->st));
@@ -808,7 +856,8 @@ wlda_status wlda_theta(wlda_sampler s, uint32_t d0, uint32_t nd, float *theta) {
     if (!s || !theta || (uint64_t)d0 + nd > s->p.D) return WLDA_E_INVALID;
     if (s->broken) return WLDA_E_HIP;
     if (s->next_phase == 0) return WLDA_E_STATE;
-    WLDA_TRY(s, launch_theta(s->recs, s->p.M, s->rowptr, s->rowidx, d0, nd, s->p.K, (float)s->p.alpha, theta,
+    WLDA_TRY(s, launch_theta(s->recs, s->p.M, s->rowptr, s->rowidx, d0, nd, s->p.K, s->a,
+                             s->asym ? s->d_alpha : nullptr, s->alpha_bar, theta,
                              s->st));
     return WLDA_OK;
 }

@@ -84,7 +84,11 @@ struct PhaseArgs {
     const uint32_t *ck = nullptr;      // c_k at the start of the phase
     uint32_t *ck_next = nullptr;       // histogram of the phase's new Z
     float prior = 0.f;                 // beta (word phase) or alpha (doc phase)
-    float mass = 0.f;                  // K beta or K alpha
+    float mass = 0.f;                  // K beta or alpha_bar
+    // doc phase with an asymmetric alpha (else null): alpha_k as binary32 and
+    // its running sums in binary64 (K entries each)
+    const float *alpha_k = nullptr;
+    const double *alpha_cum = nullptr;
     float beta_bar = 0.f;              // V beta
     unsigned long long *accepted = nullptr;
     uint32_t draw_only = 0;            // initial proposal draw (no MH)
@@ -163,19 +167,22 @@ hipError_t launch_long_segments(const PhaseArgs &a, uint32_t phase, uint32_t M,
 hipError_t launch_histogram_z(const uint64_t *recs, uint32_t T, uint32_t M, uint32_t K,
                               uint32_t *ck, hipStream_t st);
 // LL: adds the document, word and topic parts into *out (binary64).
-// Per segment: sum over nonzero counts c of lgamma(prior + c) - lgamma(prior),
-// plus lgamma(prior_total) - lgamma(prior_total + L) when length_term != 0.
+// Per segment: sum over nonzero counts c of lgamma(prior + c) - lgamma(prior)
+// (prior = alpha_k[topic] when alpha_k is given: asymmetric alpha), plus
+// lgamma(prior_total) - lgamma(prior_total + L) when length_term != 0.
 // LL parts over the segments of a list (at most block_max tokens each) and
 // over the long segments (through their global tables, which are left zeroed).
 hipError_t launch_ll_list(const uint64_t *recs, uint32_t M, const uint32_t *segptr,
                           const uint32_t *idx, const uint32_t *ids, uint32_t n, uint32_t K,
                           double prior, double prior_total, int length_term, double *out,
-                          hipStream_t st);
+                          hipStream_t st, const float *alpha_k = nullptr);
+// (takes alpha_k from a)
 hipError_t launch_ll_long(const PhaseArgs &a, uint32_t phase, uint32_t M, const LongList &l,
                           double prior, double prior_total, int length_term, double *out,
                           hipStream_t st);
 hipError_t launch_theta(const uint64_t *recs, uint32_t M, const uint32_t *rowptr, const uint32_t *rowidx,
-                        uint32_t d0, uint32_t nd, uint32_t K, float alpha, float *out, hipStream_t st);
+                        uint32_t d0, uint32_t nd, uint32_t K, float alpha, const float *alpha_k,
+                        float alpha_bar, float *out, hipStream_t st);
 hipError_t launch_phi(const uint64_t *recs, uint32_t M, const uint32_t *colptr, const uint32_t *colidx,
                       const uint32_t *ck, uint32_t w0, uint32_t nw, uint32_t K, float beta, float beta_bar,
                       float *out, hipStream_t st);

@@ -58,7 +58,7 @@ __global__ __launch_bounds__(256) void ll_seg_kernel(const uint64_t *recs, const
                                                      const uint32_t *idx, const uint32_t *ids,
                                                      uint32_t n_seg, uint32_t K, uint32_t dense_u,
                                                      double prior, double prior_total,
-                                                     int length_term, double *out) {
+                                                     int length_term, const float *alpha_k, double *out) {
     extern __shared__ uint32_t cnt[];
     const bool dense = dense_u != 0;
     const double lg_prior = lgamma(prior), lg_total = lgamma(prior_total);
@@ -79,7 +79,13 @@ __global__ __launch_bounds__(256) void ll_seg_kernel(const uint64_t *recs, const
         __syncthreads();
         for (uint32_t k = threadIdx.x; k < cap; k += 256) {
             const uint32_t v = c[k];
-            if (v) acc += lgamma(prior + (double)v) - lg_prior;
+            if (!v) continue;
+            if (alpha_k) {      // asymmetric alpha: the prior of this topic
+                const double pk = (double)alpha_k[dense ? k : key[k]];
+                acc += lgamma(pk + (double)v) - lgamma(pk);
+            } else {
+                acc += lgamma(prior + (double)v) - lg_prior;
+            }
         }
         if (length_term && threadIdx.x == 0) acc += lg_total - lgamma(prior_total + (double)L);
         __syncthreads();
@@ -92,7 +98,7 @@ __global__ __launch_bounds__(256) void ll_seg_kernel(const uint64_t *recs, const
 // histogram pass); the tables are zeroed afterwards.
 __global__ __launch_bounds__(256) void ll_tables_kernel(LongList l, const uint32_t *segptr, uint32_t K,
                                                         double prior, double prior_total,
-                                                        int length_term, double *out) {
+                                                        int length_term, const float *alpha_k, double *out) {
     const double lg_prior = lgamma(prior), lg_total = lgamma(prior_total);
     double acc = 0;
     for (uint32_t j = blockIdx.x; j < l.n; j += gridDim.x) {
@@ -102,7 +108,13 @@ __global__ __launch_bounds__(256) void ll_tables_kernel(LongList l, const uint32
         uint32_t *c = cap ? base + cap : base;
         for (uint32_t k = threadIdx.x; k < nslots; k += 256) {
             const uint32_t v = c[k];
-            if (v) acc += lgamma(prior + (double)v) - lg_prior;
+            if (!v) continue;
+            if (alpha_k) {      // asymmetric alpha (hashed keys are topic + 1)
+                const double pk = (double)alpha_k[cap ? base[k] - 1 : k];
+                acc += lgamma(pk + (double)v) - lgamma(pk);
+            } else {
+                acc += lgamma(prior + (double)v) - lg_prior;
+            }
         }
         if (length_term && threadIdx.x == 0) {
             const uint32_t s = l.ids[j];
@@ -114,11 +126,13 @@ __global__ __launch_bounds__(256) void ll_tables_kernel(LongList l, const uint32
 }
 
 // theta_hat of Eq. (4) (alpha' = alpha + 1): out[d - d0][k] =
-// (C_dk + alpha) / (L_d + K alpha) for documents d0 .. d0 + nd - 1.
+// (C_dk + alpha_k) / (L_d + alpha_bar) for documents d0 .. d0 + nd - 1
+// (alpha_k = alpha when alpha_k is null).
 template <int NW>
 __global__ __launch_bounds__(256) void theta_kernel(const uint64_t *recs, const uint32_t *rowptr,
                                                     const uint32_t *rowidx, uint32_t d0, uint32_t nd,
-                                                    uint32_t K, float alpha, float *out) {
+                                                    uint32_t K, float alpha, const float *alpha_k,
+                                                    float alpha_bar, float *out) {
     extern __shared__ uint32_t cnt[];
     for (uint32_t d = d0 + blockIdx.x; d < d0 + nd; d += gridDim.x) {
         const uint32_t beg = rowptr[d], L = rowptr[d + 1] - beg;
@@ -127,9 +141,9 @@ __global__ __launch_bounds__(256) void theta_kernel(const uint64_t *recs, const 
         for (uint32_t n = threadIdx.x; n < L; n += 256)
             atomicAdd(&cnt[fld(ld_rec<NW>(recs, rowidx[beg + n]), 0)], 1u);
         __syncthreads();
-        const float den = (float)L + (float)K * alpha;
+        const float den = (float)L + alpha_bar;
         for (uint32_t k = threadIdx.x; k < K; k += 256)
-            out[(size_t)(d - d0) * K + k] = ((float)cnt[k] + alpha) / den;
+            out[(size_t)(d - d0) * K + k] = ((float)cnt[k] + (alpha_k ? alpha_k[k] : alpha)) / den;
         __syncthreads();
     }
 }
@@ -240,7 +254,7 @@ hipError_t launch_histogram_z(const uint64_t *recs, uint32_t T, uint32_t M, uint
 
 hipError_t launch_ll_list(const uint64_t *recs, uint32_t M, const uint32_t *segptr, const uint32_t *idx,
                           const uint32_t *ids, uint32_t n, uint32_t K, double prior, double prior_total,
-                          int length_term, double *out, hipStream_t st) {
+                          int length_term, double *out, hipStream_t st, const float *alpha_k) {
     if (n == 0) return hipSuccess;
     const bool dense = K <= Tuning::LDS_DENSE_MAX;
     const size_t lds = dense ? 4ull * K : 4ull * 2 * 2 * Tuning::WIDE_MAX;
@@ -250,7 +264,7 @@ hipError_t launch_ll_list(const uint64_t *recs, uint32_t M, const uint32_t *segp
         hipError_t e = launch_dyn(ll_seg_kernel<RF>, lds);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(ll_seg_kernel<RF>, dim3(blocks), dim3(256), lds, st, recs, segptr, idx, ids, n, K,
-                           (uint32_t)dense, prior, prior_total, length_term, out);
+                           (uint32_t)dense, prior, prior_total, length_term, alpha_k, out);
         return hipGetLastError();
     });
 }
@@ -271,13 +285,14 @@ hipError_t launch_ll_long(const PhaseArgs &a, uint32_t phase, uint32_t M, const 
     }
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(ll_tables_kernel, dim3(l.n < 1024 ? l.n : 1024), dim3(256), 0, st, l, a.segptr, a.K, prior,
-                       prior_total, length_term, out);
+                       prior_total, length_term, a.alpha_k, out);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     return launch_fill_u32(l.tables, 0, l.table_words, st);
 }
 
 hipError_t launch_theta(const uint64_t *recs, uint32_t M, const uint32_t *rowptr, const uint32_t *idx,
-                        uint32_t d0, uint32_t nd, uint32_t K, float alpha, float *out, hipStream_t st) {
+                        uint32_t d0, uint32_t nd, uint32_t K, float alpha, const float *alpha_k,
+                        float alpha_bar, float *out, hipStream_t st) {
     if (nd == 0) return hipSuccess;
     if (K > LL_DENSE_MAX) return hipErrorNotSupported;
     const size_t lds = 4ull * K;
@@ -287,7 +302,7 @@ hipError_t launch_theta(const uint64_t *recs, uint32_t M, const uint32_t *rowptr
         hipError_t e = launch_dyn(theta_kernel<RF>, lds);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(theta_kernel<RF>, dim3(blocks), dim3(256), lds, st, recs, rowptr, idx, d0, nd, K,
-                           alpha, out);
+                           alpha, alpha_k, alpha_bar, out);
         return hipGetLastError();
     });
 }

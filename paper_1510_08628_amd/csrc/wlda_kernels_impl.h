@@ -333,12 +333,13 @@ __device__ __forceinline__ void add_accepted(unsigned long long *dst, unsigned l
 // list are taken in ascending order so that the rows visited at the same time
 // are neighbours (their tokens share cache lines of each column, Section 5.2).
 // --------------------------------------------------------------------------
-template <int PHASE, int M, int NW, int GROUP, int TPT, bool CDF, bool CKG, bool PK>
+template <int PHASE, int M, int NW, int GROUP, int TPT, bool CDF, bool CKG, bool PK, bool ASYM>
 __global__ __launch_bounds__(256) void seg_kernel(PhaseArgs a, SegList l, uint32_t cap_max,
                                                   uint32_t dense_u, uint32_t ck_lds_u) {
     extern __shared__ uint32_t lds[];
     constexpr int GPB = 256 / GROUP;
     static_assert(TPT * (M + 1) <= 64, "one bit per lookup of a lane's tokens");
+    static_assert(!ASYM || PHASE == PH_DOC, "alpha_k enters the doc phase only");
     // ck_lds_u: bit 0 = the c_k histogram of the new Z in LDS, bit 1 = c_k +
     // beta_bar staged in LDS (what fits the LDS budget; see run_seg)
     const bool dense = dense_u != 0, ckh_lds = (ck_lds_u & 1u) != 0, ckb_lds = (ck_lds_u & 2u) != 0;
@@ -425,6 +426,14 @@ __global__ __launch_bounds__(256) void seg_kernel(PhaseArgs a, SegList l, uint32
 #pragma unroll
                     for (int f = 0; f <= M; ++f) gck[r][f] = (float)a.ck[fld(rec[r], f)] + beta_bar;
             }
+            // alpha of the same topics under an asymmetric alpha
+            float gal[ASYM ? TPT : 1][M + 1];
+            if constexpr (ASYM) {
+#pragma unroll
+                for (int r = 0; r < TPT; ++r)
+#pragma unroll
+                    for (int f = 0; f <= M; ++f) gal[r][f] = a.alpha_k[fld(rec[r], f)];
+            }
 #pragma unroll
             for (int r = 0; r < TPT; ++r)
                 if (r * GROUP + lane < L) {
@@ -475,8 +484,9 @@ __global__ __launch_bounds__(256) void seg_kernel(PhaseArgs a, SegList l, uint32
             for (int r = 0; r < TPT; ++r) {
                 if (r * GROUP + lane < L) {
                     uint32_t s = fld(rec[r], 0), cs = cnt[r][0];
-                    float bs;
+                    float bs, as = prior;
                     if constexpr (CKG) bs = gck[r][0]; else bs = ckb[s];
+                    if constexpr (ASYM) as = gal[r][0];
                     const uint4 RA = philox(beg + r * GROUP + lane, a.iter, ph, 0, a.seed_lo, a.seed_hi);
 #pragma unroll
                     for (int i = 1; i <= M; ++i) {
@@ -484,10 +494,16 @@ __global__ __launch_bounds__(256) void seg_kernel(PhaseArgs a, SegList l, uint32
                         const float u = unif24(word4(RA, i - 1));
                         float bc;
                         if constexpr (CKG) bc = gck[r][i]; else bc = ckb[c];
-                        if (mh_accept_b(u, cc, cs, prior, bs, bc)) {
+                        bool ok;
+                        if constexpr (ASYM)
+                            ok = mh_accept_b2(u, cc, cs, gal[r][i], as, bs, bc);
+                        else
+                            ok = mh_accept_b(u, cc, cs, prior, bs, bc);
+                        if (ok) {
                             s = c;
                             cs = cc;
                             bs = bc;
+                            if constexpr (ASYM) as = gal[r][i];
                             ++acc;
                         }
                     }
@@ -561,6 +577,8 @@ __global__ __launch_bounds__(256) void seg_kernel(PhaseArgs a, SegList l, uint32
                             const uint32_t w = word4(RB, 2 * h + 1);
                             if (take_count_part(unif24(word4(RB, 2 * h)), L, mass))
                                 pw[q * M + i - 1] = zarr[dice(w, L)];
+                            else if constexpr (ASYM)
+                                pw[q * M + i - 1] = alpha_prior_topic(a.alpha_cum, K, w);
                             else
                                 pw[q * M + i - 1] = dice(w, K);
                         }
@@ -798,8 +816,16 @@ __global__ __launch_bounds__(256) void long_mh_kernel(PhaseArgs a, LongList l, u
                         cc = gtab_get(gt, gcap, c);
                         cs = gtab_get(gt, gcap, s);
                     }
-                    const bool ok = ck_lds ? mh_accept_b(uacc, cc, cs, a.prior, ckb[s], ckb[c])
-                                           : mh_accept(uacc, cc, cs, a.prior, a.ck[s], a.ck[c], a.beta_bar);
+                    float pc = a.prior, ps = a.prior;
+                    if constexpr (PHASE == PH_DOC) {
+                        if (a.alpha_k) {        // asymmetric alpha
+                            pc = a.alpha_k[c];
+                            ps = a.alpha_k[s];
+                        }
+                    }
+                    const bool ok = ck_lds ? mh_accept_b2(uacc, cc, cs, pc, ps, ckb[s], ckb[c])
+                                           : mh_accept_b2(uacc, cc, cs, pc, ps, (float)a.ck[s] + a.beta_bar,
+                                                          (float)a.ck[c] + a.beta_bar);
                     if (ok) {
                         s = c;
                         ++acc;
@@ -936,6 +962,8 @@ __global__ __launch_bounds__(256) void long_draw_kernel(PhaseArgs a, LongList l,
                             coin |= 1u << (u * M + i - 1);
                             jj[u * M + i - 1] = dice(w, L);
                             if (!by_cdf) set_fld(rec[u], i, (uint32_t)zs[jj[u * M + i - 1]]);
+                        } else if (PHASE == PH_DOC && a.alpha_cum) {
+                            set_fld(rec[u], i, alpha_prior_topic(a.alpha_cum, K, w));
                         } else {
                             set_fld(rec[u], i, dice(w, K));
                         }
@@ -1035,15 +1063,24 @@ static hipError_t run_seg(const PhaseArgs &a, const SegList &l, uint32_t cap_bou
             // dense tables of K < GROUP * TPT words always leave room for c_k
             // + beta_bar; there is no variant without it
             if (!ckb_lds) return hipErrorNotSupported;
-            return go(seg_kernel<PHASE, M, NW, GROUP, TPT, true, false, false>);
+            return go(seg_kernel<PHASE, M, NW, GROUP, TPT, true, false, false, false>);
+        }
+    } else {
+        if (a.alpha_k) {    // asymmetric alpha: doc-phase variants with alpha_k
+            if (packed) {
+                if (!ckb_lds) return go(seg_kernel<PHASE, M, NW, GROUP, TPT, false, true, true, true>);
+                return go(seg_kernel<PHASE, M, NW, GROUP, TPT, false, false, true, true>);
+            }
+            if (!ckb_lds) return go(seg_kernel<PHASE, M, NW, GROUP, TPT, false, true, false, true>);
+            return go(seg_kernel<PHASE, M, NW, GROUP, TPT, false, false, false, true>);
         }
     }
     if (packed) {
-        if (!ckb_lds) return go(seg_kernel<PHASE, M, NW, GROUP, TPT, false, true, true>);
-        return go(seg_kernel<PHASE, M, NW, GROUP, TPT, false, false, true>);
+        if (!ckb_lds) return go(seg_kernel<PHASE, M, NW, GROUP, TPT, false, true, true, false>);
+        return go(seg_kernel<PHASE, M, NW, GROUP, TPT, false, false, true, false>);
     }
-    if (!ckb_lds) return go(seg_kernel<PHASE, M, NW, GROUP, TPT, false, true, false>);
-    return go(seg_kernel<PHASE, M, NW, GROUP, TPT, false, false, false>);
+    if (!ckb_lds) return go(seg_kernel<PHASE, M, NW, GROUP, TPT, false, true, false, false>);
+    return go(seg_kernel<PHASE, M, NW, GROUP, TPT, false, false, false, false>);
 }
 
 // Calls f(std::integral_constant<int, RF>) for the record format rf of M
