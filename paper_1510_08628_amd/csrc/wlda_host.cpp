@@ -337,9 +337,14 @@ struct wlda_sampler_s {
     // bin: [word g16, g32, wave, block, wide, doc g16, g32, wave, block, wide];
     // set from the CU count at create, overridable with WLDA_SEG_BLOCKS (ten
     // comma-separated values)
-    uint32_t seg_blocks[2 * NBINS] = {768, 768, 768, 1024, 768, 512, 512, 512, 768, 512};
+    uint32_t seg_blocks[2 * NBINS] = {768, 768, 768, 1024, 768, 768, 768, 512, 768, 512};
     // grid bound of the long-segment kernels [word, doc]; WLDA_LONG_BLOCKS="a,b"
     uint32_t long_blocks[2] = {4096, 2048};
+    // LDS bytes per segment workgroup within which c_k is staged: the CU's
+    // LDS shared by the workgroups per CU the bin runs at (seg_blocks / CUs);
+    // WLDA_SEG_LDS_KIB sets one budget for all bins
+    uint32_t cus = 256;
+    uint32_t seg_lds_budget = 0;
 };
 
 namespace {
@@ -484,6 +489,12 @@ wlda_status run_phase(wlda_sampler s, uint32_t phase, uint32_t iter, bool draw_o
         const BinList &b = pl.bins[bin];
         const SegList l{b.d_ids, (uint32_t)b.ids.size(), b.d_cut, b.d_span};
         a.max_blocks = s->seg_blocks[kb + bin];
+        if (s->seg_lds_budget) {
+            a.seg_lds_budget = s->seg_lds_budget;
+        } else {
+            const uint32_t per_cu = std::max(1u, a.max_blocks / s->cus);
+            a.seg_lds_budget = std::min(Tuning::LDS_PER_CU / per_cu, Tuning::SEG_LDS_BUDGET);
+        }
         auto launch = [&] {
             return launch_segments(a, phase, s->p.M, l, bin, s->st);
         };
@@ -624,17 +635,22 @@ wlda_status wlda_create(const wlda_params *p, const uint32_t *word_ids, const ui
         // fill (4 per CU costs the row kernel 20%); the word phase's column
         // kernels peak at 2-3.  The long-segment kernels stream chunks and
         // want many more.  Multiples of the CU count keep every CU of an XCD
-        // equally loaded.  For M > 2 the sub-workgroup bins hold half as many
-        // tokens per lane, and the doc phase's run best at three per CU
-        // (measured on the PubMed-shaped corpus, K = 1e4, M = 4).
-        static const uint32_t per_cu[2 * NBINS] = {3, 3, 3, 4, 3, 2, 2, 2, 3, 2};
+        // equally loaded.  The doc phase's 16- and 32-lane groups (used where
+        // K > 1024) run at three per CU, which their LDS allows with the
+        // 16-bit c_k histogram; for M > 2 the sub-workgroup bins hold half as
+        // many tokens per lane, and the 16-lane groups run at four, the wave
+        // kernel at three (measured on the PubMed-shaped corpus, K = 1e4).
+        static const uint32_t per_cu[2 * NBINS] = {3, 3, 3, 4, 3, 3, 3, 2, 3, 2};
         static const uint32_t long_per_cu[2] = {16, 8};
         int dev = 0, cus = 0;
         if (hipGetDevice(&dev) == hipSuccess &&
             hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0) {
+            s->cus = (uint32_t)cus;
             for (int i = 0; i < 2 * NBINS; ++i) {
-                const bool doc_narrow = i >= NBINS && i < NBINS + BIN_BLOCK;
-                s->seg_blocks[i] = (p->M > 2 && doc_narrow ? 3u : per_cu[i]) * (uint32_t)cus;
+                uint32_t pc = per_cu[i];
+                if (p->M > 2 && i == NBINS + BIN_G16) pc = 4;
+                if (p->M > 2 && i == NBINS + BIN_WAVE) pc = 3;
+                s->seg_blocks[i] = pc * (uint32_t)cus;
             }
             for (int i = 0; i < 2; ++i) s->long_blocks[i] = long_per_cu[i] * (uint32_t)cus;
         }
@@ -643,6 +659,10 @@ wlda_status wlda_create(const wlda_params *p, const uint32_t *word_ids, const ui
         unsigned v[2];
         if (std::sscanf(env, "%u,%u", &v[0], &v[1]) == 2)
             for (int i = 0; i < 2; ++i) s->long_blocks[i] = v[i] < 8 ? 8 : (v[i] > 65536 ? 65536 : v[i]);
+    }
+    if (const char *env = std::getenv("WLDA_SEG_LDS_KIB")) {
+        const int v = std::atoi(env);
+        if (v >= 1 && v <= 160) s->seg_lds_budget = (uint32_t)v * 1024u;
     }
     if (const char *env = std::getenv("WLDA_SEG_BLOCKS")) {
         unsigned v[2 * NBINS];

@@ -76,6 +76,37 @@ struct LongList {
     uint32_t *tables_new = nullptr;
 };
 
+struct Tuning {
+    // wave kernel (and the 16- and 32-lane groups): TPT_WAVE tokens per lane,
+    // half as many for M > 2, whose counts and records take twice the registers
+    static constexpr int TPT_WAVE = 8;
+    // block kernels (one 256-thread workgroup per segment): the narrow one
+    // keeps TPT_BLOCK tokens per thread in registers (high occupancy), the
+    // wide one twice as many; M > 2 halves both (two-word records)
+    static constexpr int TPT_BLOCK = 8;
+    static constexpr int TPT_WIDE = 16;
+    static constexpr uint32_t WIDE_MAX = 256 * TPT_WIDE;     // longest segment below the long path
+    // segment kernels: LDS bytes per workgroup within which the c_k
+    // histogram and c_k + beta_bar are staged: the CU's LDS over the
+    // workgroups per CU a bin runs at, at most SEG_LDS_BUDGET
+    static constexpr uint32_t LDS_PER_CU = 160 * 1024;
+    static constexpr uint32_t SEG_LDS_BUDGET = 80 * 1024;
+    // beyond the budget: c_k histogram / c_k + beta_bar in LDS up to these K
+    static constexpr uint32_t CK_LDS_MAX = 4096;
+    static constexpr uint32_t CKB_LDS_MAX = 16384;
+    // long kernels: c_k + beta_bar (MH pass) and the c_k histogram (draw pass)
+    // in LDS; they run few workgroups per CU anyway, where the segment kernels
+    // would lose half their occupancy to a K-word histogram
+    static constexpr uint32_t LONG_CK_LDS_MAX = 16384;
+    // tokens per long-path chunk: LONG_CHUNK when the chunk histogram is a
+    // dense LDS array (K <= LDS_DENSE_MAX), else LONG_CHUNK_HASHED so that the
+    // LDS hash table (2 * LONG_CHUNK_HASHED slots) always has free slots
+    static constexpr uint32_t LONG_CHUNK = 8192;
+    static constexpr uint32_t LONG_CHUNK_HASHED = 4096;
+    static constexpr uint32_t LDS_DENSE_MAX = 16384;         // dense LDS counts up to this K
+    static constexpr uint32_t CDF_LDS_MAX = 16384;           // long-word prefix counts in LDS
+};
+
 struct PhaseArgs {
     uint64_t *recs = nullptr;
     const uint32_t *segptr = nullptr;
@@ -93,37 +124,10 @@ struct PhaseArgs {
     unsigned long long *accepted = nullptr;
     uint32_t draw_only = 0;            // initial proposal draw (no MH)
     uint32_t max_blocks = 2048;        // grid bound of the segment kernels (launch shape only)
+    uint32_t seg_lds_budget = Tuning::SEG_LDS_BUDGET;   // LDS bytes per segment workgroup (launch shape only)
     int rf = 1;                        // record format (see record_format)
 };
 
-struct Tuning {
-    // wave kernel (and the 16- and 32-lane groups): TPT_WAVE tokens per lane,
-    // half as many for M > 2, whose counts and records take twice the registers
-    static constexpr int TPT_WAVE = 8;
-    // block kernels (one 256-thread workgroup per segment): the narrow one
-    // keeps TPT_BLOCK tokens per thread in registers (high occupancy), the
-    // wide one twice as many; M > 2 halves both (two-word records)
-    static constexpr int TPT_BLOCK = 8;
-    static constexpr int TPT_WIDE = 16;
-    static constexpr uint32_t WIDE_MAX = 256 * TPT_WIDE;     // longest segment below the long path
-    // segment kernels: LDS bytes per workgroup within which the c_k
-    // histogram and c_k + beta_bar are staged (two workgroups per CU fit)
-    static constexpr uint64_t SEG_LDS_BUDGET = 80 * 1024;
-    // beyond the budget: c_k histogram / c_k + beta_bar in LDS up to these K
-    static constexpr uint32_t CK_LDS_MAX = 4096;
-    static constexpr uint32_t CKB_LDS_MAX = 16384;
-    // long kernels: c_k + beta_bar (MH pass) and the c_k histogram (draw pass)
-    // in LDS; they run few workgroups per CU anyway, where the segment kernels
-    // would lose half their occupancy to a K-word histogram
-    static constexpr uint32_t LONG_CK_LDS_MAX = 16384;
-    // tokens per long-path chunk: LONG_CHUNK when the chunk histogram is a
-    // dense LDS array (K <= LDS_DENSE_MAX), else LONG_CHUNK_HASHED so that the
-    // LDS hash table (2 * LONG_CHUNK_HASHED slots) always has free slots
-    static constexpr uint32_t LONG_CHUNK = 8192;
-    static constexpr uint32_t LONG_CHUNK_HASHED = 4096;
-    static constexpr uint32_t LDS_DENSE_MAX = 16384;         // dense LDS counts up to this K
-    static constexpr uint32_t CDF_LDS_MAX = 16384;           // long-word prefix counts in LDS
-};
 
 // Word proposals (count part): columns longer than K tokens (the words
 // Section 5.4 processes with intra-word parallelism and samples from a table

@@ -333,6 +333,22 @@ __device__ __forceinline__ void add_accepted(unsigned long long *dst, unsigned l
 // list are taken in ascending order so that the rows visited at the same time
 // are neighbours (their tokens share cache lines of each column, Section 5.2).
 // --------------------------------------------------------------------------
+// c_k histogram of 16-bit counters, two to a 32-bit LDS word (topic k in
+// half k & 1 of word k >> 1).  A counter never reaches 2^16: the one add that
+// takes it from 0x7FFF to 0x8000 (the atomic returns each old value exactly
+// once) moves 0x8000 to the global count and takes it off the counter again;
+// for the counter to wrap before that, the workgroup would have to add 2^15
+// more tokens of that topic between two consecutive LDS operations of one
+// wavefront.
+__device__ __forceinline__ void ckh16_add(uint32_t *ckh, uint32_t k, uint32_t *ck_next) {
+    const uint32_t sh = (k & 1u) << 4;
+    const uint32_t old = atomicAdd(&ckh[k >> 1], 1u << sh);
+    if (((old >> sh) & 0xFFFFu) == 0x7FFFu) {
+        atomicSub(&ckh[k >> 1], 0x8000u << sh);
+        atomicAdd(&ck_next[k], 0x8000u);
+    }
+}
+
 template <int PHASE, int M, int NW, int GROUP, int TPT, bool CDF, bool CKG, bool PK, bool ASYM>
 __global__ __launch_bounds__(256) void seg_kernel(PhaseArgs a, SegList l, uint32_t cap_max,
                                                   uint32_t dense_u, uint32_t ck_lds_u) {
@@ -343,11 +359,13 @@ __global__ __launch_bounds__(256) void seg_kernel(PhaseArgs a, SegList l, uint32
     // ck_lds_u: bit 0 = the c_k histogram of the new Z in LDS, bit 1 = c_k +
     // beta_bar staged in LDS (what fits the LDS budget; see run_seg)
     const bool dense = dense_u != 0, ckh_lds = (ck_lds_u & 1u) != 0, ckb_lds = (ck_lds_u & 2u) != 0;
+    const bool h16 = (ck_lds_u & 4u) != 0;   // histogram of 16-bit counters, two per word
     const uint32_t g = threadIdx.x / GROUP, lane = threadIdx.x % GROUP;
     const uint32_t K = a.K;
     // LDS: [c_k + beta_bar as binary32 (ckb_lds)] [c_k histogram of the new
     // Z (ckh_lds)], then per group [count table | new z of the segment]
-    const uint32_t ck_words = (ckb_lds ? K : 0) + (ckh_lds ? K : 0);
+    const uint32_t h_words = h16 ? (K + 1) / 2 : K;
+    const uint32_t ck_words = (ckb_lds ? K : 0) + (ckh_lds ? h_words : 0);
     // count table: dense K words, or cap_max packed words (PK), or cap_max
     // keys followed by cap_max counts
     const uint32_t tab_words = dense ? K : (PK ? cap_max : 2 * cap_max);
@@ -360,7 +378,7 @@ __global__ __launch_bounds__(256) void seg_kernel(PhaseArgs a, SegList l, uint32
 
     if (ckh_lds || ckb_lds)
         for (uint32_t i = threadIdx.x; i < K; i += 256) {
-            if (ckh_lds) ckh[i] = 0;
+            if (ckh_lds && i < h_words) ckh[i] = 0;
             if (ckb_lds) ckb[i] = (float)a.ck[i] + a.beta_bar;
         }
     if (dense)
@@ -594,10 +612,12 @@ __global__ __launch_bounds__(256) void seg_kernel(PhaseArgs a, SegList l, uint32
 #pragma unroll
                     for (int i = 1; i <= M; ++i) set_fld(out, i, pw[q * M + i - 1]);
                     st_rec<NW>(a.recs, pos[r], out);
-                    if (ckh_lds)
-                        atomicAdd(&ckh[znew[r]], 1u);
-                    else
+                    if (!ckh_lds)
                         atomicAdd(&a.ck_next[znew[r]], 1u);
+                    else if (h16)
+                        ckh16_add(ckh, znew[r], a.ck_next);
+                    else
+                        atomicAdd(&ckh[znew[r]], 1u);
                 }
             }
         }
@@ -622,7 +642,13 @@ __global__ __launch_bounds__(256) void seg_kernel(PhaseArgs a, SegList l, uint32
     }
     add_accepted(a.accepted, acc);
     __syncthreads();
-    if (ckh_lds) {
+    if (ckh_lds && h16) {
+        for (uint32_t w = threadIdx.x; w < h_words; w += 256) {
+            const uint32_t v = ckh[w];
+            if (v & 0xFFFFu) atomicAdd(&a.ck_next[2 * w], v & 0xFFFFu);
+            if (v >> 16) atomicAdd(&a.ck_next[2 * w + 1], v >> 16);
+        }
+    } else if (ckh_lds) {
         for (uint32_t k = threadIdx.x; k < K; k += 256) {
             const uint32_t v = ckh[k];
             if (v) atomicAdd(&a.ck_next[k], v);
@@ -1039,16 +1065,20 @@ static hipError_t run_seg(const PhaseArgs &a, const SegList &l, uint32_t cap_bou
     // a global atomic, which costs far more than a gather) and c_k + beta_bar
     // second (else read from global memory, all loads of a segment at once);
     // beyond the budget the old limits hold
+    // (the histogram of 16-bit counters above CK_LDS_MAX topics: half the LDS)
+    const bool h16 = a.K > Tuning::CK_LDS_MAX;
     const uint64_t tab_bytes = 4ull * GPB * (tab_words + GROUP * TPT), kb = 4ull * a.K;
-    bool ckh_lds = tab_bytes + kb <= Tuning::SEG_LDS_BUDGET;
-    bool ckb_lds = tab_bytes + (ckh_lds ? 2 : 1) * kb <= Tuning::SEG_LDS_BUDGET;
+    const uint64_t hb = h16 ? 4ull * ((a.K + 1) / 2) : kb;
+    const uint64_t budget = a.seg_lds_budget;
+    bool ckh_lds = tab_bytes + hb <= budget;
+    bool ckb_lds = tab_bytes + (ckh_lds ? hb : 0) + kb <= budget;
     if (!ckh_lds) {
         ckh_lds = a.K <= Tuning::CK_LDS_MAX;
         ckb_lds = a.K <= Tuning::CKB_LDS_MAX;
     }
-    const size_t lds = 4ull * ((ckh_lds ? a.K : 0) + (ckb_lds ? a.K : 0) + GPB * (tab_words + GROUP * TPT));
+    const size_t lds = (ckh_lds ? hb : 0) + (ckb_lds ? kb : 0) + tab_bytes;
     const uint32_t blocks = xcd_grid((l.n + GPB - 1) / GPB, a.max_blocks);
-    const uint32_t ck_flags = (uint32_t)ckh_lds | (uint32_t)ckb_lds << 1;
+    const uint32_t ck_flags = (uint32_t)ckh_lds | (uint32_t)ckb_lds << 1 | (uint32_t)(ckh_lds && h16) << 2;
     auto go = [&](auto kern) -> hipError_t {
         hipError_t e = launch_dyn(kern, lds);
         if (e != hipSuccess) return e;
