@@ -224,12 +224,14 @@ __global__ void colsum_kernel(int rows, int cols, const float *g, float *db) {
 // of val * g1[b].  The batch (CSR by document) is transposed into lists per
 // bucket u (count, exclusive scan, scatter), and one workgroup sums each
 // touched bucket's list into its gradient row: no atomics on the H-wide rows.
-// A batch with more nonzeros than the list holds (rowptr[B] > cap, known only
-// on the device) takes the atomic kernel instead; every kernel below reads
-// rowptr[B] and returns at once when it is not the one in charge.
+// A batch with more nonzeros than the list holds (rowptr[B] - rowptr[0] >
+// cap, known only on the device; rowptr may be a slice of a larger CSR, with
+// offsets into its idx and val) takes the atomic kernel instead; every kernel
+// below reads rowptr[0] and rowptr[B] and returns at once when it is not the
+// one in charge.
 __global__ __launch_bounds__(256) void embag_count_kernel(const uint32_t *rowptr, const uint32_t *idx, uint32_t B,
                                                           uint32_t cap, uint32_t *cnt) {
-    if (rowptr[B] > cap) return;
+    if (rowptr[B] - rowptr[0] > cap) return;
     const uint32_t b = blockIdx.x;
     for (uint32_t n = rowptr[b] + threadIdx.x; n < rowptr[b + 1]; n += 256) atomicAdd(&cnt[idx[n]], 1u);
 }
@@ -240,7 +242,7 @@ __global__ __launch_bounds__(256) void embag_count_kernel(const uint32_t *rowptr
 __global__ __launch_bounds__(1024) void embag_scan_kernel(const uint32_t *rowptr, uint32_t B, uint32_t cap,
                                                           uint32_t nb, const uint32_t *cnt, uint32_t *off,
                                                           uint32_t *cur) {
-    if (rowptr[B] > cap) return;
+    if (rowptr[B] - rowptr[0] > cap) return;
     __shared__ uint32_t wsum[16];
     const uint32_t wl = threadIdx.x & 63;
     uint32_t carry = 0;
@@ -283,7 +285,7 @@ __global__ __launch_bounds__(1024) void embag_scan_kernel(const uint32_t *rowptr
 __global__ __launch_bounds__(256) void embag_scatter_kernel(const uint32_t *rowptr, const uint32_t *idx,
                                                             const float *val, uint32_t B, uint32_t cap,
                                                             uint32_t *cur, uint2 *list) {
-    if (rowptr[B] > cap) return;
+    if (rowptr[B] - rowptr[0] > cap) return;
     const uint32_t b = blockIdx.x;
     for (uint32_t n = rowptr[b] + threadIdx.x; n < rowptr[b + 1]; n += 256) {
         const uint32_t q = atomicAdd(&cur[idx[n]], 1u);
@@ -296,7 +298,7 @@ __global__ __launch_bounds__(256) void embag_scatter_kernel(const uint32_t *rowp
 __global__ __launch_bounds__(256) void embag_wgrad_kernel(const uint32_t *rowptr, uint32_t B, uint32_t cap,
                                                           uint32_t nb, int H, const uint32_t *off,
                                                           const uint2 *list, const float *g1, float *dW1) {
-    if (rowptr[B] > cap) return;
+    if (rowptr[B] - rowptr[0] > cap) return;
     __shared__ uint2 ent[256];
     for (uint32_t u = blockIdx.x; u < nb; u += gridDim.x) {
         const uint32_t q0 = off[u], q1 = off[u + 1];
@@ -339,7 +341,7 @@ __global__ __launch_bounds__(256) void embag_wgrad_kernel(const uint32_t *rowptr
 __global__ __launch_bounds__(256) void embag_bwd_kernel(int H, const uint32_t *rowptr, const uint32_t *idx,
                                                         const float *val, const float *g1, float *dW1,
                                                         uint32_t B, uint32_t cap) {
-    if (rowptr[B] <= cap) return;
+    if (rowptr[B] - rowptr[0] <= cap) return;
     const int b = blockIdx.x;
     for (uint32_t n = rowptr[b]; n < rowptr[b + 1]; ++n)
         for (int j = threadIdx.x; j < H; j += 256)

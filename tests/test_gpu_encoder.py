@@ -84,6 +84,29 @@ def test_gradients_match_oracle(W, buckets, hidden, K, B):
     assert np.all(g_g[0][untouched] == 0)
 
 
+def test_gradients_of_a_batch_sliced_from_a_larger_csr(W):
+    """Training passes each batch as a slice of the whole corpus's CSR: rowptr
+    holds offsets into the full idx and val.  The transpose lists (capacity
+    counted from rowptr[0]) must take such a batch, and its forward pass and
+    gradients must equal the oracle's on the batch alone."""
+    buckets, hidden, K, B = 4000, 256, 90, 24
+    enc = W.Encoder(buckets, hidden, K, max_batch=B)
+    ws = synth.encoder_init_weights(buckets, hidden, K, 4)
+    enc.set_weights(ws)
+    docs, theta = batch(buckets, K, 640 + B, 8)
+    rowptr, idx, val = E.batch_features(buckets, docs)
+    lo = 640                            # a batch deep into the corpus:
+    assert rowptr[lo] > 4096 * B        # its offsets alone exceed the lists' capacity
+    sub_rp, sub_idx, sub_val = E.batch_features(buckets, docs[lo:lo + B])
+    loss_o, q_o, g_o = E.forward_backward(ws, sub_rp, sub_idx, sub_val, theta[lo:lo + B], round=True)
+    d_rp, d_idx, d_val, d_th = to_dev(rowptr, idx, val, theta.astype(np.float32))
+    loss_g, g_g = enc.gradients(d_rp[lo:lo + B + 1], d_idx, d_val, d_th[lo:lo + B])
+    assert abs(loss_g - loss_o) <= 1e-4 * abs(loss_o), (loss_g, loss_o)
+    q_g = enc.forward(d_rp[lo:lo + B + 1], d_idx, d_val).cpu().numpy()
+    assert np.abs(q_g - q_o).max() <= 1e-4
+    assert_grads_close(W.Encoder.NAMES, g_g, g_o, sub_idx)
+
+
 def test_gradients_past_transpose_capacity(W):
     """The first layer's gradient goes through per-bucket lists that hold 4096
     nonzeros per document of a full batch; a batch with more takes the atomic

@@ -315,3 +315,39 @@ def test_word_cdf_boundary_in_every_bin(W, K, M):
         s.doc_phase()
         o.doc_phase()
         assert_same(s, o, f"doc phase {it + 1}")
+
+
+@pytest.mark.parametrize("M", [2, 4])
+def test_topic_histogram_counter_overflow(W, M, monkeypatch):
+    """Above 4096 topics the row kernels count c_k of the new Z in 16-bit LDS
+    counters that move 0x8000 to the global count each time they reach it.
+    With every token on one topic and eight workgroups per bin, each
+    workgroup adds that topic 2^16 times or more, so the carry runs several
+    times; z, proposals and c_k must still match the oracle exactly."""
+    monkeypatch.setenv("WLDA_SEG_BLOCKS", "768,768,768,1024,768,8,8,8,8,8")
+    K = 5000
+    rng = np.random.default_rng(40 + M)
+    D = 12000
+    hi = 64 if M > 2 else 128          # every row in the 16-lane groups
+    lens = rng.integers(20, hi + 1, D)
+    T = int(lens.sum())
+    docs = np.repeat(np.arange(D, dtype=np.uint32), lens)
+    words = rng.integers(0, 50, T).astype(np.uint32)
+    perm = rng.permutation(T)
+    c = synth.Corpus(words[perm], docs[perm], 50, D)
+    s, o = make_pair(W, c, K, M, 0.01, 0.01, seed=6)
+    s.init()
+    o.init()
+    z0 = np.zeros(T, np.int32)
+    p0 = np.zeros((M, T), np.int32)
+    s.set_assignments(z0, p0)
+    o.set_csc_state(z0, p0)             # all equal: input and CSC order agree
+    for it in range(2):
+        s.word_phase()
+        o.word_phase()
+        assert_same(s, o, f"word phase {it + 1}")
+        s.doc_phase()
+        o.doc_phase()
+        assert_same(s, o, f"doc phase {it + 1}")
+        if it == 0:     # about 1.5 carries per workgroup in the first doc phase at least
+            assert o.topic_counts()[0] >= 8 * 0x8000 * 1.5
