@@ -105,6 +105,7 @@ struct Tuning {
     static constexpr uint32_t LONG_CHUNK_HASHED = 4096;
     static constexpr uint32_t LDS_DENSE_MAX = 16384;         // dense LDS counts up to this K
     static constexpr uint32_t CDF_LDS_MAX = 16384;           // long-word prefix counts in LDS
+    static constexpr uint32_t GUIDE_K_MAX = 4096;            // ... with a guide table for the search
 };
 
 struct PhaseArgs {

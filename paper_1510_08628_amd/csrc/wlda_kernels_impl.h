@@ -321,6 +321,40 @@ __device__ __forceinline__ void cdf_find_lds(const uint32_t *cum_generic, uint32
     for (int d = 0; d < N; ++d) j[d] = (uint32_t)(b[d] - cum) + (*b[d] <= j[d] ? 1u : 0u);
 }
 
+// The same inverse CDF narrowed by a guide table in LDS: guide[i] (i < nb) is
+// the smallest topic k with cum[k] > i << gs, so the answer for j lies in
+// [guide[j >> gs], guide[(j >> gs) + 1]] (the last bucket ends at K - 1) and a
+// search of that range, a few topics wide, finds it.  Same result as
+// cdf_find_lds.
+constexpr uint32_t GUIDE_MAX = 4096;     // guide entries (16-bit topics)
+template <int N>
+__device__ __forceinline__ void cdf_find_guided(const uint32_t *cum_generic, const uint16_t *guide, uint32_t gs,
+                                                uint32_t nb, uint32_t K, uint32_t (&j)[N]) {
+    lds_cu32 *cum = (lds_cu32 *)cum_generic;
+    uint32_t base[N], n[N];
+#pragma unroll
+    for (int d = 0; d < N; ++d) {
+        const uint32_t i = j[d] >> gs;
+        base[d] = guide[i];
+        n[d] = (i + 1 < nb ? (uint32_t)guide[i + 1] : K - 1) - base[d] + 1;
+    }
+    for (;;) {
+        bool open = false;
+#pragma unroll
+        for (int d = 0; d < N; ++d) {
+            if (n[d] > 1) {
+                const uint32_t half = n[d] >> 1;
+                if (cum[base[d] + half - 1] <= j[d]) base[d] += half;
+                n[d] -= half;
+                open = true;
+            }
+        }
+        if (!open) break;
+    }
+#pragma unroll
+    for (int d = 0; d < N; ++d) j[d] = base[d];
+}
+
 __device__ __forceinline__ void add_accepted(unsigned long long *dst, unsigned long long v) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
@@ -934,11 +968,13 @@ template <int PHASE, int M, int NW, typename ZT>
 __global__ __launch_bounds__(256) void long_draw_kernel(PhaseArgs a, LongList l, uint32_t ck_lds_u,
                                                         uint32_t zero_tables, uint32_t cdf_lds_u) {
     // LDS: [c_k histogram of the new Z (ck_lds) | prefix counts of the
-    // current word (cdf_lds, words past the inverse-CDF threshold)]
+    // current word (cdf_lds, words past the inverse-CDF threshold) | their
+    // guide table (bit 1 of cdf_lds_u)]
     extern __shared__ uint32_t ckh[];
-    const bool ck_lds = ck_lds_u != 0, cdf_lds = cdf_lds_u != 0;
+    const bool ck_lds = ck_lds_u != 0, cdf_lds = (cdf_lds_u & 1u) != 0, guided = (cdf_lds_u & 2u) != 0;
     const uint32_t K = a.K;
     uint32_t *cdfl = ckh + (ck_lds ? K : 0);
+    uint16_t *guide = reinterpret_cast<uint16_t *>(cdfl + K);
     const uint32_t ph = (uint32_t)PHASE << 16;
     const ZT *zc = reinterpret_cast<const ZT *>(l.zc);
     if (ck_lds) {
@@ -953,8 +989,22 @@ __global__ __launch_bounds__(256) void long_draw_kernel(PhaseArgs a, LongList l,
         const ZT *zs = zc + l.prefix[j];
         const bool by_cdf = PHASE == PH_WORD && word_cdf(L, K);
         const uint32_t *cum = l.tables_new + l.tab_off[j];
+        uint32_t gs = 0, n_bkt = 0;
         if (by_cdf && cdf_lds) {
             for (uint32_t k = threadIdx.x; k < K; k += 256) cdfl[k] = cum[k];
+            __syncthreads();
+        }
+        if (by_cdf && guided) {
+            // guide buckets of 2^gs token indices, at most GUIDE_MAX of them
+            while ((((uint64_t)L + (1u << gs) - 1) >> gs) > GUIDE_MAX) ++gs;
+            n_bkt = (uint32_t)(((uint64_t)L + (1u << gs) - 1) >> gs);
+            // topic k owns the indices [cum[k-1], cum[k]): the buckets that
+            // start there point to it (every bucket is written once)
+            for (uint32_t k = threadIdx.x; k < K; k += 256) {
+                const uint64_t c0 = k ? cdfl[k - 1] : 0u, c1 = cdfl[k];
+                const uint32_t i1 = (uint32_t)min<uint64_t>(n_bkt, (c1 + (1u << gs) - 1) >> gs);
+                for (uint32_t i = (uint32_t)((c0 + (1u << gs) - 1) >> gs); i < i1; ++i) guide[i] = (uint16_t)k;
+            }
             __syncthreads();
         }
         for (uint32_t nb = n0 + threadIdx.x; nb < n1; nb += 256 * DRAW_BATCH) {
@@ -997,7 +1047,9 @@ __global__ __launch_bounds__(256) void long_draw_kernel(PhaseArgs a, LongList l,
                 }
             }
             if (by_cdf) {
-                if (cdf_lds)
+                if (guided)
+                    cdf_find_guided<DRAW_BATCH * M>(cdfl, guide, gs, n_bkt, K, jj);
+                else if (cdf_lds)
                     cdf_find_lds<DRAW_BATCH * M>(cdfl, K, jj);
                 else
                     cdf_find_n<DRAW_BATCH * M>(cum, K, jj);
@@ -1179,11 +1231,16 @@ static hipError_t long_dispatch_z(const PhaseArgs &a, const LongList &l, hipStre
                                a.K);
             if ((e = hipGetLastError()) != hipSuccess) return e;
         }
-        const size_t lds = 4ull * ((ck_lds ? a.K : 0) + (cdf_lds ? a.K : 0));
+        // the guide table where K is small enough that building it for every
+        // chunk costs less than the binary-search steps it saves (measured:
+        // long draw 0.357 -> 0.316 ms at K = 1000, slower at K = 1e4)
+        const bool guided = cdf_lds && a.K <= Tuning::GUIDE_K_MAX;
+        const size_t lds = 4ull * ((ck_lds ? a.K : 0) + (cdf_lds ? a.K : 0) + (guided ? GUIDE_MAX / 2 : 0));
         e = launch_dyn(long_draw_kernel<PHASE, M, NW, ZT>, lds);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL((long_draw_kernel<PHASE, M, NW, ZT>), dim3(blocks), dim3(256), lds, st, a, l,
-                           (uint32_t)ck_lds, (uint32_t)(a.draw_only ? 0 : 1), (uint32_t)cdf_lds);
+                           (uint32_t)ck_lds, (uint32_t)(a.draw_only ? 0 : 1),
+                           (uint32_t)cdf_lds | (uint32_t)guided << 1);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         if (ev) return hipEventRecord(ev[3], st);
         return hipSuccess;
