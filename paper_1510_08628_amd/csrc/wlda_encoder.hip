@@ -211,12 +211,31 @@ __global__ void relu_bwd_kernel(long n, const float *d, const float *a, float *g
     }
 }
 
-// column sums of g (rows x cols) into db
-__global__ void colsum_kernel(int rows, int cols, const float *g, float *db) {
-    for (int j = blockIdx.x * 256 + threadIdx.x; j < cols; j += gridDim.x * 256) {
-        float s = 0.f;
-        for (int r = 0; r < rows; ++r) s += g[(size_t)r * cols + j];
-        db[j] = s;
+// Column sums of g (rows x cols) into db: a workgroup owns 32 columns; each
+// of its eight row groups sums every eighth row with eight loads in flight,
+// and the eight partial sums are added in a fixed order.
+__global__ __launch_bounds__(256) void colsum_kernel(int rows, int cols, const float *g, float *db) {
+    __shared__ float part[8][32];
+    const int c = threadIdx.x & 31, rg = threadIdx.x >> 5;
+    const int j = blockIdx.x * 32 + c;
+    float s = 0.f;
+    if (j < cols) {
+        int r = rg;
+        for (; r + 56 < rows; r += 64) {
+            float v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = g[(size_t)(r + 8 * u) * cols + j];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) s += v[u];
+        }
+        for (; r < rows; r += 8) s += g[(size_t)r * cols + j];
+    }
+    part[rg][c] = s;
+    __syncthreads();
+    if (rg == 0 && j < cols) {
+        float t = 0.f;
+        for (int q = 0; q < 8; ++q) t += part[q][c];
+        db[j] = t;
     }
 }
 
@@ -508,18 +527,18 @@ hipError_t backward(wlda_encoder e, uint32_t B, const uint32_t *rowptr, const ui
     if ((r = hipGetLastError())) return r;
     // layer 3
     if ((r = gemm(st, Hd, K, B, e->h2b, 1, Hd, e->g3b, K, 1, e->g[4], K, 0))) return r;
-    hipLaunchKernelGGL(colsum_kernel, dim3(grid(K)), dim3(256), 0, st, (int)B, K, e->g3, e->g[5]);
+    hipLaunchKernelGGL(colsum_kernel, dim3((K + 31) / 32), dim3(256), 0, st, (int)B, K, e->g3, e->g[5]);
     if ((r = gemm(st, B, Hd, K, e->g3b, K, 1, e->wb[2], 1, K, e->d2, Hd, 0))) return r;
     hipLaunchKernelGGL(relu_bwd_kernel, dim3(grid((long)B * Hd)), dim3(256), 0, st, (long)B * Hd, e->d2, e->a2,
                        e->g2, e->g2b);
     // layer 2
     if ((r = gemm(st, Hd, Hd, B, e->h1b, 1, Hd, e->g2b, Hd, 1, e->g[2], Hd, 0))) return r;
-    hipLaunchKernelGGL(colsum_kernel, dim3(grid(Hd)), dim3(256), 0, st, (int)B, Hd, e->g2, e->g[3]);
+    hipLaunchKernelGGL(colsum_kernel, dim3((Hd + 31) / 32), dim3(256), 0, st, (int)B, Hd, e->g2, e->g[3]);
     if ((r = gemm(st, B, Hd, Hd, e->g2b, Hd, 1, e->wb[1], 1, Hd, e->d1, Hd, 0))) return r;
     hipLaunchKernelGGL(relu_bwd_kernel, dim3(grid((long)B * Hd)), dim3(256), 0, st, (long)B * Hd, e->d1, e->a1,
                        e->g1, (uint16_t *)nullptr);
     // layer 1 (embedding bag)
-    hipLaunchKernelGGL(colsum_kernel, dim3(grid(Hd)), dim3(256), 0, st, (int)B, Hd, e->g1, e->g[1]);
+    hipLaunchKernelGGL(colsum_kernel, dim3((Hd + 31) / 32), dim3(256), 0, st, (int)B, Hd, e->g1, e->g[1]);
     hipLaunchKernelGGL(zero_f32_kernel, dim3(grid(e->n[0])), dim3(256), 0, st, e->n[0], e->g[0]);
     const uint32_t nb = e->p.buckets, cap = e->tcap;
     hipLaunchKernelGGL(zero_f32_kernel, dim3(grid(nb)), dim3(256), 0, st, (long)nb, (float *)e->tcnt);
