@@ -282,25 +282,10 @@ __device__ void group_inclusive_scan(uint32_t *a, uint32_t K, uint32_t lane) {
 
 // Inverse CDF, N lookups at once: each j[d] (< cum[K-1]) is replaced by the
 // smallest topic k with cum[k] > j[d], cum holding inclusive prefix counts
-// over topics 0..K-1.  A branch-free binary search whose trip count depends
-// on K only, so the N loads of each step are in flight together.
-template <int N>
-__device__ __forceinline__ void cdf_find_n(const uint32_t *cum, uint32_t K, uint32_t (&j)[N]) {
-    uint32_t base[N];
-#pragma unroll
-    for (int d = 0; d < N; ++d) base[d] = 0;
-    for (uint32_t n = K; n > 1;) {
-        const uint32_t half = n >> 1;
-#pragma unroll
-        for (int d = 0; d < N; ++d) base[d] = cum[base[d] + half] <= j[d] ? base[d] + half : base[d];
-        n -= half;
-    }
-#pragma unroll
-    for (int d = 0; d < N; ++d) j[d] = base[d] + (cum[base[d]] <= j[d] ? 1u : 0u);
-}
-
-// The same search over prefix counts in LDS, stepping 32-bit LDS pointers:
-// one add, one LDS load, one compare and one select per lookup and step.
+// over topics 0..K-1.  Over prefix counts in LDS, a branch-free binary search
+// whose trip count depends on K only (the N loads of each step are in
+// flight together), stepping 32-bit LDS pointers: one add, one LDS load, one
+// compare and one select per lookup and step.
 typedef __attribute__((address_space(3))) const uint32_t lds_cu32;
 template <int N>
 __device__ __forceinline__ void cdf_find_lds(const uint32_t *cum_generic, uint32_t K, uint32_t (&j)[N]) {
@@ -337,6 +322,43 @@ __device__ __forceinline__ void cdf_find_guided(const uint32_t *cum_generic, con
         const uint32_t i = j[d] >> gs;
         base[d] = guide[i];
         n[d] = (i + 1 < nb ? (uint32_t)guide[i + 1] : K - 1) - base[d] + 1;
+    }
+    for (;;) {
+        bool open = false;
+#pragma unroll
+        for (int d = 0; d < N; ++d) {
+            if (n[d] > 1) {
+                const uint32_t half = n[d] >> 1;
+                if (cum[base[d] + half - 1] <= j[d]) base[d] += half;
+                n[d] -= half;
+                open = true;
+            }
+        }
+        if (!open) break;
+    }
+#pragma unroll
+    for (int d = 0; d < N; ++d) j[d] = base[d];
+}
+
+// Guide buckets for a column of L tokens: 2^gs token indices each, the
+// smallest gs that leaves at most nb_max buckets.
+__device__ __forceinline__ uint32_t guide_shift(uint32_t L, uint32_t nb_max) {
+    uint32_t gs = 0;
+    while ((((uint64_t)L + (1u << gs) - 1) >> gs) > nb_max) ++gs;
+    return gs;
+}
+
+// cdf_find_guided over prefix counts and a guide of 32-bit topics in global
+// memory (K beyond what LDS holds).
+template <int N>
+__device__ __forceinline__ void cdf_find_guided_g(const uint32_t *cum, const uint32_t *guide, uint32_t gs,
+                                                  uint32_t nb, uint32_t K, uint32_t (&j)[N]) {
+    uint32_t base[N], n[N];
+#pragma unroll
+    for (int d = 0; d < N; ++d) {
+        const uint32_t i = j[d] >> gs;
+        base[d] = guide[i];
+        n[d] = (i + 1 < nb ? guide[i + 1] : K - 1) - base[d] + 1;
     }
     for (;;) {
         bool open = false;
@@ -922,15 +944,24 @@ __global__ __launch_bounds__(256) void long_mh_kernel(PhaseArgs a, LongList l, u
 
 // Inclusive prefix sums, in place, of the updated counts of every long word
 // past the inverse-CDF threshold (word_cdf): one workgroup per word, tiles of
-// 4096 topics.
+// 4096 topics.  Where the draw searches them in global memory (K >
+// CDF_LDS_MAX) it also writes their guide (the topic at the start of every
+// bucket of 2^gs token indices, at most K buckets) over the word's phase-start
+// counts, which the MH pass has consumed (the tables are cleared after the
+// draw).
 template <int M>
 __global__ __launch_bounds__(256) void long_cdf_kernel(LongList l, const uint32_t *segptr, uint32_t K) {
     __shared__ uint32_t wsum[4];
     constexpr int PER = 16;
+    const bool with_guide = K > Tuning::CDF_LDS_MAX;
     for (uint32_t j = blockIdx.x; j < l.n; j += gridDim.x) {
         const uint32_t s = l.ids[j];
-        if (!word_cdf(segptr[s + 1] - segptr[s], K)) continue;
+        const uint32_t L = segptr[s + 1] - segptr[s];
+        if (!word_cdf(L, K)) continue;
         uint32_t *cnt = l.tables_new + l.tab_off[j];
+        uint32_t *guide = l.tables + l.tab_off[j];
+        const uint32_t gs = with_guide ? guide_shift(L, K) : 0u;
+        const uint32_t nb = with_guide ? (uint32_t)(((uint64_t)L + (1u << gs) - 1) >> gs) : 0u;
         uint32_t carry = 0;
         for (uint32_t t0 = 0; t0 < K; t0 += 256 * PER) {
             const uint32_t k0 = t0 + threadIdx.x * PER;
@@ -955,8 +986,18 @@ __global__ __launch_bounds__(256) void long_cdf_kernel(LongList l, const uint32_
             uint32_t run = base + x - sum;
 #pragma unroll
             for (int i = 0; i < PER; ++i) {
+                const uint32_t prev = run;      // counts of the topics before k0 + i
                 run += v[i];
-                if (k0 + i < K) cnt[k0 + i] = run;
+                if (k0 + i < K) {
+                    cnt[k0 + i] = run;
+                    // topic k0 + i owns the indices [prev, run): the buckets
+                    // starting there point to it
+                    if (with_guide) {
+                        const uint32_t i1 = (uint32_t)min<uint64_t>(nb, ((uint64_t)run + (1u << gs) - 1) >> gs);
+                        for (uint32_t b = (uint32_t)(((uint64_t)prev + (1u << gs) - 1) >> gs); b < i1; ++b)
+                            guide[b] = k0 + i;
+                    }
+                }
             }
             carry += tile;
             __syncthreads();
@@ -990,6 +1031,9 @@ __global__ __launch_bounds__(256) void long_draw_kernel(PhaseArgs a, LongList l,
         const bool by_cdf = PHASE == PH_WORD && word_cdf(L, K);
         const uint32_t *cum = l.tables_new + l.tab_off[j];
         uint32_t gs = 0, n_bkt = 0;
+        // the guide long_cdf_kernel wrote where the prefix counts stay global
+        const uint32_t gs_g = by_cdf && !cdf_lds ? guide_shift(L, K) : 0u;
+        const uint32_t nb_g = (uint32_t)(((uint64_t)L + (1u << gs_g) - 1) >> gs_g);
         if (by_cdf && cdf_lds) {
             for (uint32_t k = threadIdx.x; k < K; k += 256) cdfl[k] = cum[k];
             __syncthreads();
@@ -1052,7 +1096,7 @@ __global__ __launch_bounds__(256) void long_draw_kernel(PhaseArgs a, LongList l,
                 else if (cdf_lds)
                     cdf_find_lds<DRAW_BATCH * M>(cdfl, K, jj);
                 else
-                    cdf_find_n<DRAW_BATCH * M>(cum, K, jj);
+                    cdf_find_guided_g<DRAW_BATCH * M>(cum, l.tables + l.tab_off[j], gs_g, nb_g, K, jj);
 #pragma unroll
                 for (int d = 0; d < DRAW_BATCH * M; ++d)
                     if ((coin >> d) & 1u) set_fld(rec[d / M], d % M + 1, jj[d]);
@@ -1238,10 +1282,14 @@ static hipError_t long_dispatch_z(const PhaseArgs &a, const LongList &l, hipStre
         const size_t lds = 4ull * ((ck_lds ? a.K : 0) + (cdf_lds ? a.K : 0) + (guided ? GUIDE_MAX / 2 : 0));
         e = launch_dyn(long_draw_kernel<PHASE, M, NW, ZT>, lds);
         if (e != hipSuccess) return e;
+        // the global guides live in the tables until the draw is done: clear
+        // them after it instead of inside it
+        const bool guides_g = PHASE == PH_WORD && !a.draw_only && !cdf_lds;
         hipLaunchKernelGGL((long_draw_kernel<PHASE, M, NW, ZT>), dim3(blocks), dim3(256), lds, st, a, l,
-                           (uint32_t)ck_lds, (uint32_t)(a.draw_only ? 0 : 1),
+                           (uint32_t)ck_lds, (uint32_t)(a.draw_only || guides_g ? 0 : 1),
                            (uint32_t)cdf_lds | (uint32_t)guided << 1);
         if ((e = hipGetLastError()) != hipSuccess) return e;
+        if (guides_g && (e = launch_fill_u32(l.tables, 0, l.table_words, st)) != hipSuccess) return e;
         if (ev) return hipEventRecord(ev[3], st);
         return hipSuccess;
     });
