@@ -105,7 +105,10 @@ struct Tuning {
     static constexpr uint32_t LONG_CHUNK_HASHED = 4096;
     static constexpr uint32_t LDS_DENSE_MAX = 16384;         // dense LDS counts up to this K
     static constexpr uint32_t CDF_LDS_MAX = 16384;           // long-word prefix counts in LDS
-    static constexpr uint32_t GUIDE_K_MAX = 4096;            // ... with a guide table for the search
+    // the inverse CDF of a long word starts from a guide table built in LDS
+    // for every chunk up to this K (a binary search of the LDS prefix counts
+    // up to CDF_LDS_MAX, a guide built once per word in global memory above)
+    static constexpr uint32_t GUIDE_K_MAX = 4096;
 };
 
 struct PhaseArgs {

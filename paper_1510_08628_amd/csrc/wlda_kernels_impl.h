@@ -283,9 +283,9 @@ __device__ void group_inclusive_scan(uint32_t *a, uint32_t K, uint32_t lane) {
 // Inverse CDF, N lookups at once: each j[d] (< cum[K-1]) is replaced by the
 // smallest topic k with cum[k] > j[d], cum holding inclusive prefix counts
 // over topics 0..K-1.  Over prefix counts in LDS, a branch-free binary search
-// whose trip count depends on K only (the N loads of each step are in
-// flight together), stepping 32-bit LDS pointers: one add, one LDS load, one
-// compare and one select per lookup and step.
+// whose trip count depends on K only (the N loads of each step are in flight
+// together), stepping 32-bit LDS pointers: one add, one LDS load, one compare
+// and one select per lookup and step.
 typedef __attribute__((address_space(3))) const uint32_t lds_cu32;
 template <int N>
 __device__ __forceinline__ void cdf_find_lds(const uint32_t *cum_generic, uint32_t K, uint32_t (&j)[N]) {
@@ -306,11 +306,10 @@ __device__ __forceinline__ void cdf_find_lds(const uint32_t *cum_generic, uint32
     for (int d = 0; d < N; ++d) j[d] = (uint32_t)(b[d] - cum) + (*b[d] <= j[d] ? 1u : 0u);
 }
 
-// The same inverse CDF narrowed by a guide table in LDS: guide[i] (i < nb) is
+// Through a guide table in LDS: guide[i] (i < nb) is
 // the smallest topic k with cum[k] > i << gs, so the answer for j lies in
 // [guide[j >> gs], guide[(j >> gs) + 1]] (the last bucket ends at K - 1) and a
-// search of that range, a few topics wide, finds it.  Same result as
-// cdf_find_lds.
+// binary search of that range, a few topics wide, finds it.
 constexpr uint32_t GUIDE_MAX = 4096;     // guide entries (16-bit topics)
 template <int N>
 __device__ __forceinline__ void cdf_find_guided(const uint32_t *cum_generic, const uint16_t *guide, uint32_t gs,
@@ -348,8 +347,8 @@ __device__ __forceinline__ uint32_t guide_shift(uint32_t L, uint32_t nb_max) {
     return gs;
 }
 
-// cdf_find_guided over prefix counts and a guide of 32-bit topics in global
-// memory (K beyond what LDS holds).
+// cdf_find_guided with the prefix counts and a guide of 32-bit topics in
+// global memory (K beyond what LDS holds).
 template <int N>
 __device__ __forceinline__ void cdf_find_guided_g(const uint32_t *cum, const uint32_t *guide, uint32_t gs,
                                                   uint32_t nb, uint32_t K, uint32_t (&j)[N]) {
