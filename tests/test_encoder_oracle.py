@@ -54,3 +54,32 @@ def test_gradients_match_finite_differences():
     # untouched W1 rows get exactly zero gradient
     untouched = np.setdiff1d(np.arange(buckets), idx)
     assert np.all(grads[0][untouched] == 0)
+
+
+def test_rounded_path_is_the_exact_path_up_to_bf16_rounding():
+    """The rounded mode (operands of every product rounded to bfloat16 where
+    the GPU rounds them) uses the same formulas as the exact mode that the
+    finite differences pin: its loss and probabilities agree to bfloat16
+    precision, and every gradient points the same way (cosine > 0.95; the
+    output error p - theta is small and rounds coarsely, so the backward
+    products differ by up to ~20%).  A dropped term, a wrong sign or a
+    transposed operand in the rounded path would show."""
+    rng = np.random.default_rng(3)
+    buckets, hidden, K, B = 300, 64, 20, 16
+    ws = [w.astype(np.float64) for w in synth.encoder_init_weights(buckets, hidden, K, 2)]
+    ws[1] += 0.05
+    ws[3] += 0.02
+    ws[5] += np.linspace(-0.2, 0.2, K)
+    docs = [rng.integers(0, 5000, n) for n in rng.integers(5, 200, B)]
+    rowptr, idx, val = E.batch_features(buckets, docs)
+    theta = rng.dirichlet(np.full(K, 0.3), size=B)
+    l_r, q_r, g_r = E.forward_backward(ws, rowptr, idx, val, theta, round=True)
+    l_e, q_e, g_e = E.forward_backward(ws, rowptr, idx, val, theta, round=False)
+    assert abs(l_r - l_e) <= 2e-2 * abs(l_e)
+    assert np.abs(q_r - q_e).max() <= 2e-2
+    for gr, ge in zip(g_r, g_e):
+        cos = float(np.sum(gr * ge) / (np.linalg.norm(gr) * np.linalg.norm(ge)))
+        err = np.linalg.norm(gr - ge) / np.linalg.norm(ge)
+        assert cos > 0.95 and err < 0.3, (cos, err)
+    # and they are not the same computation: rounding is applied
+    assert any(not np.array_equal(gr, ge) for gr, ge in zip(g_r, g_e))
