@@ -89,6 +89,9 @@ def lib():
         L.oracle_theta.restype = C.c_int
         L.oracle_phi.argtypes = [vp, u32, u32, vp]
         L.oracle_phi.restype = C.c_int
+        L.oracle_set_token_offsets.argtypes = [vp, u32, u32]
+        L.oracle_set_phase_state.argtypes = [vp, vp, C.c_int, u32]
+        L.oracle_set_phase_state.restype = C.c_int
         L.oracle_set_alpha.argtypes = [vp, vp]
         L.oracle_set_alpha.restype = C.c_int
         L.oracle_instant_iterate.argtypes = [vp, u32]
@@ -270,6 +273,18 @@ class Oracle:
         out = np.empty((nw, self.K), dtype=np.float64)
         self._check(lib().oracle_phi(self.h, w0, nw, _ptr(out)))
         return out
+
+    def set_token_offsets(self, csc_off: int, csr_off: int):
+        """Test harness: this corpus is one column (row) of a larger one whose
+        canonical positions start at csc_off (csr_off)."""
+        lib().oracle_set_token_offsets(self.h, csc_off, csr_off)
+
+    def set_phase_state(self, ck, next_phase: int, iteration: int):
+        """Test harness: the larger corpus's c_k at the start of the next
+        phase, that phase (PH_WORD or PH_DOC) and the completed iterations."""
+        c = np.ascontiguousarray(ck, dtype=np.int64)
+        assert c.shape == (self.K,)
+        self._check(lib().oracle_set_phase_state(self.h, _ptr(c), next_phase, iteration))
 
     def set_alpha(self, alpha):
         """Asymmetric document-topic prior alpha_k (K positive values, taken

@@ -196,6 +196,10 @@ typedef struct {
      * running sums in topic order, binary64 */
     float *alpha_k;
     double *alpha_cum;
+    /* test harness: added to the token index of the Philox counter in the
+     * word phase (CSC) and the doc phase (CSR), so that a corpus holding one
+     * column or one row of a larger corpus draws that corpus's numbers */
+    uint32_t t_off_csc, t_off_csr;
 } oracle_t;
 
 typedef struct {
@@ -335,7 +339,7 @@ static void draw_doc_proposals(oracle_t *o, uint32_t d, uint32_t iter)
         uint32_t t = o->row[beg + n];
         for (uint32_t i = 1; i <= o->M; ++i) {
             uint32_t cw_, iw;
-            draw_words(o->seed, (uint32_t)(beg + n), iter, PH_DOC, i, &cw_, &iw);
+            draw_words(o->seed, o->t_off_csr + (uint32_t)(beg + n), iter, PH_DOC, i, &cw_, &iw);
             int32_t prop;
             if (take_count_part(unif24(cw_), L, o->alpha_bar))
                 prop = o->z[o->row[beg + dice(iw, (uint32_t)L)]];
@@ -392,6 +396,28 @@ int oracle_set_alpha(oracle_t *o, const float *alpha)
     return 0;
 }
 
+/* Test harness for corpora too large for the whole oracle: a corpus that is
+ * one column (or one row) of a larger one, set to that corpus's state, runs
+ * one phase exactly as the larger corpus would for that column (row).
+ * oracle_set_token_offsets: the column's (row's) first canonical position in
+ * the larger corpus; oracle_set_phase_state: the larger corpus's c_k at the
+ * start of the phase, the phase to run next and the completed iterations
+ * (after oracle_init and oracle_set_csc_state). */
+void oracle_set_token_offsets(oracle_t *o, uint32_t csc_off, uint32_t csr_off)
+{
+    o->t_off_csc = csc_off;
+    o->t_off_csr = csr_off;
+}
+
+int oracle_set_phase_state(oracle_t *o, const int64_t *ck, int next_phase, uint32_t iter)
+{
+    if (o->next_phase == 0 || (next_phase != PH_WORD && next_phase != PH_DOC)) return -4;
+    memcpy(o->ck, ck, o->K * sizeof(int64_t));
+    o->next_phase = next_phase;
+    o->iter = iter;
+    return 0;
+}
+
 /* f_c of Section 5.1 for one column w: c_w from the column's assignments at
  * the start of the phase, M MH steps per token on its doc proposals with the
  * counts frozen (delayed update, Section 4.2), commit of the whole column,
@@ -409,7 +435,7 @@ static void word_column(oracle_t *o, uint32_t w, uint32_t iter, int64_t *ck_next
         uint32_t t = (uint32_t)(beg + n);
         int32_t s = o->z[t];
         uint32_t ra[4];
-        accept_words(o->seed, t, iter, PH_WORD, ra);
+        accept_words(o->seed, o->t_off_csc + t, iter, PH_WORD, ra);
         for (uint32_t i = 1; i <= o->M; ++i) {
             int32_t c = o->prop[(uint64_t)(i - 1) * o->T + t];
             if (mh_accept(unif24(ra[i - 1]), cw[c], cw[s], o->b, o->ck[s],
@@ -438,7 +464,7 @@ static void word_column(oracle_t *o, uint32_t w, uint32_t iter, int64_t *ck_next
         uint32_t t = (uint32_t)(beg + n);
         for (uint32_t i = 1; i <= o->M; ++i) {
             uint32_t cw_, iw;
-            draw_words(o->seed, t, iter, PH_WORD, i, &cw_, &iw);
+            draw_words(o->seed, o->t_off_csc + t, iter, PH_WORD, i, &cw_, &iw);
             int32_t prop;
             if (take_count_part(unif24(cw_), L, o->beta_k)) {
                 uint32_t j = dice(iw, (uint32_t)L);
@@ -488,7 +514,7 @@ static void doc_row(oracle_t *o, uint32_t d, uint32_t iter, int64_t *ck_next,
         uint32_t t = o->row[beg + n];
         int32_t s = o->z[t];
         uint32_t ra[4];
-        accept_words(o->seed, (uint32_t)(beg + n), iter, PH_DOC, ra);
+        accept_words(o->seed, o->t_off_csr + (uint32_t)(beg + n), iter, PH_DOC, ra);
         for (uint32_t i = 1; i <= o->M; ++i) {
             int32_t c = o->prop[(uint64_t)(i - 1) * o->T + t];
             if (mh_accept2(unif24(ra[i - 1]), cd[c], cd[s], alpha_of(o, c), alpha_of(o, s),

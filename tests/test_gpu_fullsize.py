@@ -145,3 +145,82 @@ def test_pubmed_shape_full_size_properties(W):
     assert (s.accepted(1), s.accepted(2)) == (acc_w, acc_d)
     log("replay from the saved state matches")
     s.close()
+
+
+@pytest.mark.timeout(900)
+def test_pubmed_shape_full_size_sampled_columns_and_rows(W):
+    """The PubMed-shaped workload at its full size (8M documents, 720M tokens,
+    K = 1e4, M = 4), in the benchmark's launch configuration, bit for bit on
+    sampled outputs: for columns of every length class (segment kernels and
+    the long path up to a few million tokens, inverse CDF included) the word
+    phase, and for rows of every length class (the longest included) the doc
+    phase, recomputed by the oracle one column or row at a time from the
+    sampler's own phase-start state and c_k (tests/subcorpus.py)."""
+    import sys
+    import subcorpus as SC
+    wl = synth.WORKLOADS["pubmed-shape-k1e4"]
+    log = lambda m: print(f"[pubmed sampled] {m}", file=sys.__stderr__, flush=True)
+    c = wl.make()
+    K, M, V = wl.K, wl.M, c.V
+    seed = 3
+    counts = np.bincount(c.word_ids, minlength=V)
+    colstart = np.concatenate([[0], np.cumsum(counts)])
+    order = np.argsort(counts)[::-1]
+    rng = np.random.default_rng(11)
+    words = [int(order[r]) for r in (9, 60, 400, 2000)]                 # ~7M down to ~2e4 tokens
+    words += [int(w) for w in rng.choice(np.nonzero((counts > 0) & (counts <= 2048))[0], 6, replace=False)]
+    sel = np.nonzero(np.isin(c.word_ids, words))[0]
+    cols = {w: sel[c.word_ids[sel] == w] for w in words}
+    for w, idx in cols.items():
+        assert np.all(np.diff(c.doc_ids[idx].astype(np.int64)) >= 0)  # input order is column order
+    lens = np.bincount(c.doc_ids, minlength=c.D)
+    docs = [int(np.argmax(lens))]
+    for lo, hi in ((1, 64), (65, 128), (129, 256), (257, 1024), (1025, 2048)):
+        cand = np.nonzero((lens >= lo) & (lens <= hi))[0]
+        docs += [int(d) for d in rng.choice(cand, min(3, len(cand)), replace=False)]
+    rowstart = {}
+    rows = {}
+    for d in docs:
+        a = int(np.searchsorted(c.doc_ids, d, side="left"))
+        b = int(np.searchsorted(c.doc_ids, d, side="right"))
+        rowstart[d] = a
+        rows[d] = a + np.lexsort((np.arange(b - a), c.word_ids[a:b]))
+    log(f"columns {[len(v) for v in cols.values()]}, rows {[len(v) for v in rows.values()]}")
+
+    s = W.Sampler(c.word_ids, c.doc_ids, c.V, c.D, K, M, wl.alpha, wl.beta, seed=seed)
+    s.init()
+    s.iterate(1)
+    it = s.iteration
+
+    def take(z, p, sets):
+        return {k: (z[v].copy(), p[:, v].copy()) for k, v in sets.items()}
+
+    z, p = s.assignments()
+    ck0 = s.topic_counts()
+    col_pre = take(z, p, cols)
+    del z, p
+    s.word_phase()
+    z, p = s.assignments()
+    ck1 = s.topic_counts()
+    col_post, row_pre = take(z, p, cols), take(z, p, rows)
+    del z, p
+    s.doc_phase()
+    z, p = s.assignments()
+    row_post = take(z, p, rows)
+    del z, p
+    s.close()
+    log("sampler done; oracle columns")
+    for w in words:
+        idx = cols[w]
+        zn, pn = SC.column_phase(V, K, M, wl.alpha, wl.beta, seed, it, int(colstart[w]), c.doc_ids[idx],
+                                 col_pre[w][0], col_pre[w][1], ck0)
+        assert np.array_equal(zn, col_post[w][0]), ("column", w, len(idx))
+        assert np.array_equal(pn, col_post[w][1]), ("column proposals", w, len(idx))
+    log("oracle rows")
+    for d in docs:
+        idx = rows[d]
+        zn, pn = SC.row_phase(V, K, M, wl.alpha, wl.beta, seed, it, rowstart[d], c.word_ids[idx],
+                              row_pre[d][0], row_pre[d][1], ck1)
+        assert np.array_equal(zn, row_post[d][0]), ("row", d, len(idx))
+        assert np.array_equal(pn, row_post[d][1]), ("row proposals", d, len(idx))
+    log("all sampled columns and rows match")
