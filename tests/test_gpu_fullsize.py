@@ -147,27 +147,21 @@ def test_pubmed_shape_full_size_properties(W):
     s.close()
 
 
-@pytest.mark.timeout(900)
-def test_pubmed_shape_full_size_sampled_columns_and_rows(W):
-    """The PubMed-shaped workload at its full size (8M documents, 720M tokens,
-    K = 1e4, M = 4), in the benchmark's launch configuration, bit for bit on
-    sampled outputs: for columns of every length class (segment kernels and
-    the long path up to a few million tokens, inverse CDF included) the word
-    phase, and for rows of every length class (the longest included) the doc
-    phase, recomputed by the oracle one column or row at a time from the
-    sampler's own phase-start state and c_k (tests/subcorpus.py)."""
+def sampled_check(W, wl, c, M, seed, ranks, row_bins, tag):
+    """Bit-exact word phase of sampled columns (the words of the given
+    frequency ranks and six short ones) and doc phase of sampled rows (the
+    longest and three of each length class), recomputed by the oracle one
+    column or row at a time from the sampler's own phase-start state and c_k
+    (tests/subcorpus.py)."""
     import sys
     import subcorpus as SC
-    wl = synth.WORKLOADS["pubmed-shape-k1e4"]
-    log = lambda m: print(f"[pubmed sampled] {m}", file=sys.__stderr__, flush=True)
-    c = wl.make()
-    K, M, V = wl.K, wl.M, c.V
-    seed = 3
+    log = lambda m: print(f"[{tag}] {m}", file=sys.__stderr__, flush=True)
+    K, V = wl.K, c.V
     counts = np.bincount(c.word_ids, minlength=V)
     colstart = np.concatenate([[0], np.cumsum(counts)])
     order = np.argsort(counts)[::-1]
     rng = np.random.default_rng(11)
-    words = [int(order[r]) for r in (9, 60, 400, 2000)]                 # ~7M down to ~2e4 tokens
+    words = [int(order[r]) for r in ranks]
     words += [int(w) for w in rng.choice(np.nonzero((counts > 0) & (counts <= 2048))[0], 6, replace=False)]
     sel = np.nonzero(np.isin(c.word_ids, words))[0]
     cols = {w: sel[c.word_ids[sel] == w] for w in words}
@@ -175,7 +169,7 @@ def test_pubmed_shape_full_size_sampled_columns_and_rows(W):
         assert np.all(np.diff(c.doc_ids[idx].astype(np.int64)) >= 0)  # input order is column order
     lens = np.bincount(c.doc_ids, minlength=c.D)
     docs = [int(np.argmax(lens))]
-    for lo, hi in ((1, 64), (65, 128), (129, 256), (257, 1024), (1025, 2048)):
+    for lo, hi in row_bins:
         cand = np.nonzero((lens >= lo) & (lens <= hi))[0]
         docs += [int(d) for d in rng.choice(cand, min(3, len(cand)), replace=False)]
     rowstart = {}
@@ -224,3 +218,28 @@ def test_pubmed_shape_full_size_sampled_columns_and_rows(W):
         assert np.array_equal(zn, row_post[d][0]), ("row", d, len(idx))
         assert np.array_equal(pn, row_post[d][1]), ("row proposals", d, len(idx))
     log("all sampled columns and rows match")
+
+
+@pytest.mark.timeout(900)
+def test_pubmed_shape_full_size_sampled_columns_and_rows(W):
+    """The PubMed-shaped workload at its full size (8M documents, 720M tokens,
+    K = 1e4, M = 4), in the benchmark's launch configuration, bit for bit on
+    sampled outputs: columns of every length class (segment kernels and the
+    long path up to ~7M tokens, inverse CDF included) and rows of every length
+    class (the longest, on the doc long path, included)."""
+    wl = synth.WORKLOADS["pubmed-shape-k1e4"]
+    c = wl.make()
+    sampled_check(W, wl, c, wl.M, 3, (9, 60, 400, 2000),
+                  ((1, 64), (65, 128), (129, 256), (257, 1024), (1025, 2048)), "pubmed sampled")
+
+
+@pytest.mark.timeout(900)
+def test_clueweb_share_2m_docs_sampled_columns_and_rows(W):
+    """The ClueWeb-shaped share's first 2M documents (200M tokens, V = 1M,
+    K = 1e6, M = 2), the slice the benchmark times: sampled columns (~5M
+    tokens down to segment sizes; long ones take the inverse CDF through
+    global prefix counts and their guide) and rows, bit for bit."""
+    wl = synth.WORKLOADS["clueweb-share-k1e6"]
+    c = wl.make(2_000_000)
+    sampled_check(W, wl, c, wl.M, 3, (4, 30, 300, 3000),
+                  ((1, 128), (129, 256), (257, 512), (513, 2048), (2049, 4096)), "clueweb sampled")
