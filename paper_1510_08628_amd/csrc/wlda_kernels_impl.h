@@ -883,33 +883,42 @@ __global__ __launch_bounds__(256) void long_mh_kernel(PhaseArgs a, LongList l, u
                 if (n >= n1) continue;
                 uint32_t s = fld(rec[u], 0);
                 const uint4 RA = philox(beg + n, a.iter, ph, 0, a.seed_lo, a.seed_hi);
+                const bool asym = PHASE == PH_DOC && a.alpha_k != nullptr;
+                if (lds_tab && ck_lds) {
+                    // counts and c_k + beta_bar in LDS: each step reads both
+                    // topics' (cheaper than keeping the state's in registers)
 #pragma unroll
-                for (int i = 1; i <= M; ++i) {
-                    const float uacc = unif24(word4(RA, i - 1));
-                    const uint32_t c = fld(rec[u], i);
-                    // separate paths keep LDS reads as ds_read (a pointer
-                    // selected at run time would force flat loads)
-                    uint32_t cc, cs;
-                    if (lds_tab) {
-                        cc = tab[c];
-                        cs = tab[s];
-                    } else {
-                        cc = gtab_get(gt, gcap, c);
-                        cs = gtab_get(gt, gcap, s);
-                    }
-                    float pc = a.prior, ps = a.prior;
-                    if constexpr (PHASE == PH_DOC) {
-                        if (a.alpha_k) {        // asymmetric alpha
-                            pc = a.alpha_k[c];
-                            ps = a.alpha_k[s];
+                    for (int i = 1; i <= M; ++i) {
+                        const float uacc = unif24(word4(RA, i - 1));
+                        const uint32_t c = fld(rec[u], i);
+                        const float pc = asym ? a.alpha_k[c] : a.prior;
+                        const float ps = asym ? a.alpha_k[s] : a.prior;
+                        if (mh_accept_b2(uacc, tab[c], tab[s], pc, ps, ckb[s], ckb[c])) {
+                            s = c;
+                            ++acc;
                         }
                     }
-                    const bool ok = ck_lds ? mh_accept_b2(uacc, cc, cs, pc, ps, ckb[s], ckb[c])
-                                           : mh_accept_b2(uacc, cc, cs, pc, ps, (float)a.ck[s] + a.beta_bar,
-                                                          (float)a.ck[c] + a.beta_bar);
-                    if (ok) {
-                        s = c;
-                        ++acc;
+                } else {
+                    // in global memory: the state's count, c_k + beta_bar and
+                    // prior are looked up once and carried with it, so the
+                    // candidates' lookups do not wait on the MH outcomes
+                    uint32_t cs = lds_tab ? tab[s] : gtab_get(gt, gcap, s);
+                    float bs = ck_lds ? ckb[s] : (float)a.ck[s] + a.beta_bar;
+                    float ps = asym ? a.alpha_k[s] : a.prior;
+#pragma unroll
+                    for (int i = 1; i <= M; ++i) {
+                        const float uacc = unif24(word4(RA, i - 1));
+                        const uint32_t c = fld(rec[u], i);
+                        const uint32_t cc = lds_tab ? tab[c] : gtab_get(gt, gcap, c);
+                        const float bc = ck_lds ? ckb[c] : (float)a.ck[c] + a.beta_bar;
+                        const float pc = asym ? a.alpha_k[c] : a.prior;
+                        if (mh_accept_b2(uacc, cc, cs, pc, ps, bs, bc)) {
+                            s = c;
+                            cs = cc;
+                            bs = bc;
+                            ps = pc;
+                            ++acc;
+                        }
                     }
                 }
                 zk[bt * MH_BATCH + u] = s;
