@@ -638,8 +638,9 @@ wlda_status wlda_create(const wlda_params *p, const uint32_t *word_ids, const ui
         // equally loaded.  The doc phase's 16- and 32-lane groups (used where
         // K > 1024) run at three per CU, which their LDS allows with the
         // 16-bit c_k histogram; for M > 2 the sub-workgroup bins hold half as
-        // many tokens per lane, and the 16-lane groups run at four, the wave
-        // kernel at three (measured on the PubMed-shaped corpus, K = 1e4).
+        // many tokens per lane, and the 16-lane groups and the workgroup bin
+        // run at four, the wave kernel at three (measured on the PubMed-shaped
+        // corpus, K = 1e4).
         static const uint32_t per_cu[2 * NBINS] = {3, 3, 3, 4, 3, 3, 3, 2, 3, 2};
         static const uint32_t long_per_cu[2] = {16, 8};
         int dev = 0, cus = 0;
@@ -648,7 +649,7 @@ wlda_status wlda_create(const wlda_params *p, const uint32_t *word_ids, const ui
             s->cus = (uint32_t)cus;
             for (int i = 0; i < 2 * NBINS; ++i) {
                 uint32_t pc = per_cu[i];
-                if (p->M > 2 && i == NBINS + BIN_G16) pc = 4;
+                if (p->M > 2 && (i == NBINS + BIN_G16 || i == NBINS + BIN_BLOCK)) pc = 4;
                 if (p->M > 2 && i == NBINS + BIN_WAVE) pc = 3;
                 s->seg_blocks[i] = pc * (uint32_t)cus;
             }
