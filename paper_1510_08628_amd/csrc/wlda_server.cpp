@@ -135,6 +135,10 @@ struct wlda_server_s {
     // host
     std::vector<Slot> slots;
     std::vector<uint32_t> h_off, h_len, h_req, h_sweep, h_useq, h_hoff, h_hlen;
+    // the slot list last uploaded to d_slots (valid until the retire step
+    // reuses d_slots), so that steady steps upload nothing
+    std::vector<uint32_t> up_lists;
+    bool lists_valid = false;
     Pool pool, ho_pool;
     std::deque<Pending> pending;
     std::vector<wlda_result> done;
@@ -394,16 +398,30 @@ wlda_status wlda_server_step(wlda_server s, uint32_t *n_active, uint32_t *n_pend
         if (s->slots[si].busy && !enc_now[si]) (s->slots[si].sweep == 0 ? new_list : old_list).push_back(si);
     const bool wait_deferred = !s->deferred.empty();
     const uint64_t n = s->slots.size();
-    up(s->d_off, s->h_off.data(), 4 * n, s->st);
-    up(s->d_len, s->h_len.data(), 4 * n, s->st);
-    up(s->d_req, s->h_req.data(), 4 * n, s->st);
-    up(s->d_useq, s->h_useq.data(), 4 * n, s->st);
-    up(s->d_hoff, s->h_hoff.data(), 4 * n, s->st);
-    up(s->d_hlen, s->h_hlen.data(), 4 * n, s->st);
-    for (uint32_t si : fresh) up(s->d_sweep + si, &s->h_sweep[si], 4, s->st);
+    // per-slot descriptors change only where documents were admitted: upload
+    // the range of this step's admissions (a pageable copy costs several
+    // microseconds of host time, most of a step's)
+    if (!fresh.empty()) {
+        const uint32_t lo = *std::min_element(fresh.begin(), fresh.end());
+        const uint32_t hi = *std::max_element(fresh.begin(), fresh.end()) + 1;
+        const uint64_t nb = 4ull * (hi - lo);
+        up(s->d_off + lo, s->h_off.data() + lo, nb, s->st);
+        up(s->d_len + lo, s->h_len.data() + lo, nb, s->st);
+        up(s->d_req + lo, s->h_req.data() + lo, nb, s->st);
+        up(s->d_useq + lo, s->h_useq.data() + lo, nb, s->st);
+        up(s->d_hoff + lo, s->h_hoff.data() + lo, nb, s->st);
+        up(s->d_hlen + lo, s->h_hlen.data() + lo, nb, s->st);
+        // the device advances the sweep counters of active slots: only the
+        // admitted ones are reset
+        for (uint32_t si : fresh) up(s->d_sweep + si, &s->h_sweep[si], 4, s->st);
+    }
     std::vector<uint32_t> lists(old_list);
     lists.insert(lists.end(), new_list.begin(), new_list.end());
-    up(s->d_slots, lists.data(), 4ull * lists.size(), s->st);
+    if (!s->lists_valid || lists != s->up_lists) {
+        up(s->d_slots, lists.data(), 4ull * lists.size(), s->st);
+        s->up_lists = lists;
+        s->lists_valid = true;
+    }
     // ---- encoder forward for newly admitted documents, on the encoder's
     // stream, overlapped with the sweep of the documents already in flight
     if (!e && !fresh_enc.empty()) {
@@ -513,6 +531,7 @@ wlda_status wlda_server_step(wlda_server s, uint32_t *n_active, uint32_t *n_pend
     if (!e && !retire.empty()) {
         FoldBatch br = b;
         up(s->d_slots, retire.data(), 4ull * retire.size(), s->st);
+        s->lists_valid = false;
         br.n = (uint32_t)retire.size();
         std::vector<uint32_t> hchunk(retire.size() + 1, 0);
         for (size_t r = 0; r < retire.size(); ++r)
