@@ -94,6 +94,10 @@ def lib():
         L.oracle_set_phase_state.restype = C.c_int
         L.oracle_set_alpha.argtypes = [vp, vp]
         L.oracle_set_alpha.restype = C.c_int
+        L.oracle_set_word_alias.argtypes = [vp, C.c_int]
+        L.oracle_set_word_alias.restype = C.c_int
+        L.oracle_alias_table.argtypes = [vp, u32, u64, vp, vp]
+        L.oracle_alias_table.restype = C.c_int
         L.oracle_instant_iterate.argtypes = [vp, u32]
         L.oracle_instant_iterate.restype = C.c_int
         L.oracle_foldin.argtypes = [u32, u32, u32, C.c_double, C.c_double, u64, vp, vp, vp,
@@ -123,6 +127,19 @@ def log_joint(word_ids, doc_ids, z, V, D, K, alpha, beta) -> float:
     d = np.ascontiguousarray(doc_ids, dtype=np.uint32)
     zz = np.ascontiguousarray(z, dtype=np.int32)
     return lib().oracle_log_joint(len(w), V, D, K, alpha, beta, _ptr(w), _ptr(d), _ptr(zz))
+
+
+def alias_table(counts):
+    """Walker's alias table of oracle_alias_table over integer counts (one
+    per topic, summing to L < 2^31): (thr, alias) as uint32 arrays."""
+    c = np.ascontiguousarray(counts, dtype=np.int64)
+    K = c.shape[0]
+    thr = np.zeros(K, np.uint32)
+    al = np.zeros(K, np.uint32)
+    rc = lib().oracle_alias_table(_ptr(c), K, int(c.sum()), _ptr(thr), _ptr(al))
+    if rc != 0:
+        raise ValueError("counts must be non-negative and sum to 0 < L < 2^31")
+    return thr, al
 
 
 class FrozenModel:
@@ -298,6 +315,11 @@ class Oracle:
             raise ValueError("alpha must hold K values")
         self._check(lib().oracle_set_alpha(self.h, _ptr(a)))
         self.alpha_k = a
+
+    def set_word_alias(self, on: bool):
+        """Word proposals of columns with L_w > K from Walker's alias table
+        over the updated c_w (True) or its inverse CDF (False, default)."""
+        self._check(lib().oracle_set_word_alias(self.h, int(bool(on))))
 
     def instant_iterate(self, n: int = 1):
         """n iterations of the instant-update (collapsed Gibbs-MH) variant."""

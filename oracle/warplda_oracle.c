@@ -41,6 +41,11 @@
  *     over c_w) take the inverse CDF of the updated c_w;
  *     the word-proposal mixing weight is L_w / (L_w + K beta) (the prior
  *     mass of C_wk + beta over K topics);
+ *   - optionally (oracle_set_word_alias) those words draw from Walker's alias
+ *     table over the updated c_w instead (Algorithm 2's BuildAlias and
+ *     urn.Draw), built exactly in integers by oracle_alias_table: the same
+ *     law, other random bits; the bin comes from the index word and the
+ *     position inside it from a second word (stream 1 of the same call);
  *   - all acceptance and coin arithmetic is IEEE binary32 with the exact
  *     expressions below, no fused multiply-add, strict "<";
  *   - randomness is Philox4x32-10 (Salmon et al., SC'11) with the counter
@@ -167,6 +172,80 @@ static int32_t cdf_topic(const int64_t *cum, uint32_t K, uint32_t j)
     return (int32_t)lo;
 }
 
+/* Walker's alias table (alias sampling, Section 2.2; Algorithm 2 builds one
+ * over C_w) for the counts c[0..K-1] of a column of L = sum c tokens, in
+ * integers.  Bin b carries the scaled weight x_b = c_b K, so the bins' mean
+ * weight is exactly L.  A draw picks a bin b uniformly and u uniformly from
+ * [0, L) and returns b if u < thr[b], else alias[b]; topic k is then returned
+ * with probability (thr_k + sum over bins b with alias_b = k of L - thr_b) /
+ * (K L) = c_k / L.
+ * Construction, a deterministic two-pointer sweep (the sequential "sweeping"
+ * construction of Huebschle-Schneider and Sanders, Parallel Weighted Random
+ * Sampling, ESA 2019): bins with x <= L ("light") are taken in topic order,
+ * bins with x > L ("heavy") in topic order.  The current heavy bin h, with
+ * remaining weight r, fills the next light bin i (thr_i = x_i, alias_i = h,
+ * r -= L - x_i) while r > L; once r <= L, h itself becomes a bin with
+ * thr_h = r and alias_h = the next heavy bin, whose remaining weight is its
+ * x minus the L - r it gives away.  When the heavy bins run out every bin
+ * left has x = L exactly (the weights sum to K L), and keeps itself.
+ * Returns 0, or -1 if the counts do not sum to L or L >= 2^31 (the device
+ * table keeps a flag in bit 31 of the threshold word). */
+static int alias_light(const int64_t *c, uint32_t K, uint64_t L, uint32_t b)
+{
+    return (uint64_t)c[b] * K <= L;
+}
+
+int oracle_alias_table(const int64_t *c, uint32_t K, uint64_t L, uint32_t *thr, uint32_t *alias)
+{
+    uint64_t sum = 0;
+    for (uint32_t k = 0; k < K; ++k) {
+        if (c[k] < 0) return -1;
+        sum += (uint64_t)c[k];
+    }
+    if (K == 0 || sum != L || L == 0 || L >= (1ull << 31)) return -1;
+    uint32_t i = 0, h = 0;
+    while (i < K && !alias_light(c, K, L, i)) ++i;
+    while (h < K && alias_light(c, K, L, h)) ++h;
+    if (h < K) {
+        uint64_t r = (uint64_t)c[h] * K;
+        for (;;) {
+            if (r > L) {
+                if (i >= K) return -1;             /* cannot happen: sum c = L */
+                uint64_t x = (uint64_t)c[i] * K;
+                thr[i] = (uint32_t)x;
+                alias[i] = h;
+                r -= L - x;
+                do ++i; while (i < K && !alias_light(c, K, L, i));
+            } else {
+                uint32_t hn = h + 1;
+                while (hn < K && alias_light(c, K, L, hn)) ++hn;
+                thr[h] = (uint32_t)r;
+                alias[h] = hn < K ? hn : h;
+                if (hn >= K) break;
+                r = (uint64_t)c[hn] * K - (L - r);
+                h = hn;
+            }
+        }
+    }
+    for (; i < K; ++i) {
+        if (!alias_light(c, K, L, i)) continue;
+        if ((uint64_t)c[i] * K != L) return -1;    /* cannot happen: sum c = L */
+        thr[i] = (uint32_t)L;
+        alias[i] = i;
+    }
+    return 0;
+}
+
+/* The second word of an alias draw: proposal i's position inside its bin,
+ * from the index-word slot of the same call on stream 1. */
+static uint32_t alias_u_word(uint64_t seed, uint32_t token, uint32_t iter,
+                             uint32_t phase, uint32_t i)
+{
+    uint32_t r[4];
+    rng_call(seed, token, iter, phase, (i + 1) / 2, 1, r);
+    return r[2 * ((i - 1) % 2) + 1];
+}
+
 /* ------------------------------------------------------------------------ */
 /* Sampler state                                                            */
 /* ------------------------------------------------------------------------ */
@@ -200,6 +279,10 @@ typedef struct {
      * word phase (CSC) and the doc phase (CSR), so that a corpus holding one
      * column or one row of a larger corpus draws that corpus's numbers */
     uint32_t t_off_csc, t_off_csr;
+    /* word proposals of columns with L_w > K from an alias table (1) or the
+     * inverse CDF (0) of the updated c_w */
+    int word_alias;
+    uint32_t *alias_thr, *alias_tab;   /* K each, scratch of the alias draw */
 } oracle_t;
 
 typedef struct {
@@ -284,7 +367,26 @@ void oracle_destroy(oracle_t *o)
     free(o->colptr); free(o->rowptr); free(o->row); free(o->inv);
     free(o->word_of); free(o->doc_of); free(o->z); free(o->prop); free(o->ck);
     free(o->alpha_k); free(o->alpha_cum);
+    free(o->alias_thr); free(o->alias_tab);
     free(o);
+}
+
+/* Word proposals of columns with L_w > K from Walker's alias table over the
+ * updated c_w (on != 0) or from its inverse CDF (0, the default).  Any time
+ * between phases.  Returns 0, or -1 when out of memory. */
+int oracle_set_word_alias(oracle_t *o, int on)
+{
+    if (on && !o->alias_thr) {
+        o->alias_thr = malloc(o->K * sizeof(uint32_t));
+        o->alias_tab = malloc(o->K * sizeof(uint32_t));
+        if (!o->alias_thr || !o->alias_tab) {
+            free(o->alias_thr); free(o->alias_tab);
+            o->alias_thr = o->alias_tab = NULL;
+            return -1;
+        }
+    }
+    o->word_alias = on != 0;
+    return 0;
 }
 
 /* Returns NULL on invalid input or allocation failure. */
@@ -456,9 +558,14 @@ static void word_column(oracle_t *o, uint32_t w, uint32_t iter, int64_t *ck_next
      * exceeds j.  Each token's topic occupies one unit of [0, L_w), so the
      * law is that of random positioning. */
     int by_cdf = L > o->K;
+    int by_alias = by_cdf && o->word_alias;
     if (by_cdf) {
         for (uint64_t n = 0; n < L; ++n) cw[o->z[beg + n]]++;
-        for (uint32_t k = 1; k < o->K; ++k) cw[k] += cw[k - 1];
+        if (by_alias) {
+            if (oracle_alias_table(cw, o->K, L, o->alias_thr, o->alias_tab) != 0) abort();
+        } else {
+            for (uint32_t k = 1; k < o->K; ++k) cw[k] += cw[k - 1];
+        }
     }
     for (uint64_t n = 0; n < L; ++n) {
         uint32_t t = (uint32_t)(beg + n);
@@ -467,8 +574,16 @@ static void word_column(oracle_t *o, uint32_t w, uint32_t iter, int64_t *ck_next
             draw_words(o->seed, o->t_off_csc + t, iter, PH_WORD, i, &cw_, &iw);
             int32_t prop;
             if (take_count_part(unif24(cw_), L, o->beta_k)) {
-                uint32_t j = dice(iw, (uint32_t)L);
-                prop = by_cdf ? cdf_topic(cw, o->K, j) : o->z[beg + j];
+                if (by_alias) {
+                    /* urn.Draw: a bin, then a position inside it */
+                    uint32_t b = dice(iw, o->K);
+                    uint32_t u = dice(alias_u_word(o->seed, o->t_off_csc + t, iter, PH_WORD, i),
+                                      (uint32_t)L);
+                    prop = (int32_t)(u < o->alias_thr[b] ? b : o->alias_tab[b]);
+                } else {
+                    uint32_t j = dice(iw, (uint32_t)L);
+                    prop = by_cdf ? cdf_topic(cw, o->K, j) : o->z[beg + j];
+                }
             } else {
                 prop = (int32_t)dice(iw, o->K);
             }
