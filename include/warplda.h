@@ -33,7 +33,10 @@
  *   - call j = 0 gives the M acceptance uniforms (output word i-1 for MH step
  *     i; at initialisation its word 2 gives z = Dice(K));
  *   - call j >= 1 gives the (mixture coin, index or uniform topic) words of
- *     proposals 2j-1 (output words 0, 1) and 2j (words 2, 3).
+ *     proposals 2j-1 (output words 0, 1) and 2j (words 2, 3);
+ *   - with WLDA_WORD_ALIAS, the count part of a word proposal of a word with
+ *     L_w > K takes its bin from the index word and its position inside the
+ *     bin from the same output word of the call with counter word 3 = 1.
  * t is the token's position in the order its phase visits it: the canonical
  * column-major position (tokens sorted by word, then document, then input
  * index) at initialisation and in the word phase, and the canonical row-major
@@ -93,6 +96,35 @@ wlda_status wlda_create(const wlda_params *p, const uint32_t *word_ids,
                         const uint32_t *doc_ids, uint64_t n_tokens,
                         void *dev_workspace, uint64_t workspace_bytes,
                         void *hip_stream, wlda_sampler *out);
+
+/* Options of wlda_workspace_bytes_ex / wlda_create_ex (a bit mask; 0 gives
+ * wlda_workspace_bytes / wlda_create).
+ *
+ * WLDA_WORD_ALIAS: the word proposals of words with L_w > K (Section 5.4's
+ * intra-word-parallel words) come from Walker's alias table over the K topics
+ * of the word's updated counts c_w (alias sampling, Section 2.2; Algorithm 2's
+ * BuildAlias and urn.Draw) instead of the inverse CDF of those counts.  The
+ * law of the chain is the same; the random bits used differ.  The table is
+ * exact in integers: bin k weighs c_k K against a mean of L_w; a draw takes
+ * the bin b = Dice(r, K) from the index word r and u = Dice(r', L_w) from the
+ * stream-1 word r' (see Randomness above) and returns b if u < thr_b, else
+ * alias_b.  It is built by the two-pointer sweep (light bins, c_k K <= L_w,
+ * in topic order, each topped up by the current heavy bin, heavy bins in
+ * topic order; a heavy bin left with weight r <= L_w keeps r and is topped up
+ * by the next heavy bin; bins left over weigh L_w and keep themselves), one
+ * GPU thread per word, O(K) per word and iteration.  Every word with
+ * L_w > K then runs on the long-word kernels.  Words must hold fewer than
+ * 2^31 tokens (else WLDA_E_UNSUPPORTED).  Unknown bits: WLDA_E_INVALID. */
+#define WLDA_WORD_ALIAS 1u
+
+wlda_status wlda_workspace_bytes_ex(const wlda_params *p, const uint32_t *word_ids,
+                                    const uint32_t *doc_ids, uint64_t n_tokens,
+                                    uint32_t flags, uint64_t *bytes);
+
+wlda_status wlda_create_ex(const wlda_params *p, const uint32_t *word_ids,
+                           const uint32_t *doc_ids, uint64_t n_tokens, uint32_t flags,
+                           void *dev_workspace, uint64_t workspace_bytes,
+                           void *hip_stream, wlda_sampler *out);
 
 /* Asymmetric document-topic prior (the alpha_k of Eq. (6)-(7) in their
  * general form), replacing the symmetric alpha of wlda_params.  alpha is a

@@ -15,6 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libwarplda_hip.so")
 
 WLDA_OK = 0
+WORD_ALIAS = 1          # WLDA_WORD_ALIAS: alias-table word proposals for L_w > K
 STATUS = {0: "ok", -1: "invalid argument", -2: "workspace too small or misaligned",
           -3: "HIP runtime error", -4: "call out of order", -5: "unsupported by this build",
           -6: "host memory exhausted"}
@@ -33,7 +34,8 @@ class Params(C.Structure):
 
 # Every symbol declared in include/warplda.h (checked by the CPU tests).
 EXPORTS = [
-    "wlda_workspace_bytes", "wlda_create", "wlda_set_alpha", "wlda_init", "wlda_word_phase",
+    "wlda_workspace_bytes", "wlda_create", "wlda_workspace_bytes_ex", "wlda_create_ex",
+    "wlda_set_alpha", "wlda_init", "wlda_word_phase",
     "wlda_doc_phase",
     "wlda_iterate", "wlda_log_likelihood", "wlda_copy_assignments",
     "wlda_copy_assignments_csc", "wlda_copy_topic_counts", "wlda_accepted", "wlda_iteration",
@@ -92,6 +94,8 @@ def load_library(path: str = LIB_PATH):
     sig = {
         "wlda_workspace_bytes": [P, vp, vp, u64, C.POINTER(u64)],
         "wlda_create": [P, vp, vp, u64, vp, u64, vp, C.POINTER(vp)],
+        "wlda_workspace_bytes_ex": [P, vp, vp, u64, u32, C.POINTER(u64)],
+        "wlda_create_ex": [P, vp, vp, u64, u32, vp, u64, vp, C.POINTER(vp)],
         "wlda_init": [vp], "wlda_word_phase": [vp], "wlda_doc_phase": [vp],
         "wlda_set_alpha": [vp, vp],
         "wlda_iterate": [vp, u32],
@@ -158,7 +162,7 @@ class Sampler:
     """One WarpLDA sampler on one GPU (mirrors the wlda_* calls)."""
 
     def __init__(self, word_ids, doc_ids, V, D, K, M, alpha, beta, seed=1, device="cuda:0",
-                 stream=None):
+                 stream=None, word_alias=False):
         import torch
         L = load_library()
         self.word_ids = np.ascontiguousarray(word_ids, dtype=np.uint32)
@@ -166,18 +170,19 @@ class Sampler:
         self.T = int(self.word_ids.shape[0])
         self.V, self.D, self.K, self.M = V, D, K, M
         self.params = Params(V, D, K, M, float(alpha), float(beta), int(seed))
+        self.flags = WORD_ALIAS if word_alias else 0
         nbytes = C.c_uint64(0)
-        _check("wlda_workspace_bytes",
-               L.wlda_workspace_bytes(C.byref(self.params), _ptr(self.word_ids),
-                                      _ptr(self.doc_ids), self.T, C.byref(nbytes)))
+        _check("wlda_workspace_bytes_ex",
+               L.wlda_workspace_bytes_ex(C.byref(self.params), _ptr(self.word_ids),
+                                         _ptr(self.doc_ids), self.T, self.flags, C.byref(nbytes)))
         self.device = torch.device(device)
         self.workspace = torch.empty(int(nbytes.value), dtype=torch.uint8, device=self.device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         h = C.c_void_p(0)
-        _check("wlda_create",
-               L.wlda_create(C.byref(self.params), _ptr(self.word_ids), _ptr(self.doc_ids),
-                             self.T, C.c_void_p(self.workspace.data_ptr()), int(nbytes.value),
-                             C.c_void_p(self.stream.cuda_stream), C.byref(h)))
+        _check("wlda_create_ex",
+               L.wlda_create_ex(C.byref(self.params), _ptr(self.word_ids), _ptr(self.doc_ids),
+                                self.T, self.flags, C.c_void_p(self.workspace.data_ptr()),
+                                int(nbytes.value), C.c_void_p(self.stream.cuda_stream), C.byref(h)))
         self.h = h
 
     @property

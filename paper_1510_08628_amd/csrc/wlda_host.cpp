@@ -85,8 +85,11 @@ int first_bin(uint32_t K) {
 }
 
 // Each segment goes to the first bin that holds its length (16- and 32-lane
-// groups, wave, block, wide), else to the long path.
-void build_plan(const std::vector<uint64_t> &len, uint32_t M, uint32_t K, PhasePlan &pl) {
+// groups, wave, block, wide), else to the long path.  With long_above_k every
+// segment longer than K goes to the long path (the word plan of the
+// alias-table word proposal, whose tables only the long path builds).
+void build_plan(const std::vector<uint64_t> &len, uint32_t M, uint32_t K, PhasePlan &pl,
+                bool long_above_k = false) {
     for (BinList &b : pl.bins) b.ids.clear();
     pl.long_ids.clear();
     pl.long_prefix.assign(1, 0);
@@ -94,7 +97,7 @@ void build_plan(const std::vector<uint64_t> &len, uint32_t M, uint32_t K, PhaseP
     for (uint32_t s = 0; s < len.size(); ++s) {
         const uint64_t L = len[s];
         if (L == 0) continue;
-        int bin = bin0;
+        int bin = long_above_k && L > K ? NBINS : bin0;
         while (bin < NBINS && L > bin_max_tokens(bin, M)) ++bin;
         if (bin < NBINS) {
             pl.bins[bin].ids.push_back(s);
@@ -324,6 +327,7 @@ struct wlda_sampler_s {
     // asymmetric alpha (wlda_set_alpha): alpha_k and its binary64 running
     // sums on the device, and their total
     bool asym = false;
+    bool word_alias = false;             // WLDA_WORD_ALIAS
     float *d_alpha = nullptr;
     double *d_alpha_cum = nullptr;
     double alpha_total = 0;
@@ -479,6 +483,7 @@ wlda_status run_phase(wlda_sampler s, uint32_t phase, uint32_t iter, bool draw_o
     a.beta_bar = s->beta_bar;
     a.accepted = s->acc + (phase == PH_WORD ? 0 : 1);
     a.draw_only = draw_only ? 1 : 0;
+    a.word_alias = phase == PH_WORD && s->word_alias ? 1 : 0;
     WLDA_TRY(s, launch_fill_u32(a.ck_next, 0, s->p.K, s->st));
     WLDA_TRY(s, launch_fill_u32((uint32_t *)a.accepted, 0, 2, s->st));
     const int kb = phase == PH_WORD ? 0 : NBINS;
@@ -594,27 +599,51 @@ const char *wlda_strerror(wlda_status e) {
     return "unknown status";
 }
 
-wlda_status wlda_workspace_bytes(const wlda_params *p, const uint32_t *word_ids,
-                                 const uint32_t *doc_ids, uint64_t n_tokens, uint64_t *bytes) {
+// Flags of the _ex calls: known bits, and the words an alias table can hold
+// (bit 31 of its threshold word marks a finished bin).
+wlda_status check_flags(uint32_t flags, const std::vector<uint64_t> &lw) {
+    if (flags & ~(uint32_t)WLDA_WORD_ALIAS) return WLDA_E_INVALID;
+    if (flags & WLDA_WORD_ALIAS)
+        for (uint64_t L : lw)
+            if (L >= (1ull << 31)) return WLDA_E_UNSUPPORTED;
+    return WLDA_OK;
+}
+
+wlda_status wlda_workspace_bytes_ex(const wlda_params *p, const uint32_t *word_ids,
+                                    const uint32_t *doc_ids, uint64_t n_tokens, uint32_t flags,
+                                    uint64_t *bytes) {
     if (!bytes) return WLDA_E_INVALID;
     wlda_status v = validate(p, word_ids, doc_ids, n_tokens);
     if (v != WLDA_OK) return v;
     std::vector<uint64_t> lw, ld;
     lengths(*p, word_ids, doc_ids, n_tokens, lw, ld);
+    if ((v = check_flags(flags, lw)) != WLDA_OK) return v;
     PhasePlan w, d;
-    build_plan(lw, p->M, p->K, w);
+    build_plan(lw, p->M, p->K, w, (flags & WLDA_WORD_ALIAS) != 0);
     build_plan(ld, p->M, p->K, d);
     *bytes = compute_sizes(*p, n_tokens, w, d).total;
     return WLDA_OK;
 }
 
+wlda_status wlda_workspace_bytes(const wlda_params *p, const uint32_t *word_ids,
+                                 const uint32_t *doc_ids, uint64_t n_tokens, uint64_t *bytes) {
+    return wlda_workspace_bytes_ex(p, word_ids, doc_ids, n_tokens, 0, bytes);
+}
+
 wlda_status wlda_create(const wlda_params *p, const uint32_t *word_ids, const uint32_t *doc_ids,
                         uint64_t T, void *dev_workspace, uint64_t workspace_bytes,
                         void *hip_stream, wlda_sampler *out) {
+    return wlda_create_ex(p, word_ids, doc_ids, T, 0, dev_workspace, workspace_bytes, hip_stream, out);
+}
+
+wlda_status wlda_create_ex(const wlda_params *p, const uint32_t *word_ids, const uint32_t *doc_ids,
+                           uint64_t T, uint32_t flags, void *dev_workspace, uint64_t workspace_bytes,
+                           void *hip_stream, wlda_sampler *out) {
     if (!out) return WLDA_E_INVALID;
     *out = nullptr;
     wlda_status v = validate(p, word_ids, doc_ids, T);
     if (v != WLDA_OK) return v;
+    if (flags & ~(uint32_t)WLDA_WORD_ALIAS) return WLDA_E_INVALID;
     if (!dev_workspace || ((uintptr_t)dev_workspace % ALIGN) != 0) return WLDA_E_WORKSPACE;
     wlda_sampler s = new (std::nothrow) wlda_sampler_s();
     if (!s) return WLDA_E_NOMEM;
@@ -675,7 +704,12 @@ wlda_status wlda_create(const wlda_params *p, const uint32_t *word_ids, const ui
     // ---- layout: stable order by (word, doc, input index) -------------------
     std::vector<uint64_t> lw, ld;
     lengths(*p, word_ids, doc_ids, T, lw, ld);
-    build_plan(lw, p->M, p->K, s->word);
+    if ((v = check_flags(flags, lw)) != WLDA_OK) {
+        delete s;
+        return v;
+    }
+    s->word_alias = (flags & WLDA_WORD_ALIAS) != 0;
+    build_plan(lw, p->M, p->K, s->word, s->word_alias);
     build_plan(ld, p->M, p->K, s->doc);
     for (int bin = 0; bin < NBINS; ++bin) {
         s->slot_tokens[S_WORD_BIN + bin] = list_tokens(s->word.bins[bin].ids, lw);

@@ -73,6 +73,8 @@ struct LongList {
     // threshold (word_cdf; same offsets as `tables`, which are dense for
     // those words since 2L > K), turned into inclusive
     // prefix counts for the inverse-CDF word proposals; zeroed before use.
+    // With the alias-table proposals they become the table's thresholds
+    // (ALIAS_DONE | threshold) and `tables` its alias topics.
     uint32_t *tables_new = nullptr;
 };
 
@@ -127,6 +129,7 @@ struct PhaseArgs {
     float beta_bar = 0.f;              // V beta
     unsigned long long *accepted = nullptr;
     uint32_t draw_only = 0;            // initial proposal draw (no MH)
+    uint32_t word_alias = 0;           // word phase: alias-table proposals for L > K
     uint32_t max_blocks = 2048;        // grid bound of the segment kernels (launch shape only)
     uint32_t seg_lds_budget = Tuning::SEG_LDS_BUDGET;   // LDS bytes per segment workgroup (launch shape only)
     int rf = 1;                        // record format (see record_format)
@@ -135,8 +138,9 @@ struct PhaseArgs {
 
 // Word proposals (count part): columns longer than K tokens (the words
 // Section 5.4 processes with intra-word parallelism and samples from a table
-// over c_w) take the inverse CDF of their updated counts, all others a token
-// of the updated column (random positioning); both sample the same law.
+// over c_w) take the inverse CDF of their updated counts, or with
+// WLDA_WORD_ALIAS Walker's alias table over them, all others a token of the
+// updated column (random positioning); all three sample the same law.
 __host__ __device__ inline bool word_cdf(uint32_t L, uint32_t K) { return L > K; }
 
 inline uint32_t long_chunk(uint32_t K) {

@@ -1013,7 +1013,73 @@ __global__ __launch_bounds__(256) void long_cdf_kernel(LongList l, const uint32_
     }
 }
 
-template <int PHASE, int M, int NW, typename ZT>
+// Walker's alias table (alias sampling; the word phase's BuildAlias over
+// C_w) of every long word past the inverse-CDF threshold, over its K topics,
+// exact in integers: bin k weighs c_k K against a mean of L, so a draw of a
+// uniform bin b and a uniform u in [0, L) that returns b if u < thr_b, else
+// alias_b, returns topic k with probability c_k / L.  Built by the
+// deterministic two-pointer sweep (Huebschle-Schneider and Sanders, Parallel
+// Weighted Random Sampling, ESA 2019): light bins (c K <= L) in topic order
+// are topped up by the current heavy bin (c K > L), heavy bins in topic
+// order; a heavy bin whose remaining weight r has fallen to L or below keeps
+// r and is topped up by the next heavy bin; the bins left when the heavy
+// ones run out weigh exactly L.  In place: the counts in tables_new become
+// ALIAS_DONE | threshold as each bin is finished (the flag keeps the scans
+// from reading a finished bin as unfinished), the alias topics go to
+// `tables` (the phase-start counts, consumed by the MH pass).  One thread per
+// word: the sweep is sequential, O(K) per word.
+constexpr uint32_t ALIAS_DONE = 0x80000000u;
+
+template <int M>
+__global__ __launch_bounds__(64) void long_alias_kernel(LongList l, const uint32_t *segptr, uint32_t K) {
+    const uint32_t j = blockIdx.x * 64 + threadIdx.x;
+    if (j >= l.n) return;
+    const uint32_t s_id = l.ids[j];
+    const uint32_t L = segptr[s_id + 1] - segptr[s_id];
+    if (!word_cdf(L, K)) return;
+    uint32_t *thr = l.tables_new + l.tab_off[j];
+    uint32_t *al = l.tables + l.tab_off[j];
+    const uint64_t W = L;
+    auto light = [&](uint32_t b) {
+        const uint32_t v = thr[b];
+        return v < ALIAS_DONE && (uint64_t)v * K <= W;
+    };
+    auto heavy = [&](uint32_t b) {
+        const uint32_t v = thr[b];
+        return v < ALIAS_DONE && (uint64_t)v * K > W;
+    };
+    uint32_t i = 0, h = 0;
+    while (i < K && !light(i)) ++i;
+    while (h < K && !heavy(h)) ++h;
+    if (h < K) {
+        uint64_t r = (uint64_t)thr[h] * K;
+        while (true) {
+            if (r > W) {
+                if (i >= K) break;      // unreachable: the weights sum to K L
+                const uint64_t x = (uint64_t)thr[i] * K;
+                thr[i] = ALIAS_DONE | (uint32_t)x;
+                al[i] = h;
+                r -= W - x;
+                do ++i; while (i < K && !light(i));
+            } else {
+                uint32_t hn = h + 1;
+                while (hn < K && !heavy(hn)) ++hn;
+                thr[h] = ALIAS_DONE | (uint32_t)r;
+                al[h] = hn < K ? hn : h;
+                if (hn >= K) break;
+                r = (uint64_t)thr[hn] * K - (W - r);
+                h = hn;
+            }
+        }
+    }
+    for (; i < K; ++i)
+        if (light(i)) {                 // weighs exactly L
+            thr[i] = ALIAS_DONE | L;
+            al[i] = i;
+        }
+}
+
+template <int PHASE, int M, int NW, typename ZT, bool ALIAS = false>
 __global__ __launch_bounds__(256) void long_draw_kernel(PhaseArgs a, LongList l, uint32_t ck_lds_u,
                                                         uint32_t zero_tables, uint32_t cdf_lds_u) {
     // LDS: [c_k histogram of the new Z (ck_lds) | prefix counts of the
@@ -1073,6 +1139,7 @@ __global__ __launch_bounds__(256) void long_draw_kernel(PhaseArgs a, LongList l,
             // all random-positioning reads (or CDF lookups) of the batch are
             // issued before any record is written back
             uint32_t jj[DRAW_BATCH * M] = {};
+            uint32_t uu[ALIAS ? DRAW_BATCH * M : 1] = {};
             uint32_t coin = 0;
 #pragma unroll
             for (int u = 0; u < DRAW_BATCH; ++u) {
@@ -1081,6 +1148,10 @@ __global__ __launch_bounds__(256) void long_draw_kernel(PhaseArgs a, LongList l,
 #pragma unroll
                 for (int j = 1; j <= (M + 1) / 2; ++j) {
                     const uint4 RB = philox(beg + n, a.iter, ph | j, 0, a.seed_lo, a.seed_hi);
+                    // alias draws: the position inside the bin from the same
+                    // call on stream 1
+                    uint4 RU = make_uint4(0, 0, 0, 0);
+                    if (ALIAS && by_cdf) RU = philox(beg + n, a.iter, ph | j, 1, a.seed_lo, a.seed_hi);
 #pragma unroll
                     for (int h = 0; h < 2; ++h) {
                         const int i = 2 * j - 1 + h;
@@ -1088,7 +1159,12 @@ __global__ __launch_bounds__(256) void long_draw_kernel(PhaseArgs a, LongList l,
                         const uint32_t w = word4(RB, 2 * h + 1);
                         if (take_count_part(unif24(word4(RB, 2 * h)), L, a.mass)) {
                             coin |= 1u << (u * M + i - 1);
-                            jj[u * M + i - 1] = dice(w, L);
+                            if (ALIAS && by_cdf) {
+                                jj[u * M + i - 1] = dice(w, K);
+                                uu[ALIAS ? u * M + i - 1 : 0] = dice(word4(RU, 2 * h + 1), L);
+                            } else {
+                                jj[u * M + i - 1] = dice(w, L);
+                            }
                             if (!by_cdf) set_fld(rec[u], i, (uint32_t)zs[jj[u * M + i - 1]]);
                         } else if (PHASE == PH_DOC && a.alpha_cum) {
                             set_fld(rec[u], i, alpha_prior_topic(a.alpha_cum, K, w));
@@ -1098,7 +1174,16 @@ __global__ __launch_bounds__(256) void long_draw_kernel(PhaseArgs a, LongList l,
                     }
                 }
             }
-            if (by_cdf) {
+            if (ALIAS && by_cdf) {
+                const uint32_t *thr = l.tables_new + l.tab_off[j];
+                const uint32_t *al = l.tables + l.tab_off[j];
+#pragma unroll
+                for (int d = 0; d < DRAW_BATCH * M; ++d)
+                    if ((coin >> d) & 1u) {
+                        const uint32_t b = jj[d];
+                        set_fld(rec[d / M], d % M + 1, uu[ALIAS ? d : 0] < (thr[b] & ~ALIAS_DONE) ? b : al[b]);
+                    }
+            } else if (by_cdf) {
                 if (guided)
                     cdf_find_guided<DRAW_BATCH * M>(cdfl, guide, gs, n_bkt, K, jj);
                 else if (cdf_lds)
@@ -1277,8 +1362,12 @@ static hipError_t long_dispatch_z(const PhaseArgs &a, const LongList &l, hipStre
             if ((e = hipGetLastError()) != hipSuccess) return e;
         }
         if (ev && (e = hipEventRecord(ev[2], st)) != hipSuccess) return e;
-        const bool cdf_lds = PHASE == PH_WORD && a.K <= Tuning::CDF_LDS_MAX;
-        if (PHASE == PH_WORD && !a.draw_only) {
+        const bool alias = PHASE == PH_WORD && !a.draw_only && a.word_alias;
+        const bool cdf_lds = PHASE == PH_WORD && !alias && a.K <= Tuning::CDF_LDS_MAX;
+        if (alias) {
+            hipLaunchKernelGGL(long_alias_kernel<M>, dim3((l.n + 63) / 64), dim3(64), 0, st, l, a.segptr, a.K);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+        } else if (PHASE == PH_WORD && !a.draw_only) {
             hipLaunchKernelGGL(long_cdf_kernel<M>, dim3(l.n < 1024 ? l.n : 1024), dim3(256), 0, st, l, a.segptr,
                                a.K);
             if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -1288,15 +1377,23 @@ static hipError_t long_dispatch_z(const PhaseArgs &a, const LongList &l, hipStre
         // long draw 0.357 -> 0.316 ms at K = 1000, slower at K = 1e4)
         const bool guided = cdf_lds && a.K <= Tuning::GUIDE_K_MAX;
         const size_t lds = 4ull * ((ck_lds ? a.K : 0) + (cdf_lds ? a.K : 0) + (guided ? GUIDE_MAX / 2 : 0));
-        e = launch_dyn(long_draw_kernel<PHASE, M, NW, ZT>, lds);
-        if (e != hipSuccess) return e;
-        // the global guides live in the tables until the draw is done: clear
-        // them after it instead of inside it
+        // the global guides and the alias topics live in the tables until the
+        // draw is done: clear them after it instead of inside it
         const bool guides_g = PHASE == PH_WORD && !a.draw_only && !cdf_lds;
-        hipLaunchKernelGGL((long_draw_kernel<PHASE, M, NW, ZT>), dim3(blocks), dim3(256), lds, st, a, l,
-                           (uint32_t)ck_lds, (uint32_t)(a.draw_only || guides_g ? 0 : 1),
-                           (uint32_t)cdf_lds | (uint32_t)guided << 1);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
+        auto draw = [&](auto kern) -> hipError_t {
+            hipError_t e2 = launch_dyn(kern, lds);
+            if (e2 != hipSuccess) return e2;
+            hipLaunchKernelGGL(kern, dim3(blocks), dim3(256), lds, st, a, l, (uint32_t)ck_lds,
+                               (uint32_t)(a.draw_only || guides_g ? 0 : 1),
+                               (uint32_t)cdf_lds | (uint32_t)guided << 1);
+            return hipGetLastError();
+        };
+        if constexpr (PHASE == PH_WORD) {
+            e = alias ? draw(long_draw_kernel<PHASE, M, NW, ZT, true>) : draw(long_draw_kernel<PHASE, M, NW, ZT>);
+        } else {
+            e = draw(long_draw_kernel<PHASE, M, NW, ZT>);
+        }
+        if (e != hipSuccess) return e;
         if (guides_g && (e = launch_fill_u32(l.tables, 0, l.table_words, st)) != hipSuccess) return e;
         if (ev) return hipEventRecord(ev[3], st);
         return hipSuccess;

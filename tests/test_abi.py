@@ -96,3 +96,31 @@ def test_workspace_grows_with_long_segments(lib):
     rc2, big = _ws(lib, V=64, D=64, K=100000, words=[0] * T, docs=list(np.arange(T) % 64))
     assert rc1 == rc2 == 0
     assert big > small
+
+
+def test_option_flags(lib):
+    """wlda_workspace_bytes_ex: flag 0 is wlda_workspace_bytes; the alias-table
+    word proposal moves the words with L_w > K to the long-word kernels (their
+    count tables enter the workspace); unknown bits are refused."""
+    K = 300
+    w = np.array([0] * 1000 + [1, 2], np.uint32)  # word 0: L_w = 1000 > K
+    d = np.array([0, 1] * 501, np.uint32)
+    params = W.Params(3, 2, K, 2, 0.1, 0.1, 1)
+    out = C.c_uint64(0)
+
+    def ws(flags):
+        rc = lib.wlda_workspace_bytes_ex(C.byref(params), w.ctypes.data_as(C.c_void_p),
+                                         d.ctypes.data_as(C.c_void_p), len(w), flags,
+                                         C.byref(out))
+        return rc, out.value
+
+    rc0, plain = ws(0)
+    assert rc0 == 0 and (0, plain) == _ws(lib, V=3, D=2, K=K, words=list(w), docs=list(d))
+    rc1, alias = ws(W.WORD_ALIAS)
+    assert rc1 == 0 and alias > plain
+    assert ws(2)[0] == -1 and ws(0x80000000)[0] == -1
+    h = C.c_void_p()
+    rc = lib.wlda_create_ex(C.byref(params), w.ctypes.data_as(C.c_void_p),
+                            d.ctypes.data_as(C.c_void_p), len(w), 4, C.c_void_p(0), 1 << 20, None,
+                            C.byref(h))
+    assert rc == -1
