@@ -146,13 +146,15 @@ def cpu_baseline(c1, args):
     return out
 
 
-def measure(W, c, wl, M, steps, warmup, dev, tag):
+def measure(W, c, wl, M, steps, warmup, dev, tag, word_alias=False):
     """Throughput of `steps` iterations after `warmup`, with the per-kernel
     times (HIP events around every launch on the sampler's stream), the
-    roofline of the kernel that takes the most time and of the whole sweep."""
+    roofline of the kernel that takes the most time and of the whole sweep.
+    word_alias: word proposals of words with L_w > K from alias tables."""
     import torch
     t0 = time.perf_counter()
-    s = W.Sampler(c.word_ids, c.doc_ids, c.V, c.D, wl.K, M, wl.alpha, wl.beta, seed=1, device=dev)
+    s = W.Sampler(c.word_ids, c.doc_ids, c.V, c.D, wl.K, M, wl.alpha, wl.beta, seed=1, device=dev,
+                  word_alias=word_alias)
     s.init()
     torch.cuda.synchronize()
     t_create = time.perf_counter() - t0
@@ -515,6 +517,13 @@ def main():
             r["traffic"] = measured_traffic(key, r["dominant"]["kernel"])
             configs[key] = r
             del ec
+        # the same workload with Walker's alias tables for the words with
+        # L_w > K (all of them on the long-word kernels) instead of the
+        # inverse CDF: the cost of the paper's own word proposal
+        r = measure(W, c, wl, M, args.extra_steps, 1, dev, "alias", word_alias=True)
+        r["workload"] = args.workload
+        r["word_proposal"] = "alias table (words with L_w > K)"
+        configs[args.workload + "-word-alias"] = r
         out["configs"] = configs
     if not args.no_serving:
         out["serving"] = serving_experiment(W, dev, args)

@@ -1023,22 +1023,15 @@ __global__ __launch_bounds__(256) void long_cdf_kernel(LongList l, const uint32_
 // are topped up by the current heavy bin (c K > L), heavy bins in topic
 // order; a heavy bin whose remaining weight r has fallen to L or below keeps
 // r and is topped up by the next heavy bin; the bins left when the heavy
-// ones run out weigh exactly L.  In place: the counts in tables_new become
+// ones run out weigh exactly L.  In place: thr holds the counts on entry and
 // ALIAS_DONE | threshold as each bin is finished (the flag keeps the scans
-// from reading a finished bin as unfinished), the alias topics go to
-// `tables` (the phase-start counts, consumed by the MH pass).  One thread per
-// word: the sweep is sequential, O(K) per word.
+// from reading a finished bin as unfinished); alias receives the alias
+// topics.  Sequential, O(K).
 constexpr uint32_t ALIAS_DONE = 0x80000000u;
+// K up to which a word's table is swept in LDS (8 bytes per topic)
+constexpr uint32_t ALIAS_LDS_MAX = 8192;
 
-template <int M>
-__global__ __launch_bounds__(64) void long_alias_kernel(LongList l, const uint32_t *segptr, uint32_t K) {
-    const uint32_t j = blockIdx.x * 64 + threadIdx.x;
-    if (j >= l.n) return;
-    const uint32_t s_id = l.ids[j];
-    const uint32_t L = segptr[s_id + 1] - segptr[s_id];
-    if (!word_cdf(L, K)) return;
-    uint32_t *thr = l.tables_new + l.tab_off[j];
-    uint32_t *al = l.tables + l.tab_off[j];
+__device__ __forceinline__ void alias_sweep(uint32_t *thr, uint32_t *al, uint32_t K, uint32_t L) {
     const uint64_t W = L;
     auto light = [&](uint32_t b) {
         const uint32_t v = thr[b];
@@ -1077,6 +1070,42 @@ __global__ __launch_bounds__(64) void long_alias_kernel(LongList l, const uint32
             thr[i] = ALIAS_DONE | L;
             al[i] = i;
         }
+}
+
+// The tables of the long words: the updated counts in tables_new become the
+// thresholds and the alias topics go to `tables` (the phase-start counts,
+// consumed by the MH pass).  K <= ALIAS_LDS_MAX: one workgroup per word loads
+// its counts into LDS, one lane sweeps there, all write the table back;
+// larger K: one thread per word sweeps in global memory.
+template <int M>
+__global__ __launch_bounds__(64) void long_alias_kernel(LongList l, const uint32_t *segptr, uint32_t K,
+                                                        uint32_t lds_u) {
+    extern __shared__ uint32_t sh[];
+    if (lds_u) {
+        uint32_t *thr = sh, *al = sh + K;
+        for (uint32_t j = blockIdx.x; j < l.n; j += gridDim.x) {
+            const uint32_t s_id = l.ids[j];
+            const uint32_t L = segptr[s_id + 1] - segptr[s_id];
+            if (!word_cdf(L, K)) continue;
+            uint32_t *gthr = l.tables_new + l.tab_off[j], *gal = l.tables + l.tab_off[j];
+            for (uint32_t k = threadIdx.x; k < K; k += 64) thr[k] = gthr[k];
+            __syncthreads();
+            if (threadIdx.x == 0) alias_sweep(thr, al, K, L);
+            __syncthreads();
+            for (uint32_t k = threadIdx.x; k < K; k += 64) {
+                gthr[k] = thr[k];
+                gal[k] = al[k];
+            }
+            __syncthreads();
+        }
+        return;
+    }
+    const uint32_t j = blockIdx.x * 64 + threadIdx.x;
+    if (j >= l.n) return;
+    const uint32_t s_id = l.ids[j];
+    const uint32_t L = segptr[s_id + 1] - segptr[s_id];
+    if (!word_cdf(L, K)) return;
+    alias_sweep(l.tables_new + l.tab_off[j], l.tables + l.tab_off[j], K, L);
 }
 
 template <int PHASE, int M, int NW, typename ZT, bool ALIAS = false>
@@ -1365,7 +1394,10 @@ static hipError_t long_dispatch_z(const PhaseArgs &a, const LongList &l, hipStre
         const bool alias = PHASE == PH_WORD && !a.draw_only && a.word_alias;
         const bool cdf_lds = PHASE == PH_WORD && !alias && a.K <= Tuning::CDF_LDS_MAX;
         if (alias) {
-            hipLaunchKernelGGL(long_alias_kernel<M>, dim3((l.n + 63) / 64), dim3(64), 0, st, l, a.segptr, a.K);
+            const bool alias_lds = a.K <= ALIAS_LDS_MAX;
+            const uint32_t grid = alias_lds ? (l.n < 65536 ? l.n : 65536) : (l.n + 63) / 64;
+            hipLaunchKernelGGL(long_alias_kernel<M>, dim3(grid), dim3(64), alias_lds ? 8ull * a.K : 0, st, l,
+                               a.segptr, a.K, (uint32_t)alias_lds);
             if ((e = hipGetLastError()) != hipSuccess) return e;
         } else if (PHASE == PH_WORD && !a.draw_only) {
             hipLaunchKernelGGL(long_cdf_kernel<M>, dim3(l.n < 1024 ? l.n : 1024), dim3(256), 0, st, l, a.segptr,
