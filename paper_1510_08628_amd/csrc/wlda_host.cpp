@@ -609,9 +609,9 @@ wlda_status check_flags(uint32_t flags, const std::vector<uint64_t> &lw) {
     return WLDA_OK;
 }
 
-wlda_status wlda_workspace_bytes_ex(const wlda_params *p, const uint32_t *word_ids,
-                                    const uint32_t *doc_ids, uint64_t n_tokens, uint32_t flags,
-                                    uint64_t *bytes) {
+static wlda_status workspace_bytes_impl(const wlda_params *p, const uint32_t *word_ids,
+                                        const uint32_t *doc_ids, uint64_t n_tokens, uint32_t flags,
+                                        uint64_t *bytes) {
     if (!bytes) return WLDA_E_INVALID;
     wlda_status v = validate(p, word_ids, doc_ids, n_tokens);
     if (v != WLDA_OK) return v;
@@ -623,6 +623,16 @@ wlda_status wlda_workspace_bytes_ex(const wlda_params *p, const uint32_t *word_i
     build_plan(ld, p->M, p->K, d);
     *bytes = compute_sizes(*p, n_tokens, w, d).total;
     return WLDA_OK;
+}
+
+wlda_status wlda_workspace_bytes_ex(const wlda_params *p, const uint32_t *word_ids,
+                                    const uint32_t *doc_ids, uint64_t n_tokens, uint32_t flags,
+                                    uint64_t *bytes) {
+    try {
+        return workspace_bytes_impl(p, word_ids, doc_ids, n_tokens, flags, bytes);
+    } catch (const std::bad_alloc &) {
+        return WLDA_E_NOMEM;
+    }
 }
 
 wlda_status wlda_workspace_bytes(const wlda_params *p, const uint32_t *word_ids,
@@ -703,14 +713,22 @@ wlda_status wlda_create_ex(const wlda_params *p, const uint32_t *word_ids, const
 
     // ---- layout: stable order by (word, doc, input index) -------------------
     std::vector<uint64_t> lw, ld;
-    lengths(*p, word_ids, doc_ids, T, lw, ld);
-    if ((v = check_flags(flags, lw)) != WLDA_OK) {
+    std::vector<uint32_t> colptr, rowptr;
+    try {
+        lengths(*p, word_ids, doc_ids, T, lw, ld);
+        if ((v = check_flags(flags, lw)) != WLDA_OK) {
+            delete s;
+            return v;
+        }
+        s->word_alias = (flags & WLDA_WORD_ALIAS) != 0;
+        build_plan(lw, p->M, p->K, s->word, s->word_alias);
+        build_plan(ld, p->M, p->K, s->doc);
+        colptr.resize(p->V + 1);
+        rowptr.resize(p->D + 1);
+    } catch (const std::bad_alloc &) {
         delete s;
-        return v;
+        return WLDA_E_NOMEM;
     }
-    s->word_alias = (flags & WLDA_WORD_ALIAS) != 0;
-    build_plan(lw, p->M, p->K, s->word, s->word_alias);
-    build_plan(ld, p->M, p->K, s->doc);
     for (int bin = 0; bin < NBINS; ++bin) {
         s->slot_tokens[S_WORD_BIN + bin] = list_tokens(s->word.bins[bin].ids, lw);
         s->slot_tokens[S_DOC_BIN + bin] = list_tokens(s->doc.bins[bin].ids, ld);
@@ -724,7 +742,6 @@ wlda_status wlda_create_ex(const wlda_params *p, const uint32_t *word_ids, const
         delete s;
         return WLDA_E_WORKSPACE;
     }
-    std::vector<uint32_t> colptr(p->V + 1), rowptr(p->D + 1);
     colptr[0] = rowptr[0] = 0;
     for (uint32_t w = 0; w < p->V; ++w) colptr[w + 1] = colptr[w] + (uint32_t)lw[w];
     for (uint32_t d = 0; d < p->D; ++d) rowptr[d + 1] = rowptr[d] + (uint32_t)ld[d];
