@@ -1072,11 +1072,150 @@ __device__ __forceinline__ void alias_sweep(uint32_t *thr, uint32_t *al, uint32_
         }
 }
 
+// The sweep's table in closed form, built by a whole workgroup.  With the
+// light bins in topic order l_1, l_2, ... of deficits L - x and running
+// deficit D(k) over the first k of them, and the heavy bins h_1, h_2, ... of
+// excesses x - L and running excess E(j), the sweep gives
+//   light l_k: thr = x, alias = h_j for the first j with E(j) > D(k-1)
+//              (none: x = L, it keeps itself);
+//   heavy h_j: thr = L + E(j) - D(k_j), k_j the first k with D(k) >= E(j),
+//              alias = h_{j+1}; the last heavy bin: thr = L, itself,
+// since h_j is the current heavy bin exactly while D(k-1) < E(j) and its
+// remaining weight after the k-th light bin is L + E(j) - D(k).  The running
+// sums are block-wide scans, the two searches binary searches: the same
+// table as alias_sweep, with every lane busy.  256 threads, 16 topics each.
+constexpr uint32_t ALIAS_PAR_MAX = 4096;
+constexpr uint32_t ALIAS_PAR_TPT = ALIAS_PAR_MAX / 256;
+
+__device__ __forceinline__ void alias_closed_form(const uint32_t *gcnt, uint32_t *gthr, uint32_t *gal,
+                                                  uint32_t K, uint32_t L, uint32_t *sh) {
+    // LDS: Darr[K] u64 | Earr[K] u64 | harr[K] u32 | scan: nl[256] u32, sd[256] u64, se[256] u64
+    unsigned long long *Darr = reinterpret_cast<unsigned long long *>(sh);
+    unsigned long long *Earr = Darr + K;
+    uint32_t *harr = reinterpret_cast<uint32_t *>(Earr + K);
+    unsigned long long *ssd = reinterpret_cast<unsigned long long *>(harr + ((K + 1) & ~1u));
+    unsigned long long *sse = ssd + 256;
+    uint32_t *snl = reinterpret_cast<uint32_t *>(sse + 256);
+    const uint32_t t = threadIdx.x, k0 = t * ALIAS_PAR_TPT;
+    const uint64_t W = L;
+    uint32_t c[ALIAS_PAR_TPT];
+    uint32_t nl = 0;
+    unsigned long long sd = 0, se = 0;
+#pragma unroll
+    for (uint32_t q = 0; q < ALIAS_PAR_TPT; ++q) {
+        const uint32_t k = k0 + q;
+        c[q] = k < K ? gcnt[k] : 0u;
+        if (k >= K) continue;
+        const uint64_t x = (uint64_t)c[q] * K;
+        if (x <= W) {
+            ++nl;
+            sd += W - x;
+        } else {
+            se += x - W;
+        }
+    }
+    // inclusive scans over the 256 threads, then exclusive bases
+    snl[t] = nl;
+    ssd[t] = sd;
+    sse[t] = se;
+    __syncthreads();
+    for (uint32_t off = 1; off < 256; off <<= 1) {
+        const uint32_t a = t >= off ? snl[t - off] : 0u;
+        const unsigned long long b = t >= off ? ssd[t - off] : 0ull, e = t >= off ? sse[t - off] : 0ull;
+        __syncthreads();
+        snl[t] += a;
+        ssd[t] += b;
+        sse[t] += e;
+        __syncthreads();
+    }
+    const uint32_t n_light = snl[255], n_heavy = K - n_light;
+    uint32_t lr = snl[t] - nl, hr = k0 < K ? k0 - lr : 0u;
+    unsigned long long D = ssd[t] - sd, E = sse[t] - se;
+#pragma unroll
+    for (uint32_t q = 0; q < ALIAS_PAR_TPT; ++q) {
+        const uint32_t k = k0 + q;
+        if (k >= K) continue;
+        const uint64_t x = (uint64_t)c[q] * K;
+        if (x <= W) {
+            D += W - x;
+            Darr[lr++] = D;
+        } else {
+            E += x - W;
+            Earr[hr] = E;
+            harr[hr++] = k;
+        }
+    }
+    __syncthreads();
+    lr = snl[t] - nl;
+    hr = k0 < K ? k0 - lr : 0u;
+#pragma unroll
+    for (uint32_t q = 0; q < ALIAS_PAR_TPT; ++q) {
+        const uint32_t k = k0 + q;
+        if (k >= K) continue;
+        const uint64_t x = (uint64_t)c[q] * K;
+        uint32_t thr, al;
+        if (x <= W) {
+            const unsigned long long Db = Darr[lr++] - (W - x);   // D(k-1)
+            uint32_t lo = 0, hi = n_heavy;                          // first j: Earr[j] > Db
+            while (lo < hi) {
+                const uint32_t mid = (lo + hi) >> 1;
+                if (Earr[mid] > Db) hi = mid;
+                else lo = mid + 1;
+            }
+            if (lo < n_heavy) {
+                thr = (uint32_t)x;
+                al = harr[lo];
+            } else {
+                thr = L;
+                al = k;
+            }
+        } else {
+            const uint32_t j = hr++;
+            if (j + 1 == n_heavy) {
+                thr = L;
+                al = k;
+            } else {
+                const unsigned long long Ej = Earr[j];
+                uint32_t lo = 0, hi = n_light;                      // first r: Darr[r] >= Ej
+                while (lo < hi) {
+                    const uint32_t mid = (lo + hi) >> 1;
+                    if (Darr[mid] >= Ej) hi = mid;
+                    else lo = mid + 1;
+                }
+                thr = (uint32_t)(W + Ej - Darr[lo]);
+                al = harr[j + 1];
+            }
+        }
+        gthr[k] = ALIAS_DONE | thr;
+        gal[k] = al;
+    }
+}
+
+// LDS bytes of alias_closed_form for K topics.
+__host__ __device__ inline size_t alias_par_lds(uint32_t K) {
+    return 16ull * K + 4ull * ((K + 1) & ~1u) + 256 * (8 + 8 + 4);
+}
+
 // The tables of the long words: the updated counts in tables_new become the
 // thresholds and the alias topics go to `tables` (the phase-start counts,
-// consumed by the MH pass).  K <= ALIAS_LDS_MAX: one workgroup per word loads
-// its counts into LDS, one lane sweeps there, all write the table back;
+// consumed by the MH pass).  K <= ALIAS_PAR_MAX: one 256-thread workgroup per
+// word builds the closed form; K <= ALIAS_LDS_MAX: one workgroup per word
+// loads its counts into LDS, one lane sweeps there, all write the table back;
 // larger K: one thread per word sweeps in global memory.
+template <int M>
+__global__ __launch_bounds__(256) void long_alias_par_kernel(LongList l, const uint32_t *segptr, uint32_t K) {
+    extern __shared__ unsigned long long shq[];      // 8-byte aligned for the running sums
+    uint32_t *sh = reinterpret_cast<uint32_t *>(shq);
+    for (uint32_t j = blockIdx.x; j < l.n; j += gridDim.x) {
+        const uint32_t s_id = l.ids[j];
+        const uint32_t L = segptr[s_id + 1] - segptr[s_id];
+        if (!word_cdf(L, K)) continue;
+        uint32_t *gthr = l.tables_new + l.tab_off[j], *gal = l.tables + l.tab_off[j];
+        alias_closed_form(gthr, gthr, gal, K, L, sh);
+        __syncthreads();
+    }
+}
+
 template <int M>
 __global__ __launch_bounds__(64) void long_alias_kernel(LongList l, const uint32_t *segptr, uint32_t K,
                                                         uint32_t lds_u) {
@@ -1393,7 +1532,13 @@ static hipError_t long_dispatch_z(const PhaseArgs &a, const LongList &l, hipStre
         if (ev && (e = hipEventRecord(ev[2], st)) != hipSuccess) return e;
         const bool alias = PHASE == PH_WORD && !a.draw_only && a.word_alias;
         const bool cdf_lds = PHASE == PH_WORD && !alias && a.K <= Tuning::CDF_LDS_MAX;
-        if (alias) {
+        if (alias && a.K <= ALIAS_PAR_MAX) {
+            const size_t lds = alias_par_lds(a.K);
+            if ((e = launch_dyn(long_alias_par_kernel<M>, lds)) != hipSuccess) return e;
+            hipLaunchKernelGGL(long_alias_par_kernel<M>, dim3(l.n < 65536 ? l.n : 65536), dim3(256), lds, st, l,
+                               a.segptr, a.K);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+        } else if (alias) {
             const bool alias_lds = a.K <= ALIAS_LDS_MAX;
             const uint32_t grid = alias_lds ? (l.n < 65536 ? l.n : 65536) : (l.n + 63) / 64;
             hipLaunchKernelGGL(long_alias_kernel<M>, dim3(grid), dim3(64), alias_lds ? 8ull * a.K : 0, st, l,

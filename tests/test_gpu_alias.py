@@ -45,8 +45,10 @@ def run_pair(W, c, K, M, seed, iters=3):
 
 
 # small K (most words longer than K: hundreds of long words, also ones of
-# K + 1 tokens), the record formats of M = 1..4, K past the LDS limits of the
-# long path, and K > 65535 (32-bit compact topics, 21-bit fields)
+# K + 1 tokens), the record formats of M = 1..4 (tables built by a whole
+# workgroup in closed form, K <= 4096); below, K = 6000 (one lane sweeps in
+# LDS), K past the LDS limits of the long path and K > 65535 (one thread per
+# word sweeps in global memory; 32-bit compact topics, 21-bit fields)
 @pytest.mark.parametrize("K,M", [(8, 2), (1, 1), (60, 1), (1000, 2), (256, 3), (2000, 4)])
 def test_alias_word_proposals_bit_exact(W, K, M):
     c = mixed_corpus(K + 17 * M)
@@ -54,7 +56,8 @@ def test_alias_word_proposals_bit_exact(W, K, M):
     run_pair(W, c, K, M, seed=K * 5 + M)
 
 
-@pytest.mark.parametrize("K,M,head", [(20000, 2, 60000), (70000, 3, 100000)])
+@pytest.mark.parametrize("K,M,head", [(20000, 2, 60000), (70000, 3, 100000), (4096, 2, 30000),
+                                      (6000, 4, 40000)])
 def test_alias_long_column_longer_than_large_K(W, K, M, head):
     c = head_word_corpus(K + M, head)
     run_pair(W, c, K, M, seed=K + M, iters=2)
