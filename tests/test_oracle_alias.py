@@ -194,3 +194,46 @@ def test_alias_mode_changes_bits_not_the_counts_it_reads():
     assert np.array_equal(z0, z1)           # same MH outcomes (same doc proposals)
     assert np.array_equal(p0[:, L:], p1[:, L:])
     assert not np.array_equal(p0[:, :L], p1[:, :L])
+
+
+def _closed_form(c):
+    """The sweep's table from running sums alone (the construction the GPU
+    uses for K <= 4096): light bins l_1, l_2, ... in topic order with running
+    deficit D, heavy bins h_1, h_2, ... with running excess E; light l_k
+    aliases the first h_j with E(j) > D(k-1) (none: it keeps itself at L);
+    heavy h_j keeps L + E(j) - D(k_j), k_j the first k with D(k) >= E(j),
+    and aliases h_{j+1}; the last heavy bin keeps L."""
+    c = np.asarray(c, np.int64)
+    K, L = len(c), int(c.sum())
+    x = c * K
+    lights, heavies = np.nonzero(x <= L)[0], np.nonzero(x > L)[0]
+    D, E = np.cumsum(L - x[lights]), np.cumsum(x[heavies] - L)
+    thr, al = np.zeros(K, np.int64), np.zeros(K, np.int64)
+    for r, t in enumerate(lights):
+        j = np.searchsorted(E, D[r] - (L - x[t]), side="right")
+        thr[t], al[t] = (x[t], heavies[j]) if j < len(heavies) else (L, t)
+    for j, t in enumerate(heavies):
+        if j == len(heavies) - 1:
+            thr[t], al[t] = L, t
+        else:
+            k = np.searchsorted(D, E[j], side="left")
+            thr[t], al[t] = L + E[j] - D[k], heavies[j + 1]
+    return thr, al
+
+
+def test_closed_form_equals_the_sweep():
+    rng = np.random.default_rng(11)
+    for it in range(600):
+        K = int(rng.integers(1, 60))
+        L = int(rng.integers(K + 1, 5 * K + 50))
+        if it % 3 == 0:
+            c = rng.multinomial(L, rng.dirichlet(np.full(K, 0.3)))
+        elif it % 3 == 1:
+            c = rng.multinomial(L, np.full(K, 1.0 / K))
+        else:
+            p = rng.dirichlet(np.full(K, 1.0)) * (rng.random(K) < 0.3)
+            p[0] += 1e-9
+            c = rng.multinomial(L, p / p.sum())
+        thr, al = oracle.alias_table(c)
+        t2, a2 = _closed_form(c)
+        assert np.array_equal(thr, t2) and np.array_equal(al, a2), c
