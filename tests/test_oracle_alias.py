@@ -5,7 +5,9 @@ with L_w > K.
 Pins, none of which reuses the oracle's construction:
 * the law of a table, by enumerating every (bin, position) pair of the draw:
   topic k must come out exactly c_k * K times out of K * L;
-* two tables worked by hand from the two-pointer sweep;
+* three tables worked by hand from the two-pointer sweep;
+* the closed form of the sweep's table (running deficits and excesses, the
+  construction the GPU uses for K <= 4096) equals the oracle's table;
 * the chain law in alias mode against the exact binary64 enumeration (the
   table samples the same law as the inverse CDF, so the chain is unchanged);
 * the random-word layout of a draw (bin from the index word, position from
