@@ -369,7 +369,8 @@ wlda_status wlda_encoder_train_step(wlda_encoder e, uint32_t B, const uint32_t *
  * token pool are free.  Each wlda_server_step() admits what fits, runs the
  * encoder for the newly admitted documents (learned mode, on the encoder's
  * stream, overlapped with the sweep of the documents already in flight;
- * documents encoded at admission start their sweeps at the next step),
+ * documents encoded at admission start their sweeps at the first step that
+ * finds their encoder run finished),
  * runs ONE fold-in sweep for every admitted document in one ragged launch,
  * and retires documents that have had their initialisation and `sweeps`
  * sweeps (their z and held-out log likelihood are kept for the caller).

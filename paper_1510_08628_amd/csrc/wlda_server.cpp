@@ -12,9 +12,9 @@
 // queue are encoded one step ahead, into one of two stage buffers, so that
 // by their admission the proposal is usually ready and the step does not
 // wait for the encoder; a request admitted before it was encoded is encoded
-// at admission and starts its sweeps at the next step, its first launch
-// waiting on an event, so the encoder overlaps the step's sweep instead of
-// holding it up.  A document's result
+// at admission and joins the sweeps at the first step that finds its encoder
+// run finished (an event query on the host), so the encoder overlaps the
+// sweeps instead of holding up the documents in flight.  A document's result
 // depends only on its words and request id (its random stream), not on the
 // batch it shared or on when it was encoded.
 #include <hip/hip_runtime.h>
@@ -105,11 +105,14 @@ struct wlda_server_s {
     wlda_encoder enc = nullptr;
     wlda_server_params sp{};
     hipStream_t st = nullptr, enc_st = nullptr;
-    // encoder results of the documents admitted at a step (two, alternating):
-    // those documents start their sweeps at the next step, after the event
+    // encoder runs for the documents admitted at a step (two events,
+    // alternating); documents encoded at admission wait, out of the sweep
+    // lists, until the host sees the latest such run finished (the encoder
+    // stream runs in order, so that run finishing covers the earlier ones)
     hipEvent_t enc_ev[2] = {nullptr, nullptr};
     int enc_cur = 0;                 // the event this step records
-    std::vector<uint32_t> deferred;  // documents encoded last step
+    std::vector<uint32_t> deferred;  // documents encoded at admission, not yet sweeping
+    hipEvent_t deferred_ev = nullptr;  // the encoder run they wait for
     uint32_t K = 0, M = 0, buckets = 0;
     // device
     uint32_t *d_slots = nullptr, *d_off = nullptr, *d_len = nullptr, *d_req = nullptr, *d_sweep = nullptr,
@@ -391,12 +394,21 @@ wlda_status wlda_server_step(wlda_server s, uint32_t *n_active, uint32_t *n_pend
     // Documents encoded at admission start their sweeps at the next step: the
     // encoder then overlaps this step's sweep instead of holding up the new
     // documents of the step (their launch waits for it on the device).
+    bool deferred_ready = false;
+    if (!e && !s->deferred.empty()) {
+        const hipError_t q = hipEventQuery(s->deferred_ev);
+        if (q == hipSuccess)
+            deferred_ready = true;
+        else if (q != hipErrorNotReady)
+            e = q;
+    }
     std::vector<char> enc_now(s->slots.size(), 0);
     for (uint32_t si : fresh_enc) enc_now[si] = 1;
+    if (!deferred_ready)
+        for (uint32_t si : s->deferred) enc_now[si] = 1;
     std::vector<uint32_t> old_list, new_list;
     for (uint32_t si = 0; si < s->slots.size(); ++si)
         if (s->slots[si].busy && !enc_now[si]) (s->slots[si].sweep == 0 ? new_list : old_list).push_back(si);
-    const bool wait_deferred = !s->deferred.empty();
     const uint64_t n = s->slots.size();
     // per-slot descriptors change only where documents were admitted: upload
     // the range of this step's admissions (a pageable copy costs several
@@ -509,9 +521,6 @@ wlda_status wlda_server_step(wlda_server s, uint32_t *n_active, uint32_t *n_pend
     const FoldModel &fm = model_internal(s->model);
     b.n = (uint32_t)old_list.size();
     if (!e) e = fold_launch(fm, b, s->st);
-    // the documents encoded last step wait for that encoder run (the other
-    // event than the one recorded above)
-    if (!e && wait_deferred) e = hipStreamWaitEvent(s->st, s->enc_ev[1 - s->enc_cur], 0);
     if (!e && !new_list.empty()) {
         FoldBatch bn = b;
         bn.slots = s->d_slots + old_list.size();
@@ -520,8 +529,12 @@ wlda_status wlda_server_step(wlda_server s, uint32_t *n_active, uint32_t *n_pend
     }
     for (uint32_t si : old_list) s->slots[si].sweep++;
     for (uint32_t si : new_list) s->slots[si].sweep++;
-    s->deferred = fresh_enc;
-    if (!fresh_enc.empty()) s->enc_cur = 1 - s->enc_cur;
+    if (deferred_ready) s->deferred.clear();
+    if (!fresh_enc.empty()) {
+        s->deferred.insert(s->deferred.end(), fresh_enc.begin(), fresh_enc.end());
+        s->deferred_ev = s->enc_ev[s->enc_cur];
+        s->enc_cur = 1 - s->enc_cur;
+    }
     // ---- retire documents that have had init + `sweeps` sweeps
     std::vector<uint32_t> retire;
     for (uint32_t si : lists)
