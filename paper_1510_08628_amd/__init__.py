@@ -159,7 +159,11 @@ def _ptr(a: np.ndarray):
 
 
 class Sampler:
-    """One WarpLDA sampler on one GPU (mirrors the wlda_* calls)."""
+    """One WarpLDA sampler on one GPU (mirrors the wlda_* calls).
+
+    word_alias=True creates it with WLDA_WORD_ALIAS: the word proposals of
+    words with L_w > K come from Walker's alias table over the updated c_w
+    (Algorithm 2's BuildAlias / urn.Draw) instead of its inverse CDF."""
 
     def __init__(self, word_ids, doc_ids, V, D, K, M, alpha, beta, seed=1, device="cuda:0",
                  stream=None, word_alias=False):
