@@ -1254,7 +1254,10 @@ __global__ __launch_bounds__(256) void long_draw_kernel(PhaseArgs a, LongList l,
     // current word (cdf_lds, words past the inverse-CDF threshold) | their
     // guide table (bit 1 of cdf_lds_u)]
     extern __shared__ uint32_t ckh[];
-    const bool ck_lds = ck_lds_u != 0, cdf_lds = (cdf_lds_u & 1u) != 0, guided = (cdf_lds_u & 2u) != 0;
+    // ck_lds_u: 1 = c_k histogram of the new Z in LDS, 0 = global atomics,
+    // 2 = none (long_ck_kernel counts the compact z array instead)
+    const bool ck_lds = ck_lds_u == 1, ck_none = ck_lds_u == 2;
+    const bool cdf_lds = (cdf_lds_u & 1u) != 0, guided = (cdf_lds_u & 2u) != 0;
     const uint32_t K = a.K;
     uint32_t *cdfl = ckh + (ck_lds ? K : 0);
     uint16_t *guide = reinterpret_cast<uint16_t *>(cdfl + K);
@@ -1369,7 +1372,7 @@ __global__ __launch_bounds__(256) void long_draw_kernel(PhaseArgs a, LongList l,
                 const uint32_t z = fld(rec[u], 0);
                 if (ck_lds)
                     atomicAdd(&ckh[z], 1u);
-                else
+                else if (!ck_none)
                     atomicAdd(&a.ck_next[z], 1u);
             }
         }
@@ -1389,6 +1392,33 @@ __global__ __launch_bounds__(256) void long_draw_kernel(PhaseArgs a, LongList l,
     }
 }
 
+
+// The c_k histogram of the long segments' new Z, from the compact array the
+// MH pass wrote (every long token's new topic once), for draws that leave it
+// out: an LDS histogram per workgroup, eight topics per 16-byte load, flushed
+// with one global add per nonzero topic.
+template <typename ZT>
+__global__ __launch_bounds__(256) void long_ck_kernel(const ZT *zc, uint32_t total, uint32_t K, uint32_t *ck_next) {
+    extern __shared__ uint32_t hk[];
+    for (uint32_t k = threadIdx.x; k < K; k += 256) hk[k] = 0;
+    __syncthreads();
+    constexpr uint32_t PER = 16 / sizeof(ZT);
+    const uint32_t nvec = total / PER;
+    const uint4 *zv = reinterpret_cast<const uint4 *>(zc);
+    for (uint32_t v = blockIdx.x * 256 + threadIdx.x; v < nvec; v += gridDim.x * 256) {
+        const uint4 q = zv[v];
+        const ZT *e = reinterpret_cast<const ZT *>(&q);
+#pragma unroll
+        for (uint32_t i = 0; i < PER; ++i) atomicAdd(&hk[e[i]], 1u);
+    }
+    for (uint32_t i = nvec * PER + blockIdx.x * 256 + threadIdx.x; i < total; i += gridDim.x * 256)
+        atomicAdd(&hk[zc[i]], 1u);
+    __syncthreads();
+    for (uint32_t k = threadIdx.x; k < K; k += 256) {
+        const uint32_t c = hk[k];
+        if (c) atomicAdd(&ck_next[k], c);
+    }
+}
 
 // --------------------------------------------------------------------------
 // Launchers of the kernels above (instantiated per M in wlda_kernels_m.hip)
@@ -1553,14 +1583,20 @@ static hipError_t long_dispatch_z(const PhaseArgs &a, const LongList &l, hipStre
         // chunk costs less than the binary-search steps it saves (measured:
         // long draw 0.357 -> 0.316 ms at K = 1000, slower at K = 1e4)
         const bool guided = cdf_lds && a.K <= Tuning::GUIDE_K_MAX;
-        const size_t lds = 4ull * ((ck_lds ? a.K : 0) + (cdf_lds ? a.K : 0) + (guided ? GUIDE_MAX / 2 : 0));
+        // where both the c_k histogram and the prefix counts would sit in LDS
+        // (4096 < K <= 16384), the histogram comes from a pass over the
+        // compact z array instead: the draw then needs half the LDS and runs
+        // twice as many workgroups per CU
+        const bool ck_split = PHASE == PH_WORD && !a.draw_only && cdf_lds && ck_lds && !guided;
+        const bool ck_draw = ck_lds && !ck_split;
+        const size_t lds = 4ull * ((ck_draw ? a.K : 0) + (cdf_lds ? a.K : 0) + (guided ? GUIDE_MAX / 2 : 0));
         // the global guides and the alias topics live in the tables until the
         // draw is done: clear them after it instead of inside it
         const bool guides_g = PHASE == PH_WORD && !a.draw_only && !cdf_lds;
         auto draw = [&](auto kern) -> hipError_t {
             hipError_t e2 = launch_dyn(kern, lds);
             if (e2 != hipSuccess) return e2;
-            hipLaunchKernelGGL(kern, dim3(blocks), dim3(256), lds, st, a, l, (uint32_t)ck_lds,
+            hipLaunchKernelGGL(kern, dim3(blocks), dim3(256), lds, st, a, l, ck_split ? 2u : (uint32_t)ck_draw,
                                (uint32_t)(a.draw_only || guides_g ? 0 : 1),
                                (uint32_t)cdf_lds | (uint32_t)guided << 1);
             return hipGetLastError();
@@ -1571,6 +1607,12 @@ static hipError_t long_dispatch_z(const PhaseArgs &a, const LongList &l, hipStre
             e = draw(long_draw_kernel<PHASE, M, NW, ZT>);
         }
         if (e != hipSuccess) return e;
+        if (ck_split) {
+            const uint32_t gb = a.max_blocks < 256 ? a.max_blocks : 256;
+            hipLaunchKernelGGL(long_ck_kernel<ZT>, dim3(gb), dim3(256), 4ull * a.K, st,
+                               reinterpret_cast<const ZT *>(l.zc), l.total, a.K, a.ck_next);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+        }
         if (guides_g && (e = launch_fill_u32(l.tables, 0, l.table_words, st)) != hipSuccess) return e;
         if (ev) return hipEventRecord(ev[3], st);
         return hipSuccess;
